@@ -1,0 +1,640 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests re-types the oracle's formulas: each one checks the oracle
+against a closed form, an invariant, a library routine on a special case, a
+value the paper prints, or brute force on a tiny input.  All run on the CPU.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as la
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synthetic as S
+from oracle import Oracle, OracleError
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+@pytest.fixture(scope="module")
+def paper():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def small(n=(8, 8), **kw):
+    p = S.preset("square32", n=n, **kw)
+    co, ce = S.make_mesh(p)
+    return p, co, ce, Oracle(co, ce, p)
+
+
+# ---------------------------------------------------------------- presets
+def test_presets_hold_paper_parameters(paper):
+    p = S.PRESETS["square32"]
+    for k in ("chi_pn", "chi_ps", "chi_ns", "Np", "Nn", "Ns", "eps"):
+        assert p[k] == paper["parameters"][k], k
+    lo, hi = paper["time_step_range"]["lo"], paper["time_step_range"]["hi"]
+    assert lo <= p["tau"] <= hi
+
+
+def test_mesh_counts_match_configs():
+    co, ce = S.mesh_rect_2d(32, 32)
+    assert co.shape == (1089, 2) and ce.shape == (2048, 3)
+    co, ce = S.mesh_box_3d(4, 3, 2)
+    assert co.shape == (5 * 4 * 3, 3) and ce.shape == (6 * 24, 4)
+    # Kuhn tetrahedra tile each box: volumes add up to the box volume
+    vols = []
+    for c in ce:
+        J = (co[c[1:]] - co[c[0]]).T
+        vols.append(abs(np.linalg.det(J)) / 6.0)
+    assert np.isclose(sum(vols), 1.0, rtol=1e-13)
+    assert min(vols) > 0
+
+
+def test_initial_fractions_sum_to_one():
+    php, phn, phs = S.initial_fractions(1000, 0.1, 0.1)
+    assert np.allclose(php + phn + phs, 1.0, atol=1e-15)
+    assert abs(php.mean() - 0.1) < 2e-3 and abs(phs.mean() - 0.8) < 2e-3
+    assert php.min() > 0.08 and php.max() < 0.12
+
+
+# ---------------------------------------------------------------- element and global matrices
+def test_element_matrices_right_triangle_by_hand():
+    h = 0.25
+    xv = np.array([[0, 0], [h, 0], [h, h]], float)
+    MT, KT, vol = O.element_matrices(xv)
+    assert np.isclose(vol, h * h / 2)
+    # lambda0 = 1 - x/h, lambda1 = (x - y)/h, lambda2 = y/h
+    K_hand = np.array([[0.5, -0.5, 0.0], [-0.5, 1.0, -0.5], [0.0, -0.5, 0.5]])
+    M_hand = (h * h / 2) / 12 * np.array([[2, 1, 1], [1, 2, 1], [1, 1, 2]])
+    assert np.allclose(KT, K_hand, atol=1e-15)
+    assert np.allclose(MT, M_hand, atol=1e-17)
+
+
+def test_element_matrices_reference_tet_by_hand():
+    xv = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    MT, KT, vol = O.element_matrices(xv)
+    assert np.isclose(vol, 1 / 6)
+    g = np.array([[-1, -1, -1], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    assert np.allclose(KT, g @ g.T / 6, atol=1e-15)
+    assert np.allclose(MT, (np.eye(4) + 1) / 120, atol=1e-16)
+
+
+def test_global_2d_stencils_closed_form():
+    n = 8
+    h = 1.0 / n
+    p, co, ce, o = small((n, n))
+    M = o.scipy_matrix("M").toarray()
+    K = o.scipy_matrix("K").toarray()
+    i = 4 * (n + 1) + 4                       # an interior vertex
+    nb = {i - 1: -1, i + 1: -1, i - (n + 1): -1, i + (n + 1): -1,
+          i + n + 2: 0, i - n - 2: 0}        # the right-diagonal neighbours carry 0 in K
+    assert np.isclose(K[i, i], 4.0)
+    for j, v in nb.items():
+        assert abs(K[i, j] - v) < 1e-14
+        assert np.isclose(M[i, j], h * h / 12)
+    assert np.isclose(M[i, i], h * h / 2)
+    assert np.count_nonzero(M[i]) == 7
+    rp, ci, _ = o.matrix("K")
+    assert rp[i + 1] - rp[i] == 7               # the zero entries of K stay in the pattern
+
+
+def test_global_3d_stencils_closed_form():
+    n = 4
+    h = 1.0 / n
+    co, ce = S.mesh_box_3d(n, n, n)
+    o = Oracle(co, ce, S.preset("square32"))
+    M = o.scipy_matrix("M").toarray()
+    K = o.scipy_matrix("K").toarray()
+    i = (2 * (n + 1) + 2) * (n + 1) + 2
+    rp, _, _ = o.matrix("M")
+    assert rp[i + 1] - rp[i] == 15
+    assert np.isclose(K[i, i], 6 * h)
+    face = [i - 1, i + 1, i - (n + 1), i + (n + 1), i - (n + 1) ** 2, i + (n + 1) ** 2]
+    for j in face:
+        assert np.isclose(K[i, j], -h)
+    others = [j for j in np.nonzero(M[i])[0] if j != i and j not in face]
+    assert len(others) == 8 and np.allclose(K[i, others], 0.0, atol=1e-15)
+    assert np.isclose(M[i, i], 2 * h ** 3 / 5)
+    assert np.isclose(M[i].sum(), h ** 3)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_global_invariants(dim):
+    if dim == 2:
+        co, ce = S.mesh_rect_2d(7, 5, 2.0, 0.5)
+        vol = 1.0
+    else:
+        co, ce = S.mesh_box_3d(3, 4, 2, 1.0, 1.0, 0.5)
+        vol = 0.5
+    o = Oracle(co, ce, S.preset("square32"))
+    M = o.scipy_matrix("M")
+    K = o.scipy_matrix("K")
+    one = np.ones(o.nv)
+    assert np.abs(K @ one).max() < 1e-12
+    assert np.isclose(one @ (M @ one), vol, rtol=1e-13)
+    assert abs(M - M.T).max() < 1e-17 and abs(K - K.T).max() < 1e-14
+    assert la.eigvalsh(K.toarray()).min() > -1e-12
+    # Wathen's bound for P1 mass matrices: eig(D^-1 M) in [1/2, 2] (2D), [1/2, 5/2] (3D)
+    d = M.diagonal()
+    ev = la.eigvalsh(M.toarray(), np.diag(d))
+    assert ev.min() >= 0.5 - 1e-12 and ev.max() <= (2.0 if dim == 2 else 2.5) + 1e-12
+
+
+# ---------------------------------------------------------------- quadrature and potential
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quadrature_exact_on_barycentric_monomials(dim):
+    bary, w = O.quadrature(dim)
+    assert np.isclose(w.sum(), 1.0, rtol=1e-15)
+    assert (bary >= -1e-15).all() and np.allclose(bary.sum(axis=1), 1.0)
+    for deg in range(6):
+        for alpha in itertools.product(range(deg + 1), repeat=dim + 1):
+            if sum(alpha) != deg:
+                continue
+            num = np.sum(w * np.prod(bary ** np.array(alpha), axis=1))
+            # integral over T of prod lambda^alpha / |T| = alpha! d! / (|alpha| + d)!
+            exact = (np.prod([math.factorial(a) for a in alpha]) * math.factorial(dim)
+                     / math.factorial(deg + dim))
+            assert abs(num - exact) < 1e-15, (alpha, num, exact)
+
+
+@pytest.mark.parametrize("pot", ["flory_huggins", "polynomial"])
+def test_potential_derivatives_match_finite_differences(pot):
+    p = S.preset("square32", potential=pot)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a, b = rng.uniform(0.05, 0.45, size=2)
+        f, fp, fn = O.potential(p, a, b)
+        h = 1e-6
+        # total derivative: phi_s = 1 - phi_p - phi_n moves with each unknown
+        dfp = (O.potential(p, a + h, b)[0] - O.potential(p, a - h, b)[0]) / (2 * h)
+        dfn = (O.potential(p, a, b + h)[0] - O.potential(p, a, b - h)[0]) / (2 * h)
+        assert abs(fp - dfp) < 1e-7 * max(1, abs(fp)), (a, b, fp, dfp)
+        assert abs(fn - dfn) < 1e-7 * max(1, abs(fn)), (a, b, fn, dfn)
+
+
+def test_potential_values_from_the_paper(paper):
+    p = S.preset("square32", potential="polynomial")
+    a, b = 0.3, 0.2
+    s = 1 - a - b
+    c = paper["polynomial_potential"]
+    assert np.isclose(O.potential(p, a, b)[0], c["coef_pn"] * a * a * b * b + c["coef_s"] * s * s)
+    q = S.preset("square32")
+    par = paper["parameters"]
+    fh = (a * math.log(a) / par["Np"] + b * math.log(b) / par["Nn"] + s * math.log(s) / par["Ns"]
+          + par["chi_pn"] * a * b + par["chi_ps"] * a * s + par["chi_ns"] * b * s)
+    assert np.isclose(O.potential(q, a, b)[0], fh, rtol=1e-14)
+
+
+def _poly_mul(p, q):
+    out = {}
+    for a, ca in p.items():
+        for b, cb in q.items():
+            k = tuple(x + y for x, y in zip(a, b))
+            out[k] = out.get(k, 0.0) + ca * cb
+    return out
+
+
+def _poly_int(p, dim):
+    tot = 0.0
+    for a, c in p.items():
+        tot += c * np.prod([math.factorial(x) for x in a]) * math.factorial(dim) / math.factorial(sum(a) + dim)
+    return tot
+
+
+def test_rhs_polynomial_potential_exact_integration():
+    """f_j for the polynomial potential integrated exactly in barycentric monomials."""
+    p, co, ce, o = small((4, 3), potential="polynomial", tau=2e-4, eps=5e-3)
+    php, phn, _ = S.initial_fractions(o.nv, 0.3, 0.25, amplitude=0.05, seed=7)
+    bp, bn = o.rhs(php, phn)
+    M = o.scipy_matrix("M")
+    fp = np.zeros(o.nv)
+    fn = np.zeros(o.nv)
+    for c in ce:
+        J = (co[c[1:]] - co[c[0]]).T
+        vol = abs(np.linalg.det(J)) / 2
+        lin = lambda vals: {tuple(int(k == a) for k in range(3)): vals[a] for a in range(3)}
+        P = lin(php[c])
+        Nn = lin(phn[c])
+        Sv = {(0, 0, 0): 1.0}
+        for k, v in P.items():
+            Sv[k] = Sv.get(k, 0.0) - v
+        for k, v in Nn.items():
+            Sv[k] = Sv.get(k, 0.0) - v
+        # 1 = lambda0 + lambda1 + lambda2: homogenise the constant term
+        one = {(1, 0, 0): 1.0, (0, 1, 0): 1.0, (0, 0, 1): 1.0}
+        Sv = {k: v for k, v in Sv.items() if k != (0, 0, 0)}
+        Sv = {**Sv}
+        for k, v in one.items():
+            Sv[k] = Sv.get(k, 0.0) + v
+        dfp = _poly_mul(_poly_mul(P, Nn), Nn)
+        dfp = {k: 7 * v for k, v in dfp.items()}
+        for k, v in Sv.items():
+            dfp[k] = dfp.get(k, 0.0) - 0.2 * v
+        dfn = _poly_mul(_poly_mul(P, P), Nn)
+        dfn = {k: 7 * v for k, v in dfn.items()}
+        for k, v in Sv.items():
+            dfn[k] = dfn.get(k, 0.0) - 0.2 * v
+        for a in range(3):
+            lam = {tuple(int(k == a) for k in range(3)): 1.0}
+            fp[c[a]] += vol * _poly_int(_poly_mul(dfp, lam), 2)
+            fn[c[a]] += vol * _poly_int(_poly_mul(dfn, lam), 2)
+    te = p["tau"] / p["eps"]
+    n = o.nv
+    assert np.allclose(bp[:n], M @ php, rtol=1e-14, atol=1e-18)
+    assert np.allclose(bn[:n], M @ phn, rtol=1e-14, atol=1e-18)
+    assert np.allclose(bp[n:], -te * fp, rtol=1e-12, atol=1e-17)
+    assert np.allclose(bn[n:], -te * fn, rtol=1e-12, atol=1e-17)
+
+
+def test_rhs_constant_state_flory_huggins():
+    p, co, ce, o = small((5, 4))
+    c_p, c_n = 0.12, 0.09
+    php = np.full(o.nv, c_p)
+    phn = np.full(o.nv, c_n)
+    bp, bn = o.rhs(php, phn)
+    _, fp, fn = O.potential(p, c_p, c_n)
+    m1 = o.scipy_matrix("M") @ np.ones(o.nv)
+    te = p["tau"] / p["eps"]
+    assert np.allclose(bp[o.nv:], -te * fp * m1, rtol=1e-13)
+    assert np.allclose(bn[o.nv:], -te * fn * m1, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- AMG hierarchy
+def _level_mats(o, hier, lev):
+    d = o.level(hier, lev)
+    A = sp.csr_matrix((d["A"][2], d["A"][1], d["A"][0]), shape=(d["n"], d["n"]))
+    P = None
+    if "P" in d:
+        P = sp.csr_matrix((d["P"][2], d["P"][1], d["P"][0]), shape=(d["n"], d["nc"]))
+    return d, A, P
+
+
+@pytest.mark.parametrize("hier", [0, 1])
+def test_hierarchy_invariants(hier):
+    p, co, ce, o = small((40, 37), coarse_max=20)
+    nlev = o.num_levels(hier)
+    assert nlev >= 3
+    Bc = np.ones(o.nv)
+    for lev in range(nlev - 1):
+        d, A, P = _level_mats(o, hier, lev)
+        agg = d["agg"]
+        nc = d["nc"]
+        sizes = np.bincount(agg, minlength=nc)
+        assert (agg >= 0).all() and (sizes > 0).all()          # a partition into nc aggregates
+        assert nc < d["n"]
+        # Gershgorin bound is an upper bound of the spectrum of D^-1 A
+        Ad = A.toarray()
+        lam = la.eigvalsh(Ad, np.diag(np.diag(Ad))).max()
+        assert lam <= d["rho"] * (1 + 1e-12)
+        # the smoothed prolongator reproduces (I - omega D^-1 A) B on the near-null vector
+        B = Bc
+        Bn = np.sqrt(np.bincount(agg, B * B, minlength=nc))
+        omega = 4.0 / (3.0 * d["rho"])
+        target = B - omega * (A @ B) / A.diagonal()
+        assert np.allclose(P @ Bn, target, rtol=1e-12, atol=1e-14 * np.abs(B).max())
+        # each aggregate is connected in the matrix graph
+        G = (abs(A) > 0).astype(int)
+        for a in np.unique(agg)[:50]:
+            idx = np.nonzero(agg == a)[0]
+            ncomp, _ = sp.csgraph.connected_components(G[idx][:, idx], directed=False)
+            assert ncomp == 1
+        # Galerkin coarse operator, symbolic pattern of P^T A P
+        _, Ac, _ = _level_mats(o, hier, lev + 1)
+        ref = (P.T @ A @ P).toarray()
+        assert np.abs(Ac.toarray() - ref).max() <= 1e-12 * np.abs(ref).max()
+        pat = (abs(P).T @ abs(A) @ abs(P) != 0)
+        assert (Ac.toarray() != 0).sum() <= pat.nnz
+        assert Ac.nnz == pat.nnz
+        assert la.eigvalsh(Ac.toarray()).min() > 0
+        Bc = Bn
+
+
+def test_aggregation_roots_form_distance2_mis():
+    """Brute force on a tiny mesh: the aggregates come from roots pairwise at
+    graph distance >= 3 that dominate every vertex within distance 2."""
+    p, co, ce, o = small((6, 5), coarse_max=4)
+    d, A, P = _level_mats(o, 0, 0)
+    G = (abs(A) > 0).astype(float)
+    D = sp.csgraph.shortest_path(G, unweighted=True)
+    agg = d["agg"]
+    # in each aggregate a root is adjacent to all members that are adjacent to no other root;
+    # recover the root set as the vertices whose aggregate is exactly their closed neighbourhood core
+    roots = []
+    for a in range(d["nc"]):
+        idx = np.nonzero(agg == a)[0]
+        cand = [i for i in idx if all(D[i, j] <= 2 for j in idx)]
+        assert cand, a
+        roots.append(cand)
+    # choose one root per aggregate greedily and verify the distance-2 independence of some choice
+    chosen = [c[0] for c in roots]
+    for i, j in itertools.combinations(range(len(chosen)), 2):
+        if D[chosen[i], chosen[j]] < 3:
+            alt = [r for r in roots[j] if all(D[r, chosen[k]] >= 3 for k in range(len(chosen)) if k != j)]
+            assert alt, (i, j)
+    assert (D[:, chosen].min(axis=1) <= 2).all()
+
+
+@pytest.mark.parametrize("hier", [0, 1])
+def test_vcycle_is_symmetric_positive_contraction(hier):
+    p, co, ce, o = small((12, 11), coarse_max=30)
+    n = o.nv
+    A = o.scipy_matrix("M" if hier == 0 else "As0").toarray()
+    V = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        V[:, j] = o.vcycle(hier, e)
+    assert np.abs(V - V.T).max() <= 1e-12 * np.abs(V).max()
+    ev = np.sort(la.eigvals(V @ A).real)
+    assert ev.min() > 0.0 and ev.max() <= 1.0 + 1e-10
+    assert 1.0 - ev.min() < 0.8          # the cycle contracts the error
+
+
+def test_schur_solve_reduces_error_in_energy_norm():
+    p, co, ce, o = small((16, 16))
+    As = o.scipy_matrix("As0")
+    b = np.random.default_rng(0).standard_normal(o.nv)
+    x_ex = spla.spsolve(As.tocsc(), b)
+    x1 = o.vcycle(1, b)
+    x3 = o.schur_solve(0, b)
+    en = lambda e: math.sqrt(e @ (As @ e))
+    assert en(x3 - x_ex) < 0.2 * en(x_ex)
+    assert en(x3 - x_ex) < en(x1 - x_ex)
+
+
+# ---------------------------------------------------------------- preconditioner theory
+def test_lemma1_and_ideal_preconditioner_spectrum(paper):
+    p, co, ce, o = small((10, 10))
+    tau, eps = p["tau"], p["eps"]
+    M = o.scipy_matrix("M").toarray()
+    K = o.scipy_matrix("K").toarray()
+    As = o.scipy_matrix("As0").toarray()
+    Sch = (tau / eps) * M + tau ** 2 * K @ np.linalg.solve(M, K)
+    St = As @ np.linalg.solve(M, As)
+    ev = la.eigvalsh(Sch, St)
+    lo, hi = paper["lemma1_interval"]["lo"], paper["lemma1_interval"]["hi"]
+    assert ev.min() >= lo - 1e-9 and ev.max() <= hi + 1e-9
+    A = np.block([[M, tau * K], [tau * K, -(tau / eps) * M]])
+    Pid = la.block_diag(M, Sch)
+    ev = np.sort(la.eigvals(np.linalg.solve(Pid, A)).real)
+    g = (1 + math.sqrt(5)) / 2
+    neg, pos = ev[ev < 0], ev[ev > 0]
+    assert neg.min() >= -1 - 1e-9 and neg.max() <= 1 - g + 1e-9
+    assert pos.min() >= 1 - 1e-9 and pos.max() <= g + 1e-9
+
+
+def test_saddle_operator_matches_block_form():
+    p, co, ce, o = small((6, 7), tau=3e-4, eps=2e-3, mobility=(1.5, 0.5))
+    M = o.scipy_matrix("M")
+    K = o.scipy_matrix("K")
+    x = np.random.default_rng(1).standard_normal(2 * o.nv)
+    for s, mob in enumerate((1.5, 0.5)):
+        t = p["tau"] * mob
+        A = sp.bmat([[M, t * K], [t * K, -(t / p["eps"]) * M]])
+        assert np.allclose(o.apply_saddle(s, x), A @ x, rtol=1e-13, atol=1e-18)
+
+
+# ---------------------------------------------------------------- solver and time step
+def _saddle(o, p, s=0):
+    t = p["tau"] * (p["mobility"] if not isinstance(p["mobility"], tuple) else p["mobility"][s])
+    M = o.scipy_matrix("M")
+    K = o.scipy_matrix("K")
+    return sp.bmat([[M, t * K], [t * K, -(t / p["eps"]) * M]]).tocsc()
+
+
+@pytest.mark.parametrize("rtol", [1e-8, 1e-14])
+def test_fgmres_against_sparse_lu(rtol):
+    p, co, ce, o = small((16, 16), rtol=rtol)
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    bp, bn = o.rhs(php, phn)
+    A = _saddle(o, p)
+    x_ex = spla.splu(A).solve(bp)
+    x0 = np.concatenate([php, np.zeros(o.nv)])
+    x, it, rr = o.fgmres(0, bp, x0)
+    assert rr <= rtol * 1.0000001
+    assert np.linalg.norm(bp - A @ x) <= rtol * np.linalg.norm(bp) * 1.0000001
+    kappa = np.linalg.cond(A.toarray())
+    err = np.linalg.norm(x - x_ex) / np.linalg.norm(x_ex)
+    assert err <= kappa * rtol
+    if rtol < 1e-12:
+        assert err < 1e-11
+    assert 5 <= it <= 60
+
+
+def test_step_against_sparse_lu():
+    p, co, ce, o = small((12, 12), rtol=1e-13)
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    bp, bn = o.rhs(php, phn)
+    A = _saddle(o, p)
+    lu = spla.splu(A)
+    xp, xn = lu.solve(bp), lu.solve(bn)
+    out = o.step(st)
+    n = o.nv
+    for got, ref in ((out["phi_p"], xp[:n]), (out["mu_p"], xp[n:]), (out["phi_n"], xn[:n]),
+                     (out["mu_n"], xn[n:])):
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_constant_state_is_a_fixed_point():
+    p, co, ce, o = small((9, 9))
+    c_p, c_n = 0.2, 0.15
+    st = dict(phi_p=np.full(o.nv, c_p), phi_n=np.full(o.nv, c_n),
+              mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    out = o.step(st)
+    _, fp, fn = O.potential(p, c_p, c_n)
+    assert np.abs(out["phi_p"] - c_p).max() < 1e-8 * c_p
+    assert np.abs(out["phi_n"] - c_n).max() < 1e-8 * c_n
+    assert np.abs(out["mu_p"] - fp).max() < 1e-6 * abs(fp)
+    assert np.abs(out["mu_n"] - fn).max() < 1e-6 * abs(fn)
+
+
+def test_mass_conservation_no_flux():
+    p, co, ce, o = small((16, 16))
+    M = o.scipy_matrix("M")
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    m0 = (M @ php).sum(), (M @ phn).sum()
+    for _ in range(3):
+        bp, bn = o.rhs(st["phi_p"], st["phi_n"])
+        st = o.step(st)
+        # 1^T M phi^{k+1} - 1^T M phi^k = 1^T r1, and ||r|| <= rtol ||b||
+        bound = math.sqrt(o.nv) * p["rtol"] * np.linalg.norm(bp) * 1.01
+        assert abs((M @ st["phi_p"]).sum() - m0[0]) <= 3 * bound
+        assert abs((M @ st["phi_n"]).sum() - m0[1]) <= 3 * bound
+
+
+def test_energy_decays_on_square32():
+    p = S.preset("square32")
+    co, ce = S.make_mesh(p)
+    o = Oracle(co, ce, p)
+    php, phn, _ = S.initial_fractions(o.nv, p["mean_p"], p["mean_n"])
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    E = [o.energy(php, phn)]
+    for _ in range(p["steps"]):
+        st = o.step(st)
+        E.append(o.energy(st["phi_p"], st["phi_n"]))
+    assert all(b <= a + 1e-15 * abs(a) for a, b in zip(E, E[1:])), E
+
+
+def test_manufactured_solution_second_order_in_space():
+    """f = 0, no flux: phi = exp(-4 pi^4 eps t) cos(pi x) cos(pi y), tau ~ h^2."""
+    eps, T = 1e-2, 0.05
+    errs = []
+    for n in (8, 16, 32):
+        steps = 4 * (n // 8) ** 2
+        p = S.preset("square32", n=(n, n), potential="none", eps=eps, tau=T / steps, rtol=1e-12)
+        co, ce = S.make_mesh(p)
+        o = Oracle(co, ce, p)
+        u0 = np.cos(math.pi * co[:, 0]) * np.cos(math.pi * co[:, 1])
+        st = dict(phi_p=u0.copy(), phi_n=0.5 * u0, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+        for _ in range(steps):
+            st = o.step(st)
+        ex = math.exp(-4 * math.pi ** 4 * eps * T) * u0
+        M = o.scipy_matrix("M")
+        e = st["phi_p"] - ex
+        errs.append(math.sqrt(e @ (M @ e)))
+        em = st["mu_p"] - 2 * math.pi ** 2 * eps * ex
+        assert math.sqrt(em @ (M @ em)) < 0.2 * 2 * math.pi ** 2 * eps
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.7 < r < 2.4 for r in rates), (errs, rates)
+
+
+def test_temporal_order_close_to_one(paper):
+    """IMEX Euler is first order; the paper measured 0.789 / 0.788."""
+    T = 4e-3
+    sols = {}
+    for steps in (4, 8, 16, 128):
+        p = S.preset("square32", n=(12, 12), potential="polynomial", tau=T / steps, rtol=1e-12,
+                     eps=1e-2)
+        co, ce = S.make_mesh(p)
+        o = Oracle(co, ce, p)
+        php, phn, _ = S.initial_fractions(o.nv, 0.35, 0.35)
+        st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+        for _ in range(steps):
+            st = o.step(st)
+        sols[steps] = st["phi_p"]
+    e = [np.linalg.norm(sols[s] - sols[128]) for s in (4, 8, 16)]
+    eoc = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert all(0.7 < r < 1.2 for r in eoc), eoc
+    assert abs(eoc[-1] - paper["temporal_eoc"]["phi_p"]) < 0.35
+
+
+# ---------------------------------------------------------------- failures and determinism
+def test_nonconvergence_reports_and_keeps_state():
+    p, co, ce, o = small((10, 10), max_iters=2)
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    with pytest.raises(OracleError) as ei:
+        o.step(st)
+    assert ei.value.code == -4
+    assert np.array_equal(st["phi_p"], php)
+
+
+def test_nan_input_is_detected():
+    p, co, ce, o = small((6, 6))
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    php[3] = np.nan
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    with pytest.raises(OracleError) as ei:
+        o.step(st)
+    assert ei.value.code == -5
+
+
+def test_evaporation_removes_solvent_uniformly():
+    p, co, ce, o = small((8, 8), evap_ds=0.01, steps=2)
+    php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    q, _, _, oq = small((8, 8))
+    ref = oq.step(dict(st))
+    out = o.step(dict(st))
+    s_ref = 1 - ref["phi_p"] - ref["phi_n"]
+    s_out = 1 - out["phi_p"] - out["phi_n"]
+    assert np.allclose(s_ref - s_out, 0.01, atol=1e-14)
+    ratio = out["phi_p"] / out["phi_n"]
+    assert np.allclose(ratio, ref["phi_p"] / ref["phi_n"], rtol=1e-13)
+    out = o.step(out)                         # second (last) evaporating step
+    out3 = o.step(out)                        # evap_steps = 2: the third step removes nothing
+    ref3 = oq.step(dict(out))
+    assert np.array_equal(out3["phi_p"], ref3["phi_p"])
+    assert np.array_equal(out3["phi_n"], ref3["phi_n"])
+
+
+def test_runs_are_bitwise_deterministic():
+    outs = []
+    for _ in range(2):
+        p, co, ce, o = small((10, 9))
+        php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
+        st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+        outs.append(o.step(st))
+    for k in ("phi_p", "phi_n", "mu_p", "mu_n"):
+        assert np.array_equal(outs[0][k], outs[1][k])
+
+
+# ---------------------------------------------------------------- smoother, inner CG, Algorithm 1
+@pytest.mark.parametrize("hier,degree,ratio", [(1, 4, 30.0), (0, 2, 4.0), (1, 3, 10.0)])
+def test_chebyshev_smoother_error_polynomial(hier, degree, ratio):
+    """Error propagation of the smoother is T_k((theta - D^-1 A)/delta) / T_k(theta/delta)."""
+    key = "cheb_degree" if hier == 1 else "cheb_degree_mass"
+    rkey = "cheb_ratio" if hier == 1 else "cheb_ratio_mass"
+    p, co, ce, o = small((7, 6), **{key: degree, rkey: ratio})
+    d = o.level(hier, 0)
+    A = sp.csr_matrix((d["A"][2], d["A"][1], d["A"][0]), shape=(d["n"], d["n"])).toarray()
+    n = d["n"]
+    E = np.zeros((n, n))
+    for j in range(n):                     # e -> e - S(A e) with x0 = 0 (b = A e)
+        e = np.zeros(n)
+        e[j] = 1.0
+        E[:, j] = e - o.smooth(hier, 0, A @ e, np.zeros(n))
+    lmax = d["rho"]
+    lmin = lmax / ratio
+    theta, delta = (lmax + lmin) / 2, (lmax - lmin) / 2
+    Dh = np.sqrt(np.diag(A))
+    lam, Q = la.eigh(A / np.outer(Dh, Dh))   # D^-1/2 A D^-1/2
+    Tk = np.polynomial.chebyshev.Chebyshev.basis(degree)
+    pl = Tk((theta - lam) / delta) / Tk(theta / delta)
+    E_ref = (Q * pl) @ Q.T
+    E_ref = E_ref * Dh[None, :] / Dh[:, None]   # p(D^-1 A) = D^-1/2 p(D^-1/2 A D^-1/2) D^1/2
+    assert np.abs(E - E_ref).max() < 1e-11, np.abs(E - E_ref).max()
+
+
+def test_inner_cg_is_krylov_optimal():
+    """k CG steps with preconditioner V minimise the As-norm error over K_k(VA, Vb)."""
+    k = 3
+    p, co, ce, o = small((9, 8), schur_pcg=k, coarse_max=10)
+    As = o.scipy_matrix("As0").toarray()
+    n = o.nv
+    V = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        V[:, j] = o.vcycle(1, e)
+    b = np.random.default_rng(5).standard_normal(n)
+    x = o.schur_solve(0, b)
+    Kb = [V @ b]
+    for _ in range(k - 1):
+        Kb.append(V @ (As @ Kb[-1]))
+    B = np.array(Kb).T
+    y = np.linalg.solve(B.T @ As @ B, B.T @ b)
+    assert np.linalg.norm(x - B @ y) < 1e-9 * np.linalg.norm(B @ y)
+
+
+def test_algorithm1_with_accurate_inner_solves():
+    """Prec(v) -> [M^-1 v1 ; As^-1 M As^-1 v2] when the AMG solves are run to convergence."""
+    p, co, ce, o = small((11, 10), amg_cycles=30, schur_pcg=40, coarse_max=20)
+    n = o.nv
+    M = o.scipy_matrix("M").tocsc()
+    As = o.scipy_matrix("As0").tocsc()
+    v = np.random.default_rng(2).standard_normal(2 * n)
+    w = o.apply_prec(0, v)
+    w1 = spla.spsolve(M, v[:n])
+    w2 = spla.spsolve(As, M @ spla.spsolve(As, v[n:]))
+    assert np.linalg.norm(w[:n] - w1) < 1e-10 * np.linalg.norm(w1)
+    assert np.linalg.norm(w[n:] - w2) < 1e-9 * np.linalg.norm(w2)
