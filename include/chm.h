@@ -1,0 +1,179 @@
+/*
+ * chm.h -- C ABI of the MI355X library for the per-time-step solve of the
+ * ternary Cahn-Hilliard model of Bergermann, Deibel, Herzog, MacKenzie,
+ * Pietschmann and Stoll, "Preconditioning for a Phase-Field Model with
+ * Application to Morphology Evolution in Organic Semiconductors".
+ *
+ * What one time step computes (paper Section 3):
+ *   for each species i in {polymer, acceptor}, with tau' = tau * mobility_i,
+ *   solve the symmetric saddle-point system (eq. saddle_point_system)
+ *       [ M        tau' K          ] [phi^{k+1}]   [ M phi^k               ]
+ *       [ tau' K   -(tau'/eps_i) M ] [ mu^{k+1}] = [ -(tau'/eps_i) f_i^k   ]
+ *   where M, K are the P1 mass and stiffness matrices and
+ *   f_i^k = integral of (d f / d phi_i)(phi_h^k) times each hat function
+ *   (the explicit part of the IMEX scheme eq. chternary_space), by
+ *   right-preconditioned flexible GMRES with the block-diagonal preconditioner
+ *   of Algorithm 1 (mass block by AMG; Schur block by the matching
+ *   approximation (tau' K + sqrt(tau'/eps) M) M^-1 (tau' K + sqrt(tau'/eps) M)
+ *   justified by Lemma 1), then set phi_s = 1 - phi_p - phi_n (Section 2).
+ *   The AMG is smoothed aggregation with Chebyshev or Jacobi smoothing.
+ *
+ * Conventions
+ *   - Every call returns CHM_OK (0) or a negative CHM_E* code; no exception
+ *     or abort crosses the ABI.  chm_last_error() gives the message.
+ *   - The caller owns every pointer it passes.  The library copies mesh and
+ *     fields into device memory it allocates itself; chm_destroy frees it.
+ *   - All GPU work is enqueued on the HIP stream given to chm_create (NULL =
+ *     the default stream).  Calls that return host data synchronise it.
+ *   - Fields are FP64, one value per mesh vertex, in vertex order.
+ *   - "on_device" arguments: 1 = the pointers are device memory on the
+ *     library's device, 0 = host memory.
+ *   - A handle is not thread safe; separate handles are independent.
+ */
+#ifndef CHM_H
+#define CHM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHM_OK 0
+#define CHM_EINVAL (-1)   /* bad argument or unsupported configuration */
+#define CHM_ENOMEM (-2)   /* device allocation failed */
+#define CHM_EHIP (-3)     /* a HIP runtime call failed */
+#define CHM_ENOCONV (-4)  /* FGMRES did not reach rtol within max_iters */
+#define CHM_ENAN (-5)     /* a non-finite value appeared */
+
+#define CHM_POT_FLORY_HUGGINS 0 /* eq. logarithmicpotential (Section 2) */
+#define CHM_POT_POLYNOMIAL 1    /* eq. polynomial_potential (Section 4) */
+#define CHM_POT_NONE 2          /* f = 0: linear fourth-order problem */
+
+#define CHM_SMOOTH_CHEBYSHEV 0
+#define CHM_SMOOTH_JACOBI 1
+
+typedef struct chm_solver chm_solver_t;
+
+/* A conforming simplex mesh: triangles (dim 2) or tetrahedra (dim 3).
+ * coords: host, n_vertices * dim doubles, vertex-major.
+ * cells:  host, n_cells * (dim + 1) vertex indices, each in [0, n_vertices).
+ * Cells must have non-zero volume.  The library copies both. */
+typedef struct {
+    int32_t dim;
+    int64_t n_vertices;
+    const double *coords;
+    int64_t n_cells;
+    const int32_t *cells;
+} chm_mesh_t;
+
+/* Model and solver parameters.  Model values of the paper (Section 4):
+ * chi_pn = 1, chi_ps = chi_ns = 0.3, N_p = N_n = 20, N_s = 1, eps = 1e-3,
+ * tau between 1e-7 and 1e-4.  Both species must share tau * mobility and
+ * eps (they then share the As hierarchy); other combinations give
+ * CHM_EINVAL. */
+typedef struct {
+    double tau;            /* time step */
+    double eps[2];         /* interface parameter per species (0 polymer, 1 acceptor) */
+    double mobility[2];    /* mobility per species; multiplies tau */
+    int32_t potential;     /* CHM_POT_* */
+    double Np, Nn, Ns;     /* degrees of polymerisation (Flory-Huggins) */
+    double chi_pn, chi_ps, chi_ns; /* interaction parameters (Flory-Huggins) */
+    double log_floor;      /* log arguments below this are clamped to it */
+    double evap_ds;        /* solvent fraction removed per step (0 = off) */
+    int32_t evap_steps;    /* steps, counted from creation, that remove solvent */
+    double rtol;           /* FGMRES: ||b - A x||_2 <= rtol ||b||_2 per species */
+    int32_t restart;       /* FGMRES restart length m, 1..64 */
+    int32_t max_iters;     /* FGMRES iterations allowed per species and step */
+    int32_t amg_cycles;    /* V-cycles per mass-matrix solve */
+    int32_t schur_pcg;     /* CG steps (one V-cycle each) per As solve; 0 = amg_cycles V-cycles */
+    int32_t smoother;      /* CHM_SMOOTH_* */
+    int32_t cheb_degree;   /* As hierarchy: Chebyshev degree or Jacobi sweeps (1..31) */
+    double cheb_ratio;     /* As hierarchy: Chebyshev interval [rho/ratio, rho] */
+    int32_t cheb_degree_mass; /* mass hierarchy: the same two */
+    double cheb_ratio_mass;
+    int32_t coarse_max;    /* coarsen until a level has at most this many rows */
+    int32_t max_levels;    /* at most this many levels (1..24) */
+} chm_params_t;
+
+/* Per-step statistics. */
+typedef struct {
+    int32_t iters[2];      /* FGMRES iterations per species */
+    double relres[2];      /* final true residual / ||b|| per species */
+    int32_t status;        /* CHM_OK or the step's error code */
+    int32_t clamped;       /* clamped log arguments in the right-hand side */
+    double t_step_ms;      /* wall time of the step on the stream */
+} chm_stats_t;
+
+/* Build the solver: upload the mesh, colour the cells, assemble M and K by
+ * coloured scatter, form As = tau' K + sqrt(tau'/eps) M (Algorithm 1), build
+ * the two smoothed-aggregation hierarchies (for M and for As) and allocate
+ * the Krylov workspace.  `stream` is a hipStream_t (may be NULL).  The
+ * initial state is phi = mu = 0.  On error *out is left NULL and the message
+ * is available from chm_last_error(NULL). */
+int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
+               chm_solver_t **out);
+
+/* Set the state.  phi_p, phi_n: required, n_vertices values each.  mu_p,
+ * mu_n: optional (NULL = 0); they are only the first Krylov guess of the
+ * next step. */
+int chm_set_fields(chm_solver_t *s, const double *phi_p, const double *phi_n,
+                   const double *mu_p, const double *mu_n, int32_t on_device);
+
+/* Advance nsteps time steps (eq. FE_systems for both species, then
+ * phi_s = 1 - phi_p - phi_n and the optional solvent removal).  stats may be
+ * NULL or hold nsteps entries.  On CHM_ENOCONV / CHM_ENAN the state is left
+ * at the last completed step and the failing step's stats are filled. */
+int chm_step(chm_solver_t *s, int32_t nsteps, chm_stats_t *stats);
+
+/* Copy out the state; any pointer may be NULL. */
+int chm_get_fields(chm_solver_t *s, double *phi_p, double *phi_n, double *phi_s,
+                   double *mu_p, double *mu_n, int32_t on_device);
+
+int chm_destroy(chm_solver_t *s);
+
+/* Message of the last failed call on s (s = NULL: of the last failed
+ * chm_create on this thread).  Valid until the next call on s. */
+const char *chm_last_error(const chm_solver_t *s);
+
+/* ---- inspection (used by the parity tests; all synchronise the stream) ---- */
+
+/* nnz of the shared pattern of M, K, As */
+int64_t chm_nnz(const chm_solver_t *s);
+/* which: 0 = M, 1 = K, 2 = As.  Host buffers rowptr[n+1], col[nnz], val[nnz]
+ * (any may be NULL). */
+int chm_get_matrix(chm_solver_t *s, int32_t which, int32_t *rowptr, int32_t *col, double *val);
+/* hierarchy: 0 = mass, 1 = As */
+int chm_num_levels(const chm_solver_t *s, int32_t hierarchy);
+int chm_level_info(const chm_solver_t *s, int32_t hierarchy, int32_t level, int64_t *n,
+                   int64_t *nnz_a, int64_t *nnz_p, double *rho);
+/* Host buffers; agg/P arrays are left untouched on the coarsest level. */
+int chm_level_get(chm_solver_t *s, int32_t hierarchy, int32_t level, int32_t *a_rowptr,
+                  int32_t *a_col, double *a_val, int32_t *agg, int32_t *p_rowptr,
+                  int32_t *p_col, double *p_val);
+/* Device pair vectors (double2[n]: species 0 in .x, 1 in .y). */
+int chm_vcycle(chm_solver_t *s, int32_t hierarchy, const double *b, double *x);
+int chm_schur_solve(chm_solver_t *s, const double *b, double *x);
+/* Device block vectors (double2[2n]: rows [0,n) phi block, [n,2n) mu block). */
+int chm_apply_saddle(chm_solver_t *s, const double *x, double *y);
+int chm_apply_prec(chm_solver_t *s, const double *v, double *w);
+/* right-hand side of the current state into a device block vector b */
+int chm_rhs(chm_solver_t *s, double *b);
+
+/* Host-only: the quadrature rule of the right-hand side (barycentric points
+ * [npts][dim+1], weights summing to 1); bary and w hold at least 64 points. */
+int chm_quadrature(int32_t dim, int32_t *npts, double *bary, double *w);
+
+/* Per-launch timing of one kernel kind with HIP events on the solver's
+ * stream (kind 0: fine-level Chebyshev step of the As hierarchy).  enable
+ * resets the counters. */
+int chm_timer_enable(chm_solver_t *s, int32_t kind, int32_t enable);
+int chm_timer_read(chm_solver_t *s, int64_t *launches, double *total_ms, int64_t *bytes);
+/* setup time of chm_create in ms and device bytes held */
+int chm_setup_info(const chm_solver_t *s, double *setup_ms, int64_t *levels_m,
+                   int64_t *levels_as);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,319 @@
+"""Python binding of the C ABI in include/chm.h (argument marshalling only).
+
+Every function here forwards to the same-named symbol of ``libchm.so``; the
+computation runs in the library's HIP kernels.  PyTorch supplies device memory
+(``tensor.data_ptr()``) and the HIP stream.  If the library is not built the
+import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchm.so")
+
+CHM_OK, CHM_EINVAL, CHM_ENOMEM, CHM_EHIP, CHM_ENOCONV, CHM_ENAN = 0, -1, -2, -3, -4, -5
+CODES = {0: "CHM_OK", -1: "CHM_EINVAL", -2: "CHM_ENOMEM", -3: "CHM_EHIP", -4: "CHM_ENOCONV",
+         -5: "CHM_ENAN"}
+POTENTIALS = {"flory_huggins": 0, "polynomial": 1, "none": 2}
+SMOOTHERS = {"chebyshev": 0, "jacobi": 1}
+
+# exported entry points (must match include/chm.h)
+ENTRY_POINTS = [
+    "chm_create", "chm_set_fields", "chm_step", "chm_get_fields", "chm_destroy",
+    "chm_last_error", "chm_nnz", "chm_get_matrix", "chm_num_levels", "chm_level_info",
+    "chm_level_get", "chm_vcycle", "chm_schur_solve", "chm_apply_saddle", "chm_apply_prec",
+    "chm_rhs", "chm_quadrature", "chm_timer_enable", "chm_timer_read", "chm_setup_info",
+]
+
+
+class ChmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class chm_mesh_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int64), ("coords", C.c_void_p),
+                ("n_cells", C.c_int64), ("cells", C.c_void_p)]
+
+
+class chm_params_t(C.Structure):
+    _fields_ = [
+        ("tau", C.c_double), ("eps", C.c_double * 2), ("mobility", C.c_double * 2),
+        ("potential", C.c_int32), ("Np", C.c_double), ("Nn", C.c_double), ("Ns", C.c_double),
+        ("chi_pn", C.c_double), ("chi_ps", C.c_double), ("chi_ns", C.c_double),
+        ("log_floor", C.c_double), ("evap_ds", C.c_double), ("evap_steps", C.c_int32),
+        ("rtol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
+        ("amg_cycles", C.c_int32), ("schur_pcg", C.c_int32), ("smoother", C.c_int32),
+        ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
+        ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
+        ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+    ]
+
+
+class chm_stats_t(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 2), ("relres", C.c_double * 2), ("status", C.c_int32),
+                ("clamped", C.c_int32), ("t_step_ms", C.c_double)]
+
+
+_lib = None
+
+
+def library():
+    """Load libchm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        lib = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        P = C.POINTER
+        sig = {
+            "chm_create": ([P(chm_mesh_t), P(chm_params_t), vp, P(vp)], C.c_int),
+            "chm_set_fields": ([vp, vp, vp, vp, vp, i32], C.c_int),
+            "chm_step": ([vp, i32, P(chm_stats_t)], C.c_int),
+            "chm_get_fields": ([vp, vp, vp, vp, vp, vp, i32], C.c_int),
+            "chm_destroy": ([vp], C.c_int),
+            "chm_last_error": ([vp], C.c_char_p),
+            "chm_nnz": ([vp], i64),
+            "chm_get_matrix": ([vp, i32, vp, vp, vp], C.c_int),
+            "chm_num_levels": ([vp, i32], C.c_int),
+            "chm_level_info": ([vp, i32, i32, P(i64), P(i64), P(i64), P(d)], C.c_int),
+            "chm_level_get": ([vp, i32, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "chm_vcycle": ([vp, i32, vp, vp], C.c_int),
+            "chm_schur_solve": ([vp, vp, vp], C.c_int),
+            "chm_apply_saddle": ([vp, vp, vp], C.c_int),
+            "chm_apply_prec": ([vp, vp, vp], C.c_int),
+            "chm_rhs": ([vp, vp], C.c_int),
+            "chm_quadrature": ([i32, P(i32), vp, vp], C.c_int),
+            "chm_timer_enable": ([vp, i32, i32], C.c_int),
+            "chm_timer_read": ([vp, P(i64), P(d), P(i64)], C.c_int),
+            "chm_setup_info": ([vp, P(d), P(i64), P(i64)], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def params_from_dict(p: dict) -> chm_params_t:
+    s = chm_params_t()
+    s.tau = p["tau"]
+    eps = p["eps"] if isinstance(p["eps"], (list, tuple)) else (p["eps"], p["eps"])
+    mob = p["mobility"] if isinstance(p["mobility"], (list, tuple)) else (p["mobility"],) * 2
+    s.eps[0], s.eps[1] = eps
+    s.mobility[0], s.mobility[1] = mob
+    s.potential = POTENTIALS[p["potential"]]
+    for k in ("Np", "Nn", "Ns", "chi_pn", "chi_ps", "chi_ns", "log_floor", "rtol",
+              "cheb_ratio", "cheb_ratio_mass"):
+        setattr(s, k, float(p[k]))
+    s.evap_ds = float(p.get("evap_ds", 0.0))
+    s.evap_steps = int(p.get("evap_steps", p.get("steps", 0))) if s.evap_ds > 0 else 0
+    for k in ("restart", "max_iters", "amg_cycles", "schur_pcg", "cheb_degree",
+              "cheb_degree_mass", "coarse_max", "max_levels"):
+        setattr(s, k, int(p[k]))
+    s.smoother = SMOOTHERS[p["smoother"]]
+    return s
+
+
+def _check(h, rc: int, what: str):
+    if rc != CHM_OK:
+        msg = library().chm_last_error(h)
+        raise ChmError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def chm_quadrature(dim: int):
+    bary = np.zeros(64 * 4)
+    w = np.zeros(64)
+    n = C.c_int32()
+    rc = library().chm_quadrature(dim, C.byref(n), bary.ctypes.data_as(C.c_void_p),
+                                  w.ctypes.data_as(C.c_void_p))
+    if rc:
+        raise ChmError(rc, "chm_quadrature")
+    k = n.value
+    return bary[: k * (dim + 1)].reshape(k, dim + 1).copy(), w[:k].copy()
+
+
+class Solver:
+    """One chm_solver_t on the current torch device and stream."""
+
+    def __init__(self, coords: np.ndarray, cells: np.ndarray, params: dict, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        self.coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self.cells = np.ascontiguousarray(cells, dtype=np.int32)
+        self.dim = self.coords.shape[1]
+        self.nv = self.coords.shape[0]
+        self.params = dict(params)
+        mesh = chm_mesh_t(self.dim, self.nv, self.coords.ctypes.data_as(C.c_void_p),
+                          self.cells.shape[0], self.cells.ctypes.data_as(C.c_void_p))
+        self._prm = params_from_dict(params)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        rc = self.lib.chm_create(C.byref(mesh), C.byref(self._prm), C.c_void_p(stream), C.byref(h))
+        if rc != CHM_OK:
+            msg = self.lib.chm_last_error(None)
+            raise ChmError(rc, f"chm_create: {msg.decode() if msg else ''}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- state
+    def set_fields(self, phi_p, phi_n, mu_p=None, mu_n=None):
+        torch = self.torch
+        ts = [None if a is None else torch.as_tensor(np.asarray(a, dtype=np.float64)).cuda()
+              for a in (phi_p, phi_n, mu_p, mu_n)]
+        ptrs = [None if t is None else _dev_ptr(t) for t in ts]
+        rc = self.lib.chm_set_fields(self.h, *ptrs, 1)
+        _check(self.h, rc, "chm_set_fields")
+
+    def get_fields(self) -> dict:
+        torch = self.torch
+        out = {k: torch.empty(self.nv, dtype=torch.float64, device="cuda")
+               for k in ("phi_p", "phi_n", "phi_s", "mu_p", "mu_n")}
+        rc = self.lib.chm_get_fields(self.h, *(_dev_ptr(out[k]) for k in
+                                               ("phi_p", "phi_n", "phi_s", "mu_p", "mu_n")), 1)
+        _check(self.h, rc, "chm_get_fields")
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+    def step(self, nsteps: int = 1):
+        st = (chm_stats_t * max(1, nsteps))()
+        rc = self.lib.chm_step(self.h, nsteps, st)
+        stats = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
+                      status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms)
+                 for s in st[:nsteps]]
+        if rc != CHM_OK:
+            msg = self.lib.chm_last_error(self.h)
+            err = ChmError(rc, f"chm_step: {msg.decode() if msg else ''}")
+            err.stats = stats
+            raise err
+        return stats
+
+    # ---- inspection
+    def nnz(self) -> int:
+        return self.lib.chm_nnz(self.h)
+
+    def matrix(self, which: str):
+        idx = {"M": 0, "K": 1, "As": 2}[which]
+        nnz = self.nnz()
+        rp = np.zeros(self.nv + 1, np.int32)
+        ci = np.zeros(nnz, np.int32)
+        v = np.zeros(nnz)
+        rc = self.lib.chm_get_matrix(self.h, idx, rp.ctypes.data_as(C.c_void_p),
+                                     ci.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p))
+        _check(self.h, rc, "chm_get_matrix")
+        return rp, ci, v
+
+    def num_levels(self, hier: int) -> int:
+        return self.lib.chm_num_levels(self.h, hier)
+
+    def level(self, hier: int, lev: int) -> dict:
+        n, na, npp = C.c_int64(), C.c_int64(), C.c_int64()
+        rho = C.c_double()
+        rc = self.lib.chm_level_info(self.h, hier, lev, C.byref(n), C.byref(na), C.byref(npp),
+                                     C.byref(rho))
+        _check(self.h, rc, "chm_level_info")
+        n, na, npp = n.value, na.value, npp.value
+        arr = dict(Arp=np.zeros(n + 1, np.int32), Aci=np.zeros(na, np.int32), Av=np.zeros(na),
+                   agg=np.full(n, -1, np.int32), Prp=np.zeros(n + 1, np.int32),
+                   Pci=np.zeros(npp, np.int32), Pv=np.zeros(npp))
+        rc = self.lib.chm_level_get(self.h, hier, lev,
+                                    *(arr[k].ctypes.data_as(C.c_void_p) for k in
+                                      ("Arp", "Aci", "Av", "agg", "Prp", "Pci", "Pv")))
+        _check(self.h, rc, "chm_level_get")
+        out = dict(n=n, rho=rho.value, A=(arr["Arp"], arr["Aci"], arr["Av"]))
+        if npp:
+            out.update(agg=arr["agg"], P=(arr["Prp"], arr["Pci"], arr["Pv"]),
+                       nc=int(arr["agg"].max()) + 1)
+        return out
+
+    def _pairs(self, a, b=None):
+        """[n] x 2 pair layout from one or two host arrays."""
+        torch = self.torch
+        a = np.asarray(a, dtype=np.float64)
+        if b is None:
+            b = a
+        t = torch.tensor(np.stack([a, np.asarray(b, dtype=np.float64)], axis=1), device="cuda")
+        return t.contiguous()
+
+    def vcycle(self, hier: int, b0, b1=None):
+        """One V-cycle from zero on two right-hand sides; returns (x0, x1)."""
+        torch = self.torch
+        b = self._pairs(b0, b1)
+        x = torch.zeros_like(b)
+        rc = self.lib.chm_vcycle(self.h, hier, _dev_ptr(b), _dev_ptr(x))
+        _check(self.h, rc, "chm_vcycle")
+        x = x.cpu().numpy()
+        return x[:, 0].copy(), x[:, 1].copy()
+
+    def schur_solve(self, b0, b1=None):
+        torch = self.torch
+        b = self._pairs(b0, b1)
+        x = torch.zeros_like(b)
+        rc = self.lib.chm_schur_solve(self.h, _dev_ptr(b), _dev_ptr(x))
+        _check(self.h, rc, "chm_schur_solve")
+        x = x.cpu().numpy()
+        return x[:, 0].copy(), x[:, 1].copy()
+
+    def _block(self, v0, v1):
+        """Block-vector layout from two species' vectors of length 2n."""
+        v0 = np.asarray(v0, dtype=np.float64)
+        v1 = np.asarray(v1, dtype=np.float64)
+        return self.torch.tensor(np.stack([v0, v1], axis=1), device="cuda").contiguous()
+
+    def _unblock(self, t):
+        a = t.cpu().numpy()
+        return a[:, 0].copy(), a[:, 1].copy()
+
+    def apply_saddle(self, x0, x1):
+        x = self._block(x0, x1)
+        y = self.torch.zeros_like(x)
+        rc = self.lib.chm_apply_saddle(self.h, _dev_ptr(x), _dev_ptr(y))
+        _check(self.h, rc, "chm_apply_saddle")
+        return self._unblock(y)
+
+    def apply_prec(self, v0, v1):
+        v = self._block(v0, v1)
+        w = self.torch.zeros_like(v)
+        rc = self.lib.chm_apply_prec(self.h, _dev_ptr(v), _dev_ptr(w))
+        _check(self.h, rc, "chm_apply_prec")
+        return self._unblock(w)
+
+    def rhs(self):
+        b = self.torch.zeros((2 * self.nv, 2), dtype=self.torch.float64, device="cuda")
+        rc = self.lib.chm_rhs(self.h, _dev_ptr(b))
+        _check(self.h, rc, "chm_rhs")
+        return self._unblock(b)
+
+    def timer_enable(self, kind: int = 0, enable: bool = True):
+        _check(self.h, self.lib.chm_timer_enable(self.h, kind, int(enable)), "chm_timer_enable")
+
+    def timer_read(self):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_int64()
+        _check(self.h, self.lib.chm_timer_read(self.h, C.byref(n), C.byref(ms), C.byref(by)),
+               "chm_timer_read")
+        return n.value, ms.value, by.value
+
+    def setup_info(self):
+        ms, lm, la = C.c_double(), C.c_int64(), C.c_int64()
+        self.lib.chm_setup_info(self.h, C.byref(ms), C.byref(lm), C.byref(la))
+        return dict(setup_ms=ms.value, levels_mass=lm.value, levels_as=la.value)

@@ -1,0 +1,467 @@
+// C ABI of the library (declared in include/chm.h).  Argument checking,
+// error capture and marshalling only; every step of the computation runs in
+// the kernels of mesh_setup.hip, amg_setup.hip and solve.hip.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "chm_internal.h"
+
+struct chm_solver {
+    chm::Solver s;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(chm_solver *h, int code, const std::string &msg)
+{
+    if (h) {
+        h->s.err.code = code;
+        h->s.err.msg = msg;
+    } else {
+        g_create_error = msg;
+    }
+    return code;
+}
+
+template <class F> int guarded(chm_solver *h, F &&f)
+{
+    try {
+        return f();
+    } catch (const chm::Failure &e) {
+        return fail(h, e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(h, CHM_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(h, CHM_EINVAL, e.what());
+    }
+}
+
+const char *check_params(const chm_params_t &p)
+{
+    if (!(p.tau > 0.0) || !std::isfinite(p.tau))
+        return "tau must be positive";
+    for (int s = 0; s < 2; ++s) {
+        if (!(p.eps[s] > 0.0) || !(p.mobility[s] > 0.0))
+            return "eps and mobility must be positive";
+    }
+    if (p.eps[0] != p.eps[1] || p.mobility[0] != p.mobility[1])
+        return "both species must share eps and mobility (one As hierarchy)";
+    if (p.potential < 0 || p.potential > 2)
+        return "unknown potential";
+    if (p.potential == CHM_POT_FLORY_HUGGINS &&
+        (!(p.Np > 0) || !(p.Nn > 0) || !(p.Ns > 0) || !(p.log_floor > 0.0)))
+        return "Flory-Huggins needs positive N_p, N_n, N_s and log_floor";
+    if (!(p.rtol > 0.0) || p.restart < 1 || p.restart > chm::kMaxRestart || p.max_iters < 1)
+        return "need rtol > 0, 1 <= restart <= 64, max_iters >= 1";
+    if (p.amg_cycles < 1 || p.schur_pcg < 0 || p.schur_pcg > 39)
+        return "need amg_cycles >= 1 and 0 <= schur_pcg <= 39";
+    if (p.smoother != CHM_SMOOTH_CHEBYSHEV && p.smoother != CHM_SMOOTH_JACOBI)
+        return "unknown smoother";
+    if (p.cheb_degree < 1 || p.cheb_degree > 31 || p.cheb_degree_mass < 1 || p.cheb_degree_mass > 31)
+        return "smoother degrees must be in 1..31";
+    if (!(p.cheb_ratio > 1.0) || !(p.cheb_ratio_mass > 1.0))
+        return "Chebyshev ratios must exceed 1";
+    if (p.coarse_max < 1 || p.max_levels < 1 || p.max_levels > chm::kMaxLevels)
+        return "need coarse_max >= 1 and 1 <= max_levels <= 24";
+    if (p.evap_ds < 0.0 || p.evap_steps < 0)
+        return "evaporation settings must be non-negative";
+    return nullptr;
+}
+
+void copy_field(double *dst_dev_pair, int n, int comp, const double *src, bool on_device,
+                hipStream_t st)
+{
+    // scatter one field into component `comp` of a pair vector
+    CHM_HIP(hipMemcpy2DAsync(reinterpret_cast<char *>(dst_dev_pair) + comp * sizeof(double),
+                             2 * sizeof(double), src, sizeof(double), sizeof(double), n,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+}
+
+void get_field(double *dst, const double *src_dev_pair, int n, int comp, bool on_device,
+               hipStream_t st)
+{
+    CHM_HIP(hipMemcpy2DAsync(dst, sizeof(double),
+                             reinterpret_cast<const char *>(src_dev_pair) + comp * sizeof(double),
+                             2 * sizeof(double), sizeof(double), n,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
+               chm_solver_t **out)
+{
+    if (out)
+        *out = nullptr;
+    if (!mesh || !params || !out)
+        return fail(nullptr, CHM_EINVAL, "chm_create: NULL argument");
+    if ((mesh->dim != 2 && mesh->dim != 3) || mesh->n_vertices < 1 || mesh->n_cells < 1 ||
+        !mesh->coords || !mesh->cells || mesh->n_vertices > 0x3fffffff || mesh->n_cells > 0x1fffffff)
+        return fail(nullptr, CHM_EINVAL, "chm_create: bad mesh dimensions or pointers");
+    if (const char *why = check_params(*params))
+        return fail(nullptr, CHM_EINVAL, std::string("chm_create: ") + why);
+    const int nl = mesh->dim + 1;
+    for (int64_t i = 0; i < mesh->n_cells * nl; ++i)
+        if (mesh->cells[i] < 0 || mesh->cells[i] >= mesh->n_vertices)
+            return fail(nullptr, CHM_EINVAL, "chm_create: cell vertex index out of range");
+    for (int64_t i = 0; i < mesh->n_vertices * mesh->dim; ++i)
+        if (!std::isfinite(mesh->coords[i]))
+            return fail(nullptr, CHM_EINVAL, "chm_create: non-finite coordinate");
+
+    chm_solver *h = new (std::nothrow) chm_solver;
+    if (!h)
+        return fail(nullptr, CHM_ENOMEM, "chm_create: host allocation failed");
+    int rc = guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        auto t0 = std::chrono::steady_clock::now();
+        S.stream = static_cast<hipStream_t>(stream);
+        S.prm = *params;
+        S.dim = mesh->dim;
+        S.nv = (int)mesh->n_vertices;
+        S.ncell = (int)mesh->n_cells;
+        S.nl = nl;
+        for (int s = 0; s < 2; ++s) {
+            S.tau_s[s] = S.prm.tau * S.prm.mobility[s];
+            S.te_s[s] = S.tau_s[s] / S.prm.eps[s];
+        }
+        S.coords = S.pool.get<double>((size_t)S.nv * S.dim);
+        S.cells = S.pool.get<int>((size_t)S.ncell * nl);
+        CHM_HIP(hipMemcpyAsync(S.coords, mesh->coords, sizeof(double) * S.nv * S.dim,
+                               hipMemcpyHostToDevice, S.stream));
+        CHM_HIP(hipMemcpyAsync(S.cells, mesh->cells, sizeof(int) * (size_t)S.ncell * nl,
+                               hipMemcpyHostToDevice, S.stream));
+        chm::mesh_setup(S);
+        S.hM.degree = S.prm.cheb_degree_mass;
+        S.hM.ratio = S.prm.cheb_ratio_mass;
+        S.hM.jacobi = S.prm.smoother == CHM_SMOOTH_JACOBI;
+        S.hA.degree = S.prm.cheb_degree;
+        S.hA.ratio = S.prm.cheb_ratio;
+        S.hA.jacobi = S.hM.jacobi;
+        chm::amg_build(S, S.hM, S.M);
+        chm::amg_build(S, S.hA, S.As);
+        chm::alloc_workspace(S);
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        S.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return CHM_OK;
+    });
+    if (rc != CHM_OK) {
+        g_create_error = h->s.err.msg;
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (h->s.hctl)
+            (void)hipHostFree(h->s.hctl);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return CHM_OK;
+}
+
+int chm_set_fields(chm_solver_t *h, const double *phi_p, const double *phi_n, const double *mu_p,
+                   const double *mu_n, int32_t on_device)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_set_fields: NULL handle");
+    if (!phi_p || !phi_n)
+        return fail(h, CHM_EINVAL, "chm_set_fields: phi_p and phi_n are required");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        const int n = S.nv;
+        double *x = reinterpret_cast<double *>(S.x);
+        copy_field(x, n, 0, phi_p, on_device, S.stream);
+        copy_field(x, n, 1, phi_n, on_device, S.stream);
+        double *mu = reinterpret_cast<double *>(S.x + n);
+        chm::fill_double(mu, 0.0, 2 * (size_t)n, S.stream);
+        if (mu_p)
+            copy_field(mu, n, 0, mu_p, on_device, S.stream);
+        if (mu_n)
+            copy_field(mu, n, 1, mu_n, on_device, S.stream);
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_step: NULL handle");
+    if (nsteps < 0)
+        return fail(h, CHM_EINVAL, "chm_step: nsteps < 0");
+    return guarded(h, [&]() {
+        for (int k = 0; k < nsteps; ++k) {
+            int rc = chm::step_once(h->s, stats ? stats + k : nullptr);
+            if (rc != CHM_OK)
+                return fail(h, rc, rc == CHM_ENOCONV ? "FGMRES did not converge within max_iters"
+                                                     : "non-finite value in the solve");
+        }
+        return CHM_OK;
+    });
+}
+
+int chm_get_fields(chm_solver_t *h, double *phi_p, double *phi_n, double *phi_s, double *mu_p,
+                   double *mu_n, int32_t on_device)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_get_fields: NULL handle");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        const int n = S.nv;
+        const double *x = reinterpret_cast<const double *>(S.x);
+        const double *mu = reinterpret_cast<const double *>(S.x + n);
+        if (phi_p)
+            get_field(phi_p, x, n, 0, on_device, S.stream);
+        if (phi_n)
+            get_field(phi_n, x, n, 1, on_device, S.stream);
+        if (mu_p)
+            get_field(mu_p, mu, n, 0, on_device, S.stream);
+        if (mu_n)
+            get_field(mu_n, mu, n, 1, on_device, S.stream);
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        if (phi_s) {
+            // phi_s = 1 - phi_p - phi_n (Section 2), formed from the copied fields
+            std::vector<double> a(n), b(n);
+            get_field(a.data(), x, n, 0, false, S.stream);
+            get_field(b.data(), x, n, 1, false, S.stream);
+            CHM_HIP(hipStreamSynchronize(S.stream));
+            std::vector<double> s(n);
+            for (int i = 0; i < n; ++i)
+                s[i] = 1.0 - a[i] - b[i];
+            CHM_HIP(hipMemcpyAsync(phi_s, s.data(), sizeof(double) * n,
+                                   on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, S.stream));
+            CHM_HIP(hipStreamSynchronize(S.stream));
+        }
+        return CHM_OK;
+    });
+}
+
+int chm_destroy(chm_solver_t *h)
+{
+    if (!h)
+        return CHM_OK;
+    (void)hipStreamSynchronize(h->s.stream);
+    for (hipEvent_t e : h->s.timer.ev)
+        (void)hipEventDestroy(e);
+    if (h->s.hctl)
+        (void)hipHostFree(h->s.hctl);
+    delete h;
+    return CHM_OK;
+}
+
+const char *chm_last_error(const chm_solver_t *h)
+{
+    if (!h)
+        return g_create_error.c_str();
+    return h->s.err.msg.c_str();
+}
+
+int64_t chm_nnz(const chm_solver_t *h) { return h ? h->s.M.nnz : -1; }
+
+int chm_get_matrix(chm_solver_t *h, int32_t which, int32_t *rowptr, int32_t *col, double *val)
+{
+    if (!h || which < 0 || which > 2)
+        return fail(h, CHM_EINVAL, "chm_get_matrix: bad arguments");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        const chm::Csr &A = which == 0 ? S.M : which == 1 ? S.K : S.As;
+        if (rowptr)
+            CHM_HIP(hipMemcpy(rowptr, A.rp, sizeof(int) * (A.n + 1), hipMemcpyDeviceToHost));
+        if (col)
+            CHM_HIP(hipMemcpy(col, A.ci, sizeof(int) * A.nnz, hipMemcpyDeviceToHost));
+        if (val)
+            CHM_HIP(hipMemcpy(val, A.v, sizeof(double) * A.nnz, hipMemcpyDeviceToHost));
+        return CHM_OK;
+    });
+}
+
+static const chm::Hierarchy *hier_of(const chm_solver_t *h, int hier)
+{
+    if (!h || hier < 0 || hier > 1)
+        return nullptr;
+    return hier == 0 ? &h->s.hM : &h->s.hA;
+}
+
+int chm_num_levels(const chm_solver_t *h, int32_t hierarchy)
+{
+    const chm::Hierarchy *H = hier_of(h, hierarchy);
+    return H ? H->nlev : CHM_EINVAL;
+}
+
+int chm_level_info(const chm_solver_t *h, int32_t hierarchy, int32_t level, int64_t *n,
+                   int64_t *nnz_a, int64_t *nnz_p, double *rho)
+{
+    const chm::Hierarchy *H = hier_of(h, hierarchy);
+    if (!H || level < 0 || level >= H->nlev)
+        return CHM_EINVAL;
+    const chm::Level &L = H->lev[level];
+    if (n)
+        *n = L.n;
+    if (nnz_a)
+        *nnz_a = L.A.nnz;
+    if (nnz_p)
+        *nnz_p = (level + 1 < H->nlev) ? L.P.nnz : 0;
+    if (rho)
+        *rho = L.rho;
+    return CHM_OK;
+}
+
+int chm_level_get(chm_solver_t *h, int32_t hierarchy, int32_t level, int32_t *a_rowptr,
+                  int32_t *a_col, double *a_val, int32_t *agg, int32_t *p_rowptr, int32_t *p_col,
+                  double *p_val)
+{
+    const chm::Hierarchy *H = hier_of(h, hierarchy);
+    if (!H || level < 0 || level >= H->nlev)
+        return fail(h ? const_cast<chm_solver_t *>(h) : nullptr, CHM_EINVAL, "chm_level_get: bad level");
+    return guarded(h, [&]() {
+        const chm::Level &L = H->lev[level];
+        CHM_HIP(hipStreamSynchronize(h->s.stream));
+        if (a_rowptr)
+            CHM_HIP(hipMemcpy(a_rowptr, L.A.rp, sizeof(int) * (L.n + 1), hipMemcpyDeviceToHost));
+        if (a_col)
+            CHM_HIP(hipMemcpy(a_col, L.A.ci, sizeof(int) * L.A.nnz, hipMemcpyDeviceToHost));
+        if (a_val)
+            CHM_HIP(hipMemcpy(a_val, L.A.v, sizeof(double) * L.A.nnz, hipMemcpyDeviceToHost));
+        if (level + 1 < H->nlev) {
+            if (agg)
+                CHM_HIP(hipMemcpy(agg, L.agg, sizeof(int) * L.n, hipMemcpyDeviceToHost));
+            if (p_rowptr)
+                CHM_HIP(hipMemcpy(p_rowptr, L.P.rp, sizeof(int) * (L.n + 1), hipMemcpyDeviceToHost));
+            if (p_col)
+                CHM_HIP(hipMemcpy(p_col, L.P.ci, sizeof(int) * L.P.nnz, hipMemcpyDeviceToHost));
+            if (p_val)
+                CHM_HIP(hipMemcpy(p_val, L.P.v, sizeof(double) * L.P.nnz, hipMemcpyDeviceToHost));
+        }
+        return CHM_OK;
+    });
+}
+
+int chm_vcycle(chm_solver_t *h, int32_t hierarchy, const double *b, double *x)
+{
+    if (!h || hierarchy < 0 || hierarchy > 1 || !b || !x)
+        return fail(h, CHM_EINVAL, "chm_vcycle: bad arguments");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        chm::vcycle(S, hierarchy == 0 ? S.hM : S.hA, reinterpret_cast<const double2 *>(b),
+                    reinterpret_cast<double2 *>(x));
+        CHM_HIP(hipGetLastError());
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_schur_solve(chm_solver_t *h, const double *b, double *x)
+{
+    if (!h || !b || !x)
+        return fail(h, CHM_EINVAL, "chm_schur_solve: bad arguments");
+    return guarded(h, [&]() {
+        chm::schur_solve(h->s, reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(x));
+        CHM_HIP(hipGetLastError());
+        CHM_HIP(hipStreamSynchronize(h->s.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_apply_saddle(chm_solver_t *h, const double *x, double *y)
+{
+    if (!h || !x || !y)
+        return fail(h, CHM_EINVAL, "chm_apply_saddle: bad arguments");
+    return guarded(h, [&]() {
+        chm::apply_saddle(h->s, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y));
+        CHM_HIP(hipGetLastError());
+        CHM_HIP(hipStreamSynchronize(h->s.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_apply_prec(chm_solver_t *h, const double *v, double *w)
+{
+    if (!h || !v || !w)
+        return fail(h, CHM_EINVAL, "chm_apply_prec: bad arguments");
+    return guarded(h, [&]() {
+        chm::apply_prec(h->s, reinterpret_cast<const double2 *>(v), reinterpret_cast<double2 *>(w));
+        CHM_HIP(hipGetLastError());
+        CHM_HIP(hipStreamSynchronize(h->s.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_rhs(chm_solver_t *h, double *b)
+{
+    if (!h || !b)
+        return fail(h, CHM_EINVAL, "chm_rhs: bad arguments");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        chm::compute_rhs(S);
+        CHM_HIP(hipMemcpyAsync(b, S.b, sizeof(double2) * 2 * (size_t)S.nv, hipMemcpyDeviceToDevice,
+                               S.stream));
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_quadrature(int32_t dim, int32_t *npts, double *bary, double *w)
+{
+    if ((dim != 2 && dim != 3) || !npts || !bary || !w)
+        return CHM_EINVAL;
+    std::vector<double> b, ww;
+    chm::build_quadrature(dim, b, ww);
+    *npts = (int32_t)ww.size();
+    std::memcpy(bary, b.data(), sizeof(double) * b.size());
+    std::memcpy(w, ww.data(), sizeof(double) * ww.size());
+    return CHM_OK;
+}
+
+int chm_timer_enable(chm_solver_t *h, int32_t kind, int32_t enable)
+{
+    if (!h || kind != 0)
+        return fail(h, CHM_EINVAL, "chm_timer_enable: unknown kernel kind");
+    chm::Timer &T = h->s.timer;
+    T.on = enable != 0;
+    T.kind = kind;
+    T.used = 0;
+    T.total_ms = 0.0;
+    T.count = 0;
+    T.bytes = 0;
+    return CHM_OK;
+}
+
+int chm_timer_read(chm_solver_t *h, int64_t *launches, double *total_ms, int64_t *bytes)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_timer_read: NULL handle");
+    return guarded(h, [&]() {
+        chm::Timer &T = h->s.timer;
+        CHM_HIP(hipStreamSynchronize(h->s.stream));
+        for (size_t i = 0; i + 1 < T.used; i += 2) {
+            float ms = 0.f;
+            CHM_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+            T.total_ms += ms;
+        }
+        T.used = 0;
+        if (launches)
+            *launches = T.count;
+        if (total_ms)
+            *total_ms = T.total_ms;
+        if (bytes)
+            *bytes = T.bytes;
+        return CHM_OK;
+    });
+}
+
+int chm_setup_info(const chm_solver_t *h, double *setup_ms, int64_t *levels_m, int64_t *levels_as)
+{
+    if (!h)
+        return CHM_EINVAL;
+    if (setup_ms)
+        *setup_ms = h->s.setup_ms;
+    if (levels_m)
+        *levels_m = h->s.hM.nlev;
+    if (levels_as)
+        *levels_as = h->s.hA.nlev;
+    return CHM_OK;
+}
+
+}  // extern "C"

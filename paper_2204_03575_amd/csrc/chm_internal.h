@@ -1,0 +1,219 @@
+// Internal declarations of the MI355X Cahn-Hilliard library.
+//
+// Vector layouts on the device:
+//   * "pair" vectors: double2[n], .x = species 0 (polymer), .y = species 1
+//     (acceptor).  Every multigrid kernel works on pairs, so each matrix entry
+//     is read once for both species.
+//   * block vectors (Krylov space of the saddle-point system): double2[2n],
+//     entries [0, n) hold the volume-fraction block, [n, 2n) the
+//     chemical-potential block.
+//
+// Sparse matrices are kept in CSR for setup and in SELL-64 for the solve:
+// slice s holds rows [64 s, 64 s + 64); entry k of the row in lane l sits at
+// sptr[s] + 64 k + l; rows shorter than the slice width are padded with
+// (col = row, val = 0).  One wave64 handles one slice, so every col/val load
+// of a wave is one contiguous 256-byte (col) or 512-byte (val) access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chm.h"
+
+namespace chm {
+
+constexpr int kSlice = 64;      // SELL slice height = wavefront size
+constexpr int kBlock = 256;     // threads per block for row kernels
+constexpr int kMaxLevels = 24;
+constexpr int kMaxRestart = 64;
+constexpr int kRedBlocks = 1024;  // blocks of the two-stage reductions
+
+struct Err {
+    int code = CHM_OK;
+    std::string msg;
+};
+
+#define CHM_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::chm::Failure(CHM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Failure {
+    int code;
+    std::string msg;
+    Failure(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// device memory owned by one solver
+class Pool {
+  public:
+    ~Pool() { release(); }
+    template <class T> T *get(size_t count) {
+        if (count == 0)
+            count = 1;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess)
+            throw Failure(CHM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        ptrs_.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void release() {
+        for (void *p : ptrs_)
+            (void)hipFree(p);
+        ptrs_.clear();
+    }
+    size_t count() const { return ptrs_.size(); }
+
+  private:
+    std::vector<void *> ptrs_;
+};
+
+struct Csr {       // device CSR
+    int n = 0, m = 0, nnz = 0;
+    int *rp = nullptr, *ci = nullptr;
+    double *v = nullptr;
+};
+
+struct Sell {      // device SELL-64
+    int n = 0, nslices = 0;
+    int64_t stored = 0;   // padded entry count
+    int *sptr = nullptr;  // nslices + 1 offsets
+    int *col = nullptr;
+    double *val = nullptr;
+};
+
+struct Level {
+    int n = 0, nc = 0;
+    Csr A, P, R;
+    Sell sA, sP, sR;
+    double *dinv = nullptr;
+    double rho = 0.0;
+    int *agg = nullptr;
+    // Chebyshev coefficients: step 0 uses c2[0] (c1 = 0); step k uses c1[k], c2[k]
+    double cheb_c1[32], cheb_c2[32];
+    double jac_omega = 0.0;
+    // coarsest level: dense inverse, column-major n x n
+    double *inv = nullptr;
+};
+
+struct Hierarchy {
+    int nlev = 0;
+    int degree = 2;
+    double ratio = 30.0;
+    bool jacobi = false;
+    Level lev[kMaxLevels];
+    // per-level work vectors (pairs)
+    double2 *x[kMaxLevels], *xt[kMaxLevels], *b[kMaxLevels], *r[kMaxLevels], *d[kMaxLevels];
+};
+
+// device-side FGMRES control block (one per solver).  The small fields come
+// first: the host reads only that prefix after each Arnoldi step.
+struct Ctl {
+    alignas(16) double nrm[2];   // last computed squared norms (||b||^2, true residual^2)
+    alignas(16) double tol[2];
+    alignas(16) double bnorm[2]; // ||b|| per species
+    alignas(16) double resest[2];
+    alignas(16) double hn[2];    // ||w|| of the last Arnoldi step before rotation
+    int active[2];       // species still iterating in this cycle
+    int k[2];            // Arnoldi steps of the species in this cycle
+    int clamped;         // log-argument clamps in the last right-hand side
+    int nan;             // a non-finite value was seen
+    int pad[2];
+    // large part
+    double H[2][(kMaxRestart + 1) * kMaxRestart];
+    double cs[2][kMaxRestart], sn[2][kMaxRestart];
+    double g[2][kMaxRestart + 1];
+    double y[2][kMaxRestart];
+};
+constexpr size_t kCtlHead = offsetof(Ctl, H);
+
+struct Timer {
+    bool on = false;
+    int kind = -1;                 // which kernel to time
+    std::vector<hipEvent_t> ev;    // pairs
+    size_t used = 0;
+    double total_ms = 0.0;
+    int64_t count = 0;
+    int64_t bytes = 0;             // algorithmic bytes of the timed launches
+};
+
+struct Solver {
+    Err err;
+    hipStream_t stream = nullptr;
+    chm_params_t prm{};
+    int dim = 0, nv = 0, ncell = 0, nl = 0;
+    Pool pool;
+
+    // mesh
+    double *coords = nullptr;
+    int *cells = nullptr;
+    double *vol = nullptr;
+    int ncolors = 0;
+    std::vector<int> color_ptr;   // host copy of colour offsets
+    int *color_cells = nullptr;
+    // quadrature (barycentric points, weights summing to 1)
+    int nq = 0;
+    double *qb = nullptr, *qw = nullptr;
+
+    // matrices (shared pattern)
+    Csr M, K, As;       // As values share M's pattern
+    Sell sM;            // SELL of the pattern with M values
+    double *sK = nullptr, *sAs = nullptr;  // SELL values of K and As on sM's layout
+    double tau_s[2], te_s[2];
+
+    Hierarchy hM, hA;
+
+    // state and Krylov workspace
+    int m = 30;
+    double2 *x = nullptr;      // current state as a block vector: (phi, mu)
+    double2 *xk = nullptr;     // FGMRES iterate (committed to x on success)
+    double2 *b = nullptr, *r = nullptr;
+    double2 *V = nullptr, *Z = nullptr;
+    double2 *f = nullptr;      // potential term of the right-hand side (pairs)
+    double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
+    double2 *pcg_s = nullptr;  // CG scalars: rz[0..k], dq[0..k]
+    double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+    double2 *hbuf1 = nullptr, *hbuf2 = nullptr, *nrm2 = nullptr;  // CGS2 results
+    double2 *red = nullptr;    // reduction partials
+    unsigned *ticket = nullptr;
+    Ctl *ctl = nullptr;        // device
+    Ctl *hctl = nullptr;       // pinned host mirror
+    int64_t step_count = 0;
+    double setup_ms = 0.0;
+    Timer timer;
+};
+
+// ---- util.hip
+void scan_exclusive(int *d_in_out, int n, int *d_total, Pool &pool, hipStream_t s);
+void fill_int(int *p, int v, size_t n, hipStream_t s);
+void fill_double(double *p, double v, size_t n, hipStream_t s);
+int read_int(const int *d, hipStream_t s);
+double reduce_max_host(const double *d, int n, Pool &pool, hipStream_t s);
+void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s);
+void sell_values(const Csr &A, const Sell &S, const double *csr_vals, double *sell_vals, hipStream_t s);
+
+// ---- mesh_setup.hip
+void build_quadrature(int dim, std::vector<double> &bary, std::vector<double> &w);
+void mesh_setup(Solver &S);
+
+// ---- amg_setup.hip
+void amg_build(Solver &S, Hierarchy &H, const Csr &A0);
+
+// ---- solve.hip
+void alloc_workspace(Solver &S);
+void vcycle(Solver &S, Hierarchy &H, const double2 *b, double2 *x);
+void schur_solve(Solver &S, const double2 *b, double2 *x);
+void mass_solve(Solver &S, const double2 *b, double2 *x);
+void apply_prec(Solver &S, const double2 *v, double2 *w);
+void apply_saddle(Solver &S, const double2 *x, double2 *y);
+void compute_rhs(Solver &S);
+int step_once(Solver &S, chm_stats_t *st);
+
+}  // namespace chm

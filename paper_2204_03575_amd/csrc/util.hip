@@ -1,0 +1,232 @@
+// Small device utilities: exclusive scan, fills, max reduction, CSR -> SELL-64.
+#include "chm_internal.h"
+
+namespace chm {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 4;
+constexpr int kScanTile = kScanThreads * kScanPerThread;
+
+__global__ void __launch_bounds__(kScanThreads) k_tile_sums(const int *in, int n, int *sums)
+{
+    __shared__ int sh[kScanThreads];
+    const int t = threadIdx.x;
+    const long base = (long)blockIdx.x * kScanTile + (long)t * kScanPerThread;
+    int s = 0;
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (base + k < n)
+            s += in[base + k];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if (t < off)
+            sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    if (t == 0)
+        sums[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of one tile, shifted by offsets[tile]; the last tile writes the total
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan(int *data, int n, const int *offsets,
+                                                            int *total)
+{
+    __shared__ int sh[kScanThreads];
+    const int t = threadIdx.x;
+    const long base = (long)blockIdx.x * kScanTile + (long)t * kScanPerThread;
+    int v[kScanPerThread];
+    int s = 0;
+    for (int k = 0; k < kScanPerThread; ++k) {
+        v[k] = (base + k < n) ? data[base + k] : 0;
+        s += v[k];
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int excl = sh[t] - s + (offsets ? offsets[blockIdx.x] : 0);
+    for (int k = 0; k < kScanPerThread; ++k) {
+        if (base + k < n)
+            data[base + k] = excl;
+        excl += v[k];
+    }
+    if (total && t == kScanThreads - 1 && blockIdx.x == gridDim.x - 1)
+        *total = excl;
+}
+
+__global__ void k_fill_int(int *p, int v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ void k_fill_double(double *p, double v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_max_partial(const double *in, int n, double *out)
+{
+    __shared__ double sh[256];
+    int t = threadIdx.x;
+    double m = -1.0e300;
+    for (int i = blockIdx.x * 256 + t; i < n; i += gridDim.x * 256)
+        m = fmax(m, in[i]);
+    sh[t] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+            sh[t] = fmax(sh[t], sh[t + off]);
+        __syncthreads();
+    }
+    if (t == 0)
+        out[blockIdx.x] = sh[0];
+}
+
+// width of each SELL slice, times the slice height
+__global__ void k_slice_width(const int *rp, int n, int nslices, int *w)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices)
+        return;
+    int r0 = s * kSlice, r1 = min(n, r0 + kSlice), mx = 0;
+    for (int r = r0; r < r1; ++r)
+        mx = max(mx, rp[r + 1] - rp[r]);
+    w[s] = mx * kSlice;
+}
+
+__global__ void k_sell_fill(const int *rp, const int *ci, const double *v, int n, int nslices,
+                            const int *sptr, int *col, double *val)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nslices * kSlice)
+        return;
+    int s = row / kSlice, lane = row % kSlice;
+    int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    int b = 0, len = 0;
+    if (row < n) {
+        b = rp[row];
+        len = rp[row + 1] - b;
+    }
+    for (int k = 0; k < width; ++k) {
+        int idx = base + k * kSlice + lane;
+        if (k < len) {
+            if (col)
+                col[idx] = ci[b + k];
+            val[idx] = v[b + k];
+        } else {
+            if (col)
+                col[idx] = row < n ? row : 0;
+            val[idx] = 0.0;
+        }
+    }
+}
+
+}  // namespace
+
+void scan_exclusive(int *d, int n, int *d_total, Pool &pool, hipStream_t s)
+{
+    if (n <= 0) {
+        if (d_total)
+            fill_int(d_total, 0, 1, s);
+        return;
+    }
+    int tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 1) {
+        k_tile_scan<<<1, kScanThreads, 0, s>>>(d, n, nullptr, d_total);
+        CHM_HIP(hipGetLastError());
+        return;
+    }
+    int *sums = pool.get<int>(tiles);
+    k_tile_sums<<<tiles, kScanThreads, 0, s>>>(d, n, sums);
+    CHM_HIP(hipGetLastError());
+    scan_exclusive(sums, tiles, nullptr, pool, s);
+    k_tile_scan<<<tiles, kScanThreads, 0, s>>>(d, n, sums, d_total);
+    CHM_HIP(hipGetLastError());
+}
+
+void fill_int(int *p, int v, size_t n, hipStream_t s)
+{
+    if (!n)
+        return;
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    k_fill_int<<<blocks, 256, 0, s>>>(p, v, n);
+    CHM_HIP(hipGetLastError());
+}
+
+void fill_double(double *p, double v, size_t n, hipStream_t s)
+{
+    if (!n)
+        return;
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    k_fill_double<<<blocks, 256, 0, s>>>(p, v, n);
+    CHM_HIP(hipGetLastError());
+}
+
+int read_int(const int *d, hipStream_t s)
+{
+    int v = 0;
+    CHM_HIP(hipMemcpyAsync(&v, d, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHM_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+double reduce_max_host(const double *d, int n, Pool &pool, hipStream_t s)
+{
+    int blocks = std::max(1, std::min((n + 255) / 256, 1024));
+    double *part = pool.get<double>(blocks);
+    k_max_partial<<<blocks, 256, 0, s>>>(d, n, part);
+    CHM_HIP(hipGetLastError());
+    std::vector<double> h(blocks);
+    CHM_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * blocks, hipMemcpyDeviceToHost, s));
+    CHM_HIP(hipStreamSynchronize(s));
+    double m = -1.0e300;
+    for (double v : h)
+        m = std::max(m, v);
+    return m;
+}
+
+void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s)
+{
+    S.n = A.n;
+    S.nslices = (A.n + kSlice - 1) / kSlice;
+    S.sptr = pool.get<int>(S.nslices + 1);
+    if (S.nslices > 0) {
+        k_slice_width<<<(S.nslices + 255) / 256, 256, 0, s>>>(A.rp, A.n, S.nslices, S.sptr);
+        CHM_HIP(hipGetLastError());
+    }
+    scan_exclusive(S.sptr, S.nslices, S.sptr + S.nslices, pool, s);
+    S.stored = read_int(S.sptr + S.nslices, s);
+    S.col = pool.get<int>(S.stored);
+    S.val = pool.get<double>(S.stored);
+    int rows = S.nslices * kSlice;
+    if (rows > 0) {
+        k_sell_fill<<<(rows + 255) / 256, 256, 0, s>>>(A.rp, A.ci, A.v, A.n, S.nslices, S.sptr,
+                                                       S.col, S.val);
+        CHM_HIP(hipGetLastError());
+    }
+}
+
+void sell_values(const Csr &A, const Sell &S, const double *csr_vals, double *sell_vals,
+                 hipStream_t s)
+{
+    int rows = S.nslices * kSlice;
+    if (rows > 0) {
+        k_sell_fill<<<(rows + 255) / 256, 256, 0, s>>>(A.rp, A.ci, csr_vals, A.n, S.nslices,
+                                                       S.sptr, nullptr, sell_vals);
+        CHM_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace chm
