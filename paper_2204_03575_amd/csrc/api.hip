@@ -195,8 +195,9 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
         for (int k = 0; k < nsteps; ++k) {
             int rc = chm::step_once(h->s, stats ? stats + k : nullptr);
             if (rc != CHM_OK)
-                return fail(h, rc, rc == CHM_ENOCONV ? "FGMRES did not converge within max_iters"
-                                                     : "non-finite value in the solve");
+                return fail(h, rc, rc == CHM_ENOCONV
+                                       ? "FGMRES did not converge within max_iters"
+                                       : "non-finite value in the solve (" + h->s.nan_where + ")");
         }
         return CHM_OK;
     });

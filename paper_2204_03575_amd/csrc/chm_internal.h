@@ -188,6 +188,7 @@ struct Solver {
     int64_t step_count = 0;
     double setup_ms = 0.0;
     Timer timer;
+    std::string nan_where;     // where the last CHM_ENAN was detected
 };
 
 // ---- util.hip

@@ -915,6 +915,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
         }
         if (!finite) {
             rc = CHM_ENAN;
+            S.nan_where = "residual check: |r| = (" + std::to_string(res[0]) + ", " +
+                          std::to_string(res[1]) + "), |b| = (" + std::to_string(bn[0]) + ", " +
+                          std::to_string(bn[1]) + "), iterations (" + std::to_string(total[0]) +
+                          ", " + std::to_string(total[1]) + ")";
             break;
         }
         if (!act[0] && !act[1])
@@ -954,6 +958,12 @@ int step_once(Solver &S, chm_stats_t *st_out)
                 k_deactivate<<<1, 64, 0, st>>>(S.ctl, act[0], act[1]);
             if (S.hctl->nan) {
                 rc = CHM_ENAN;
+                S.nan_where = "Arnoldi step " + std::to_string(j) + ": estimates (" +
+                              std::to_string(S.hctl->resest[0]) + ", " +
+                              std::to_string(S.hctl->resest[1]) + "), |w| (" +
+                              std::to_string(S.hctl->hn[0]) + ", " + std::to_string(S.hctl->hn[1]) +
+                              "), iterations (" + std::to_string(total[0]) + ", " +
+                              std::to_string(total[1]) + ")";
                 break;
             }
             if (!any)
@@ -968,8 +978,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
     if (rc == CHM_OK) {
         k_finite<<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.ctl);
         read_ctl(S);
-        if (S.hctl->nan)
+        if (S.hctl->nan) {
             rc = CHM_ENAN;
+            S.nan_where = "final iterate";
+        }
     }
     stats.clamped = S.hctl->clamped;
     if (rc == CHM_OK) {

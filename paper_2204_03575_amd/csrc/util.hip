@@ -119,6 +119,9 @@ __global__ void k_sell_fill(const int *rp, const int *ci, const double *v, int n
         b = rp[row];
         len = rp[row + 1] - b;
     }
+    // padding repeats the row's last column (a valid index of the input vector
+    // for square and rectangular matrices alike) with value 0
+    const int pad_col = len > 0 ? ci[b + len - 1] : 0;
     for (int k = 0; k < width; ++k) {
         int idx = base + k * kSlice + lane;
         if (k < len) {
@@ -127,10 +130,17 @@ __global__ void k_sell_fill(const int *rp, const int *ci, const double *v, int n
             val[idx] = v[b + k];
         } else {
             if (col)
-                col[idx] = row < n ? row : 0;
+                col[idx] = pad_col;
             val[idx] = 0.0;
         }
     }
+}
+
+__global__ void k_check_cols(const int *col, int64_t stored, int ncols, int *bad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < stored && (col[i] < 0 || col[i] >= ncols))
+        atomicAdd(bad, 1);
 }
 
 }  // namespace
@@ -215,6 +225,15 @@ void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s)
         k_sell_fill<<<(rows + 255) / 256, 256, 0, s>>>(A.rp, A.ci, A.v, A.n, S.nslices, S.sptr,
                                                        S.col, S.val);
         CHM_HIP(hipGetLastError());
+    }
+    // every stored column (padding included) must index the input vector
+    if (S.stored > 0) {
+        int *bad = pool.get<int>(1);
+        fill_int(bad, 0, 1, s);
+        k_check_cols<<<(int)((S.stored + 255) / 256), 256, 0, s>>>(S.col, S.stored, A.m, bad);
+        CHM_HIP(hipGetLastError());
+        if (read_int(bad, s))
+            throw Failure(CHM_EINVAL, "SELL conversion produced a column outside the matrix");
     }
 }
 

@@ -233,12 +233,15 @@ def test_nan_is_reported():
 def test_runs_are_bitwise_deterministic():
     case("determinism 24x24, 2 steps, two solvers")
     outs = []
-    for _ in range(2):
+    for rep in range(2):
         p, co, ce, g, o = make(n=(24, 24))
         php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
         g.set_fields(php, phn)
-        g.step(2)
+        for k in range(2):
+            st = g.step(1)[0]
+            print(f"solver {rep} step {k}: {st}", flush=True)
         outs.append(g.get_fields())
+        del g
     for f in FIELDS:
         assert np.array_equal(outs[0][f], outs[1][f]), f
 
