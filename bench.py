@@ -1,0 +1,137 @@
+"""Benchmark: time steps of the 512x512 P1 workload on one MI355X.
+
+One timed "step" is one time step of the whole per-step path: right-hand side
+(coloured quadrature of f' and M phi), FGMRES to 1e-8 relative residual for
+both species with Algorithm 1 as preconditioner (AMG V-cycles, CG-accelerated
+As solves), state update and solvent removal.  The setup (assembly and the two
+AMG hierarchies) runs once before the warm-up and is reported separately.
+
+Metric: DOF * Krylov iterations per second = sum over steps and species of
+(2 N * FGMRES iterations) / timed seconds, N = mesh vertices (each species'
+system has 2N unknowns); also time steps per second ("solves/s").
+
+Prints one JSON line.  Extra objects:
+  roofline      the fine-level Chebyshev smoothing kernel of the As hierarchy
+                (the dominant kernel), timed per launch with HIP events on the
+                solver's stream, against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle, one time step of the same workload (its AMG
+                setup excluded), single thread.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF·Krylov-iters/s and solves/s at 1e-8 rel. residual; mixed+learned vs FP64"
+HBM_PEAK_GBS = 8000.0
+# HBM traffic of the timed kernel per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE,
+# scaled by the copy-kernel calibration (None until measured for the current kernel)
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512, help="squares per side of the unit square")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, co, ce, php, phn):
+    import numpy as np
+    from oracle import Oracle
+    o = Oracle(co, ce, p)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros_like(php), mu_n=np.zeros_like(php))
+    t0 = time.perf_counter()
+    out = o.step(st)
+    dt = time.perf_counter() - t0
+    its = out["stats"]["iters"]
+    dof = 2 * co.shape[0]
+    return {"value": dof * (its[0] + its[1]) / dt, "unit": "DOF*iters/s", "cores": 1,
+            "kind": "oracle", "solves_per_s": 1.0 / dt, "iters": list(its),
+            "sample": f"1 time step of the {p['n'][0]}x{p['n'][1]} workload from the same initial "
+                      f"state, plain C oracle (gcc -O2, one thread), its AMG setup excluded; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
+                                   "part of this build (see DESIGN.md for how it would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2204_03575_amd import Solver
+
+    p = S.preset("square512", n=(args.n, args.n))
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    php, phn, _ = S.initial_fractions(nv, p["mean_p"], p["mean_n"])
+    torch.cuda.init()
+    print(f"# setup {args.n}x{args.n} ({nv} vertices)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = Solver(co, ce, p)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = g.setup_info()
+    g.set_fields(php, phn)
+    for k in range(args.warmup):
+        st = g.step(1)[0]
+        print(f"# warmup step {k}: iters {st['iters']}", file=sys.stderr, flush=True)
+    if not args.no_timer:
+        g.timer_enable(0, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = g.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    iters = [s["iters"][0] + s["iters"][1] for s in stats]
+    dof = 2 * nv
+    value = dof * sum(iters) / dt
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF*iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D unit square {args.n}x{args.n} P1 ({nv} vertices, "
+                               f"{2 * nv} unknowns per species), Flory-Huggins, "
+                               f"evaporation 0.0025/step, FGMRES rtol 1e-8, FP64",
+                   "global_batch": 2, "parallelism": "none"},
+        "solves_per_s": args.steps / dt,
+        "fgmres_iters_per_step": [list(s["iters"]) for s in stats],
+        "max_relres": max(max(s["relres"]) for s in stats),
+        "setup_ms": 1e3 * setup_s, "amg_levels": [info["levels_mass"], info["levels_as"]],
+    }
+    if not args.no_timer:
+        launches, ms, nbytes = g.timer_read()
+        avg_s = ms * 1e-3 / max(1, launches)
+        per_launch = nbytes / max(1, launches)
+        achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+        traffic = TRAFFIC_BYTES_PER_LAUNCH
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "k_cheb (fine level, As hierarchy)",
+                           "launches": launches, "avg_us": avg_s * 1e6,
+                           "bytes_per_launch": per_launch}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, co, ce, php, phn)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -640,13 +640,32 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         CHM_HIP(hipStreamSynchronize(st));
     }
 
-    // SELL copies and work vectors
+    // SELL copies, kernel shapes and work vectors
+    // One lane per row (SELL-64) for short rows when there are enough rows to
+    // fill the chip; otherwise a power-of-two group of lanes per row, enough to
+    // reach about 128k threads but no wider than the rows.
+    auto lanes_per_row = [](const Csr &A) {
+        const double avg = A.n > 0 ? double(A.nnz) / A.n : 0.0;
+        const long target = 131072;
+        if (avg < 12.0 && A.n >= target)
+            return 0;
+        int want = 4;
+        while (want < 32 && (long)want * A.n < target)
+            want *= 2;
+        int cap = 4;
+        while (cap < 32 && cap < avg)
+            cap *= 2;
+        return std::min(want, cap);
+    };
     for (int l = 0; l < H.nlev; ++l) {
         Level &L = H.lev[l];
         csr_to_sell(L.A, L.sA, pool, st);
+        L.gsA = lanes_per_row(L.A);
         if (l + 1 < H.nlev) {
             csr_to_sell(L.P, L.sP, pool, st);
             csr_to_sell(L.R, L.sR, pool, st);
+            L.gsP = lanes_per_row(L.P);
+            L.gsR = lanes_per_row(L.R);
         }
         H.x[l] = pool.get<double2>(L.n);
         H.xt[l] = pool.get<double2>(L.n);

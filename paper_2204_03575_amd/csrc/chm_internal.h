@@ -30,7 +30,7 @@ constexpr int kSlice = 64;      // SELL slice height = wavefront size
 constexpr int kBlock = 256;     // threads per block for row kernels
 constexpr int kMaxLevels = 24;
 constexpr int kMaxRestart = 64;
-constexpr int kRedBlocks = 1024;  // blocks of the two-stage reductions
+constexpr int kRedBlocks = 256;   // blocks of the two-stage reductions (one per CU)
 
 struct Err {
     int code = CHM_OK;
@@ -93,6 +93,9 @@ struct Level {
     int n = 0, nc = 0;
     Csr A, P, R;
     Sell sA, sP, sR;
+    // lanes per row of the SpMV kernels: 0 = SELL-64 with one lane per row,
+    // 4..32 = CSR with that many lanes per row (long rows)
+    int gsA = 0, gsP = 0, gsR = 0;
     double *dinv = nullptr;
     double rho = 0.0;
     int *agg = nullptr;
@@ -178,11 +181,8 @@ struct Solver {
     double2 *V = nullptr, *Z = nullptr;
     double2 *f = nullptr;      // potential term of the right-hand side (pairs)
     double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
-    double2 *pcg_s = nullptr;  // CG scalars: rz[0..k], dq[0..k]
     double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
-    double2 *hbuf1 = nullptr, *hbuf2 = nullptr, *nrm2 = nullptr;  // CGS2 results
-    double2 *red = nullptr;    // reduction partials
-    unsigned *ticket = nullptr;
+    double2 *red = nullptr;    // slots of per-block partial sums (kRedBlocks each)
     Ctl *ctl = nullptr;        // device
     Ctl *hctl = nullptr;       // pinned host mirror
     int64_t step_count = 0;

@@ -7,9 +7,11 @@
 // device.  Both species run through every kernel together (pair vectors),
 // each with its own scalars, convergence flag and iteration count.
 //
-// All reductions are deterministic: a fixed grid writes one partial per block,
-// and the last block to finish (ticket counter) adds the partials in block
-// order.
+// Reductions are deterministic and need no inter-block synchronisation: a
+// producer kernel with a fixed grid of at most 256 blocks writes one partial
+// sum per block; every consumer block adds the partials itself in a fixed
+// order (so all blocks obtain the same bits), after the kernel boundary has
+// made them visible.
 #include <chrono>
 #include <cmath>
 
@@ -52,56 +54,66 @@ __device__ inline double2 block_sum(double2 v, double2 *sh)
     return r;
 }
 
-__device__ inline void store_partial(double2 *p, double2 v)
+// out[v] = sum over g < G of part[v * G + g] for v < nvec (G <= 256), into
+// LDS, visible to the whole block on return.  Wave w takes vectors w, w + 4,
+// ...; lane l adds g = l, l + 64, ... and the wave adds its lanes with a
+// fixed shuffle tree.
+__device__ inline void reduce_parts(const double2 *__restrict__ part, int nvec, int G, double2 *out)
 {
-    __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline double2 load_partial(const double2 *p)
-{
-    double2 v;
-    v.x = __hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    v.y = __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return v;
-}
-
-// true in every thread of the block that finishes last
-__device__ inline bool last_block(unsigned *ticket)
-{
-    __shared__ int am_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(ticket, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (am_last)
-        __threadfence();
-    return am_last != 0;
-}
-
-// the last block adds partials[v * G + g] over g in order into out[v]
-__device__ inline void finish_partials(const double2 *partials, int nvec, double2 *out,
-                                       unsigned *ticket)
-{
-    const int G = gridDim.x;
-    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int v = wid; v < nvec; v += kBlock / 64) {
         double2 s = d2(0.0, 0.0);
-        for (int g = 0; g < G; ++g) {
-            double2 p = load_partial(partials + (size_t)v * G + g);
+        for (int g = lane; g < G; g += 64) {
+            const double2 p = part[(size_t)v * G + g];
             s.x += p.x;
             s.y += p.y;
         }
-        out[v] = s;
+        s = wave_sum(s);
+        if (lane == 0)
+            out[v] = s;
     }
-    if (threadIdx.x == 0)
-        *ticket = 0u;
+    __syncthreads();
+}
+
+// two independent scalars at once (waves 0 and 1)
+__device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
+                                  int G, double2 *out)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (wid < 2) {
+        const double2 *p = wid == 0 ? pa : pb;
+        double2 s = d2(0.0, 0.0);
+        for (int g = lane; g < G; g += 64) {
+            const double2 q = p[g];
+            s.x += q.x;
+            s.y += q.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0)
+            out[wid] = s;
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ SELL SpMV family (pairs)
 enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
+
+__device__ inline double2 sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
+                                   const double *__restrict__ val, const double2 *__restrict__ x,
+                                   int row)
+{
+    const int s = row / kSlice, lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    double ax = 0.0, ay = 0.0;
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        const double a = val[idx];
+        const double2 xv = x[col[idx]];
+        ax += a * xv.x;
+        ay += a * xv.y;
+    }
+    return d2(ax, ay);
+}
 
 // SP_SET: y = A x; SP_ADD: y += A x; SP_RESID: y = b - A x
 template <int MODE>
@@ -114,89 +126,156 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    const int s = row / kSlice, lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-    double ax = 0.0, ay = 0.0;
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const double a = val[idx];
-        const double2 xv = x[col[idx]];
-        ax += a * xv.x;
-        ay += a * xv.y;
-    }
+    const double2 s = sell_row(sptr, col, val, x, row);
     if (MODE == SP_SET) {
-        y[row] = d2(ax, ay);
+        y[row] = s;
     } else if (MODE == SP_ADD) {
-        double2 o = y[row];
-        y[row] = d2(o.x + ax, o.y + ay);
+        const double2 o = y[row];
+        y[row] = d2(o.x + s.x, o.y + s.y);
     } else {
-        double2 bb = b[row];
-        y[row] = d2(bb.x - ax, bb.y - ay);
+        const double2 bb = b[row];
+        y[row] = d2(bb.x - s.x, bb.y - s.y);
     }
 }
 
-// One smoothing step: r = b - A x_in; d = c1 d + c2 D^-1 r; x_out = x_in + d.
+// Chebyshev (or damped Jacobi) step in two-buffer form:
+//   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (b - A x_k),
+// the same polynomial as the update d_k = c1 d_{k-1} + c2 D^-1 r_k with
+// d_{k-1} = x_k - x_{k-1}.  x_{k+1} overwrites x_{k-1} row by row; with
+// prev = 0 the previous iterate is taken as zero (start from x = 0) or is not
+// needed (c1 = 0).
+__device__ inline double2 cheb_update(double2 s, const double2 *__restrict__ b,
+                                      const double2 *__restrict__ xk,
+                                      const double *__restrict__ dinv, const double2 *xprev,
+                                      int row, double c1, double c2, int prev)
+{
+    const double2 bb = b[row], xi = xk[row];
+    const double di = dinv[row];
+    double2 xp = d2(0.0, 0.0);
+    if (prev)
+        xp = xprev[row];
+    return d2(xi.x + c1 * (xi.x - xp.x) + c2 * (di * (bb.x - s.x)),
+              xi.y + c1 * (xi.y - xp.y) + c2 * (di * (bb.y - s.y)));
+}
+
 __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ sptr,
                                                  const int *__restrict__ col,
                                                  const double *__restrict__ val,
                                                  const double *__restrict__ dinv,
                                                  const double2 *__restrict__ b,
-                                                 const double2 *__restrict__ xin,
-                                                 double2 *__restrict__ xout, double2 *d, double c1,
-                                                 double c2)
+                                                 const double2 *__restrict__ xk, double2 *xprev,
+                                                 double c1, double c2, int prev)
 {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    const int s = row / kSlice, lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-    double ax = 0.0, ay = 0.0;
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const double a = val[idx];
-        const double2 xv = xin[col[idx]];
-        ax += a * xv.x;
-        ay += a * xv.y;
-    }
-    const double2 bb = b[row], xi = xin[row];
-    const double di = dinv[row];
-    double2 dd = d2(0.0, 0.0);
-    if (c1 != 0.0)
-        dd = d[row];
-    dd.x = c1 * dd.x + c2 * (di * (bb.x - ax));
-    dd.y = c1 * dd.y + c2 * (di * (bb.y - ay));
-    d[row] = dd;
-    xout[row] = d2(xi.x + dd.x, xi.y + dd.y);
+    const double2 s = sell_row(sptr, col, val, xk, row);
+    xprev[row] = cheb_update(s, b, xk, dinv, xprev, row, c1, c2, prev);
 }
 
-// first smoothing step from x = 0: d = c2 D^-1 b; x = d
+// first smoothing step from x = 0: x = c2 D^-1 b
 __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const double *__restrict__ dinv,
                                                   const double2 *__restrict__ b, double2 *x,
-                                                  double2 *d, double c2)
+                                                  double c2)
 {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
     const double2 bb = b[row];
     const double di = dinv[row];
-    const double2 dd = d2(c2 * (di * bb.x), c2 * (di * bb.y));
-    d[row] = dd;
-    x[row] = dd;
+    x[row] = d2(c2 * (di * bb.x), c2 * (di * bb.y));
 }
 
-// coarsest level: x = A^-1 b with the inverse stored column-major
+// ---- the same operations with a group of GS lanes per row (CSR), for
+// matrices with long rows or few rows: lane l of the group takes entries
+// l, l + GS, ... of the row and the group adds its lanes with a fixed shuffle
+// tree.  Whole groups share a row, so they exit together.
+template <int GS>
+__device__ inline double2 row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                  const double *__restrict__ v, const double2 *__restrict__ x,
+                                  int row, int lane)
+{
+    double ax = 0.0, ay = 0.0;
+    const int e = rp[row + 1];
+    for (int k = rp[row] + lane; k < e; k += GS) {
+        const double a = v[k];
+        const double2 xv = x[ci[k]];
+        ax += a * xv.x;
+        ay += a * xv.y;
+    }
+#pragma unroll
+    for (int off = GS / 2; off > 0; off >>= 1) {
+        ax += __shfl_down(ax, off, GS);
+        ay += __shfl_down(ay, off, GS);
+    }
+    return d2(ax, ay);
+}
+
+template <int GS, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const double *__restrict__ v,
+                                                   const double2 *__restrict__ x,
+                                                   const double2 *__restrict__ b, double2 *y)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    const double2 s = row_dot<GS>(rp, ci, v, x, row, lane);
+    if (lane != 0)
+        return;
+    if (MODE == SP_SET) {
+        y[row] = s;
+    } else if (MODE == SP_ADD) {
+        const double2 o = y[row];
+        y[row] = d2(o.x + s.x, o.y + s.y);
+    } else {
+        const double2 bb = b[row];
+        y[row] = d2(bb.x - s.x, bb.y - s.y);
+    }
+}
+
+template <int GS>
+__global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const double *__restrict__ v,
+                                                   const double *__restrict__ dinv,
+                                                   const double2 *__restrict__ b,
+                                                   const double2 *__restrict__ xk, double2 *xprev,
+                                                   double c1, double c2, int prev)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    const double2 s = row_dot<GS>(rp, ci, v, xk, row, lane);
+    if (lane != 0)
+        return;
+    xprev[row] = cheb_update(s, b, xk, dinv, xprev, row, c1, c2, prev);
+}
+
+// coarsest level: x = A^-1 b with the inverse stored column-major; b is staged
+// in LDS by the whole block, the inner products are unrolled so the loads of
+// a thread's row are in flight together
+constexpr int kDenseMax = 2048;
+
 __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
                                                   const double2 *__restrict__ b, double2 *x)
 {
+    __shared__ double2 bs[kDenseMax];
+    for (int j = threadIdx.x; j < n; j += kBlock)
+        bs[j] = b[j];
+    __syncthreads();
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
     double ax = 0.0, ay = 0.0;
+#pragma unroll 8
     for (int j = 0; j < n; ++j) {
         const double a = inv[(size_t)j * n + row];
-        const double2 bv = b[j];
-        ax += a * bv.x;
-        ay += a * bv.y;
+        ax += a * bs[j].x;
+        ay += a * bs[j].y;
     }
     x[row] = d2(ax, ay);
 }
@@ -206,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const double2 *__res
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    double2 a = x[row], b = e[row];
+    const double2 a = x[row], b = e[row];
     x[row] = d2(a.x + b.x, a.y + b.y);
 }
 
@@ -217,10 +296,9 @@ __global__ void __launch_bounds__(kBlock) k_copy(int n, const double2 *__restric
         b[row] = a[row];
 }
 
-// ------------------------------------------------------------------ dots (pairs, per species)
+// ------------------------------------------------------------------ dot partials (pairs)
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const double2 *__restrict__ a,
-                                                const double2 *__restrict__ b, double2 *partials,
-                                                double2 *out, unsigned *ticket)
+                                                const double2 *__restrict__ b, double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
     double2 acc = d2(0.0, 0.0);
@@ -229,32 +307,33 @@ __global__ void __launch_bounds__(kBlock) k_dot(int n, const double2 *__restrict
         acc.x += x.x * y.x;
         acc.y += x.y * y.y;
     }
-    double2 s = block_sum(acc, sh);
+    const double2 s = block_sum(acc, sh);
     if (threadIdx.x == 0)
-        store_partial(partials + blockIdx.x, s);
-    if (last_block(ticket))
-        finish_partials(partials, 1, out, ticket);
+        part[blockIdx.x] = s;
 }
 
 // ------------------------------------------------------------------ inner CG for As
-// step length from slots: alpha = rz / dq per species (0 where dq == 0)
 __device__ inline double2 ratio_or_zero(double2 num, double2 den)
 {
     return d2(den.x != 0.0 ? num.x / den.x : 0.0, den.y != 0.0 ? num.y / den.y : 0.0);
 }
 
-// first == 1: x = alpha d, r = b - alpha q (x = 0 and r = b before the step)
+// alpha = rz / dq from partials; first == 1: x = alpha d, r = b - alpha q
+// (x = 0 and r = b before the step), else x += alpha d, r -= alpha q
 __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, double2 *x, double2 *r,
                                                    const double2 *__restrict__ b,
                                                    const double2 *__restrict__ d,
                                                    const double2 *__restrict__ q,
-                                                   const double2 *__restrict__ rz,
-                                                   const double2 *__restrict__ dq, int first)
+                                                   const double2 *__restrict__ rz_part,
+                                                   const double2 *__restrict__ dq_part, int G,
+                                                   int first)
 {
+    __shared__ double2 sc[2];
+    reduce_two(rz_part, dq_part, G, sc);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
-    const double2 al = ratio_or_zero(*rz, *dq);
+    const double2 al = ratio_or_zero(sc[0], sc[1]);
     const double2 dv = d[i], qv = q[i];
     double2 xv = first ? d2(0.0, 0.0) : x[i];
     double2 rv = first ? b[i] : r[i];
@@ -268,9 +347,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, double2 *x, double2 *r
 
 // d = z + beta d with beta = rz_new / rz_old (0 where rz_old == 0); first: d = z
 __global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const double2 *__restrict__ z, double2 *d,
-                                                    const double2 *__restrict__ rz_new,
-                                                    const double2 *__restrict__ rz_old, int first)
+                                                    const double2 *__restrict__ new_part,
+                                                    const double2 *__restrict__ old_part, int G,
+                                                    int first)
 {
+    __shared__ double2 sc[2];
+    if (!first)
+        reduce_two(new_part, old_part, G, sc);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
@@ -279,79 +362,99 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const double2 *__rest
         d[i] = zv;
         return;
     }
-    const double2 be = ratio_or_zero(*rz_new, *rz_old);
+    const double2 be = ratio_or_zero(sc[0], sc[1]);
     const double2 dv = d[i];
     d[i] = d2(zv.x + be.x * dv.x, zv.y + be.y * dv.y);
 }
 
 // ------------------------------------------------------------------ saddle-point operator
-// y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te);  RESID: y = b - A x,
-// and the squared 2-norm of y per species goes to *out.
-template <bool RESID>
+// y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
+__device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
+                                  const int *__restrict__ col, const double *__restrict__ vm,
+                                  const double *__restrict__ vk, const double2 *__restrict__ x,
+                                  double2 t, double2 te, double2 &y0, double2 &y1)
+{
+    const int s = row / kSlice, lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        const int c = col[idx];
+        const double am = vm[idx], ak = vk[idx];
+        const double2 x0 = x[c], x1 = x[n + c];
+        m0x += am * x0.x;
+        m0y += am * x0.y;
+        k1x += ak * x1.x;
+        k1y += ak * x1.y;
+        k0x += ak * x0.x;
+        k0y += ak * x0.y;
+        m1x += am * x1.x;
+        m1y += am * x1.y;
+    }
+    y0 = d2(m0x + t.x * k1x, m0y + t.y * k1y);
+    y1 = d2(t.x * k0x - te.x * m1x, t.y * k0y - te.y * m1y);
+}
+
 __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict__ sptr,
                                                    const int *__restrict__ col,
                                                    const double *__restrict__ vm,
                                                    const double *__restrict__ vk,
-                                                   const double2 *__restrict__ x,
-                                                   const double2 *__restrict__ b, double2 *y,
-                                                   double2 t, double2 te, double2 *partials,
-                                                   double2 *out, unsigned *ticket)
+                                                   const double2 *__restrict__ x, double2 *y,
+                                                   double2 t, double2 te)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    double2 y0, y1;
+    saddle_row(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+    y[row] = y0;
+    y[n + row] = y1;
+}
+
+// y = b - A x over a grid-stride loop, and partial sums of |y|^2 per species
+__global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
+                                                         const int *__restrict__ col,
+                                                         const double *__restrict__ vm,
+                                                         const double *__restrict__ vk,
+                                                         const double2 *__restrict__ x,
+                                                         const double2 *__restrict__ b, double2 *y,
+                                                         double2 t, double2 te, double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
-    const int row = blockIdx.x * kBlock + threadIdx.x;
     double2 nrm = d2(0.0, 0.0);
-    if (row < n) {
-        const int s = row / kSlice, lane = row % kSlice;
-        const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-        double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
-        for (int k = 0; k < width; ++k) {
-            const int idx = base + k * kSlice + lane;
-            const int c = col[idx];
-            const double am = vm[idx], ak = vk[idx];
-            const double2 x0 = x[c], x1 = x[n + c];
-            m0x += am * x0.x;
-            m0y += am * x0.y;
-            k1x += ak * x1.x;
-            k1y += ak * x1.y;
-            k0x += ak * x0.x;
-            k0y += ak * x0.y;
-            m1x += am * x1.x;
-            m1y += am * x1.y;
-        }
-        double2 y0 = d2(m0x + t.x * k1x, m0y + t.y * k1y);
-        double2 y1 = d2(t.x * k0x - te.x * m1x, t.y * k0y - te.y * m1y);
-        if (RESID) {
-            const double2 b0 = b[row], b1 = b[n + row];
-            y0 = d2(b0.x - y0.x, b0.y - y0.y);
-            y1 = d2(b1.x - y1.x, b1.y - y1.y);
-            nrm = d2(y0.x * y0.x + y1.x * y1.x, y0.y * y0.y + y1.y * y1.y);
-        }
+    for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
+        double2 y0, y1;
+        saddle_row(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+        const double2 b0 = b[row], b1 = b[n + row];
+        y0 = d2(b0.x - y0.x, b0.y - y0.y);
+        y1 = d2(b1.x - y1.x, b1.y - y1.y);
+        nrm.x += y0.x * y0.x + y1.x * y1.x;
+        nrm.y += y0.y * y0.y + y1.y * y1.y;
         y[row] = y0;
         y[n + row] = y1;
     }
-    if (RESID) {
-        double2 s = block_sum(nrm, sh);
-        if (threadIdx.x == 0)
-            store_partial(partials + blockIdx.x, s);
-        if (last_block(ticket))
-            finish_partials(partials, 1, out, ticket);
-    }
+    const double2 s = block_sum(nrm, sh);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s;
 }
 
 // ------------------------------------------------------------------ Gram-Schmidt passes
-// MODE 0: out[i] = V_i . w;  MODE 1: w -= sum_i V_i h[i], then out[i] = V_i . w;
-// MODE 2: w -= sum_i V_i h[i], then out[0] = w . w.  All per species; len = 2n.
+// MODE 0: partials of V_i . w;  MODE 1: h = sum of the MODE-0 partials,
+// w -= sum_i V_i h[i], partials of V_i . w;  MODE 2: the same update with the
+// MODE-1 results, partials of w . w.  All per species; len = 2n.
 constexpr int kChunk = 8;
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restrict__ V, int nvec,
-                                               double2 *w, const double2 *__restrict__ h,
-                                               double2 *partials, double2 *out, unsigned *ticket)
+                                               double2 *w, const double2 *__restrict__ hpart,
+                                               double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
+    __shared__ double2 h[kMaxRestart + 1];
     const int G = gridDim.x;
     const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
     if (MODE > 0) {
+        reduce_parts(hpart, nvec, G, h);
         for (int i = start; i < len; i += stride) {
             double2 wv = w[i];
             for (int v = 0; v < nvec; ++v) {
@@ -369,11 +472,9 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
             acc.x += wv.x * wv.x;
             acc.y += wv.y * wv.y;
         }
-        double2 s = block_sum(acc, sh);
+        const double2 s = block_sum(acc, sh);
         if (threadIdx.x == 0)
-            store_partial(partials + blockIdx.x, s);
-        if (last_block(ticket))
-            finish_partials(partials, 1, out, ticket);
+            part[blockIdx.x] = s;
         return;
     }
     for (int v0 = 0; v0 < nvec; v0 += kChunk) {
@@ -392,16 +493,39 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
             }
         }
         for (int c = 0; c < kChunk && v0 + c < nvec; ++c) {
-            double2 s = block_sum(acc[c], sh);
+            const double2 s = block_sum(acc[c], sh);
             if (threadIdx.x == 0)
-                store_partial(partials + (size_t)(v0 + c) * G + blockIdx.x, s);
+                part[(size_t)(v0 + c) * G + blockIdx.x] = s;
         }
     }
-    if (last_block(ticket))
-        finish_partials(partials, nvec, out, ticket);
 }
 
 // ------------------------------------------------------------------ FGMRES control (one block)
+// ||b||^2 from partials; tol = rtol ||b|| per species
+__global__ void __launch_bounds__(kBlock) k_tol(Ctl *c, const double2 *__restrict__ part, int G,
+                                                double rtol)
+{
+    __shared__ double2 r[1];
+    reduce_parts(part, 1, G, r);
+    if (threadIdx.x < 2) {
+        const int s = threadIdx.x;
+        const double nb = s == 0 ? r[0].x : r[0].y;
+        const double bn = sqrt(nb);
+        c->nrm[s] = nb;
+        c->bnorm[s] = bn;
+        c->tol[s] = rtol * bn;
+    }
+}
+
+// squared residual norms from partials
+__global__ void __launch_bounds__(kBlock) k_nrm(Ctl *c, const double2 *__restrict__ part, int G)
+{
+    __shared__ double2 r[1];
+    reduce_parts(part, 1, G, r);
+    if (threadIdx.x < 2)
+        c->nrm[threadIdx.x] = threadIdx.x == 0 ? r[0].x : r[0].y;
+}
+
 // start of a cycle: g = (||r||, 0, ...), active flags from the host, k = 0
 __global__ void k_cycle_init(Ctl *c, int act0, int act1)
 {
@@ -437,16 +561,22 @@ __global__ void __launch_bounds__(kBlock) k_scale_first(int len, const double2 *
 // Column j of the Hessenberg matrix from the two Gram-Schmidt passes, the
 // previous rotations applied, a new rotation that zeroes H[j+1][j], the
 // residual estimate |g[j+1]|, and the convergence test against tol.
-__global__ void k_givens(Ctl *c, int j, int m, const double2 *__restrict__ h1,
-                         const double2 *__restrict__ h2, const double2 *__restrict__ nrm2)
+__global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
+                                                   const double2 *__restrict__ p1,
+                                                   const double2 *__restrict__ p2,
+                                                   const double2 *__restrict__ p3, int G)
 {
+    __shared__ double2 h1[kMaxRestart + 1], h2[kMaxRestart + 1], nn[1];
+    reduce_parts(p1, j + 1, G, h1);
+    reduce_parts(p2, j + 1, G, h2);
+    reduce_parts(p3, 1, G, nn);
     const int s = threadIdx.x;
     if (s >= 2 || !c->active[s])
         return;
     double *H = c->H[s];
     for (int i = 0; i <= j; ++i)
         H[i * m + j] = (s == 0 ? h1[i].x + h2[i].x : h1[i].y + h2[i].y);
-    const double hn = sqrt(s == 0 ? nrm2->x : nrm2->y);
+    const double hn = sqrt(s == 0 ? nn[0].x : nn[0].y);
     c->hn[s] = hn;
     H[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
@@ -525,16 +655,6 @@ __global__ void __launch_bounds__(kBlock) k_update_x(int len, double2 *x, const 
     x[i] = xv;
 }
 
-__global__ void k_tol(Ctl *c, double rtol)
-{
-    const int s = threadIdx.x;
-    if (s >= 2)
-        return;
-    const double bn = sqrt(c->nrm[s]);
-    c->bnorm[s] = bn;
-    c->tol[s] = rtol * bn;
-}
-
 __global__ void __launch_bounds__(kBlock) k_finite(int len, const double2 *__restrict__ x, Ctl *c)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -582,8 +702,9 @@ __device__ inline void dpot(const Pot &P, double p, double q, double &fp, double
 
 // f[v] += sum over the quadrature of f'(phi_h) lambda_v |T| for the cells of
 // one colour (no two share a vertex, so the += are race free)
+template <int NL>
 __global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ list, int count,
-                                                      const int *__restrict__ cells, int nl,
+                                                      const int *__restrict__ cells,
                                                       const double *__restrict__ vol,
                                                       const double *__restrict__ qb,
                                                       const double *__restrict__ qw, int nq,
@@ -594,33 +715,37 @@ __global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ li
     if (t >= count)
         return;
     const int c = list[t];
-    int vtx[4];
-    double2 ph[4], acc[4];
-    for (int a = 0; a < nl; ++a) {
-        vtx[a] = cells[(size_t)c * nl + a];
+    int vtx[NL];
+    double2 ph[NL], acc[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+        vtx[a] = cells[(size_t)c * NL + a];
         ph[a] = phi[vtx[a]];
         acc[a] = d2(0.0, 0.0);
     }
     int clamps = 0;
     for (int q = 0; q < nq; ++q) {
         double p = 0.0, r = 0.0;
-        for (int a = 0; a < nl; ++a) {
-            const double l = qb[q * nl + a];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            const double l = qb[q * NL + a];
             p += l * ph[a].x;
             r += l * ph[a].y;
         }
         double fp, fr;
         dpot(P, p, r, fp, fr, clamps);
         const double wq = qw[q];
-        for (int a = 0; a < nl; ++a) {
-            const double l = qb[q * nl + a];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            const double l = qb[q * NL + a];
             acc[a].x += wq * fp * l;
             acc[a].y += wq * fr * l;
         }
     }
     const double vc = vol[c];
-    for (int a = 0; a < nl; ++a) {
-        double2 o = f[vtx[a]];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+        const double2 o = f[vtx[a]];
         f[vtx[a]] = d2(o.x + vc * acc[a].x, o.y + vc * acc[a].y);
     }
     if (clamps)
@@ -665,6 +790,13 @@ __global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, doubl
 }
 
 // ------------------------------------------------------------------ host helpers
+// partial-sum slots (kRedBlocks pairs each) in S.red
+constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotP1 = 82,
+              kSlotP2 = kSlotP1 + kMaxRestart + 1, kSlotP3 = kSlotP2 + kMaxRestart + 1,
+              kSlots = kSlotP3 + 1;
+
+inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
+
 void timer_mark(Solver &S, bool begin)
 {
     Timer &T = S.timer;
@@ -683,23 +815,72 @@ void timer_mark(Solver &S, bool begin)
         for (size_t i = old; i < T.ev.size(); ++i)
             CHM_HIP(hipEventCreate(&T.ev[i]));
     }
-    (void)begin;
     CHM_HIP(hipEventRecord(T.ev[T.used++], S.stream));
 }
 
-void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2 *xin, double2 *xout,
-                 double2 *d, double c1, double c2)
+// y = A x / y += A x / y = b - A x with the kernel shape chosen for the matrix
+template <int MODE>
+void spmv_op(hipStream_t st, const Csr &C, const Sell &Sl, int gs, const double2 *x,
+             const double2 *b, double2 *y)
+{
+    const int n = C.n;
+    switch (gs) {
+    case 0:
+        k_spmv<MODE><<<nblk(n), kBlock, 0, st>>>(n, Sl.sptr, Sl.col, Sl.val, x, b, y);
+        break;
+    case 4:
+        k_spmv_v<4, MODE><<<nblk(4l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
+        break;
+    case 8:
+        k_spmv_v<8, MODE><<<nblk(8l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
+        break;
+    case 16:
+        k_spmv_v<16, MODE><<<nblk(16l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
+        break;
+    default:
+        k_spmv_v<32, MODE><<<nblk(32l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
+        break;
+    }
+}
+
+// one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
+void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2 *xk,
+                 double2 *xprev, double c1, double c2, int prev)
 {
     Level &L = H.lev[l];
+    const int n = L.n;
+    hipStream_t st = S.stream;
     const bool timed = S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
     if (timed)
         timer_mark(S, true);
-    k_cheb<<<nblk(L.n), kBlock, 0, S.stream>>>(L.n, L.sA.sptr, L.sA.col, L.sA.val, L.dinv, b, xin,
-                                                xout, d, c1, c2);
+    switch (L.gsA) {
+    case 0:
+        k_cheb<<<nblk(n), kBlock, 0, st>>>(n, L.sA.sptr, L.sA.col, L.sA.val, L.dinv, b, xk, xprev,
+                                           c1, c2, prev);
+        break;
+    case 4:
+        k_cheb_v<4><<<nblk(4l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk, xprev,
+                                                     c1, c2, prev);
+        break;
+    case 8:
+        k_cheb_v<8><<<nblk(8l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk, xprev,
+                                                     c1, c2, prev);
+        break;
+    case 16:
+        k_cheb_v<16><<<nblk(16l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk,
+                                                       xprev, c1, c2, prev);
+        break;
+    default:
+        k_cheb_v<32><<<nblk(32l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk,
+                                                       xprev, c1, c2, prev);
+        break;
+    }
     if (timed) {
+        // algorithmic bytes: col + val per nonzero; per row x_k (gathered once),
+        // b, D^-1, x_{k-1} (when read) and the written x_{k+1}
         timer_mark(S, false);
         S.timer.count += 1;
-        S.timer.bytes += 12ll * L.A.nnz + 88ll * L.n;
+        S.timer.bytes += 12ll * L.A.nnz + (prev ? 72ll : 56ll) * L.n;
     }
 }
 
@@ -712,25 +893,24 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const double2 *b, double2 *x)
         return;
     }
     const int deg = H.degree;
-    double2 *xt = H.xt[l], *d = H.d[l], *r = H.r[l];
+    double2 *xt = H.xt[l], *r = H.r[l];
     auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
-    // pre-smoothing from zero; 2 deg - 1 ping-pong steps follow, so starting in
-    // xt leaves the result in x
-    k_cheb0<<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv, b, xt, d, c2(1));
+    // Pre-smoothing from zero.  Every step after the first writes the buffer
+    // not holding the current iterate; 2 deg - 1 such steps follow the first,
+    // so starting in xt leaves the result in x.
+    k_cheb0<<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv, b, xt, c2(1));
     double2 *cur = xt, *oth = x;
-    for (int k = 2; k <= deg; ++k) {
-        launch_cheb(S, H, l, b, cur, oth, d, c1(k), c2(k));
+    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
+        launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
         std::swap(cur, oth);
     }
-    k_spmv<SP_RESID><<<nblk(L.n), kBlock, 0, st>>>(L.n, L.sA.sptr, L.sA.col, L.sA.val, cur, b, r);
-    k_spmv<SP_SET><<<nblk(L.nc), kBlock, 0, st>>>(L.nc, L.sR.sptr, L.sR.col, L.sR.val, r, nullptr,
-                                                  H.b[l + 1]);
+    spmv_op<SP_RESID>(st, L.A, L.sA, L.gsA, cur, b, r);
+    spmv_op<SP_SET>(st, L.R, L.sR, L.gsR, r, nullptr, H.b[l + 1]);
     vcycle_level(S, H, l + 1, H.b[l + 1], H.x[l + 1]);
-    k_spmv<SP_ADD><<<nblk(L.n), kBlock, 0, st>>>(L.n, L.sP.sptr, L.sP.col, L.sP.val, H.x[l + 1],
-                                                 nullptr, cur);
+    spmv_op<SP_ADD>(st, L.P, L.sP, L.gsP, H.x[l + 1], nullptr, cur);
     for (int k = 1; k <= deg; ++k) {
-        launch_cheb(S, H, l, b, cur, oth, d, c1(k), c2(k));
+        launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 1 && !H.jacobi);
         std::swap(cur, oth);
     }
 }
@@ -751,8 +931,7 @@ void mass_solve(Solver &S, const double2 *b, double2 *x)
     const int n = S.nv;
     vcycle(S, H, b, x);
     for (int c = 1; c < S.prm.amg_cycles; ++c) {
-        k_spmv<SP_RESID><<<nblk(n), kBlock, 0, S.stream>>>(n, H.lev[0].sA.sptr, H.lev[0].sA.col,
-                                                           H.lev[0].sA.val, x, b, S.mr);
+        spmv_op<SP_RESID>(S.stream, H.lev[0].A, H.lev[0].sA, H.lev[0].gsA, x, b, S.mr);
         vcycle(S, H, S.mr, S.me);
         k_axpy_add<<<nblk(n), kBlock, 0, S.stream>>>(n, S.me, x);
     }
@@ -765,31 +944,32 @@ void schur_solve(Solver &S, const double2 *b, double2 *x)
     Hierarchy &H = S.hA;
     const int n = S.nv, k = S.prm.schur_pcg;
     hipStream_t st = S.stream;
-    const Sell &A = H.lev[0].sA;
+    const Level &L0 = H.lev[0];
     if (k <= 0) {
         vcycle(S, H, b, x);
         for (int c = 1; c < S.prm.amg_cycles; ++c) {
-            k_spmv<SP_RESID><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.val, x, b, S.mr);
+            spmv_op<SP_RESID>(st, L0.A, L0.sA, L0.gsA, x, b, S.mr);
             vcycle(S, H, S.mr, S.me);
             k_axpy_add<<<nblk(n), kBlock, 0, st>>>(n, S.me, x);
         }
         return;
     }
     double2 *r = S.pcg_r, *z = S.pcg_z, *d = S.pcg_d, *q = S.pcg_q;
-    double2 *rz = S.pcg_s, *dq = S.pcg_s + 40;
     const int G = red_blocks(n);
     vcycle(S, H, b, z);                                            // z = V(b), r = b
-    k_dot<<<G, kBlock, 0, st>>>(n, b, z, S.red, rz + 0, S.ticket);
-    k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, rz, rz, 1);      // d = z
+    k_dot<<<G, kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
+    k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
     for (int it = 1; it <= k; ++it) {
-        k_spmv<SP_SET><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.val, d, nullptr, q);
-        k_dot<<<G, kBlock, 0, st>>>(n, d, q, S.red, dq + it, S.ticket);
-        k_pcg_xr<<<nblk(n), kBlock, 0, st>>>(n, x, r, b, d, q, rz + it - 1, dq + it, it == 1);
+        spmv_op<SP_SET>(st, L0.A, L0.sA, L0.gsA, d, nullptr, q);
+        k_dot<<<G, kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
+        k_pcg_xr<<<nblk(n), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
+                                             slot(S, kSlotDq + it), G, it == 1);
         if (it == k)
             break;
         vcycle(S, H, r, z);
-        k_dot<<<G, kBlock, 0, st>>>(n, r, z, S.red, rz + it, S.ticket);
-        k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, rz + it, rz + it - 1, 0);
+        k_dot<<<G, kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
+        k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
+                                              slot(S, kSlotRz + it - 1), G, 0);
     }
 }
 
@@ -807,9 +987,8 @@ void apply_prec(Solver &S, const double2 *v, double2 *w)
 void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
     const int n = S.nv;
-    k_saddle<false><<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
-                                                       nullptr, y, pair(S.tau_s), pair(S.te_s),
-                                                       nullptr, nullptr, nullptr);
+    k_saddle<<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, y,
+                                               pair(S.tau_s), pair(S.te_s));
 }
 
 // b = (M phi, -(tau'/eps) f) for the current state
@@ -825,9 +1004,13 @@ void compute_rhs(Solver &S)
         const int cnt = S.color_ptr[c + 1] - S.color_ptr[c];
         if (!cnt)
             continue;
-        k_rhs_color<<<nblk(cnt), kBlock, 0, st>>>(S.color_cells + S.color_ptr[c], cnt, S.cells,
-                                                  S.nl, S.vol, S.qb, S.qw, S.nq, S.x, P, S.f,
-                                                  &S.ctl->clamped);
+        const int *list = S.color_cells + S.color_ptr[c];
+        if (S.nl == 3)
+            k_rhs_color<3><<<nblk(cnt), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb, S.qw, S.nq,
+                                                         S.x, P, S.f, &S.ctl->clamped);
+        else
+            k_rhs_color<4><<<nblk(cnt), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb, S.qw, S.nq,
+                                                         S.x, P, S.f, &S.ctl->clamped);
     }
     k_spmv<SP_SET><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.x, nullptr, S.b);
     k_rhs_second<<<nblk(n), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
@@ -851,17 +1034,11 @@ void alloc_workspace(Solver &S)
     S.pcg_z = p.get<double2>(n);
     S.pcg_d = p.get<double2>(n);
     S.pcg_q = p.get<double2>(n);
-    S.pcg_s = p.get<double2>(80);
     S.tmp = p.get<double2>(n);
     S.tmp2 = p.get<double2>(n);
     S.mr = p.get<double2>(n);
     S.me = p.get<double2>(n);
-    S.hbuf1 = p.get<double2>(kMaxRestart + 1);
-    S.hbuf2 = p.get<double2>(kMaxRestart + 1);
-    S.nrm2 = p.get<double2>(1);
-    S.red = p.get<double2>(std::max<size_t>((size_t)kRedBlocks * (kMaxRestart + 1), nblk(n)));
-    S.ticket = p.get<unsigned>(1);
-    fill_int(reinterpret_cast<int *>(S.ticket), 0, 1, S.stream);
+    S.red = p.get<double2>((size_t)kSlots * kRedBlocks);
     S.ctl = p.get<Ctl>(1);
     fill_int(reinterpret_cast<int *>(S.ctl), 0, sizeof(Ctl) / sizeof(int), S.stream);
     CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), sizeof(Ctl), hipHostMallocDefault));
@@ -884,14 +1061,13 @@ int step_once(Solver &S, chm_stats_t *st_out)
 {
     const int n = S.nv, len = 2 * n, m = S.m;
     hipStream_t st = S.stream;
-    const int Gv = red_blocks(len);
+    const int Gv = red_blocks(len), Gn = red_blocks(n);
     auto t0 = std::chrono::steady_clock::now();
     chm_stats_t stats{};
 
     compute_rhs(S);
-    k_dot<<<Gv, kBlock, 0, st>>>(len, S.b, S.b, S.red, reinterpret_cast<double2 *>(S.ctl->nrm),
-                                 S.ticket);
-    k_tol<<<1, 64, 0, st>>>(S.ctl, S.prm.rtol);
+    k_dot<<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
+    k_tol<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
     k_copy<<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
     fill_int(&S.ctl->nan, 0, 1, st);
 
@@ -899,9 +1075,9 @@ int step_once(Solver &S, chm_stats_t *st_out)
     int rc = CHM_OK;
     double res[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0};
     for (;;) {
-        k_saddle<true><<<nblk(n), kBlock, 0, st>>>(
-            n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b, S.r, pair(S.tau_s), pair(S.te_s),
-            S.red, reinterpret_cast<double2 *>(S.ctl->nrm), S.ticket);
+        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b,
+                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotR));
+        k_nrm<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotR), Gn);
         CHM_HIP(hipGetLastError());
         read_ctl(S);
         const Ctl &h = *S.hctl;
@@ -935,10 +1111,11 @@ int step_once(Solver &S, chm_stats_t *st_out)
             double2 *w = S.V + (size_t)(j + 1) * len;
             apply_prec(S, vj, zj);
             apply_saddle(S, zj, w);
-            k_gs<0><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, S.red, S.hbuf1, S.ticket);
-            k_gs<1><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, S.hbuf1, S.red, S.hbuf2, S.ticket);
-            k_gs<2><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, S.hbuf2, S.red, S.nrm2, S.ticket);
-            k_givens<<<1, 64, 0, st>>>(S.ctl, j, m, S.hbuf1, S.hbuf2, S.nrm2);
+            k_gs<0><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, slot(S, kSlotP1));
+            k_gs<1><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, slot(S, kSlotP1), slot(S, kSlotP2));
+            k_gs<2><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, slot(S, kSlotP2), slot(S, kSlotP3));
+            k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, slot(S, kSlotP1), slot(S, kSlotP2),
+                                           slot(S, kSlotP3), Gv);
             k_scale_next<<<nblk(len), kBlock, 0, st>>>(len, w, S.ctl);
             CHM_HIP(hipGetLastError());
             for (int s = 0; s < 2; ++s)
