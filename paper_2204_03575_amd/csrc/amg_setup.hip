@@ -398,44 +398,48 @@ __global__ void k_dense_from_csr(const int *rp, const int *ci, const double *v, 
         row[ci[k]] = v[k];
 }
 
-constexpr int kGJThreads = 1024;
 constexpr int kGJMax = 2048;
 
-__global__ void __launch_bounds__(kGJThreads) k_gauss_jordan(int n, double *aug, int *bad)
+// Gauss-Jordan inverse of an SPD matrix, one pivot per pair of launches (no
+// pivoting is needed: every pivot of an SPD matrix is positive).
+// Pivot k: rowk = row k of [A | I] divided by its pivot, colk = column k.
+__global__ void k_gj_pivot(int n, const double *aug, int k, double *rowk, double *colk, int *bad)
 {
-    __shared__ double rowk[2 * kGJMax];
-    __shared__ double colk[kGJMax];
-    const int t = threadIdx.x, w = 2 * n;
-    for (int k = 0; k < n; ++k) {
-        double piv = aug[(size_t)k * w + k];
-        if (!(piv > 0.0)) {   // SPD: every pivot is positive
-            if (t == 0)
-                atomicAdd(bad, 1);
-            return;
-        }
-        double ip = 1.0 / piv;
-        for (int j = t; j < w; j += kGJThreads)
-            rowk[j] = aug[(size_t)k * w + j] * ip;
-        for (int i = t; i < n; i += kGJThreads)
-            colk[i] = aug[(size_t)i * w + k];
-        __syncthreads();
-        for (long idx = t; idx < (long)n * w; idx += kGJThreads) {
-            int i = (int)(idx / w), j = (int)(idx % w);
-            if (i == k)
-                aug[idx] = rowk[j];
-            else
-                aug[idx] -= colk[i] * rowk[j];
-        }
-        __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = 2 * n;
+    const double piv = aug[(size_t)k * w + k];
+    if (!(piv > 0.0)) {
+        if (t == 0)
+            atomicAdd(bad, 1);
+        return;
     }
+    if (t < w)
+        rowk[t] = aug[(size_t)k * w + t] / piv;
+    if (t < n)
+        colk[t] = aug[(size_t)t * w + k];
 }
 
+// eliminate column k from every other row; row k becomes rowk
+__global__ void k_gj_update(int n, double *aug, int k, const double *rowk, const double *colk)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = 2 * n;
+    if (idx >= (long)n * w)
+        return;
+    const int i = (int)(idx / w), j = (int)(idx % w);
+    if (i == k)
+        aug[idx] = rowk[j];
+    else
+        aug[idx] -= colk[i] * rowk[j];
+}
+
+// inverse, row-major: inv[i * n + j] = (A^-1)[i][j]
 __global__ void k_extract_inverse(const double *aug, int n, double *inv)
 {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n)
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n)
         return;
-    int i = idx % n, j = idx / n;   // inv column-major: inv[j*n + i] = (A^-1)[i][j]
+    const int i = (int)(idx / n), j = (int)(idx % n);
     inv[idx] = aug[(size_t)i * 2 * n + n + j];
 }
 
@@ -631,7 +635,12 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         double *aug = tmp.get<double>((size_t)nc * 2 * nc);
         k_dense_from_csr<<<nblk(nc), kBlock, 0, st>>>(Lc.A.rp, Lc.A.ci, Lc.A.v, nc, aug);
         fill_int(flags + 3, 0, 1, st);
-        k_gauss_jordan<<<1, kGJThreads, 0, st>>>(nc, aug, flags + 3);
+        double *rowk = tmp.get<double>(2 * (size_t)nc), *colk = tmp.get<double>(nc);
+        const long cells = (long)nc * 2 * nc;
+        for (int k = 0; k < nc; ++k) {
+            k_gj_pivot<<<nblk(2l * nc), kBlock, 0, st>>>(nc, aug, k, rowk, colk, flags + 3);
+            k_gj_update<<<nblk(cells), kBlock, 0, st>>>(nc, aug, k, rowk, colk);
+        }
         Lc.inv = pool.get<double>((size_t)nc * nc);
         k_extract_inverse<<<nblk((long)nc * nc), kBlock, 0, st>>>(aug, nc, Lc.inv);
         CHM_HIP(hipGetLastError());

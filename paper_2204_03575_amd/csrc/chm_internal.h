@@ -31,6 +31,7 @@ constexpr int kBlock = 256;     // threads per block for row kernels
 constexpr int kMaxLevels = 24;
 constexpr int kMaxRestart = 64;
 constexpr int kRedBlocks = 256;   // blocks of the two-stage reductions (one per CU)
+constexpr int kGsBlocks = 1024;   // blocks of the Gram-Schmidt passes (four per CU)
 
 struct Err {
     int code = CHM_OK;
@@ -183,6 +184,8 @@ struct Solver {
     double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
     double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
     double2 *red = nullptr;    // slots of per-block partial sums (kRedBlocks each)
+    double2 *gsp1 = nullptr, *gsp2 = nullptr, *gsp3 = nullptr;  // Gram-Schmidt partials
+    double2 *hfin = nullptr;   // finalised Gram-Schmidt coefficients of both passes
     Ctl *ctl = nullptr;        // device
     Ctl *hctl = nullptr;       // pinned host mirror
     int64_t step_count = 0;

@@ -105,6 +105,7 @@ __device__ inline double2 sell_row(const int *__restrict__ sptr, const int *__re
     const int s = row / kSlice, lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
     double ax = 0.0, ay = 0.0;
+#pragma unroll 4
     for (int k = 0; k < width; ++k) {
         const int idx = base + k * kSlice + lane;
         const double a = val[idx];
@@ -255,29 +256,27 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
     xprev[row] = cheb_update(s, b, xk, dinv, xprev, row, c1, c2, prev);
 }
 
-// coarsest level: x = A^-1 b with the inverse stored column-major; b is staged
-// in LDS by the whole block, the inner products are unrolled so the loads of
-// a thread's row are in flight together
-constexpr int kDenseMax = 2048;
-
+// coarsest level: x = A^-1 b with the inverse stored row-major; one wave per
+// row, lane l takes columns l, l + 64, ..., the wave adds its lanes with a
+// fixed shuffle tree
 __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
                                                   const double2 *__restrict__ b, double2 *x)
 {
-    __shared__ double2 bs[kDenseMax];
-    for (int j = threadIdx.x; j < n; j += kBlock)
-        bs[j] = b[j];
-    __syncthreads();
-    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= n)
         return;
-    double ax = 0.0, ay = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < n; ++j) {
-        const double a = inv[(size_t)j * n + row];
-        ax += a * bs[j].x;
-        ay += a * bs[j].y;
+    const double *a = inv + (size_t)row * n;
+    double2 acc = d2(0.0, 0.0);
+    for (int j = lane; j < n; j += 64) {
+        const double v = a[j];
+        const double2 bv = b[j];
+        acc.x += v * bv.x;
+        acc.y += v * bv.y;
     }
-    x[row] = d2(ax, ay);
+    acc = wave_sum(acc);
+    if (lane == 0)
+        x[row] = acc;
 }
 
 __global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const double2 *__restrict__ e, double2 *x)
@@ -439,14 +438,15 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
 }
 
 // ------------------------------------------------------------------ Gram-Schmidt passes
-// MODE 0: partials of V_i . w;  MODE 1: h = sum of the MODE-0 partials,
-// w -= sum_i V_i h[i], partials of V_i . w;  MODE 2: the same update with the
-// MODE-1 results, partials of w . w.  All per species; len = 2n.
+// MODE 0: partials of V_i . w;  MODE 1: w -= sum_i V_i h[i] with the
+// finalised MODE-0 results h, then partials of V_i . w;  MODE 2: the same
+// update with the MODE-1 results, then partials of w . w.  All per species;
+// len = 2n.  The grid (up to kGsBlocks blocks) keeps several blocks per CU.
 constexpr int kChunk = 8;
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restrict__ V, int nvec,
-                                               double2 *w, const double2 *__restrict__ hpart,
+                                               double2 *w, const double2 *__restrict__ hin,
                                                double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
@@ -454,7 +454,9 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
     const int G = gridDim.x;
     const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
     if (MODE > 0) {
-        reduce_parts(hpart, nvec, G, h);
+        for (int v = threadIdx.x; v < nvec; v += kBlock)
+            h[v] = hin[v];
+        __syncthreads();
         for (int i = start; i < len; i += stride) {
             double2 wv = w[i];
             for (int v = 0; v < nvec; ++v) {
@@ -498,6 +500,16 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
                 part[(size_t)(v0 + c) * G + blockIdx.x] = s;
         }
     }
+}
+
+// out[v] = sum of the G partials of vector v (one block)
+__global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ part, int nvec, int G,
+                                                  double2 *out)
+{
+    __shared__ double2 r[kMaxRestart + 1];
+    reduce_parts(part, nvec, G, r);
+    for (int v = threadIdx.x; v < nvec; v += kBlock)
+        out[v] = r[v];
 }
 
 // ------------------------------------------------------------------ FGMRES control (one block)
@@ -562,13 +574,11 @@ __global__ void __launch_bounds__(kBlock) k_scale_first(int len, const double2 *
 // previous rotations applied, a new rotation that zeroes H[j+1][j], the
 // residual estimate |g[j+1]|, and the convergence test against tol.
 __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
-                                                   const double2 *__restrict__ p1,
-                                                   const double2 *__restrict__ p2,
+                                                   const double2 *__restrict__ h1,
+                                                   const double2 *__restrict__ h2,
                                                    const double2 *__restrict__ p3, int G)
 {
-    __shared__ double2 h1[kMaxRestart + 1], h2[kMaxRestart + 1], nn[1];
-    reduce_parts(p1, j + 1, G, h1);
-    reduce_parts(p2, j + 1, G, h2);
+    __shared__ double2 nn[1];
     reduce_parts(p3, 1, G, nn);
     const int s = threadIdx.x;
     if (s >= 2 || !c->active[s])
@@ -791,9 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, doubl
 
 // ------------------------------------------------------------------ host helpers
 // partial-sum slots (kRedBlocks pairs each) in S.red
-constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotP1 = 82,
-              kSlotP2 = kSlotP1 + kMaxRestart + 1, kSlotP3 = kSlotP2 + kMaxRestart + 1,
-              kSlots = kSlotP3 + 1;
+constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlots = 82;
 
 inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
 
@@ -889,7 +897,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const double2 *b, double2 *x)
     Level &L = H.lev[l];
     hipStream_t st = S.stream;
     if (l == H.nlev - 1) {
-        k_dense<<<nblk(L.n), kBlock, 0, st>>>(L.n, L.inv, b, x);
+        k_dense<<<nblk(L.n, kBlock / 64), kBlock, 0, st>>>(L.n, L.inv, b, x);
         return;
     }
     const int deg = H.degree;
@@ -1039,6 +1047,10 @@ void alloc_workspace(Solver &S)
     S.mr = p.get<double2>(n);
     S.me = p.get<double2>(n);
     S.red = p.get<double2>((size_t)kSlots * kRedBlocks);
+    S.gsp1 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
+    S.gsp2 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
+    S.gsp3 = p.get<double2>(kGsBlocks);
+    S.hfin = p.get<double2>(2 * (kMaxRestart + 1));
     S.ctl = p.get<Ctl>(1);
     fill_int(reinterpret_cast<int *>(S.ctl), 0, sizeof(Ctl) / sizeof(int), S.stream);
     CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), sizeof(Ctl), hipHostMallocDefault));
@@ -1062,6 +1074,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
     const int n = S.nv, len = 2 * n, m = S.m;
     hipStream_t st = S.stream;
     const int Gv = red_blocks(len), Gn = red_blocks(n);
+    const int Gg = (int)std::min<long>(kGsBlocks, nblk(len));
     auto t0 = std::chrono::steady_clock::now();
     chm_stats_t stats{};
 
@@ -1111,11 +1124,13 @@ int step_once(Solver &S, chm_stats_t *st_out)
             double2 *w = S.V + (size_t)(j + 1) * len;
             apply_prec(S, vj, zj);
             apply_saddle(S, zj, w);
-            k_gs<0><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, slot(S, kSlotP1));
-            k_gs<1><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, slot(S, kSlotP1), slot(S, kSlotP2));
-            k_gs<2><<<Gv, kBlock, 0, st>>>(len, S.V, j + 1, w, slot(S, kSlotP2), slot(S, kSlotP3));
-            k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, slot(S, kSlotP1), slot(S, kSlotP2),
-                                           slot(S, kSlotP3), Gv);
+            double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
+            k_gs<0><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, S.gsp1);
+            k_finish<<<1, kBlock, 0, st>>>(S.gsp1, j + 1, Gg, h1);
+            k_gs<1><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h1, S.gsp2);
+            k_finish<<<1, kBlock, 0, st>>>(S.gsp2, j + 1, Gg, h2);
+            k_gs<2><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h2, S.gsp3);
+            k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, h1, h2, S.gsp3, Gg);
             k_scale_next<<<nblk(len), kBlock, 0, st>>>(len, w, S.ctl);
             CHM_HIP(hipGetLastError());
             for (int s = 0; s < 2; ++s)

@@ -145,10 +145,10 @@ PRESETS = {
                      mean_p=0.1, mean_n=0.1, steps=5, evap_ds=0.0, evap_stop=0.0),
     # 2D unit square, 512x512 squares, 200 steps, solvent lowered linearly
     # from 0.8 to 0.3 (0.0025 per step).
-    "square512": dict(_COMMON, dim=2, n=(512, 512), extent=(1.0, 1.0),
+    "square512": dict(_COMMON, dim=2, n=(512, 512), extent=(1.0, 1.0), coarse_max=2048,
                       mean_p=0.1, mean_n=0.1, steps=200, evap_ds=0.0025, evap_stop=0.3),
     # 3D box of 96x96x48 cubes, Kuhn tetrahedra, 50 steps.
-    "box96": dict(_COMMON, dim=3, n=(96, 96, 48), extent=(1.0, 1.0, 0.5),
+    "box96": dict(_COMMON, dim=3, n=(96, 96, 48), extent=(1.0, 1.0, 0.5), coarse_max=2048,
                   mean_p=0.1, mean_n=0.1, steps=50, evap_ds=0.0, evap_stop=0.0),
 }
 
