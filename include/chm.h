@@ -94,6 +94,8 @@ typedef struct {
     double cheb_ratio_mass;
     int32_t coarse_max;    /* coarsen until a level has at most this many rows */
     int32_t max_levels;    /* at most this many levels (1..24) */
+    int32_t use_graphs;    /* 1: each FGMRES iteration runs as a captured HIP graph
+                              (the same kernels, bitwise the same results); 0: eager */
 } chm_params_t;
 
 /* Per-step statistics. */

@@ -51,7 +51,7 @@ class chm_params_t(C.Structure):
         ("amg_cycles", C.c_int32), ("schur_pcg", C.c_int32), ("smoother", C.c_int32),
         ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
         ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
-        ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+        ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("use_graphs", C.c_int32),
     ]
 
 
@@ -119,6 +119,7 @@ def params_from_dict(p: dict) -> chm_params_t:
               "cheb_degree_mass", "coarse_max", "max_levels"):
         setattr(s, k, int(p[k]))
     s.smoother = SMOOTHERS[p["smoother"]]
+    s.use_graphs = int(p.get("use_graphs", 1))
     return s
 
 

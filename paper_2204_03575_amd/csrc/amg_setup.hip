@@ -105,16 +105,21 @@ __global__ void k_mis_sweep(const int *rp, const int *ci, int n, const Tup *tin,
 
 __global__ void k_mis_update(int *state, const Tup *t, int n, int *undecided)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || state[i] != UND)
-        return;
-    Tup b = t[i];
-    if (b.idx == i)
-        state[i] = IN;
-    else if (b.state == IN)
-        state[i] = OUT;
-    else
-        atomicAdd(undecided, 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool still = false;
+    if (i < n && state[i] == UND) {
+        const Tup b = t[i];
+        if (b.idx == i)
+            state[i] = IN;
+        else if (b.state == IN)
+            state[i] = OUT;
+        else
+            still = true;
+    }
+    // one atomic per wave for the count of vertices still undecided
+    const unsigned long long m = __ballot(still);
+    if ((threadIdx.x & 63) == 0 && m)
+        atomicAdd(undecided, __popcll(m));
 }
 
 __global__ void k_root_flags(const int *state, int n, int *flag)

@@ -246,6 +246,11 @@ int chm_destroy(chm_solver_t *h)
     (void)hipStreamSynchronize(h->s.stream);
     for (hipEvent_t e : h->s.timer.ev)
         (void)hipEventDestroy(e);
+    for (hipGraphExec_t g : h->s.iter_graphs)
+        if (g)
+            (void)hipGraphExecDestroy(g);
+    if (h->s.cap_stream)
+        (void)hipStreamDestroy(h->s.cap_stream);
     if (h->s.hctl)
         (void)hipHostFree(h->s.hctl);
     delete h;

@@ -192,6 +192,10 @@ struct Solver {
     double setup_ms = 0.0;
     Timer timer;
     std::string nan_where;     // where the last CHM_ENAN was detected
+    // HIP graphs of the FGMRES iteration body, one per Arnoldi index j,
+    // captured on a library-owned stream and launched on `stream`
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraphExec_t> iter_graphs;
 };
 
 // ---- util.hip

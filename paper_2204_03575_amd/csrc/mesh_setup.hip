@@ -107,50 +107,64 @@ __global__ void k_pattern(const int *cells, int nl, const int *inc_ptr, const in
 // start of the round whose (hash, index) beats every uncoloured neighbour
 // takes the smallest colour absent among its coloured neighbours.  Reads
 // col_in, writes col_out, so decisions depend on the previous round only.
+// one atomic per wave: lane 0 adds the number of lanes with pred set (every
+// lane of the wave must reach the call)
+__device__ inline void count_in_wave(int *counter, bool pred)
+{
+    const unsigned long long m = __ballot(pred);
+    if ((threadIdx.x & 63) == 0 && m)
+        atomicAdd(counter, __popcll(m));
+}
+
 __global__ void k_jp_round(const int *cells, int nl, int ncell, const int *inc_ptr, const int *inc,
                            const int *col_in, int *col_out, int *remaining, int *maxcolor,
                            int *overflow)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell)
-        return;
-    int mine = col_in[c];
-    col_out[c] = mine;
-    if (mine >= 0)
-        return;
-    uint64_t hc = mix_hash(0x632BE59BD9B4E019ull + (uint64_t)c * 0x9E3779B97F4A7C15ull);
-    uint64_t used0 = 0, used1 = 0;
-    for (int a = 0; a < nl; ++a) {
-        int v = cells[(size_t)c * nl + a];
-        for (int k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
-            int e = inc[k];
-            if (e == c)
-                continue;
-            int ce = col_in[e];
-            if (ce < 0) {
-                uint64_t he = mix_hash(0x632BE59BD9B4E019ull + (uint64_t)e * 0x9E3779B97F4A7C15ull);
-                if (he > hc || (he == hc && e > c)) {
-                    atomicAdd(remaining, 1);
-                    return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool waiting = false;
+    if (c < ncell) {
+        const int mine = col_in[c];
+        col_out[c] = mine;
+        if (mine < 0) {
+            const uint64_t hc = mix_hash(0x632BE59BD9B4E019ull + (uint64_t)c * 0x9E3779B97F4A7C15ull);
+            uint64_t used0 = 0, used1 = 0;
+            for (int a = 0; a < nl && !waiting; ++a) {
+                const int v = cells[(size_t)c * nl + a];
+                for (int k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+                    const int e = inc[k];
+                    if (e == c)
+                        continue;
+                    const int ce = col_in[e];
+                    if (ce < 0) {
+                        const uint64_t he =
+                            mix_hash(0x632BE59BD9B4E019ull + (uint64_t)e * 0x9E3779B97F4A7C15ull);
+                        if (he > hc || (he == hc && e > c)) {
+                            waiting = true;
+                            break;
+                        }
+                    } else if (ce < 64) {
+                        used0 |= 1ull << ce;
+                    } else {
+                        used1 |= 1ull << (ce - 64);
+                    }
                 }
-            } else if (ce < 64) {
-                used0 |= 1ull << ce;
-            } else {
-                used1 |= 1ull << (ce - 64);
+            }
+            if (!waiting) {
+                int pick = -1;
+                if (~used0)
+                    pick = __ffsll((unsigned long long)~used0) - 1;
+                else if (~used1)
+                    pick = 64 + __ffsll((unsigned long long)~used1) - 1;
+                if (pick < 0) {
+                    atomicAdd(overflow, 1);
+                } else {
+                    col_out[c] = pick;
+                    atomicMax(maxcolor, pick);
+                }
             }
         }
     }
-    int pick;
-    if (~used0)
-        pick = __ffsll((unsigned long long)~used0) - 1;
-    else if (~used1)
-        pick = 64 + __ffsll((unsigned long long)~used1) - 1;
-    else {
-        atomicAdd(overflow, 1);
-        return;
-    }
-    col_out[c] = pick;
-    atomicMax(maxcolor, pick);
+    count_in_wave(remaining, waiting);
 }
 
 __global__ void k_color_count(const int *color, int ncell, int *cnt)

@@ -502,14 +502,22 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
     }
 }
 
-// out[v] = sum of the G partials of vector v (one block)
-__global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ part, int nvec, int G,
+// out[v] = sum of the G partials of vector v; block v handles vector v
+// (thread t adds g = t, t + 256, ... in order, then a fixed block tree)
+__global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ part, int G,
                                                   double2 *out)
 {
-    __shared__ double2 r[kMaxRestart + 1];
-    reduce_parts(part, nvec, G, r);
-    for (int v = threadIdx.x; v < nvec; v += kBlock)
-        out[v] = r[v];
+    __shared__ double2 sh[kBlock / 64];
+    const int v = blockIdx.x;
+    double2 s = d2(0.0, 0.0);
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+        const double2 p = part[(size_t)v * G + g];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0)
+        out[v] = s;
 }
 
 // ------------------------------------------------------------------ FGMRES control (one block)
@@ -578,23 +586,36 @@ __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
                                                    const double2 *__restrict__ h2,
                                                    const double2 *__restrict__ p3, int G)
 {
+    // the column and the previous rotations are staged in LDS by the whole
+    // block, so the sequential rotation loop below touches no global memory
     __shared__ double2 nn[1];
-    reduce_parts(p3, 1, G, nn);
+    __shared__ double col[2][kMaxRestart + 1], csl[2][kMaxRestart], snl[2][kMaxRestart];
+    for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock) {
+        const int s = t / (j + 1), i = t % (j + 1);
+        col[s][i] = s == 0 ? h1[i].x + h2[i].x : h1[i].y + h2[i].y;
+    }
+    for (int t = threadIdx.x; t < 2 * j; t += kBlock) {
+        const int s = t / j, i = t % j;
+        csl[s][i] = c->cs[s][i];
+        snl[s][i] = c->sn[s][i];
+    }
+    reduce_parts(p3, 1, G, nn);   // ends with a block barrier
     const int s = threadIdx.x;
     if (s >= 2 || !c->active[s])
         return;
     double *H = c->H[s];
-    for (int i = 0; i <= j; ++i)
-        H[i * m + j] = (s == 0 ? h1[i].x + h2[i].x : h1[i].y + h2[i].y);
+    double *cl = col[s];
     const double hn = sqrt(s == 0 ? nn[0].x : nn[0].y);
     c->hn[s] = hn;
-    H[(j + 1) * m + j] = hn;
+    cl[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = c->cs[s][i] * a + c->sn[s][i] * b;
-        H[(i + 1) * m + j] = -c->sn[s][i] * a + c->cs[s][i] * b;
+        const double a = cl[i], b = cl[i + 1];
+        cl[i] = csl[s][i] * a + snl[s][i] * b;
+        cl[i + 1] = -snl[s][i] * a + csl[s][i] * b;
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    for (int i = 0; i < j; ++i)
+        H[i * m + j] = cl[i];
+    const double a = cl[j], b = cl[j + 1];
     const double rr = sqrt(a * a + b * b);
     double cs = 1.0, sn = 0.0;
     if (rr != 0.0) {
@@ -851,6 +872,14 @@ void spmv_op(hipStream_t st, const Csr &C, const Sell &Sl, int gs, const double2
     }
 }
 
+// The event timer brackets each run of back-to-back smoothing launches on the
+// fine level of the As hierarchy (the pre- and post-smoothing sequences), so
+// the event overhead is spread over the launches of a run.
+bool timed_level(const Solver &S, const Hierarchy &H, int l)
+{
+    return S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
+}
+
 // one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
 void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2 *xk,
                  double2 *xprev, double c1, double c2, int prev)
@@ -858,9 +887,7 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2
     Level &L = H.lev[l];
     const int n = L.n;
     hipStream_t st = S.stream;
-    const bool timed = S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
-    if (timed)
-        timer_mark(S, true);
+    const bool timed = timed_level(S, H, l);
     switch (L.gsA) {
     case 0:
         k_cheb<<<nblk(n), kBlock, 0, st>>>(n, L.sA.sptr, L.sA.col, L.sA.val, L.dinv, b, xk, xprev,
@@ -886,7 +913,6 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2
     if (timed) {
         // algorithmic bytes: col + val per nonzero; per row x_k (gathered once),
         // b, D^-1, x_{k-1} (when read) and the written x_{k+1}
-        timer_mark(S, false);
         S.timer.count += 1;
         S.timer.bytes += 12ll * L.A.nnz + (prev ? 72ll : 56ll) * L.n;
     }
@@ -909,18 +935,27 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const double2 *b, double2 *x)
     // so starting in xt leaves the result in x.
     k_cheb0<<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv, b, xt, c2(1));
     double2 *cur = xt, *oth = x;
+    const bool timed = timed_level(S, H, l);
+    if (timed && deg >= 2)
+        timer_mark(S, true);
     for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
         launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
         std::swap(cur, oth);
     }
+    if (timed && deg >= 2)
+        timer_mark(S, false);
     spmv_op<SP_RESID>(st, L.A, L.sA, L.gsA, cur, b, r);
     spmv_op<SP_SET>(st, L.R, L.sR, L.gsR, r, nullptr, H.b[l + 1]);
     vcycle_level(S, H, l + 1, H.b[l + 1], H.x[l + 1]);
     spmv_op<SP_ADD>(st, L.P, L.sP, L.gsP, H.x[l + 1], nullptr, cur);
+    if (timed)
+        timer_mark(S, true);
     for (int k = 1; k <= deg; ++k) {
         launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 1 && !H.jacobi);
         std::swap(cur, oth);
     }
+    if (timed)
+        timer_mark(S, false);
 }
 
 inline double2 pair(const double *a) { return make_double2(a[0], a[1]); }
@@ -1066,6 +1101,74 @@ void read_ctl(Solver &S)
     CHM_HIP(hipStreamSynchronize(S.stream));
 }
 
+// One Arnoldi step j of FGMRES for both species: z_j = Prec(v_j) (Algorithm 1),
+// w = A z_j, two Gram-Schmidt passes, the Givens update and v_{j+1} = w/|w|,
+// then the head of the control block is copied to pinned host memory.
+// Everything is enqueued on S.stream without host synchronisation, so the
+// sequence can be captured as a graph.
+void iteration_body(Solver &S, int j)
+{
+    const int len = 2 * S.nv, m = S.m;
+    hipStream_t st = S.stream;
+    const int Gg = (int)std::min<long>(kGsBlocks, nblk(len));
+    double2 *vj = S.V + (size_t)j * len, *zj = S.Z + (size_t)j * len;
+    double2 *w = S.V + (size_t)(j + 1) * len;
+    apply_prec(S, vj, zj);
+    apply_saddle(S, zj, w);
+    double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
+    k_gs<0><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, S.gsp1);
+    k_finish<<<j + 1, kBlock, 0, st>>>(S.gsp1, Gg, h1);
+    k_gs<1><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h1, S.gsp2);
+    k_finish<<<j + 1, kBlock, 0, st>>>(S.gsp2, Gg, h2);
+    k_gs<2><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h2, S.gsp3);
+    k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, h1, h2, S.gsp3, Gg);
+    k_scale_next<<<nblk(len), kBlock, 0, st>>>(len, w, S.ctl);
+    CHM_HIP(hipGetLastError());
+    CHM_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlHead, hipMemcpyDeviceToHost, st));
+}
+
+// Run iteration_body(j), as a HIP graph when enabled (captured once per j on
+// the library's own stream, launched on the caller's stream), and wait for it.
+// The event timer records around kernels, so timed runs stay eager.
+void run_iteration(Solver &S, int j)
+{
+    if (!S.prm.use_graphs || S.timer.on) {
+        iteration_body(S, j);
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return;
+    }
+    if ((int)S.iter_graphs.size() <= j)
+        S.iter_graphs.resize(j + 1, nullptr);
+    if (!S.iter_graphs[j]) {
+        if (!S.cap_stream)
+            CHM_HIP(hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking));
+        // the capture stream must not start before earlier work on the caller's stream
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        hipStream_t user = S.stream;
+        S.stream = S.cap_stream;
+        hipGraph_t g = nullptr;
+        CHM_HIP(hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            iteration_body(S, j);
+        } catch (...) {
+            (void)hipStreamEndCapture(S.cap_stream, &g);
+            if (g)
+                (void)hipGraphDestroy(g);
+            S.stream = user;
+            throw;
+        }
+        S.stream = user;
+        CHM_HIP(hipStreamEndCapture(S.cap_stream, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CHM_HIP(e);
+        S.iter_graphs[j] = ex;
+    }
+    CHM_HIP(hipGraphLaunch(S.iter_graphs[j], S.stream));
+    CHM_HIP(hipStreamSynchronize(S.stream));
+}
+
 }  // namespace
 
 // One time step: right-hand side, FGMRES for both species, commit and solvent removal.
@@ -1074,7 +1177,6 @@ int step_once(Solver &S, chm_stats_t *st_out)
     const int n = S.nv, len = 2 * n, m = S.m;
     hipStream_t st = S.stream;
     const int Gv = red_blocks(len), Gn = red_blocks(n);
-    const int Gg = (int)std::min<long>(kGsBlocks, nblk(len));
     auto t0 = std::chrono::steady_clock::now();
     chm_stats_t stats{};
 
@@ -1120,22 +1222,9 @@ int step_once(Solver &S, chm_stats_t *st_out)
         k_scale_first<<<nblk(len), kBlock, 0, st>>>(len, S.r, S.V, S.ctl);
         int kmax = 0;
         for (int j = 0; j < m; ++j) {
-            double2 *vj = S.V + (size_t)j * len, *zj = S.Z + (size_t)j * len;
-            double2 *w = S.V + (size_t)(j + 1) * len;
-            apply_prec(S, vj, zj);
-            apply_saddle(S, zj, w);
-            double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
-            k_gs<0><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, S.gsp1);
-            k_finish<<<1, kBlock, 0, st>>>(S.gsp1, j + 1, Gg, h1);
-            k_gs<1><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h1, S.gsp2);
-            k_finish<<<1, kBlock, 0, st>>>(S.gsp2, j + 1, Gg, h2);
-            k_gs<2><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h2, S.gsp3);
-            k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, h1, h2, S.gsp3, Gg);
-            k_scale_next<<<nblk(len), kBlock, 0, st>>>(len, w, S.ctl);
-            CHM_HIP(hipGetLastError());
+            run_iteration(S, j);
             for (int s = 0; s < 2; ++s)
                 total[s] += act[s];
-            read_ctl(S);
             kmax = std::max(S.hctl->k[0], S.hctl->k[1]);
             bool any = false, capped = false;
             for (int s = 0; s < 2; ++s) {
