@@ -34,9 +34,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF·Krylov-iters/s and solves/s at 1e-8 rel. residual; mixed+learned vs FP64"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the timed kernel per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE,
-# scaled by the copy-kernel calibration (None until measured for the current kernel)
-TRAFFIC_BYTES_PER_LAUNCH = None
+# Memory traffic of the timed kernel per launch (L2 <-> HBM/Infinity Cache) from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+# scaled by what the same counters read for a 512 MB elementwise copy (FETCH_SIZE x 2.000,
+# WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Set to None whenever
+# the kernel changes until the counters are taken again.
+TRAFFIC_BYTES_PER_LAUNCH = 39.89e6
 
 
 def parse():
@@ -49,6 +52,9 @@ def parse():
     ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
     ap.add_argument("--kernel-steps", type=int, default=2,
                     help="time steps of the event-timed pass of the dominant kernel")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="also run 3 plain device copies of this many MB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -136,6 +142,13 @@ def main():
                            "bytes_per_launch": per_launch,
                            "timing": f"HIP events around each run of back-to-back launches in "
                                      f"{args.kernel_steps} further time steps (eager)"}
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):   # an elementwise kernel (copy_ may use a DMA engine)
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p, co, ce, php, phn)

@@ -26,6 +26,20 @@ inline int red_blocks(long n) { return (int)std::min<long>(kRedBlocks, nblk(n));
 
 __device__ inline double2 d2(double a, double b) { return make_double2(a, b); }
 
+// XCD-aware block index.  The hardware hands workgroup b to XCD b mod 8; this
+// renumbering gives every XCD one contiguous range of blocks, so the
+// neighbouring rows that an SpMV row gathers from mostly sit in the same
+// XCD's L2.  It is a bijection of [0, gridDim.x).
+constexpr int kXcds = 8;
+
+__device__ inline int xcd_block()
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + min(x, r) + j;
+}
+
 // ------------------------------------------------------------------ reductions
 __device__ inline double2 wave_sum(double2 v)
 {
@@ -124,7 +138,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
                                                  const double2 *__restrict__ x,
                                                  const double2 *__restrict__ b, double2 *y)
 {
-    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
     const double2 s = sell_row(sptr, col, val, x, row);
@@ -167,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
                                                  const double2 *__restrict__ xk, double2 *xprev,
                                                  double c1, double c2, int prev)
 {
-    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
     const double2 s = sell_row(sptr, col, val, xk, row);
@@ -219,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict_
                                                    const double2 *__restrict__ x,
                                                    const double2 *__restrict__ b, double2 *y)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block() * kBlock + threadIdx.x;
     const int row = t / GS, lane = t % GS;
     if (row >= n)
         return;
@@ -246,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
                                                    const double2 *__restrict__ xk, double2 *xprev,
                                                    double c1, double c2, int prev)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block() * kBlock + threadIdx.x;
     const int row = t / GS, lane = t % GS;
     if (row >= n)
         return;
@@ -401,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
                                                    const double2 *__restrict__ x, double2 *y,
                                                    double2 t, double2 te)
 {
-    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
     double2 y0, y1;
