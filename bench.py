@@ -19,7 +19,11 @@ Prints one JSON line.  Extra objects:
                 timed region itself runs the captured graphs), against the
                 8 TB/s HBM peak;
   cpu_baseline  the CPU oracle, one time step of the same workload (its AMG
-                setup excluded), single thread.
+                setup excluded), single thread;
+  mixed         the same steps with the FP32 preconditioner (FP64 Krylov
+                method): its throughput, iterations, final residuals and the
+                relative field difference from the FP64 run after the same
+                steps from the same state.
 """
 from __future__ import annotations
 
@@ -52,6 +56,8 @@ def parse():
     ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
     ap.add_argument("--kernel-steps", type=int, default=2,
                     help="time steps of the event-timed pass of the dominant kernel")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the run with the FP32 preconditioner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run 3 plain device copies of this many MB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -73,6 +79,27 @@ def cpu_baseline(p, co, ce, php, phn):
             "sample": f"1 time step of the {p['n'][0]}x{p['n'][1]} workload from the same initial "
                       f"state, plain C oracle (gcc -O2, one thread), its AMG setup excluded; "
                       f"{dt:.1f} s"}
+
+
+def timed_run(g, php, phn, warmup, steps, label):
+    import torch
+    g.set_fields(php, phn)
+    for k in range(warmup):
+        st = g.step(1)[0]
+        print(f"# {label} warmup step {k}: iters {st['iters']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = g.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"# {label} timed {steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    return stats, dt
+
+
+def field_diff(a, b):
+    import numpy as np
+    return max(float(np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f]))
+               for f in ("phi_p", "phi_n", "mu_p", "mu_n"))
 
 
 def main():
@@ -99,16 +126,8 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = g.setup_info()
-    g.set_fields(php, phn)
-    for k in range(args.warmup):
-        st = g.step(1)[0]
-        print(f"# warmup step {k}: iters {st['iters']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = g.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    stats, dt = timed_run(g, php, phn, args.warmup, args.steps, "fp64")
+    fields64 = g.get_fields()
     iters = [s["iters"][0] + s["iters"][1] for s in stats]
     dof = 2 * nv
     value = dof * sum(iters) / dt
@@ -126,6 +145,32 @@ def main():
         "max_relres": max(max(s["relres"]) for s in stats),
         "setup_ms": 1e3 * setup_s, "amg_levels": [info["levels_mass"], info["levels_as"]],
     }
+    if not args.no_mixed:
+        gm = Solver(co, ce, dict(p, precision="fp32"))
+        mstats, mdt = timed_run(gm, php, phn, args.warmup, args.steps, "fp32 preconditioner")
+        miters = [st["iters"][0] + st["iters"][1] for st in mstats]
+        out["mixed"] = {
+            "precision": "FP32 Algorithm 1 (V-cycles, inner CG, products with M); FP64 FGMRES, "
+                         "residual, orthogonalisation, coarsest solve, right-hand side",
+            "value": dof * sum(miters) / mdt, "unit": "DOF*iters/s",
+            "solves_per_s": args.steps / mdt, "ms_per_step": 1e3 * mdt / args.steps,
+            "speedup_vs_fp64_solves": (args.steps / mdt) / (args.steps / dt),
+            "fgmres_iters_per_step": [list(st["iters"]) for st in mstats],
+            "max_relres": max(max(st["relres"]) for st in mstats),
+            "field_rel_diff_vs_fp64": field_diff(gm.get_fields(), fields64),
+        }
+        if not args.no_timer:
+            gm.timer_enable(0, True)
+            gm.step(args.kernel_steps)
+            launches, ms, nbytes = gm.timer_read()
+            gm.timer_enable(0, False)
+            avg_s = ms * 1e-3 / max(1, launches)
+            achieved = nbytes / max(1, launches) / avg_s / 1e9 if avg_s > 0 else 0.0
+            out["mixed"]["k_cheb_fp32"] = {"achieved": achieved, "unit": "GB/s",
+                                           "frac": achieved / HBM_PEAK_GBS,
+                                           "avg_us": avg_s * 1e6, "launches": launches,
+                                           "bytes_per_launch": nbytes / max(1, launches)}
+        del gm
     if not args.no_timer:
         g.timer_enable(0, True)
         g.step(args.kernel_steps)

@@ -53,6 +53,16 @@ extern "C" {
 #define CHM_SMOOTH_CHEBYSHEV 0
 #define CHM_SMOOTH_JACOBI 1
 
+/* Arithmetic of the block preconditioner (Algorithm 1).  FP32: V-cycles
+ * (smoothing, residual, restriction, prolongation), the inner CG of the As
+ * solves and the product with M run in FP32 on FP32 copies of the matrix
+ * values; the coarsest-level inverse and all dot-product sums stay FP64, and
+ * the preconditioner takes and returns FP64 vectors.  The Krylov method, the
+ * saddle-point residual, the orthogonalisation and the right-hand side are
+ * FP64 in both settings. */
+#define CHM_PREC_FP64 0
+#define CHM_PREC_FP32 1
+
 typedef struct chm_solver chm_solver_t;
 
 /* A conforming simplex mesh: triangles (dim 2) or tetrahedra (dim 3).
@@ -96,6 +106,7 @@ typedef struct {
     int32_t max_levels;    /* at most this many levels (1..24) */
     int32_t use_graphs;    /* 1: each FGMRES iteration runs as a captured HIP graph
                               (the same kernels, bitwise the same results); 0: eager */
+    int32_t precision;     /* CHM_PREC_*: arithmetic of the preconditioner */
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -153,7 +164,8 @@ int chm_level_info(const chm_solver_t *s, int32_t hierarchy, int32_t level, int6
 int chm_level_get(chm_solver_t *s, int32_t hierarchy, int32_t level, int32_t *a_rowptr,
                   int32_t *a_col, double *a_val, int32_t *agg, int32_t *p_rowptr,
                   int32_t *p_col, double *p_val);
-/* Device pair vectors (double2[n]: species 0 in .x, 1 in .y). */
+/* Device pair vectors (double2[n]: species 0 in .x, 1 in .y).  These and
+ * chm_apply_prec run in the configured precision (FP64 vectors in and out). */
 int chm_vcycle(chm_solver_t *s, int32_t hierarchy, const double *b, double *x);
 int chm_schur_solve(chm_solver_t *s, const double *b, double *x);
 /* Device block vectors (double2[2n]: rows [0,n) phi block, [n,2n) mu block). */

@@ -52,6 +52,7 @@ class chm_params_t(C.Structure):
         ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
         ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("use_graphs", C.c_int32),
+        ("precision", C.c_int32),
     ]
 
 
@@ -120,6 +121,7 @@ def params_from_dict(p: dict) -> chm_params_t:
         setattr(s, k, int(p[k]))
     s.smoother = SMOOTHERS[p["smoother"]]
     s.use_graphs = int(p.get("use_graphs", 1))
+    s.precision = {"fp64": 0, "fp32": 1}[p.get("precision", "fp64")]
     return s
 
 

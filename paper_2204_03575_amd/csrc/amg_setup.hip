@@ -685,7 +685,6 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         H.xt[l] = pool.get<double2>(L.n);
         H.b[l] = pool.get<double2>(L.n);
         H.r[l] = pool.get<double2>(L.n);
-        H.d[l] = pool.get<double2>(L.n);
     }
     CHM_HIP(hipStreamSynchronize(st));
 }

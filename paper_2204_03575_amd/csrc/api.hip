@@ -68,6 +68,8 @@ const char *check_params(const chm_params_t &p)
         return "need coarse_max >= 1 and 1 <= max_levels <= 24";
     if (p.evap_ds < 0.0 || p.evap_steps < 0)
         return "evaporation settings must be non-negative";
+    if (p.precision != CHM_PREC_FP64 && p.precision != CHM_PREC_FP32)
+        return "unknown precision";
     return nullptr;
 }
 
@@ -144,6 +146,8 @@ int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
         S.hA.jacobi = S.hM.jacobi;
         chm::amg_build(S, S.hM, S.M);
         chm::amg_build(S, S.hA, S.As);
+        S.mixed = S.prm.precision == CHM_PREC_FP32;
+        chm::prec_setup(S);
         chm::alloc_workspace(S);
         CHM_HIP(hipStreamSynchronize(S.stream));
         S.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -350,7 +354,7 @@ int chm_vcycle(chm_solver_t *h, int32_t hierarchy, const double *b, double *x)
         return fail(h, CHM_EINVAL, "chm_vcycle: bad arguments");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
-        chm::vcycle(S, hierarchy == 0 ? S.hM : S.hA, reinterpret_cast<const double2 *>(b),
+        chm::vcycle(S, hierarchy, reinterpret_cast<const double2 *>(b),
                     reinterpret_cast<double2 *>(x));
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(S.stream));

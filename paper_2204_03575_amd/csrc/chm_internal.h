@@ -90,22 +90,61 @@ struct Sell {      // device SELL-64
     double *val = nullptr;
 };
 
+// One matrix of a level as the solve kernels see it, in value type T: the
+// SELL-64 layout (sptr, col, sval) and the CSR layout (rp, ci, cval) share the
+// pattern; gs = lanes per row (0: SELL-64 with one lane per row, 4..32: CSR
+// with that many lanes per row, for long or few rows).
+template <class T> struct MatView {
+    int n = 0, nnz = 0, gs = 0;
+    const int *sptr = nullptr, *col = nullptr, *rp = nullptr, *ci = nullptr;
+    const T *sval = nullptr, *cval = nullptr;
+};
+
 struct Level {
     int n = 0, nc = 0;
     Csr A, P, R;
     Sell sA, sP, sR;
-    // lanes per row of the SpMV kernels: 0 = SELL-64 with one lane per row,
-    // 4..32 = CSR with that many lanes per row (long rows)
-    int gsA = 0, gsP = 0, gsR = 0;
+    int gsA = 0, gsP = 0, gsR = 0;   // lanes per row (see MatView)
     double *dinv = nullptr;
     double rho = 0.0;
     int *agg = nullptr;
-    // Chebyshev coefficients: step 0 uses c2[0] (c1 = 0); step k uses c1[k], c2[k]
+    // Chebyshev coefficients: step 1 uses c2[1] (c1 = 0); step k uses c1[k], c2[k]
     double cheb_c1[32], cheb_c2[32];
     double jac_omega = 0.0;
-    // coarsest level: dense inverse, column-major n x n
+    // coarsest level: dense inverse (FP64 in both precisions), row-major n x n
     double *inv = nullptr;
+    // FP32 copies of the values for the mixed-precision preconditioner
+    float *fA_s = nullptr, *fA_c = nullptr, *fP_s = nullptr, *fP_c = nullptr;
+    float *fR_s = nullptr, *fR_c = nullptr, *fdinv = nullptr;
+
+    template <class T> MatView<T> viewA() const;
+    template <class T> MatView<T> viewP() const;
+    template <class T> MatView<T> viewR() const;
+    template <class T> const T *dinv_t() const;
 };
+
+template <class T> inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, const T *sv, const T *cv)
+{
+    MatView<T> m;
+    m.n = C.n;
+    m.nnz = C.nnz;
+    m.gs = gs;
+    m.sptr = S.sptr;
+    m.col = S.col;
+    m.rp = C.rp;
+    m.ci = C.ci;
+    m.sval = sv;
+    m.cval = cv;
+    return m;
+}
+template <> inline MatView<double> Level::viewA<double>() const { return make_view<double>(A, sA, gsA, sA.val, A.v); }
+template <> inline MatView<double> Level::viewP<double>() const { return make_view<double>(P, sP, gsP, sP.val, P.v); }
+template <> inline MatView<double> Level::viewR<double>() const { return make_view<double>(R, sR, gsR, sR.val, R.v); }
+template <> inline MatView<float> Level::viewA<float>() const { return make_view<float>(A, sA, gsA, fA_s, fA_c); }
+template <> inline MatView<float> Level::viewP<float>() const { return make_view<float>(P, sP, gsP, fP_s, fP_c); }
+template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, fR_s, fR_c); }
+template <> inline const double *Level::dinv_t<double>() const { return dinv; }
+template <> inline const float *Level::dinv_t<float>() const { return fdinv; }
 
 struct Hierarchy {
     int nlev = 0;
@@ -113,8 +152,20 @@ struct Hierarchy {
     double ratio = 30.0;
     bool jacobi = false;
     Level lev[kMaxLevels];
-    // per-level work vectors (pairs)
-    double2 *x[kMaxLevels], *xt[kMaxLevels], *b[kMaxLevels], *r[kMaxLevels], *d[kMaxLevels];
+    // per-level work vectors (pairs), FP64 and FP32
+    double2 *x[kMaxLevels], *xt[kMaxLevels], *b[kMaxLevels], *r[kMaxLevels];
+    float2 *fx[kMaxLevels], *fxt[kMaxLevels], *fb[kMaxLevels], *fr[kMaxLevels];
+};
+
+template <class T> struct Work;   // per-precision work vectors of the preconditioner
+template <> struct Work<double> {
+    double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
+    double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+};
+template <> struct Work<float> {
+    float2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
+    float2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+    float2 *vin = nullptr, *wout = nullptr;   // block vectors at the FP64 boundary
 };
 
 // device-side FGMRES control block (one per solver).  The small fields come
@@ -181,8 +232,10 @@ struct Solver {
     double2 *b = nullptr, *r = nullptr;
     double2 *V = nullptr, *Z = nullptr;
     double2 *f = nullptr;      // potential term of the right-hand side (pairs)
-    double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
-    double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+    Work<double> w64;
+    Work<float> w32;
+    float *fsM = nullptr;      // FP32 SELL values of M (Algorithm 1's product with M)
+    bool mixed = false;        // FP32 preconditioner (precision = 1)
     double2 *red = nullptr;    // slots of per-block partial sums (kRedBlocks each)
     double2 *gsp1 = nullptr, *gsp2 = nullptr, *gsp3 = nullptr;  // Gram-Schmidt partials
     double2 *hfin = nullptr;   // finalised Gram-Schmidt coefficients of both passes
@@ -214,14 +267,18 @@ void mesh_setup(Solver &S);
 // ---- amg_setup.hip
 void amg_build(Solver &S, Hierarchy &H, const Csr &A0);
 
+// ---- prec.hip (preconditioner; FP64 vectors at the interface, the
+// configured precision inside)
+void prec_setup(Solver &S);   // FP32 copies and work vectors (mixed precision)
+void vcycle(Solver &S, int hier, const double2 *b, double2 *x);
+void schur_solve(Solver &S, const double2 *b, double2 *x);
+void apply_prec(Solver &S, const double2 *v, double2 *w);
+
 // ---- solve.hip
 void alloc_workspace(Solver &S);
-void vcycle(Solver &S, Hierarchy &H, const double2 *b, double2 *x);
-void schur_solve(Solver &S, const double2 *b, double2 *x);
-void mass_solve(Solver &S, const double2 *b, double2 *x);
-void apply_prec(Solver &S, const double2 *v, double2 *w);
 void apply_saddle(Solver &S, const double2 *x, double2 *y);
 void compute_rhs(Solver &S);
 int step_once(Solver &S, chm_stats_t *st);
+void timer_mark(Solver &S, bool begin);
 
 }  // namespace chm

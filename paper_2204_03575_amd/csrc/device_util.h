@@ -1,0 +1,268 @@
+// Device helpers and kernels shared by the preconditioner (prec.hip) and the
+// Krylov solver (solve.hip): pair types, the XCD-aware block numbering, the
+// deterministic reductions and the SpMV kernels, templated on the value type
+// (double for the FP64 path, float for the FP32 preconditioner).  Everything
+// sits in an unnamed namespace, so each source file has its own copies.
+//
+// Reductions need no inter-block synchronisation: a producer kernel with a
+// fixed grid writes one partial sum per block; every consumer block adds the
+// partials itself in a fixed order (so all blocks obtain the same bits) after
+// the kernel boundary has made them visible.
+#pragma once
+
+#include "chm_internal.h"
+
+namespace chm {
+namespace {
+
+inline int nblk(long n, int bs = kBlock) { return (int)std::max<long>(1, (n + bs - 1) / bs); }
+inline int red_blocks(long n) { return (int)std::min<long>(kRedBlocks, nblk(n)); }
+
+__device__ inline double2 d2(double a, double b) { return make_double2(a, b); }
+
+// pair type of a value type: double -> double2, float -> float2
+template <class T> struct PairOf;
+template <> struct PairOf<double> { using type = double2; };
+template <> struct PairOf<float> { using type = float2; };
+template <class T> using pair_t = typename PairOf<T>::type;
+
+template <class T> __device__ inline pair_t<T> mk(T a, T b);
+template <> __device__ inline double2 mk<double>(double a, double b) { return make_double2(a, b); }
+template <> __device__ inline float2 mk<float>(float a, float b) { return make_float2(a, b); }
+
+// XCD-aware block index.  The hardware hands workgroup b to XCD b mod 8; this
+// renumbering gives every XCD one contiguous range of blocks, so the
+// neighbouring rows that an SpMV row gathers from mostly sit in the same
+// XCD's L2.  It is a bijection of [0, gridDim.x).
+constexpr int kXcds = 8;
+
+__device__ inline int xcd_block()
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + min(x, r) + j;
+}
+
+__device__ inline double2 wave_sum(double2 v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_down(v.x, off, 64);
+        v.y += __shfl_down(v.y, off, 64);
+    }
+    return v;
+}
+
+// sum over a 256-thread block; the result is valid in thread 0
+__device__ inline double2 block_sum(double2 v, double2 *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        sh[wid] = v;
+    __syncthreads();
+    double2 r = d2(0.0, 0.0);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) {
+            r.x += sh[w].x;
+            r.y += sh[w].y;
+        }
+    __syncthreads();
+    return r;
+}
+
+// out[v] = sum over g < G of part[v * G + g] for v < nvec, into LDS, visible
+// to the whole block on return.  Wave w takes vectors w, w + 4, ...; lane l
+// adds g = l, l + 64, ... and the wave adds its lanes with a fixed shuffle
+// tree.
+__device__ inline void reduce_parts(const double2 *__restrict__ part, int nvec, int G, double2 *out)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int v = wid; v < nvec; v += kBlock / 64) {
+        double2 s = d2(0.0, 0.0);
+        for (int g = lane; g < G; g += 64) {
+            const double2 p = part[(size_t)v * G + g];
+            s.x += p.x;
+            s.y += p.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0)
+            out[v] = s;
+    }
+    __syncthreads();
+}
+
+// two independent scalars at once (waves 0 and 1)
+__device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
+                                  int G, double2 *out)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (wid < 2) {
+        const double2 *p = wid == 0 ? pa : pb;
+        double2 s = d2(0.0, 0.0);
+        for (int g = lane; g < G; g += 64) {
+            const double2 q = p[g];
+            s.x += q.x;
+            s.y += q.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0)
+            out[wid] = s;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ partial-sum slots
+// kRedBlocks pairs each, in Solver::red: the inner CG uses rz (0..39) and
+// dq (40..79), the Krylov solver the right-hand-side norm (80) and the
+// residual norm (81).
+constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlots = 82;
+
+inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
+
+// ------------------------------------------------------------------ SpMV family (pairs)
+// SP_SET: y = A x; SP_ADD: y += A x; SP_RESID: y = b - A x
+enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
+
+// row of a SELL-64 matrix (one lane per row, columns of a slice stored
+// column-major so that the 64 lanes read consecutive words)
+template <class T>
+__device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
+                                     const T *__restrict__ val, const pair_t<T> *__restrict__ x,
+                                     int row)
+{
+    const int s = row / kSlice, lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    T ax = 0, ay = 0;
+#pragma unroll 4
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        const T a = val[idx];
+        const pair_t<T> xv = x[col[idx]];
+        ax += a * xv.x;
+        ay += a * xv.y;
+    }
+    return mk<T>(ax, ay);
+}
+
+template <int MODE, class T>
+__device__ inline void spmv_store(pair_t<T> s, const pair_t<T> *__restrict__ b, pair_t<T> *y, int row)
+{
+    if (MODE == SP_SET) {
+        y[row] = s;
+    } else if (MODE == SP_ADD) {
+        const pair_t<T> o = y[row];
+        y[row] = mk<T>(o.x + s.x, o.y + s.y);
+    } else {
+        const pair_t<T> bb = b[row];
+        y[row] = mk<T>(bb.x - s.x, bb.y - s.y);
+    }
+}
+
+template <int MODE, class T>
+__global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
+                                                 const int *__restrict__ col,
+                                                 const T *__restrict__ val,
+                                                 const pair_t<T> *__restrict__ x,
+                                                 const pair_t<T> *__restrict__ b, pair_t<T> *y)
+{
+    const int row = xcd_block() * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    spmv_store<MODE, T>(sell_row<T>(sptr, col, val, x, row), b, y, row);
+}
+
+// The same with a group of GS lanes per row (CSR), for matrices with long rows
+// or few rows: lane l of the group takes entries l, l + GS, ... of the row and
+// the group adds its lanes with a fixed shuffle tree.  Whole groups share a
+// row, so they exit together.
+template <int GS, class T>
+__device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                    const T *__restrict__ v, const pair_t<T> *__restrict__ x,
+                                    int row, int lane)
+{
+    T ax = 0, ay = 0;
+    const int e = rp[row + 1];
+    for (int k = rp[row] + lane; k < e; k += GS) {
+        const T a = v[k];
+        const pair_t<T> xv = x[ci[k]];
+        ax += a * xv.x;
+        ay += a * xv.y;
+    }
+#pragma unroll
+    for (int off = GS / 2; off > 0; off >>= 1) {
+        ax += __shfl_down(ax, off, GS);
+        ay += __shfl_down(ay, off, GS);
+    }
+    return mk<T>(ax, ay);
+}
+
+template <int GS, int MODE, class T>
+__global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const T *__restrict__ v,
+                                                   const pair_t<T> *__restrict__ x,
+                                                   const pair_t<T> *__restrict__ b, pair_t<T> *y)
+{
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    const pair_t<T> s = row_dot<GS, T>(rp, ci, v, x, row, lane);
+    if (lane == 0)
+        spmv_store<MODE, T>(s, b, y, row);
+}
+
+// y = A x / y += A x / y = b - A x with the kernel shape chosen for the matrix
+template <int MODE, class T>
+void spmv_op(hipStream_t st, const MatView<T> &A, const pair_t<T> *x, const pair_t<T> *b,
+             pair_t<T> *y)
+{
+    const int n = A.n;
+    switch (A.gs) {
+    case 0:
+        k_spmv<MODE, T><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, x, b, y);
+        break;
+    case 4:
+        k_spmv_v<4, MODE, T><<<nblk(4l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        break;
+    case 8:
+        k_spmv_v<8, MODE, T><<<nblk(8l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        break;
+    case 16:
+        k_spmv_v<16, MODE, T><<<nblk(16l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        break;
+    default:
+        k_spmv_v<32, MODE, T><<<nblk(32l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        break;
+    }
+}
+
+// ------------------------------------------------------------------ vector kernels
+// per-block partial sums of the two species' dot products, accumulated in FP64
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restrict__ a,
+                                                const pair_t<T> *__restrict__ b, double2 *part)
+{
+    __shared__ double2 sh[kBlock / 64];
+    double2 acc = d2(0.0, 0.0);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const pair_t<T> x = a[i], y = b[i];
+        acc.x += double(x.x) * double(y.x);
+        acc.y += double(x.y) * double(y.y);
+    }
+    const double2 s = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s;
+}
+
+template <class P>
+__global__ void __launch_bounds__(kBlock) k_copy(int n, const P *__restrict__ a, P *b)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row < n)
+        b[row] = a[row];
+}
+
+}  // namespace
+}  // namespace chm

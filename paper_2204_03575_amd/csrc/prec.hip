@@ -1,0 +1,531 @@
+// The block preconditioner of Algorithm 1 on the GPU: the mass block by AMG
+// V-cycles, the Schur block by the matching approximation As M^-1 As with
+// As = tau' K + sqrt(tau'/eps) M, each As solve done with CG steps
+// preconditioned by one V-cycle.  Both species run through every kernel
+// together (pair vectors), each with its own CG scalars.
+//
+// All of it is templated on the value type T.  T = double is the FP64 path.
+// T = float is the mixed-precision preconditioner: FP32 matrix values, work
+// vectors, smoothing, restriction, prolongation and the product with M inside
+// Algorithm 1; the dot products of the inner CG are still accumulated in FP64,
+// the coarsest level still applies its FP64 inverse with FP64 sums, and the
+// vectors at the interface (the Krylov basis vector in, the preconditioned
+// vector out) stay FP64.  The flexible Krylov method outside accepts a
+// preconditioner that varies with its input, so rounding at FP32 changes
+// iteration counts, not the converged residual.
+#include "device_util.h"
+
+namespace chm {
+
+namespace {
+
+// ------------------------------------------------------------------ smoothing
+// Chebyshev (or damped Jacobi) step in two-buffer form:
+//   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (b - A x_k),
+// the same polynomial as the update d_k = c1 d_{k-1} + c2 D^-1 r_k with
+// d_{k-1} = x_k - x_{k-1}.  x_{k+1} overwrites x_{k-1} row by row; with
+// prev = 0 the previous iterate is taken as zero (start from x = 0) or is not
+// needed (c1 = 0).
+template <class T>
+__device__ inline pair_t<T> cheb_update(pair_t<T> s, const pair_t<T> *__restrict__ b,
+                                        const pair_t<T> *__restrict__ xk,
+                                        const T *__restrict__ dinv, const pair_t<T> *xprev,
+                                        int row, T c1, T c2, int prev)
+{
+    const pair_t<T> bb = b[row], xi = xk[row];
+    const T di = dinv[row];
+    pair_t<T> xp = mk<T>(0, 0);
+    if (prev)
+        xp = xprev[row];
+    return mk<T>(xi.x + c1 * (xi.x - xp.x) + c2 * (di * (bb.x - s.x)),
+                 xi.y + c1 * (xi.y - xp.y) + c2 * (di * (bb.y - s.y)));
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ sptr,
+                                                 const int *__restrict__ col,
+                                                 const T *__restrict__ val,
+                                                 const T *__restrict__ dinv,
+                                                 const pair_t<T> *__restrict__ b,
+                                                 const pair_t<T> *__restrict__ xk, pair_t<T> *xprev,
+                                                 T c1, T c2, int prev)
+{
+    const int row = xcd_block() * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    const pair_t<T> s = sell_row<T>(sptr, col, val, xk, row);
+    xprev[row] = cheb_update<T>(s, b, xk, dinv, xprev, row, c1, c2, prev);
+}
+
+template <int GS, class T>
+__global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const T *__restrict__ v,
+                                                   const T *__restrict__ dinv,
+                                                   const pair_t<T> *__restrict__ b,
+                                                   const pair_t<T> *__restrict__ xk,
+                                                   pair_t<T> *xprev, T c1, T c2, int prev)
+{
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    const pair_t<T> s = row_dot<GS, T>(rp, ci, v, xk, row, lane);
+    if (lane != 0)
+        return;
+    xprev[row] = cheb_update<T>(s, b, xk, dinv, xprev, row, c1, c2, prev);
+}
+
+// first smoothing step from x = 0: x = c2 D^-1 b
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ dinv,
+                                                  const pair_t<T> *__restrict__ b, pair_t<T> *x,
+                                                  T c2)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    const pair_t<T> bb = b[row];
+    const T di = dinv[row];
+    x[row] = mk<T>(c2 * (di * bb.x), c2 * (di * bb.y));
+}
+
+// coarsest level: x = A^-1 b with the FP64 inverse stored row-major; one wave
+// per row, lane l takes columns l, l + 64, ..., the wave adds its lanes with a
+// fixed shuffle tree (FP64 sums in both precisions)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
+                                                  const pair_t<T> *__restrict__ b, pair_t<T> *x)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (row >= n)
+        return;
+    const double *a = inv + (size_t)row * n;
+    double2 acc = d2(0.0, 0.0);
+    for (int j = lane; j < n; j += 64) {
+        const double v = a[j];
+        const pair_t<T> bv = b[j];
+        acc.x += v * double(bv.x);
+        acc.y += v * double(bv.y);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0)
+        x[row] = mk<T>(T(acc.x), T(acc.y));
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const pair_t<T> *__restrict__ e,
+                                                     pair_t<T> *x)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    const pair_t<T> a = x[row], b = e[row];
+    x[row] = mk<T>(a.x + b.x, a.y + b.y);
+}
+
+// ------------------------------------------------------------------ inner CG for As
+__device__ inline double2 ratio_or_zero(double2 num, double2 den)
+{
+    return d2(den.x != 0.0 ? num.x / den.x : 0.0, den.y != 0.0 ? num.y / den.y : 0.0);
+}
+
+// alpha = rz / dq from partials; first == 1: x = alpha d, r = b - alpha q
+// (x = 0 and r = b before the step), else x += alpha d, r -= alpha q
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, pair_t<T> *x, pair_t<T> *r,
+                                                   const pair_t<T> *__restrict__ b,
+                                                   const pair_t<T> *__restrict__ d,
+                                                   const pair_t<T> *__restrict__ q,
+                                                   const double2 *__restrict__ rz_part,
+                                                   const double2 *__restrict__ dq_part, int G,
+                                                   int first)
+{
+    __shared__ double2 sc[2];
+    reduce_two(rz_part, dq_part, G, sc);
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const double2 al = ratio_or_zero(sc[0], sc[1]);
+    const T ax = T(al.x), ay = T(al.y);
+    const pair_t<T> dv = d[i], qv = q[i];
+    pair_t<T> xv = first ? mk<T>(0, 0) : x[i];
+    pair_t<T> rv = first ? b[i] : r[i];
+    xv.x += ax * dv.x;
+    xv.y += ay * dv.y;
+    rv.x -= ax * qv.x;
+    rv.y -= ay * qv.y;
+    x[i] = xv;
+    r[i] = rv;
+}
+
+// d = z + beta d with beta = rz_new / rz_old (0 where rz_old == 0); first: d = z
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const pair_t<T> *__restrict__ z,
+                                                    pair_t<T> *d,
+                                                    const double2 *__restrict__ new_part,
+                                                    const double2 *__restrict__ old_part, int G,
+                                                    int first)
+{
+    __shared__ double2 sc[2];
+    if (!first)
+        reduce_two(new_part, old_part, G, sc);
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const pair_t<T> zv = z[i];
+    if (first) {
+        d[i] = zv;
+        return;
+    }
+    const double2 be = ratio_or_zero(sc[0], sc[1]);
+    const T bx = T(be.x), by = T(be.y);
+    const pair_t<T> dv = d[i];
+    d[i] = mk<T>(zv.x + bx * dv.x, zv.y + by * dv.y);
+}
+
+// ------------------------------------------------------------------ precision boundary
+__global__ void __launch_bounds__(kBlock) k_narrow_pairs(int n, const double2 *__restrict__ a,
+                                                         float2 *b)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double2 v = a[i];
+        b[i] = make_float2(float(v.x), float(v.y));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_widen_pairs(int n, const float2 *__restrict__ a,
+                                                        double2 *b)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const float2 v = a[i];
+        b[i] = make_double2(double(v.x), double(v.y));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_narrow(long n, const double *__restrict__ a, float *b)
+{
+    const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        b[i] = float(a[i]);
+}
+
+// ------------------------------------------------------------------ per-precision buffers
+template <class T> struct Vecs {
+    pair_t<T> *x, *xt, *b, *r;
+};
+template <class T> Vecs<T> vecs(Hierarchy &H, int l);
+template <> Vecs<double> vecs<double>(Hierarchy &H, int l) { return {H.x[l], H.xt[l], H.b[l], H.r[l]}; }
+template <> Vecs<float> vecs<float>(Hierarchy &H, int l) { return {H.fx[l], H.fxt[l], H.fb[l], H.fr[l]}; }
+
+template <class T> Work<T> &work(Solver &S);
+template <> Work<double> &work<double>(Solver &S) { return S.w64; }
+template <> Work<float> &work<float>(Solver &S) { return S.w32; }
+
+template <class T> const T *mass_sell_values(const Solver &S);
+template <> const double *mass_sell_values<double>(const Solver &S) { return S.sM.val; }
+template <> const float *mass_sell_values<float>(const Solver &S) { return S.fsM; }
+
+// ------------------------------------------------------------------ V-cycle (host)
+// The event timer brackets each run of back-to-back smoothing launches on the
+// fine level of the As hierarchy (the pre- and post-smoothing sequences), so
+// the event overhead is spread over the launches of a run.
+bool timed_level(const Solver &S, const Hierarchy &H, int l)
+{
+    return S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
+}
+
+// one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
+template <class T>
+void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_t<T> *xk,
+                 pair_t<T> *xprev, double c1d, double c2d, int prev)
+{
+    const Level &L = H.lev[l];
+    const MatView<T> A = L.viewA<T>();
+    const T *dinv = L.dinv_t<T>();
+    const T c1 = T(c1d), c2 = T(c2d);
+    const int n = L.n;
+    hipStream_t st = S.stream;
+    switch (A.gs) {
+    case 0:
+        k_cheb<T><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b, xk, xprev, c1, c2,
+                                              prev);
+        break;
+    case 4:
+        k_cheb_v<4, T><<<nblk(4l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk, xprev,
+                                                        c1, c2, prev);
+        break;
+    case 8:
+        k_cheb_v<8, T><<<nblk(8l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk, xprev,
+                                                        c1, c2, prev);
+        break;
+    case 16:
+        k_cheb_v<16, T><<<nblk(16l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
+                                                          xprev, c1, c2, prev);
+        break;
+    default:
+        k_cheb_v<32, T><<<nblk(32l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
+                                                          xprev, c1, c2, prev);
+        break;
+    }
+    if (timed_level(S, H, l)) {
+        // algorithmic bytes: column index + value per nonzero; per row x_k
+        // (gathered once), b, D^-1, x_{k-1} (when read) and the written x_{k+1}
+        S.timer.count += 1;
+        S.timer.bytes += (long long)(sizeof(int) + sizeof(T)) * L.A.nnz +
+                         (long long)(prev ? 9 : 7) * sizeof(T) * L.n;
+    }
+}
+
+template <class T>
+void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> *x)
+{
+    const Level &L = H.lev[l];
+    hipStream_t st = S.stream;
+    if (l == H.nlev - 1) {
+        k_dense<T><<<nblk(L.n, kBlock / 64), kBlock, 0, st>>>(L.n, L.inv, b, x);
+        return;
+    }
+    const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
+    const int deg = H.degree;
+    auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
+    auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
+    // Pre-smoothing from zero.  Every step after the first writes the buffer
+    // not holding the current iterate; 2 deg - 1 such steps follow the first,
+    // so starting in xt leaves the result in x.
+    k_cheb0<T><<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv_t<T>(), b, V.xt, T(c2(1)));
+    pair_t<T> *cur = V.xt, *oth = x;
+    const bool timed = timed_level(S, H, l);
+    if (timed && deg >= 2)
+        timer_mark(S, true);
+    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
+        launch_cheb<T>(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
+        std::swap(cur, oth);
+    }
+    if (timed && deg >= 2)
+        timer_mark(S, false);
+    spmv_op<SP_RESID, T>(st, L.viewA<T>(), cur, b, V.r);
+    spmv_op<SP_SET, T>(st, L.viewR<T>(), V.r, nullptr, Vc.b);
+    vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
+    spmv_op<SP_ADD, T>(st, L.viewP<T>(), Vc.x, nullptr, cur);
+    if (timed)
+        timer_mark(S, true);
+    for (int k = 1; k <= deg; ++k) {
+        launch_cheb<T>(S, H, l, b, cur, oth, c1(k), c2(k), k > 1 && !H.jacobi);
+        std::swap(cur, oth);
+    }
+    if (timed)
+        timer_mark(S, false);
+}
+
+// stationary AMG solve: x = V(b), then x += V(b - A x) for the further cycles
+template <class T>
+void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
+{
+    Work<T> &W = work<T>(S);
+    const Level &L0 = H.lev[0];
+    const int n = L0.n;
+    vcycle_level<T>(S, H, 0, b, x);
+    for (int c = 1; c < S.prm.amg_cycles; ++c) {
+        spmv_op<SP_RESID, T>(S.stream, L0.viewA<T>(), x, b, W.mr);
+        vcycle_level<T>(S, H, 0, W.mr, W.me);
+        k_axpy_add<T><<<nblk(n), kBlock, 0, S.stream>>>(n, W.me, x);
+    }
+}
+
+// As solve of Algorithm 1: schur_pcg CG steps preconditioned by one V-cycle
+// (or amg_cycles stationary V-cycles when schur_pcg = 0)
+template <class T>
+void schur_solve_t(Solver &S, const pair_t<T> *b, pair_t<T> *x)
+{
+    Hierarchy &H = S.hA;
+    const int n = S.nv, k = S.prm.schur_pcg;
+    hipStream_t st = S.stream;
+    if (k <= 0) {
+        stationary<T>(S, H, b, x);
+        return;
+    }
+    Work<T> &W = work<T>(S);
+    const MatView<T> A = H.lev[0].viewA<T>();
+    pair_t<T> *r = W.pcg_r, *z = W.pcg_z, *d = W.pcg_d, *q = W.pcg_q;
+    const int G = red_blocks(n);
+    vcycle_level<T>(S, H, 0, b, z);                                    // z = V(b), r = b
+    k_dot<T><<<G, kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
+    k_pcg_dir<T><<<nblk(n), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
+    for (int it = 1; it <= k; ++it) {
+        spmv_op<SP_SET, T>(st, A, d, nullptr, q);
+        k_dot<T><<<G, kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
+        k_pcg_xr<T><<<nblk(n), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
+                                                slot(S, kSlotDq + it), G, it == 1);
+        if (it == k)
+            break;
+        vcycle_level<T>(S, H, 0, r, z);
+        k_dot<T><<<G, kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
+        k_pcg_dir<T><<<nblk(n), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
+                                                 slot(S, kSlotRz + it - 1), G, 0);
+    }
+}
+
+// Algorithm 1 on a block vector: w1 = AMG(M) v1; w2 = As^-1 M As^-1 v2
+template <class T>
+void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
+{
+    Work<T> &W = work<T>(S);
+    const int n = S.nv;
+    stationary<T>(S, S.hM, v, w);
+    schur_solve_t<T>(S, v + n, W.tmp);
+    k_spmv<SP_SET, T><<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col,
+                                                         mass_sell_values<T>(S), W.tmp, nullptr,
+                                                         W.tmp2);
+    schur_solve_t<T>(S, W.tmp2, w + n);
+}
+
+void narrow(Solver &S, int n, const double2 *a, float2 *b)
+{
+    k_narrow_pairs<<<nblk(n), kBlock, 0, S.stream>>>(n, a, b);
+}
+
+void widen(Solver &S, int n, const float2 *a, double2 *b)
+{
+    k_widen_pairs<<<nblk(n), kBlock, 0, S.stream>>>(n, a, b);
+}
+
+float *narrow_copy(Pool &pool, hipStream_t st, const double *a, long n)
+{
+    if (!a || n <= 0)
+        return nullptr;
+    float *b = pool.get<float>(n);
+    k_narrow<<<nblk(n), kBlock, 0, st>>>(n, a, b);
+    CHM_HIP(hipGetLastError());
+    return b;
+}
+
+// FP32 values of one matrix: only the layout its kernels read
+void narrow_matrix(Pool &pool, hipStream_t st, const Csr &C, const Sell &Sl, int gs, float *&fs,
+                   float *&fc)
+{
+    if (gs == 0)
+        fs = narrow_copy(pool, st, Sl.val, (long)Sl.stored);
+    else
+        fc = narrow_copy(pool, st, C.v, (long)C.nnz);
+}
+
+void narrow_hierarchy(Solver &S, Hierarchy &H)
+{
+    Pool &pool = S.pool;
+    hipStream_t st = S.stream;
+    for (int l = 0; l < H.nlev; ++l) {
+        Level &L = H.lev[l];
+        H.fx[l] = pool.get<float2>(L.n);
+        H.fxt[l] = pool.get<float2>(L.n);
+        H.fb[l] = pool.get<float2>(L.n);
+        H.fr[l] = pool.get<float2>(L.n);
+        // A on every level: the fine one also serves the inner CG and the
+        // stationary cycles when it is the coarsest
+        narrow_matrix(pool, st, L.A, L.sA, L.gsA, L.fA_s, L.fA_c);
+        if (l == H.nlev - 1)
+            break;   // the coarsest level solves with its FP64 inverse
+        narrow_matrix(pool, st, L.P, L.sP, L.gsP, L.fP_s, L.fP_c);
+        narrow_matrix(pool, st, L.R, L.sR, L.gsR, L.fR_s, L.fR_c);
+        L.fdinv = narrow_copy(pool, st, L.dinv, L.n);
+    }
+}
+
+}  // namespace
+
+void timer_mark(Solver &S, bool begin)
+{
+    Timer &T = S.timer;
+    if (T.used >= T.ev.size() && T.used >= 8192 && begin) {   // fold finished pairs
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        for (size_t i = 0; i + 1 < T.used; i += 2) {
+            float ms = 0.f;
+            CHM_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+            T.total_ms += ms;
+        }
+        T.used = 0;
+    }
+    if (T.used >= T.ev.size()) {   // grow the event pool
+        size_t old = T.ev.size();
+        T.ev.resize(old + 2048);
+        for (size_t i = old; i < T.ev.size(); ++i)
+            CHM_HIP(hipEventCreate(&T.ev[i]));
+    }
+    CHM_HIP(hipEventRecord(T.ev[T.used++], S.stream));
+}
+
+// work vectors of both precisions (FP32 ones and FP32 matrix copies only for
+// the mixed-precision preconditioner); after amg_build of both hierarchies
+void prec_setup(Solver &S)
+{
+    Pool &p = S.pool;
+    const int n = S.nv;
+    Work<double> &D = S.w64;
+    D.pcg_r = p.get<double2>(n);
+    D.pcg_z = p.get<double2>(n);
+    D.pcg_d = p.get<double2>(n);
+    D.pcg_q = p.get<double2>(n);
+    D.tmp = p.get<double2>(n);
+    D.tmp2 = p.get<double2>(n);
+    D.mr = p.get<double2>(n);
+    D.me = p.get<double2>(n);
+    if (!S.mixed)
+        return;
+    Work<float> &F = S.w32;
+    F.pcg_r = p.get<float2>(n);
+    F.pcg_z = p.get<float2>(n);
+    F.pcg_d = p.get<float2>(n);
+    F.pcg_q = p.get<float2>(n);
+    F.tmp = p.get<float2>(n);
+    F.tmp2 = p.get<float2>(n);
+    F.mr = p.get<float2>(n);
+    F.me = p.get<float2>(n);
+    F.vin = p.get<float2>(2 * (size_t)n);
+    F.wout = p.get<float2>(2 * (size_t)n);
+    S.fsM = narrow_copy(p, S.stream, S.sM.val, (long)S.sM.stored);
+    narrow_hierarchy(S, S.hM);
+    narrow_hierarchy(S, S.hA);
+    CHM_HIP(hipStreamSynchronize(S.stream));
+}
+
+void vcycle(Solver &S, int hier, const double2 *b, double2 *x)
+{
+    Hierarchy &H = hier == 0 ? S.hM : S.hA;
+    if (!S.mixed) {
+        vcycle_level<double>(S, H, 0, b, x);
+        return;
+    }
+    const int n = H.lev[0].n;
+    narrow(S, n, b, S.w32.vin);
+    vcycle_level<float>(S, H, 0, S.w32.vin, S.w32.wout);
+    widen(S, n, S.w32.wout, x);
+}
+
+void schur_solve(Solver &S, const double2 *b, double2 *x)
+{
+    if (!S.mixed) {
+        schur_solve_t<double>(S, b, x);
+        return;
+    }
+    const int n = S.nv;
+    narrow(S, n, b, S.w32.vin);
+    schur_solve_t<float>(S, S.w32.vin, S.w32.wout);
+    widen(S, n, S.w32.wout, x);
+}
+
+void apply_prec(Solver &S, const double2 *v, double2 *w)
+{
+    if (!S.mixed) {
+        apply_prec_t<double>(S, v, w);
+        return;
+    }
+    const int len = 2 * S.nv;
+    narrow(S, len, v, S.w32.vin);
+    apply_prec_t<float>(S, S.w32.vin, S.w32.wout);
+    widen(S, len, S.w32.wout, w);
+}
+
+}  // namespace chm

@@ -1,384 +1,17 @@
-// Per-time-step solve on the GPU: right-hand side, Algorithm 1 of the paper
-// (mass block by one AMG V-cycle; Schur block by the matching approximation
-// As M^-1 As with As = tau' K + sqrt(tau'/eps) M, each As solve done with CG
-// steps preconditioned by one V-cycle), the saddle-point operator of
-// eq. saddle_point_system, and right-preconditioned flexible GMRES with
+// Per-time-step solve on the GPU: right-hand side, the saddle-point operator
+// of eq. saddle_point_system, and right-preconditioned flexible GMRES with
 // classical Gram-Schmidt applied twice and Givens rotations kept on the
-// device.  Both species run through every kernel together (pair vectors),
-// each with its own scalars, convergence flag and iteration count.
-//
-// Reductions are deterministic and need no inter-block synchronisation: a
-// producer kernel with a fixed grid of at most 256 blocks writes one partial
-// sum per block; every consumer block adds the partials itself in a fixed
-// order (so all blocks obtain the same bits), after the kernel boundary has
-// made them visible.
+// device, preconditioned by Algorithm 1 (prec.hip).  Both species run through
+// every kernel together (pair vectors), each with its own scalars,
+// convergence flag and iteration count.  All of it is FP64.
 #include <chrono>
 #include <cmath>
 
-#include "chm_internal.h"
+#include "device_util.h"
 
 namespace chm {
 
 namespace {
-
-inline int nblk(long n, int bs = kBlock) { return (int)std::max<long>(1, (n + bs - 1) / bs); }
-inline int red_blocks(long n) { return (int)std::min<long>(kRedBlocks, nblk(n)); }
-
-__device__ inline double2 d2(double a, double b) { return make_double2(a, b); }
-
-// XCD-aware block index.  The hardware hands workgroup b to XCD b mod 8; this
-// renumbering gives every XCD one contiguous range of blocks, so the
-// neighbouring rows that an SpMV row gathers from mostly sit in the same
-// XCD's L2.  It is a bijection of [0, gridDim.x).
-constexpr int kXcds = 8;
-
-__device__ inline int xcd_block()
-{
-    const int G = gridDim.x, b = blockIdx.x;
-    const int q = G / kXcds, r = G % kXcds;
-    const int x = b % kXcds, j = b / kXcds;
-    return x * q + min(x, r) + j;
-}
-
-// ------------------------------------------------------------------ reductions
-__device__ inline double2 wave_sum(double2 v)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        v.x += __shfl_down(v.x, off, 64);
-        v.y += __shfl_down(v.y, off, 64);
-    }
-    return v;
-}
-
-// sum over a 256-thread block; the result is valid in thread 0
-__device__ inline double2 block_sum(double2 v, double2 *sh)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-        sh[wid] = v;
-    __syncthreads();
-    double2 r = d2(0.0, 0.0);
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) {
-            r.x += sh[w].x;
-            r.y += sh[w].y;
-        }
-    __syncthreads();
-    return r;
-}
-
-// out[v] = sum over g < G of part[v * G + g] for v < nvec (G <= 256), into
-// LDS, visible to the whole block on return.  Wave w takes vectors w, w + 4,
-// ...; lane l adds g = l, l + 64, ... and the wave adds its lanes with a
-// fixed shuffle tree.
-__device__ inline void reduce_parts(const double2 *__restrict__ part, int nvec, int G, double2 *out)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int v = wid; v < nvec; v += kBlock / 64) {
-        double2 s = d2(0.0, 0.0);
-        for (int g = lane; g < G; g += 64) {
-            const double2 p = part[(size_t)v * G + g];
-            s.x += p.x;
-            s.y += p.y;
-        }
-        s = wave_sum(s);
-        if (lane == 0)
-            out[v] = s;
-    }
-    __syncthreads();
-}
-
-// two independent scalars at once (waves 0 and 1)
-__device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 *__restrict__ pb,
-                                  int G, double2 *out)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (wid < 2) {
-        const double2 *p = wid == 0 ? pa : pb;
-        double2 s = d2(0.0, 0.0);
-        for (int g = lane; g < G; g += 64) {
-            const double2 q = p[g];
-            s.x += q.x;
-            s.y += q.y;
-        }
-        s = wave_sum(s);
-        if (lane == 0)
-            out[wid] = s;
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------ SELL SpMV family (pairs)
-enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
-
-__device__ inline double2 sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
-                                   const double *__restrict__ val, const double2 *__restrict__ x,
-                                   int row)
-{
-    const int s = row / kSlice, lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-    double ax = 0.0, ay = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const double a = val[idx];
-        const double2 xv = x[col[idx]];
-        ax += a * xv.x;
-        ay += a * xv.y;
-    }
-    return d2(ax, ay);
-}
-
-// SP_SET: y = A x; SP_ADD: y += A x; SP_RESID: y = b - A x
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
-                                                 const int *__restrict__ col,
-                                                 const double *__restrict__ val,
-                                                 const double2 *__restrict__ x,
-                                                 const double2 *__restrict__ b, double2 *y)
-{
-    const int row = xcd_block() * kBlock + threadIdx.x;
-    if (row >= n)
-        return;
-    const double2 s = sell_row(sptr, col, val, x, row);
-    if (MODE == SP_SET) {
-        y[row] = s;
-    } else if (MODE == SP_ADD) {
-        const double2 o = y[row];
-        y[row] = d2(o.x + s.x, o.y + s.y);
-    } else {
-        const double2 bb = b[row];
-        y[row] = d2(bb.x - s.x, bb.y - s.y);
-    }
-}
-
-// Chebyshev (or damped Jacobi) step in two-buffer form:
-//   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (b - A x_k),
-// the same polynomial as the update d_k = c1 d_{k-1} + c2 D^-1 r_k with
-// d_{k-1} = x_k - x_{k-1}.  x_{k+1} overwrites x_{k-1} row by row; with
-// prev = 0 the previous iterate is taken as zero (start from x = 0) or is not
-// needed (c1 = 0).
-__device__ inline double2 cheb_update(double2 s, const double2 *__restrict__ b,
-                                      const double2 *__restrict__ xk,
-                                      const double *__restrict__ dinv, const double2 *xprev,
-                                      int row, double c1, double c2, int prev)
-{
-    const double2 bb = b[row], xi = xk[row];
-    const double di = dinv[row];
-    double2 xp = d2(0.0, 0.0);
-    if (prev)
-        xp = xprev[row];
-    return d2(xi.x + c1 * (xi.x - xp.x) + c2 * (di * (bb.x - s.x)),
-              xi.y + c1 * (xi.y - xp.y) + c2 * (di * (bb.y - s.y)));
-}
-
-__global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ sptr,
-                                                 const int *__restrict__ col,
-                                                 const double *__restrict__ val,
-                                                 const double *__restrict__ dinv,
-                                                 const double2 *__restrict__ b,
-                                                 const double2 *__restrict__ xk, double2 *xprev,
-                                                 double c1, double c2, int prev)
-{
-    const int row = xcd_block() * kBlock + threadIdx.x;
-    if (row >= n)
-        return;
-    const double2 s = sell_row(sptr, col, val, xk, row);
-    xprev[row] = cheb_update(s, b, xk, dinv, xprev, row, c1, c2, prev);
-}
-
-// first smoothing step from x = 0: x = c2 D^-1 b
-__global__ void __launch_bounds__(kBlock) k_cheb0(int n, const double *__restrict__ dinv,
-                                                  const double2 *__restrict__ b, double2 *x,
-                                                  double c2)
-{
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row >= n)
-        return;
-    const double2 bb = b[row];
-    const double di = dinv[row];
-    x[row] = d2(c2 * (di * bb.x), c2 * (di * bb.y));
-}
-
-// ---- the same operations with a group of GS lanes per row (CSR), for
-// matrices with long rows or few rows: lane l of the group takes entries
-// l, l + GS, ... of the row and the group adds its lanes with a fixed shuffle
-// tree.  Whole groups share a row, so they exit together.
-template <int GS>
-__device__ inline double2 row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
-                                  const double *__restrict__ v, const double2 *__restrict__ x,
-                                  int row, int lane)
-{
-    double ax = 0.0, ay = 0.0;
-    const int e = rp[row + 1];
-    for (int k = rp[row] + lane; k < e; k += GS) {
-        const double a = v[k];
-        const double2 xv = x[ci[k]];
-        ax += a * xv.x;
-        ay += a * xv.y;
-    }
-#pragma unroll
-    for (int off = GS / 2; off > 0; off >>= 1) {
-        ax += __shfl_down(ax, off, GS);
-        ay += __shfl_down(ay, off, GS);
-    }
-    return d2(ax, ay);
-}
-
-template <int GS, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict__ rp,
-                                                   const int *__restrict__ ci,
-                                                   const double *__restrict__ v,
-                                                   const double2 *__restrict__ x,
-                                                   const double2 *__restrict__ b, double2 *y)
-{
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int row = t / GS, lane = t % GS;
-    if (row >= n)
-        return;
-    const double2 s = row_dot<GS>(rp, ci, v, x, row, lane);
-    if (lane != 0)
-        return;
-    if (MODE == SP_SET) {
-        y[row] = s;
-    } else if (MODE == SP_ADD) {
-        const double2 o = y[row];
-        y[row] = d2(o.x + s.x, o.y + s.y);
-    } else {
-        const double2 bb = b[row];
-        y[row] = d2(bb.x - s.x, bb.y - s.y);
-    }
-}
-
-template <int GS>
-__global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict__ rp,
-                                                   const int *__restrict__ ci,
-                                                   const double *__restrict__ v,
-                                                   const double *__restrict__ dinv,
-                                                   const double2 *__restrict__ b,
-                                                   const double2 *__restrict__ xk, double2 *xprev,
-                                                   double c1, double c2, int prev)
-{
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int row = t / GS, lane = t % GS;
-    if (row >= n)
-        return;
-    const double2 s = row_dot<GS>(rp, ci, v, xk, row, lane);
-    if (lane != 0)
-        return;
-    xprev[row] = cheb_update(s, b, xk, dinv, xprev, row, c1, c2, prev);
-}
-
-// coarsest level: x = A^-1 b with the inverse stored row-major; one wave per
-// row, lane l takes columns l, l + 64, ..., the wave adds its lanes with a
-// fixed shuffle tree
-__global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
-                                                  const double2 *__restrict__ b, double2 *x)
-{
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (row >= n)
-        return;
-    const double *a = inv + (size_t)row * n;
-    double2 acc = d2(0.0, 0.0);
-    for (int j = lane; j < n; j += 64) {
-        const double v = a[j];
-        const double2 bv = b[j];
-        acc.x += v * bv.x;
-        acc.y += v * bv.y;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0)
-        x[row] = acc;
-}
-
-__global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const double2 *__restrict__ e, double2 *x)
-{
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row >= n)
-        return;
-    const double2 a = x[row], b = e[row];
-    x[row] = d2(a.x + b.x, a.y + b.y);
-}
-
-__global__ void __launch_bounds__(kBlock) k_copy(int n, const double2 *__restrict__ a, double2 *b)
-{
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row < n)
-        b[row] = a[row];
-}
-
-// ------------------------------------------------------------------ dot partials (pairs)
-__global__ void __launch_bounds__(kBlock) k_dot(int n, const double2 *__restrict__ a,
-                                                const double2 *__restrict__ b, double2 *part)
-{
-    __shared__ double2 sh[kBlock / 64];
-    double2 acc = d2(0.0, 0.0);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double2 x = a[i], y = b[i];
-        acc.x += x.x * y.x;
-        acc.y += x.y * y.y;
-    }
-    const double2 s = block_sum(acc, sh);
-    if (threadIdx.x == 0)
-        part[blockIdx.x] = s;
-}
-
-// ------------------------------------------------------------------ inner CG for As
-__device__ inline double2 ratio_or_zero(double2 num, double2 den)
-{
-    return d2(den.x != 0.0 ? num.x / den.x : 0.0, den.y != 0.0 ? num.y / den.y : 0.0);
-}
-
-// alpha = rz / dq from partials; first == 1: x = alpha d, r = b - alpha q
-// (x = 0 and r = b before the step), else x += alpha d, r -= alpha q
-__global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, double2 *x, double2 *r,
-                                                   const double2 *__restrict__ b,
-                                                   const double2 *__restrict__ d,
-                                                   const double2 *__restrict__ q,
-                                                   const double2 *__restrict__ rz_part,
-                                                   const double2 *__restrict__ dq_part, int G,
-                                                   int first)
-{
-    __shared__ double2 sc[2];
-    reduce_two(rz_part, dq_part, G, sc);
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    const double2 al = ratio_or_zero(sc[0], sc[1]);
-    const double2 dv = d[i], qv = q[i];
-    double2 xv = first ? d2(0.0, 0.0) : x[i];
-    double2 rv = first ? b[i] : r[i];
-    xv.x += al.x * dv.x;
-    xv.y += al.y * dv.y;
-    rv.x -= al.x * qv.x;
-    rv.y -= al.y * qv.y;
-    x[i] = xv;
-    r[i] = rv;
-}
-
-// d = z + beta d with beta = rz_new / rz_old (0 where rz_old == 0); first: d = z
-__global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const double2 *__restrict__ z, double2 *d,
-                                                    const double2 *__restrict__ new_part,
-                                                    const double2 *__restrict__ old_part, int G,
-                                                    int first)
-{
-    __shared__ double2 sc[2];
-    if (!first)
-        reduce_two(new_part, old_part, G, sc);
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n)
-        return;
-    const double2 zv = z[i];
-    if (first) {
-        d[i] = zv;
-        return;
-    }
-    const double2 be = ratio_or_zero(sc[0], sc[1]);
-    const double2 dv = d[i];
-    d[i] = d2(zv.x + be.x * dv.x, zv.y + be.y * dv.y);
-}
 
 // ------------------------------------------------------------------ saddle-point operator
 // y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
@@ -835,211 +468,9 @@ __global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, doubl
 }
 
 // ------------------------------------------------------------------ host helpers
-// partial-sum slots (kRedBlocks pairs each) in S.red
-constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlots = 82;
-
-inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
-
-void timer_mark(Solver &S, bool begin)
-{
-    Timer &T = S.timer;
-    if (T.used >= T.ev.size() && T.used >= 8192 && begin) {   // fold finished pairs
-        CHM_HIP(hipStreamSynchronize(S.stream));
-        for (size_t i = 0; i + 1 < T.used; i += 2) {
-            float ms = 0.f;
-            CHM_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
-            T.total_ms += ms;
-        }
-        T.used = 0;
-    }
-    if (T.used >= T.ev.size()) {   // grow the event pool
-        size_t old = T.ev.size();
-        T.ev.resize(old + 2048);
-        for (size_t i = old; i < T.ev.size(); ++i)
-            CHM_HIP(hipEventCreate(&T.ev[i]));
-    }
-    CHM_HIP(hipEventRecord(T.ev[T.used++], S.stream));
-}
-
-// y = A x / y += A x / y = b - A x with the kernel shape chosen for the matrix
-template <int MODE>
-void spmv_op(hipStream_t st, const Csr &C, const Sell &Sl, int gs, const double2 *x,
-             const double2 *b, double2 *y)
-{
-    const int n = C.n;
-    switch (gs) {
-    case 0:
-        k_spmv<MODE><<<nblk(n), kBlock, 0, st>>>(n, Sl.sptr, Sl.col, Sl.val, x, b, y);
-        break;
-    case 4:
-        k_spmv_v<4, MODE><<<nblk(4l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
-        break;
-    case 8:
-        k_spmv_v<8, MODE><<<nblk(8l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
-        break;
-    case 16:
-        k_spmv_v<16, MODE><<<nblk(16l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
-        break;
-    default:
-        k_spmv_v<32, MODE><<<nblk(32l * n), kBlock, 0, st>>>(n, C.rp, C.ci, C.v, x, b, y);
-        break;
-    }
-}
-
-// The event timer brackets each run of back-to-back smoothing launches on the
-// fine level of the As hierarchy (the pre- and post-smoothing sequences), so
-// the event overhead is spread over the launches of a run.
-bool timed_level(const Solver &S, const Hierarchy &H, int l)
-{
-    return S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
-}
-
-// one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
-void launch_cheb(Solver &S, Hierarchy &H, int l, const double2 *b, const double2 *xk,
-                 double2 *xprev, double c1, double c2, int prev)
-{
-    Level &L = H.lev[l];
-    const int n = L.n;
-    hipStream_t st = S.stream;
-    const bool timed = timed_level(S, H, l);
-    switch (L.gsA) {
-    case 0:
-        k_cheb<<<nblk(n), kBlock, 0, st>>>(n, L.sA.sptr, L.sA.col, L.sA.val, L.dinv, b, xk, xprev,
-                                           c1, c2, prev);
-        break;
-    case 4:
-        k_cheb_v<4><<<nblk(4l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk, xprev,
-                                                     c1, c2, prev);
-        break;
-    case 8:
-        k_cheb_v<8><<<nblk(8l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk, xprev,
-                                                     c1, c2, prev);
-        break;
-    case 16:
-        k_cheb_v<16><<<nblk(16l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk,
-                                                       xprev, c1, c2, prev);
-        break;
-    default:
-        k_cheb_v<32><<<nblk(32l * n), kBlock, 0, st>>>(n, L.A.rp, L.A.ci, L.A.v, L.dinv, b, xk,
-                                                       xprev, c1, c2, prev);
-        break;
-    }
-    if (timed) {
-        // algorithmic bytes: col + val per nonzero; per row x_k (gathered once),
-        // b, D^-1, x_{k-1} (when read) and the written x_{k+1}
-        S.timer.count += 1;
-        S.timer.bytes += 12ll * L.A.nnz + (prev ? 72ll : 56ll) * L.n;
-    }
-}
-
-void vcycle_level(Solver &S, Hierarchy &H, int l, const double2 *b, double2 *x)
-{
-    Level &L = H.lev[l];
-    hipStream_t st = S.stream;
-    if (l == H.nlev - 1) {
-        k_dense<<<nblk(L.n, kBlock / 64), kBlock, 0, st>>>(L.n, L.inv, b, x);
-        return;
-    }
-    const int deg = H.degree;
-    double2 *xt = H.xt[l], *r = H.r[l];
-    auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
-    auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
-    // Pre-smoothing from zero.  Every step after the first writes the buffer
-    // not holding the current iterate; 2 deg - 1 such steps follow the first,
-    // so starting in xt leaves the result in x.
-    k_cheb0<<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv, b, xt, c2(1));
-    double2 *cur = xt, *oth = x;
-    const bool timed = timed_level(S, H, l);
-    if (timed && deg >= 2)
-        timer_mark(S, true);
-    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
-        launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
-        std::swap(cur, oth);
-    }
-    if (timed && deg >= 2)
-        timer_mark(S, false);
-    spmv_op<SP_RESID>(st, L.A, L.sA, L.gsA, cur, b, r);
-    spmv_op<SP_SET>(st, L.R, L.sR, L.gsR, r, nullptr, H.b[l + 1]);
-    vcycle_level(S, H, l + 1, H.b[l + 1], H.x[l + 1]);
-    spmv_op<SP_ADD>(st, L.P, L.sP, L.gsP, H.x[l + 1], nullptr, cur);
-    if (timed)
-        timer_mark(S, true);
-    for (int k = 1; k <= deg; ++k) {
-        launch_cheb(S, H, l, b, cur, oth, c1(k), c2(k), k > 1 && !H.jacobi);
-        std::swap(cur, oth);
-    }
-    if (timed)
-        timer_mark(S, false);
-}
-
 inline double2 pair(const double *a) { return make_double2(a[0], a[1]); }
 
 }  // namespace
-
-void vcycle(Solver &S, Hierarchy &H, const double2 *b, double2 *x)
-{
-    vcycle_level(S, H, 0, b, x);
-}
-
-// stationary AMG solve of the mass matrix: x = V(b), then x += V(b - M x)
-void mass_solve(Solver &S, const double2 *b, double2 *x)
-{
-    Hierarchy &H = S.hM;
-    const int n = S.nv;
-    vcycle(S, H, b, x);
-    for (int c = 1; c < S.prm.amg_cycles; ++c) {
-        spmv_op<SP_RESID>(S.stream, H.lev[0].A, H.lev[0].sA, H.lev[0].gsA, x, b, S.mr);
-        vcycle(S, H, S.mr, S.me);
-        k_axpy_add<<<nblk(n), kBlock, 0, S.stream>>>(n, S.me, x);
-    }
-}
-
-// As solve of Algorithm 1: schur_pcg CG steps preconditioned by one V-cycle
-// (or amg_cycles stationary V-cycles when schur_pcg = 0)
-void schur_solve(Solver &S, const double2 *b, double2 *x)
-{
-    Hierarchy &H = S.hA;
-    const int n = S.nv, k = S.prm.schur_pcg;
-    hipStream_t st = S.stream;
-    const Level &L0 = H.lev[0];
-    if (k <= 0) {
-        vcycle(S, H, b, x);
-        for (int c = 1; c < S.prm.amg_cycles; ++c) {
-            spmv_op<SP_RESID>(st, L0.A, L0.sA, L0.gsA, x, b, S.mr);
-            vcycle(S, H, S.mr, S.me);
-            k_axpy_add<<<nblk(n), kBlock, 0, st>>>(n, S.me, x);
-        }
-        return;
-    }
-    double2 *r = S.pcg_r, *z = S.pcg_z, *d = S.pcg_d, *q = S.pcg_q;
-    const int G = red_blocks(n);
-    vcycle(S, H, b, z);                                            // z = V(b), r = b
-    k_dot<<<G, kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
-    k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
-    for (int it = 1; it <= k; ++it) {
-        spmv_op<SP_SET>(st, L0.A, L0.sA, L0.gsA, d, nullptr, q);
-        k_dot<<<G, kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
-        k_pcg_xr<<<nblk(n), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
-                                             slot(S, kSlotDq + it), G, it == 1);
-        if (it == k)
-            break;
-        vcycle(S, H, r, z);
-        k_dot<<<G, kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
-        k_pcg_dir<<<nblk(n), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
-                                              slot(S, kSlotRz + it - 1), G, 0);
-    }
-}
-
-// Algorithm 1 on a block vector: w1 = AMG(M) v1; w2 = As^-1 M As^-1 v2
-void apply_prec(Solver &S, const double2 *v, double2 *w)
-{
-    const int n = S.nv;
-    mass_solve(S, v, w);
-    schur_solve(S, v + n, S.tmp);
-    k_spmv<SP_SET><<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.tmp,
-                                                      nullptr, S.tmp2);
-    schur_solve(S, S.tmp2, w + n);
-}
 
 void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
@@ -1069,7 +500,7 @@ void compute_rhs(Solver &S)
             k_rhs_color<4><<<nblk(cnt), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb, S.qw, S.nq,
                                                          S.x, P, S.f, &S.ctl->clamped);
     }
-    k_spmv<SP_SET><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.x, nullptr, S.b);
+    k_spmv<SP_SET, double><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.x, nullptr, S.b);
     k_rhs_second<<<nblk(n), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());
 }
@@ -1087,14 +518,6 @@ void alloc_workspace(Solver &S)
     S.V = p.get<double2>(len * (S.m + 1));
     S.Z = p.get<double2>(len * S.m);
     S.f = p.get<double2>(n);
-    S.pcg_r = p.get<double2>(n);
-    S.pcg_z = p.get<double2>(n);
-    S.pcg_d = p.get<double2>(n);
-    S.pcg_q = p.get<double2>(n);
-    S.tmp = p.get<double2>(n);
-    S.tmp2 = p.get<double2>(n);
-    S.mr = p.get<double2>(n);
-    S.me = p.get<double2>(n);
     S.red = p.get<double2>((size_t)kSlots * kRedBlocks);
     S.gsp1 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
     S.gsp2 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
@@ -1195,9 +618,9 @@ int step_once(Solver &S, chm_stats_t *st_out)
     chm_stats_t stats{};
 
     compute_rhs(S);
-    k_dot<<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
+    k_dot<double><<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
     k_tol<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
-    k_copy<<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
+    k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
     fill_int(&S.ctl->nan, 0, 1, st);
 
     int total[2] = {0, 0};
@@ -1280,7 +703,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
     }
     stats.clamped = S.hctl->clamped;
     if (rc == CHM_OK) {
-        k_copy<<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.x);
+        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.x);
         if (S.prm.evap_ds > 0.0 && S.step_count < S.prm.evap_steps)
             k_evaporate<<<nblk(n), kBlock, 0, st>>>(n, S.x, S.prm.evap_ds);
         CHM_HIP(hipGetLastError());
