@@ -1,4 +1,5 @@
-"""Benchmark: time steps of the 512x512 P1 workload on one MI355X.
+"""Benchmark: time steps of the 512x512 P1 workload on one MI355X (or, with
+--workload box96, of the 96x96x48 tetrahedral box).
 
 One timed "step" is one time step of the whole per-step path: right-hand side
 (coloured quadrature of f' and M phi), FGMRES to 1e-8 relative residual for
@@ -41,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # Memory traffic of the timed kernel per launch (L2 <-> HBM/Infinity Cache) from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
 # scaled by what the same counters read for a 512 MB elementwise copy (FETCH_SIZE x 2.000,
-# WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Set to None whenever
-# the kernel changes until the counters are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = 39.89e6
+# WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Keyed by workload and
+# precision; None where the counters were not taken (or the kernel changed since).
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 39.89e6, ("square512", "fp32"): 23.65e6}
 
 
 def parse():
@@ -51,7 +52,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=512, help="squares per side of the unit square")
+    ap.add_argument("--workload", choices=("square512", "box96"), default="square512")
+    ap.add_argument("--n", type=int, default=512,
+                    help="squares per side of the unit square (square512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
     ap.add_argument("--kernel-steps", type=int, default=2,
@@ -76,9 +79,18 @@ def cpu_baseline(p, co, ce, php, phn):
     dof = 2 * co.shape[0]
     return {"value": dof * (its[0] + its[1]) / dt, "unit": "DOF*iters/s", "cores": 1,
             "kind": "oracle", "solves_per_s": 1.0 / dt, "iters": list(its),
-            "sample": f"1 time step of the {p['n'][0]}x{p['n'][1]} workload from the same initial "
+            "sample": f"1 time step of the {'x'.join(map(str, p['n']))} workload from the same initial "
                       f"state, plain C oracle (gcc -O2, one thread), its AMG setup excluded; "
                       f"{dt:.1f} s"}
+
+
+def describe(p, nv):
+    shape = "x".join(map(str, p["n"]))
+    dom = ("2D unit square" if p["dim"] == 2 else
+           "3D box " + "x".join(f"{e:g}" for e in p["extent"]) + ", Kuhn tetrahedra,")
+    evap = f"evaporation {p['evap_ds']:g}/step" if p["evap_ds"] > 0 else "no evaporation"
+    return (f"{dom} {shape} P1 ({nv} vertices, {2 * nv} unknowns per species), Flory-Huggins, "
+            f"{evap}, FGMRES rtol {p['rtol']:g}, FP64")
 
 
 def timed_run(g, php, phn, warmup, steps, label):
@@ -115,12 +127,16 @@ def main():
     import synthetic as S
     from paper_2204_03575_amd import Solver
 
-    p = S.preset("square512", n=(args.n, args.n))
+    if args.workload == "square512":
+        p = S.preset("square512", n=(args.n, args.n))
+    else:
+        p = S.preset("box96")
     co, ce = S.make_mesh(p)
     nv = co.shape[0]
     php, phn, _ = S.initial_fractions(nv, p["mean_p"], p["mean_n"])
     torch.cuda.init()
-    print(f"# setup {args.n}x{args.n} ({nv} vertices)", file=sys.stderr, flush=True)
+    shape = "x".join(map(str, p["n"]))
+    print(f"# setup {shape} ({nv} vertices)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     g = Solver(co, ce, p)
     torch.cuda.synchronize()
@@ -136,9 +152,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D unit square {args.n}x{args.n} P1 ({nv} vertices, "
-                               f"{2 * nv} unknowns per species), Flory-Huggins, "
-                               f"evaporation 0.0025/step, FGMRES rtol 1e-8, FP64",
+        "config": {"workload": describe(p, nv),
                    "global_batch": 2, "parallelism": "none"},
         "solves_per_s": args.steps / dt,
         "fgmres_iters_per_step": [list(s["iters"]) for s in stats],
@@ -166,8 +180,10 @@ def main():
             gm.timer_enable(0, False)
             avg_s = ms * 1e-3 / max(1, launches)
             achieved = nbytes / max(1, launches) / avg_s / 1e9 if avg_s > 0 else 0.0
+            traffic = (TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, "fp32"))
+                       if args.n == 512 else None)
             out["mixed"]["k_cheb_fp32"] = {"achieved": achieved, "unit": "GB/s",
-                                           "frac": achieved / HBM_PEAK_GBS,
+                                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                                            "avg_us": avg_s * 1e6, "launches": launches,
                                            "bytes_per_launch": nbytes / max(1, launches)}
         del gm
@@ -179,7 +195,7 @@ def main():
         avg_s = ms * 1e-3 / max(1, launches)
         per_launch = nbytes / max(1, launches)
         achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-        traffic = TRAFFIC_BYTES_PER_LAUNCH
+        traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, "fp64")) if args.n == 512 else None
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": "k_cheb (fine level, As hierarchy)",

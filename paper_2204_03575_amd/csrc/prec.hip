@@ -90,28 +90,27 @@ __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ d
     x[row] = mk<T>(c2 * (di * bb.x), c2 * (di * bb.y));
 }
 
-// coarsest level: x = A^-1 b with the FP64 inverse stored row-major; one wave
-// per row, lane l takes columns l, l + 64, ..., the wave adds its lanes with a
-// fixed shuffle tree (FP64 sums in both precisions)
+// coarsest level: x = A^-1 b with the FP64 inverse stored row-major.  One
+// block per row: thread t takes columns t, t + 256, ... (coalesced reads of the
+// row; b stays in L2), then a fixed wave-shuffle and LDS tree; FP64 sums in
+// both precisions.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
                                                   const pair_t<T> *__restrict__ b, pair_t<T> *x)
 {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (row >= n)
-        return;
+    __shared__ double2 sh[kBlock / 64];
+    const int row = blockIdx.x;
     const double *a = inv + (size_t)row * n;
     double2 acc = d2(0.0, 0.0);
-    for (int j = lane; j < n; j += 64) {
+    for (int j = threadIdx.x; j < n; j += kBlock) {
         const double v = a[j];
         const pair_t<T> bv = b[j];
         acc.x += v * double(bv.x);
         acc.y += v * double(bv.y);
     }
-    acc = wave_sum(acc);
-    if (lane == 0)
-        x[row] = mk<T>(T(acc.x), T(acc.y));
+    const double2 s = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        x[row] = mk<T>(T(s.x), T(s.y));
 }
 
 template <class T>
@@ -286,7 +285,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     const Level &L = H.lev[l];
     hipStream_t st = S.stream;
     if (l == H.nlev - 1) {
-        k_dense<T><<<nblk(L.n, kBlock / 64), kBlock, 0, st>>>(L.n, L.inv, b, x);
+        k_dense<T><<<L.n, kBlock, 0, st>>>(L.n, L.inv, b, x);
         return;
     }
     const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
