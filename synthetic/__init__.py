@@ -127,6 +127,26 @@ def initial_fractions(n_vertices: int, mean_p: float, mean_n: float,
             np.ascontiguousarray(raw[:, 2]))
 
 
+NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))   # (c_in, c_out) of the 3x3 layers
+
+
+def net_init(seed: int = BASE_SEED + 7, zero_last: bool = True, bias_scale: float = 0.0):
+    """Seeded FP32 parameters [(w [3, 3, c_in, c_out], b [c_out]), ...] of the
+    guess network: w uniform in +-sqrt(6 / (9 c_in)) (He-uniform), biases
+    uniform in +-bias_scale; the last layer zero when ``zero_last``."""
+    params = []
+    for k, (ci, co) in enumerate(NET_LAYERS):
+        u = uniform01(seed + 1000 * k, 9 * ci * co + co)
+        a = np.sqrt(6.0 / (9 * ci))
+        w = ((2.0 * u[:9 * ci * co] - 1.0) * a).reshape(3, 3, ci, co).astype(np.float32)
+        b = ((2.0 * u[9 * ci * co:] - 1.0) * bias_scale).astype(np.float32)
+        if zero_last and k == len(NET_LAYERS) - 1:
+            w[:] = 0.0
+            b[:] = 0.0
+        params.append((w, b))
+    return params
+
+
 # Parameter presets.  Values the paper states (Section 4): chi_pn=1,
 # chi_ps=chi_ns=0.3, N_p=N_n=20, N_s=1, eps=1e-3, tau between 1e-7 and 1e-4.
 _COMMON = dict(
