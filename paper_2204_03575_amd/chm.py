@@ -27,7 +27,14 @@ ENTRY_POINTS = [
     "chm_last_error", "chm_nnz", "chm_get_matrix", "chm_num_levels", "chm_level_info",
     "chm_level_get", "chm_vcycle", "chm_schur_solve", "chm_apply_saddle", "chm_apply_prec",
     "chm_rhs", "chm_quadrature", "chm_timer_enable", "chm_timer_read", "chm_setup_info",
+    "chm_net_create", "chm_net_destroy", "chm_net_last_error", "chm_net_set_params",
+    "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
+    "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
 ]
+
+NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
+NET_NPARAMS = sum(9 * ci * co + co for ci, co in NET_LAYERS)
+GUESS_MODES = {"previous": 0, "linear": 1, "learned": 2}
 
 
 class ChmError(RuntimeError):
@@ -58,7 +65,7 @@ class chm_params_t(C.Structure):
 
 class chm_stats_t(C.Structure):
     _fields_ = [("iters", C.c_int32 * 2), ("relres", C.c_double * 2), ("status", C.c_int32),
-                ("clamped", C.c_int32), ("t_step_ms", C.c_double)]
+                ("clamped", C.c_int32), ("t_step_ms", C.c_double), ("guess_used", C.c_int32 * 2)]
 
 
 _lib = None
@@ -94,6 +101,20 @@ def library():
             "chm_timer_enable": ([vp, i32, i32], C.c_int),
             "chm_timer_read": ([vp, P(i64), P(d), P(i64)], C.c_int),
             "chm_setup_info": ([vp, P(d), P(i64), P(i64)], C.c_int),
+            "chm_net_create": ([i64, vp, P(vp)], C.c_int),
+            "chm_net_destroy": ([vp], C.c_int),
+            "chm_net_last_error": ([vp], C.c_char_p),
+            "chm_net_set_params": ([vp, vp], C.c_int),
+            "chm_net_get_params": ([vp, vp], C.c_int),
+            "chm_net_features": ([vp, i32, i32, vp, vp, vp, vp], C.c_int),
+            "chm_net_forward": ([vp, i32, i32, i32, vp, vp], C.c_int),
+            "chm_net_gradients": ([vp, i32, i32, i32, vp, vp, vp, vp, P(d)], C.c_int),
+            "chm_net_adam": ([vp, vp, C.c_float], C.c_int),
+            "chm_net_guess": ([vp, i32, i32, vp, vp, vp], C.c_int),
+            "chm_net_train_step": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, C.c_float,
+                                    P(d)], C.c_int),
+            "chm_set_guess": ([vp, i32, vp, i32, i32], C.c_int),
+            "chm_get_state": ([vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -202,7 +223,8 @@ class Solver:
         st = (chm_stats_t * max(1, nsteps))()
         rc = self.lib.chm_step(self.h, nsteps, st)
         stats = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
-                      status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms)
+                      status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms,
+                      guess_used=(s.guess_used[0], s.guess_used[1]))
                  for s in st[:nsteps]]
         if rc != CHM_OK:
             msg = self.lib.chm_last_error(self.h)
@@ -210,6 +232,17 @@ class Solver:
             err.stats = stats
             raise err
         return stats
+
+    def set_guess(self, mode: str, net=None, H: int = 0, W: int = 0):
+        rc = self.lib.chm_set_guess(self.h, GUESS_MODES[mode], net.h if net is not None else None,
+                                    H, W)
+        _check(self.h, rc, "chm_set_guess")
+
+    def get_state(self):
+        """The state vector (4 n doubles, solver block layout) as a CUDA tensor."""
+        out = self.torch.empty(4 * self.nv, dtype=self.torch.float64, device="cuda")
+        _check(self.h, self.lib.chm_get_state(self.h, _dev_ptr(out)), "chm_get_state")
+        return out
 
     # ---- inspection
     def nnz(self) -> int:
@@ -320,3 +353,127 @@ class Solver:
         ms, lm, la = C.c_double(), C.c_int64(), C.c_int64()
         self.lib.chm_setup_info(self.h, C.byref(ms), C.byref(lm), C.byref(la))
         return dict(setup_ms=ms.value, levels_mass=lm.value, levels_as=la.value)
+
+
+# ---------------------------------------------------------------- learned guess
+def flatten_params(params) -> np.ndarray:
+    """[(w [3, 3, ci, co], b [co]), ...] -> the flat FP32 parameter layout."""
+    out = []
+    for (w, b), (ci, co) in zip(params, NET_LAYERS):
+        w = np.asarray(w, dtype=np.float32)
+        b = np.asarray(b, dtype=np.float32)
+        assert w.shape == (3, 3, ci, co) and b.shape == (co,)
+        out += [w.ravel(), b.ravel()]
+    flat = np.concatenate(out)
+    assert flat.size == NET_NPARAMS
+    return np.ascontiguousarray(flat)
+
+
+def unflatten_params(flat) -> list:
+    flat = np.asarray(flat, dtype=np.float32)
+    out, k = [], 0
+    for ci, co in NET_LAYERS:
+        w = flat[k:k + 9 * ci * co].reshape(3, 3, ci, co).copy()
+        k += 9 * ci * co
+        b = flat[k:k + co].copy()
+        k += co
+        out.append((w, b))
+    return out
+
+
+class Net:
+    """One chm_net_t (the guess network) on the current torch stream.
+    Tensors passed in are torch CUDA tensors; marshalling only."""
+
+    def __init__(self, max_pixels: int, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        rc = self.lib.chm_net_create(int(max_pixels), C.c_void_p(stream), C.byref(h))
+        if rc != CHM_OK:
+            msg = self.lib.chm_net_last_error(None)
+            raise ChmError(rc, f"chm_net_create: {msg.decode() if msg else ''}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chm_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != CHM_OK:
+            msg = self.lib.chm_net_last_error(self.h)
+            raise ChmError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_params(self, params):
+        flat = params if isinstance(params, np.ndarray) else flatten_params(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(self.lib.chm_net_set_params(self.h, flat.ctypes.data_as(C.c_void_p)),
+                    "chm_net_set_params")
+
+    def get_params(self, flat: bool = False):
+        out = np.zeros(NET_NPARAMS, np.float32)
+        self._check(self.lib.chm_net_get_params(self.h, out.ctypes.data_as(C.c_void_p)),
+                    "chm_net_get_params")
+        return out if flat else unflatten_params(out)
+
+    def features(self, H: int, W: int, x2, x1):
+        torch = self.torch
+        feats = torch.empty((H, W, 8), dtype=torch.float32, device="cuda")
+        sigma = np.zeros(4)
+        self._check(self.lib.chm_net_features(self.h, H, W, _dev_ptr(x2), _dev_ptr(x1),
+                                              _dev_ptr(feats), sigma.ctypes.data_as(C.c_void_p)),
+                    "chm_net_features")
+        return feats, sigma
+
+    def forward(self, feats):
+        torch = self.torch
+        feats = feats.contiguous()
+        B, h, w, _ = feats.shape
+        y = torch.empty((B, h, w, 4), dtype=torch.float32, device="cuda")
+        self._check(self.lib.chm_net_forward(self.h, B, h, w, _dev_ptr(feats), _dev_ptr(y)),
+                    "chm_net_forward")
+        return y
+
+    def gradients(self, feats, target, mask):
+        feats, target = feats.contiguous(), target.contiguous()
+        mask = mask.to(self.torch.uint8).contiguous()
+        B, h, w, _ = feats.shape
+        g = np.zeros(NET_NPARAMS, np.float32)
+        loss = C.c_double()
+        self._check(self.lib.chm_net_gradients(self.h, B, h, w, _dev_ptr(feats), _dev_ptr(target),
+                                               _dev_ptr(mask), g.ctypes.data_as(C.c_void_p),
+                                               C.byref(loss)), "chm_net_gradients")
+        return unflatten_params(g), loss.value
+
+    def adam(self, grads, lr: float):
+        flat = grads if isinstance(grads, np.ndarray) else flatten_params(grads)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(self.lib.chm_net_adam(self.h, flat.ctypes.data_as(C.c_void_p), float(lr)),
+                    "chm_net_adam")
+
+    def guess(self, H: int, W: int, x2, x1):
+        out = self.torch.empty_like(x1)
+        self._check(self.lib.chm_net_guess(self.h, H, W, _dev_ptr(x2), _dev_ptr(x1), _dev_ptr(out)),
+                    "chm_net_guess")
+        return out
+
+    def train_step(self, H: int, W: int, crop_h: int, crop_w: int, x2s, x1s, x0s, oy, ox,
+                   lr: float) -> float:
+        B = len(x2s)
+        arr = lambda ts: (C.c_void_p * B)(*[t.data_ptr() for t in ts])
+        oy = np.ascontiguousarray(oy, dtype=np.int32)
+        ox = np.ascontiguousarray(ox, dtype=np.int32)
+        loss = C.c_double()
+        self._check(self.lib.chm_net_train_step(self.h, B, H, W, crop_h, crop_w, arr(x2s), arr(x1s),
+                                                arr(x0s), oy.ctypes.data_as(C.c_void_p),
+                                                ox.ctypes.data_as(C.c_void_p), float(lr),
+                                                C.byref(loss)), "chm_net_train_step")
+        return loss.value
+

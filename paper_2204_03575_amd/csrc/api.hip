@@ -184,6 +184,7 @@ int chm_set_fields(chm_solver_t *h, const double *phi_p, const double *phi_n, co
             copy_field(mu, n, 0, mu_p, on_device, S.stream);
         if (mu_n)
             copy_field(mu, n, 1, mu_n, on_device, S.stream);
+        S.hist = false;   // a new state has no previous step
         CHM_HIP(hipStreamSynchronize(S.stream));
         return CHM_OK;
     });
@@ -472,6 +473,42 @@ int chm_setup_info(const chm_solver_t *h, double *setup_ms, int64_t *levels_m, i
     if (levels_as)
         *levels_as = h->s.hA.nlev;
     return CHM_OK;
+}
+
+int chm_set_guess(chm_solver_t *h, int32_t mode, chm_net_t *net, int32_t H, int32_t W)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_set_guess: NULL handle");
+    chm::Solver &S = h->s;
+    if (mode != CHM_GUESS_PREVIOUS && mode != CHM_GUESS_LINEAR && mode != CHM_GUESS_LEARNED)
+        return fail(h, CHM_EINVAL, "chm_set_guess: unknown mode");
+    if (mode == CHM_GUESS_LEARNED) {
+        if (!net)
+            return fail(h, CHM_EINVAL, "chm_set_guess: the learned guess needs a network");
+        if (S.dim != 2 || H < 2 || W < 2 || (int64_t)H * W != S.nv)
+            return fail(h, CHM_EINVAL, "chm_set_guess: the learned guess needs a 2D H x W vertex "
+                                       "grid with H * W = n_vertices");
+        if ((long long)H * W > chm::net_max_pixels(net))
+            return fail(h, CHM_EINVAL, "chm_set_guess: the grid exceeds the network's max_pixels");
+    }
+    S.guess_mode = mode;
+    S.net = mode == CHM_GUESS_LEARNED ? net : nullptr;
+    S.gH = H;
+    S.gW = W;
+    return CHM_OK;
+}
+
+int chm_get_state(chm_solver_t *h, double *state)
+{
+    if (!h || !state)
+        return fail(h, CHM_EINVAL, "chm_get_state: bad arguments");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        CHM_HIP(hipMemcpyAsync(state, S.x, sizeof(double2) * 2 * (size_t)S.nv,
+                               hipMemcpyDeviceToDevice, S.stream));
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
 }
 
 }  // extern "C"

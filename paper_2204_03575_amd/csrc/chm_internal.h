@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/chm.h"
+#include "../../include/chm_net.h"
 
 namespace chm {
 
@@ -180,7 +181,7 @@ struct Ctl {
     int k[2];            // Arnoldi steps of the species in this cycle
     int clamped;         // log-argument clamps in the last right-hand side
     int nan;             // a non-finite value was seen
-    int pad[2];
+    int guess_used[2];   // the step started from the guess candidate
     // large part
     double H[2][(kMaxRestart + 1) * kMaxRestart];
     double cs[2][kMaxRestart], sn[2][kMaxRestart];
@@ -249,6 +250,12 @@ struct Solver {
     // captured on a library-owned stream and launched on `stream`
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> iter_graphs;
+    // initial guess of each Krylov solve (CHM_GUESS_*)
+    int guess_mode = 0;
+    chm_net *net = nullptr;
+    int gH = 0, gW = 0;
+    double2 *xhist = nullptr;  // state at the start of the previous step
+    bool hist = false;         // xhist holds it
 };
 
 // ---- util.hip
@@ -273,6 +280,12 @@ void prec_setup(Solver &S);   // FP32 copies and work vectors (mixed precision)
 void vcycle(Solver &S, int hier, const double2 *b, double2 *x);
 void schur_solve(Solver &S, const double2 *b, double2 *x);
 void apply_prec(Solver &S, const double2 *v, double2 *w);
+
+// ---- net.hip
+long long net_max_pixels(const chm_net *net);
+// the network's guess (device state vectors, solver layout) on stream st
+void net_guess_on(chm_net *net, hipStream_t st, int H, int W, const double *x2, const double *x1,
+                  double *out);
 
 // ---- solve.hip
 void alloc_workspace(Solver &S);

@@ -467,6 +467,39 @@ __global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, doubl
     phi[i] = v;
 }
 
+// ------------------------------------------------------------------ initial guess
+// xg = x + (x - xh): linear extrapolation of the last increment
+__global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *__restrict__ xh,
+                                                        const double2 *__restrict__ x, double2 *xg)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len)
+        return;
+    const double2 a = x[i], h = xh[i];
+    xg[i] = d2(a.x + (a.x - h.x), a.y + (a.y - h.y));
+}
+
+// Per species, keep the candidate xg where its squared residual norm (partials
+// pg) is below the previous state's (partials px), else take x; a non-finite
+// candidate norm never wins.  Records the choice in the control block.
+__global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *__restrict__ x,
+                                                       double2 *xg, const double2 *__restrict__ pg,
+                                                       const double2 *__restrict__ px, int G, Ctl *c)
+{
+    __shared__ double2 sc[2];
+    reduce_two(pg, px, G, sc);
+    const bool ux = sc[0].x < sc[1].x, uy = sc[0].y < sc[1].y;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        c->guess_used[0] = ux;
+        c->guess_used[1] = uy;
+    }
+    if (i >= len)
+        return;
+    const double2 g = xg[i], p = x[i];
+    xg[i] = d2(ux ? g.x : p.x, uy ? g.y : p.y);
+}
+
 // ------------------------------------------------------------------ host helpers
 inline double2 pair(const double *a) { return make_double2(a[0], a[1]); }
 
@@ -513,6 +546,7 @@ void alloc_workspace(Solver &S)
     S.m = S.prm.restart;
     S.x = p.get<double2>(len);
     S.xk = p.get<double2>(len);
+    S.xhist = p.get<double2>(len);
     S.b = p.get<double2>(len);
     S.r = p.get<double2>(len);
     S.V = p.get<double2>(len * (S.m + 1));
@@ -620,7 +654,25 @@ int step_once(Solver &S, chm_stats_t *st_out)
     compute_rhs(S);
     k_dot<double><<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
     k_tol<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
-    k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
+    if (S.guess_mode != CHM_GUESS_PREVIOUS && S.hist) {
+        // candidate start: linear extrapolation or the network's guess; each
+        // species keeps it only if its residual is smaller than the previous
+        // state's
+        if (S.guess_mode == CHM_GUESS_LINEAR)
+            k_extrapolate<<<nblk(len), kBlock, 0, st>>>(len, S.xhist, S.x, S.xk);
+        else
+            net_guess_on(S.net, st, S.gH, S.gW, reinterpret_cast<const double *>(S.xhist),
+                         reinterpret_cast<const double *>(S.x), reinterpret_cast<double *>(S.xk));
+        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b,
+                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotRg));
+        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.x, S.b,
+                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotR));
+        k_pick_guess<<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk, slot(S, kSlotRg),
+                                                   slot(S, kSlotR), Gn, S.ctl);
+    } else {
+        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
+        fill_int(S.ctl->guess_used, 0, 2, st);
+    }
     fill_int(&S.ctl->nan, 0, 1, st);
 
     int total[2] = {0, 0};
@@ -702,7 +754,11 @@ int step_once(Solver &S, chm_stats_t *st_out)
         }
     }
     stats.clamped = S.hctl->clamped;
+    stats.guess_used[0] = S.hctl->guess_used[0];
+    stats.guess_used[1] = S.hctl->guess_used[1];
     if (rc == CHM_OK) {
+        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xhist);   // becomes x^{n-2}
+        S.hist = true;
         k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.x);
         if (S.prm.evap_ds > 0.0 && S.step_count < S.prm.evap_steps)
             k_evaporate<<<nblk(n), kBlock, 0, st>>>(n, S.x, S.prm.evap_ds);

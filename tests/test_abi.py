@@ -1,5 +1,5 @@
 """CPU-side checks of the C ABI: the library loads, every entry point declared
-in include/chm.h is exported, and the host-only quadrature routine is exact."""
+in include/*.h is exported, and the host-only quadrature routine is exact."""
 import ctypes
 import itertools
 import math
@@ -13,8 +13,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    with open(os.path.join(ROOT, "include", "chm.h")) as f:
-        text = f.read()
+    text = ""
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            with open(os.path.join(ROOT, "include", name)) as f:
+                text += f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(chm_[a-z_]+)\s*\(", text)))
 
