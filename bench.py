@@ -1,5 +1,6 @@
 """Benchmark: time steps of the 512x512 P1 workload on one MI355X (or, with
---workload box96, of the 96x96x48 tetrahedral box).
+--workload box96, of the 96x96x48 tetrahedral box; with --workload guess256,
+500-step runs on a 256x256 square comparing the starts of the Krylov solve).
 
 One timed "step" is one time step of the whole per-step path: right-hand side
 (coloured quadrature of f' and M phi), FGMRES to 1e-8 relative residual for
@@ -52,7 +53,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("square512", "box96"), default="square512")
+    ap.add_argument("--workload", choices=("square512", "box96", "guess256"), default="square512")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2204_03575_amd", "weights",
+                                                      "guess256.npy"),
+                    help="trained guess network (guess256 workload)")
     ap.add_argument("--n", type=int, default=512,
                     help="squares per side of the unit square (square512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,6 +118,71 @@ def field_diff(a, b):
                for f in ("phi_p", "phi_n", "mu_p", "mu_n"))
 
 
+GUESS_MODES = (("fp64", "previous"), ("fp64", "linear"), ("fp64", "learned"),
+               ("fp32", "previous"), ("fp32", "linear"), ("fp32", "learned"))
+
+
+def guess_main(args):
+    """500-step runs of a held-out evaporation run on the 256x256 square with
+    every start mode and both preconditioner precisions; the FP64 run from the
+    previous state is the reference."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2204_03575_amd import Net, Solver
+    from paper_2204_03575_amd import guess_train as T
+    n, steps = 256, args.steps if args.steps != 10 else 500
+    params = np.load(args.weights)   # a plain float32 array written by guess_train
+    p, seed = T.run_params(n, 1000, 20220500)   # outside the training runs (0..39)
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    H = W = n + 1
+    php, phn, _ = S.initial_fractions(nv, p["mean_p"], p["mean_n"], seed=seed)
+    torch.cuda.init()
+    net = Net(H * W)
+    net.set_params(params)
+    modes, ref = {}, None
+    for prec, guess in GUESS_MODES:
+        g = Solver(co, ce, dict(p, precision=prec))
+        g.set_fields(php, phn)
+        g.set_guess(guess, net if guess == "learned" else None, H, W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        f = g.get_fields()
+        its = np.array([s["iters"] for s in stats])
+        used = np.array([s["guess_used"] for s in stats]).ravel()
+        key = f"{prec}+{guess}"
+        modes[key] = {"solves_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+                      "dof_iters_per_s": 2 * nv * int(its.sum()) / dt,
+                      "iters_per_species_step": float(its.mean()),
+                      "max_relres": max(max(s["relres"]) for s in stats),
+                      "start_chosen": {k: int((used == i).sum()) for i, k in
+                                       enumerate(("previous", "linear", "learned"))}}
+        if ref is None:
+            ref = f
+        modes[key]["field_rel_diff_vs_fp64_previous"] = field_diff(f, ref)
+        print(f"# {key}: {modes[key]}", file=sys.stderr, flush=True)
+        del g
+    base = modes["fp64+previous"]
+    for m in modes.values():
+        m["speedup_solves_vs_fp64_previous"] = m["solves_per_s"] / base["solves_per_s"]
+    out = {"metric": METRIC, "value": modes["fp32+learned"]["solves_per_s"], "unit": "solves/s",
+           "n_gpus": 1, "steps": steps, "warmup": 0,
+           "ms_per_step": modes["fp32+learned"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32 preconditioner+bf16 network",
+           "data": "synthetic",
+           "config": {"workload": describe(p, nv) + f", chi_pn {p['chi_pn']:.3f}, "
+                                  f"{steps} steps, learned start from {os.path.basename(args.weights)}",
+                      "global_batch": 2, "parallelism": "none"},
+           "mixed_learned_vs_fp64_solves": modes["fp32+learned"]["speedup_solves_vs_fp64_previous"],
+           "modes": modes}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -121,6 +190,9 @@ def main():
                                    "part of this build (see DESIGN.md for how it would shard)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "guess256":
+        guess_main(args)
+        return
     import numpy as np
     import torch
 

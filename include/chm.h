@@ -116,8 +116,9 @@ typedef struct {
     int32_t status;        /* CHM_OK or the step's error code */
     int32_t clamped;       /* clamped log arguments in the right-hand side */
     double t_step_ms;      /* wall time of the step on the stream */
-    int32_t guess_used[2]; /* 1: the species started from the chm_set_guess candidate
-                              (see chm_net.h), 0: from the previous state */
+    int32_t guess_used[2]; /* CHM_GUESS_* (chm_net.h) of the start each species'
+                              solve used: 0 the previous state */
+    double res0[2];        /* relative residual of that start per species */
 } chm_stats_t;
 
 /* Build the solver: upload the mesh, colour the cells, assemble M and K by

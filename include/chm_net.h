@@ -12,7 +12,8 @@
  * of the four fields, 4 * H * W doubles: [2v] phi_p, [2v + 1] phi_n,
  * [2 H W + 2v] mu_p, [2 H W + 2v + 1] mu_n.
  *
- * Features (8 channels) from the states x2 (step n-2) and x1 (step n-1):
+ * Features (8 channels) from the states x2 (step n-2) and x1 (step n-1),
+ * in the solver: the solutions of the solves of those steps (chm_set_guess):
  * d = x1 - x2 divided by its root mean square per field (sigma_c), and
  * x1 minus its mean divided by the root mean square of that (tau_c); a zero
  * root mean square gives zero features.  Each feature is rounded FP64 ->
@@ -34,8 +35,15 @@
  * followed by b[c_out].
  *
  * Training: the target is t_c = (x0_c - x1_c - d_c) / sigma_c for the
- * solution x0 at step n; the loss is the mean of (y - t)^2 over the 4
- * channels and the unmasked vertices; gradients of the loss and of every
+ * solution x0 at step n; the loss is the mean over the samples s of a batch
+ * of w_s times the mean of (y - t)^2 over the 4 channels and the unmasked
+ * vertices of s, with w_s = 1 / (q_s + 1e-4) and q_s the mean of t^2 over
+ * the whole grid and the 4 channels (each sample counts by its error
+ * relative to its own target), plus smooth times the same mean of
+ * (e_p - e_q)^2 over neighbouring pixel pairs p, q (horizontal and vertical,
+ * both unmasked), e = y - t, so that a rough error costs more than a smooth
+ * one of the same size (a rough start costs the Krylov solve more
+ * iterations); gradients of the loss and of every
  * activation are rounded to BF16, weight gradients are FP32 sums; Adam
  * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) updates FP32 master
  * parameters.  Training runs on crops of the grid, each padded like the
@@ -64,8 +72,8 @@ extern "C" {
 
 /* Initial guess of each step's Krylov solve (chm_set_guess). */
 #define CHM_GUESS_PREVIOUS 0   /* the state of the previous step */
-#define CHM_GUESS_LINEAR 1     /* 2 x1 - x2 */
-#define CHM_GUESS_LEARNED 2    /* the network's guess */
+#define CHM_GUESS_LINEAR 1     /* linear extrapolation 2 y1 - y2 */
+#define CHM_GUESS_LEARNED 2    /* the network's guess (or linear extrapolation) */
 
 typedef struct chm_net chm_net_t;
 
@@ -94,10 +102,13 @@ int chm_net_forward(chm_net_t *net, int32_t batch, int32_t h, int32_t w, const f
 
 /* Loss and parameter gradients (host, CHM_NET_NPARAMS FP32 values, the layout
  * of the parameters) for device features [batch][h][w][8], targets
- * [batch][h][w][4] (FP32) and mask [batch][h][w] (0 or 1).  loss may be NULL.
- * The parameters are not changed. */
+ * [batch][h][w][4] (FP32), mask [batch][h][w] (0 or 1), host sample
+ * weights[batch] (NULL: all 1) and the neighbour-difference weight smooth
+ * (>= 0, see the loss above).  loss may be NULL.  The parameters are not
+ * changed. */
 int chm_net_gradients(chm_net_t *net, int32_t batch, int32_t h, int32_t w, const float *feats,
-                      const float *target, const uint8_t *mask, float *grads, double *loss);
+                      const float *target, const uint8_t *mask, const double *weights,
+                      float smooth, float *grads, double *loss);
 
 /* One Adam step with host gradients grads[CHM_NET_NPARAMS] and step size lr. */
 int chm_net_adam(chm_net_t *net, const float *grads, float lr);
@@ -111,27 +122,36 @@ int chm_net_guess(chm_net_t *net, int32_t H, int32_t W, const double *x2, const 
  * vectors x2[i], x1[i], x0[i] (steps n-2, n-1, n of one run on the H x W
  * grid; the arrays of pointers are host arrays), the crop of crop_h x crop_w
  * vertices with top-left vertex (oy[i], ox[i]); features, targets and masks
- * as above, forward, loss, backward and one Adam step with step size lr.
- * loss (may be NULL) receives the batch loss before the step. */
+ * as above, forward, loss (neighbour-difference weight smooth), backward and
+ * one Adam step with step size lr.  loss (may be NULL) receives the batch
+ * loss before the step. */
 int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int32_t crop_h,
                        int32_t crop_w, const double *const *x2, const double *const *x1,
                        const double *const *x0, const int32_t *oy, const int32_t *ox, float lr,
-                       double *loss);
+                       float smooth, double *loss);
 
-/* Choose how chm_step starts each Krylov solve (CHM_GUESS_*).  LINEAR and
- * LEARNED need the states of the two previous steps, so the first step after
- * chm_create or chm_set_fields starts from the previous state.  Each species
- * starts from the candidate only where its residual norm is smaller than the
- * previous state's, else from the previous state (chm_stats_t.guess_used).
+/* Choose how chm_step starts each Krylov solve (CHM_GUESS_*).  The
+ * candidates are built from the last two solutions of the solve, y_{n-2} and
+ * y_{n-1} (taken before the solvent removal, so that they extrapolate to the
+ * next solution and not to the next stored state; the state set by
+ * chm_set_fields counts as a solution), so the first step after chm_create or
+ * chm_set_fields starts from the previous state.  LINEAR offers the linear
+ * extrapolation 2 y_{n-1} - y_{n-2}, LEARNED that and the network's guess;
+ * each species starts from whichever of the offered candidates and the
+ * previous state has the smallest residual norm (ties: the simpler one;
+ * chm_stats_t.guess_used and .res0 report the choice).
  * LEARNED needs net (used on the solver's stream, kept by the caller until
  * replaced or the solver is destroyed) and a structured mesh with
  * H * W = n_vertices in the vertex order described above (H, W >= 2, at most
  * the network's max_pixels). */
 int chm_set_guess(chm_solver_t *s, int32_t mode, chm_net_t *net, int32_t H, int32_t W);
 
-/* Copy the current state vector (4 n_vertices doubles, layout above) into
- * device memory. */
-int chm_get_state(chm_solver_t *s, double *state);
+/* Copy a state vector (4 n_vertices doubles, layout above) into device
+ * memory: which = 0 the current state, 1 the last solution of the solve (the
+ * current state before the solvent removal of the last step; the state set by
+ * chm_set_fields before the first step).  The learned guess is trained on the
+ * sequence of solutions (which = 1). */
+int chm_get_state(chm_solver_t *s, int32_t which, double *state);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,14 @@ What is computed (the conventions the GPU kernels follow):
   increment plus a learned correction measured in units of the previous
   increment.  With a zero last layer the guess is linear extrapolation.
 * Training target: t_c = (x0_c - x1_c - d_c) / sigma_c for the solution x0
-  at step n; loss = mean over masked pixels and the 4 channels of (y - t)^2.
+  at step n.  Loss: the mean over samples s of w_s times the mean of
+  (y - t)^2 over the masked pixels and the 4 channels of sample s (plus an
+  optional penalty on differences of y - t between neighbouring pixels,
+  loss_and_grad_output), with the
+  sample weight w_s = 1 / (q_s + 1e-4), q_s the mean of t^2 over the whole
+  grid and the 4 channels: every sample counts by its error relative to its
+  own target, so the large targets of the first, fast steps of a run do not
+  swamp the many small ones of its smooth later steps.
 * Backward: the loss gradient is rounded to BF16, and so is every
   activation gradient after the ReLU mask; weight and bias gradients are FP32
   sums; the transpose of the reflective padding folds the padded border back
@@ -129,15 +136,45 @@ def forward(params, feats: np.ndarray, quantize: bool = True):
     raise AssertionError("last layer must be linear")
 
 
-def loss_and_grad_output(y, t, mask, quantize: bool = True):
-    """Masked mean-square loss over the 4 output channels and its gradient
-    dL/dy (rounded to BF16 when quantize).  mask: [B, H, W] of 0/1."""
+WEIGHT_FLOOR = 1e-4
+
+
+def loss_and_grad_output(y, t, mask, weights=None, smooth: float = 0.0, quantize: bool = True):
+    """Loss = (1/B) sum over samples of w_s / (4 m_s) times the sum over the 4
+    channels of [sum over masked pixels of e^2 + smooth * sum over the
+    horizontal and vertical neighbour pairs with both pixels masked of
+    (e_p - e_q)^2], e = y - t, m_s the masked pixels of sample s; and its
+    gradient dL/dy (rounded to BF16 when quantize).  The pair term makes a
+    rough error cost more than a smooth one of the same size.
+    mask: [B, H, W] of 0/1; weights: [B] (None: all 1)."""
+    B = y.shape[0]
+    w = np.ones(B) if weights is None else np.asarray(weights, dtype=np.float64)
     m = np.asarray(mask, dtype=np.float64)[..., None]
-    count = 4.0 * m.sum()
-    diff = np.asarray(y, dtype=np.float64) - np.asarray(t, dtype=np.float64)
-    loss = float((m * diff * diff).sum() / count)
-    gy = 2.0 * m * diff / count
+    denom = 4.0 * m.reshape(B, -1).sum(axis=1) * B            # 4 m_s B per sample
+    scale = (w / denom)[:, None, None, None]
+    e = np.asarray(y, dtype=np.float64) - np.asarray(t, dtype=np.float64)
+    loss = float((scale * m * e * e).sum())
+    g = 2.0 * m * e
+    if smooth:
+        ex = e[:, :, 1:] - e[:, :, :-1]
+        mx = m[:, :, 1:] * m[:, :, :-1]
+        ey = e[:, 1:] - e[:, :-1]
+        my = m[:, 1:] * m[:, :-1]
+        loss += smooth * float((scale * mx * ex * ex).sum() + (scale * my * ey * ey).sum())
+        gx = 2.0 * smooth * mx * ex
+        gyy = 2.0 * smooth * my * ey
+        g[:, :, 1:] += gx
+        g[:, :, :-1] -= gx
+        g[:, 1:] += gyy
+        g[:, :-1] -= gyy
+    gy = w[:, None, None, None] * g / denom[:, None, None, None]
     return loss, (bf16(gy.astype(np.float32)) if quantize else gy)
+
+
+def sample_weight(x2: np.ndarray, x1: np.ndarray, x0: np.ndarray, sigma: np.ndarray) -> float:
+    """w = 1 / (mean over the grid and channels of t^2 + WEIGHT_FLOOR) (FP64)."""
+    t = (x0 - x1 - (x1 - x2)) * _inv(sigma)[:, None, None]
+    return 1.0 / (float(np.mean(np.mean(t * t, axis=(1, 2)))) + WEIGHT_FLOOR)
 
 
 def backward(params, acts, gy, quantize: bool = True):

@@ -65,7 +65,8 @@ class chm_params_t(C.Structure):
 
 class chm_stats_t(C.Structure):
     _fields_ = [("iters", C.c_int32 * 2), ("relres", C.c_double * 2), ("status", C.c_int32),
-                ("clamped", C.c_int32), ("t_step_ms", C.c_double), ("guess_used", C.c_int32 * 2)]
+                ("clamped", C.c_int32), ("t_step_ms", C.c_double), ("guess_used", C.c_int32 * 2),
+                ("res0", C.c_double * 2)]
 
 
 _lib = None
@@ -108,13 +109,14 @@ def library():
             "chm_net_get_params": ([vp, vp], C.c_int),
             "chm_net_features": ([vp, i32, i32, vp, vp, vp, vp], C.c_int),
             "chm_net_forward": ([vp, i32, i32, i32, vp, vp], C.c_int),
-            "chm_net_gradients": ([vp, i32, i32, i32, vp, vp, vp, vp, P(d)], C.c_int),
+            "chm_net_gradients": ([vp, i32, i32, i32, vp, vp, vp, vp, C.c_float, vp, P(d)],
+                                  C.c_int),
             "chm_net_adam": ([vp, vp, C.c_float], C.c_int),
             "chm_net_guess": ([vp, i32, i32, vp, vp, vp], C.c_int),
             "chm_net_train_step": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, C.c_float,
-                                    P(d)], C.c_int),
+                                    C.c_float, P(d)], C.c_int),
             "chm_set_guess": ([vp, i32, vp, i32, i32], C.c_int),
-            "chm_get_state": ([vp, vp], C.c_int),
+            "chm_get_state": ([vp, i32, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -224,7 +226,8 @@ class Solver:
         rc = self.lib.chm_step(self.h, nsteps, st)
         stats = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
                       status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms,
-                      guess_used=(s.guess_used[0], s.guess_used[1]))
+                      guess_used=(s.guess_used[0], s.guess_used[1]),
+                      res0=(s.res0[0], s.res0[1]))
                  for s in st[:nsteps]]
         if rc != CHM_OK:
             msg = self.lib.chm_last_error(self.h)
@@ -238,10 +241,12 @@ class Solver:
                                     H, W)
         _check(self.h, rc, "chm_set_guess")
 
-    def get_state(self):
-        """The state vector (4 n doubles, solver block layout) as a CUDA tensor."""
+    def get_state(self, solution: bool = False):
+        """The state vector (4 n doubles, solver block layout) as a CUDA tensor;
+        solution=True: the last solution of the solve (before solvent removal)."""
         out = self.torch.empty(4 * self.nv, dtype=self.torch.float64, device="cuda")
-        _check(self.h, self.lib.chm_get_state(self.h, _dev_ptr(out)), "chm_get_state")
+        _check(self.h, self.lib.chm_get_state(self.h, int(solution), _dev_ptr(out)),
+               "chm_get_state")
         return out
 
     # ---- inspection
@@ -441,15 +446,17 @@ class Net:
                     "chm_net_forward")
         return y
 
-    def gradients(self, feats, target, mask):
+    def gradients(self, feats, target, mask, weights=None, smooth: float = 0.0):
         feats, target = feats.contiguous(), target.contiguous()
         mask = mask.to(self.torch.uint8).contiguous()
         B, h, w, _ = feats.shape
         g = np.zeros(NET_NPARAMS, np.float32)
         loss = C.c_double()
-        self._check(self.lib.chm_net_gradients(self.h, B, h, w, _dev_ptr(feats), _dev_ptr(target),
-                                               _dev_ptr(mask), g.ctypes.data_as(C.c_void_p),
-                                               C.byref(loss)), "chm_net_gradients")
+        wts = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        self._check(self.lib.chm_net_gradients(
+            self.h, B, h, w, _dev_ptr(feats), _dev_ptr(target), _dev_ptr(mask),
+            None if wts is None else wts.ctypes.data_as(C.c_void_p), float(smooth),
+            g.ctypes.data_as(C.c_void_p), C.byref(loss)), "chm_net_gradients")
         return unflatten_params(g), loss.value
 
     def adam(self, grads, lr: float):
@@ -465,7 +472,7 @@ class Net:
         return out
 
     def train_step(self, H: int, W: int, crop_h: int, crop_w: int, x2s, x1s, x0s, oy, ox,
-                   lr: float) -> float:
+                   lr: float, smooth: float = 0.0) -> float:
         B = len(x2s)
         arr = lambda ts: (C.c_void_p * B)(*[t.data_ptr() for t in ts])
         oy = np.ascontiguousarray(oy, dtype=np.int32)
@@ -474,6 +481,6 @@ class Net:
         self._check(self.lib.chm_net_train_step(self.h, B, H, W, crop_h, crop_w, arr(x2s), arr(x1s),
                                                 arr(x0s), oy.ctypes.data_as(C.c_void_p),
                                                 ox.ctypes.data_as(C.c_void_p), float(lr),
-                                                C.byref(loss)), "chm_net_train_step")
+                                                float(smooth), C.byref(loss)), "chm_net_train_step")
         return loss.value
 

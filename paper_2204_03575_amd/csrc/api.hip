@@ -184,7 +184,10 @@ int chm_set_fields(chm_solver_t *h, const double *phi_p, const double *phi_n, co
             copy_field(mu, n, 0, mu_p, on_device, S.stream);
         if (mu_n)
             copy_field(mu, n, 1, mu_n, on_device, S.stream);
-        S.hist = false;   // a new state has no previous step
+        // the new state starts the history of solutions
+        CHM_HIP(hipMemcpyAsync(S.yh1, S.x, sizeof(double2) * 2 * (size_t)n,
+                               hipMemcpyDeviceToDevice, S.stream));
+        S.hist = 1;
         CHM_HIP(hipStreamSynchronize(S.stream));
         return CHM_OK;
     });
@@ -498,13 +501,15 @@ int chm_set_guess(chm_solver_t *h, int32_t mode, chm_net_t *net, int32_t H, int3
     return CHM_OK;
 }
 
-int chm_get_state(chm_solver_t *h, double *state)
+int chm_get_state(chm_solver_t *h, int32_t which, double *state)
 {
-    if (!h || !state)
+    if (!h || !state || which < 0 || which > 1)
         return fail(h, CHM_EINVAL, "chm_get_state: bad arguments");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
-        CHM_HIP(hipMemcpyAsync(state, S.x, sizeof(double2) * 2 * (size_t)S.nv,
+        if (which == 1 && S.hist < 1)
+            throw chm::Failure(CHM_EINVAL, "chm_get_state: no solution yet");
+        CHM_HIP(hipMemcpyAsync(state, which == 0 ? S.x : S.yh1, sizeof(double2) * 2 * (size_t)S.nv,
                                hipMemcpyDeviceToDevice, S.stream));
         CHM_HIP(hipStreamSynchronize(S.stream));
         return CHM_OK;

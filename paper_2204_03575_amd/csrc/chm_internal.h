@@ -181,7 +181,7 @@ struct Ctl {
     int k[2];            // Arnoldi steps of the species in this cycle
     int clamped;         // log-argument clamps in the last right-hand side
     int nan;             // a non-finite value was seen
-    int guess_used[2];   // the step started from the guess candidate
+    int guess_used[2];   // CHM_GUESS_* of the start the step used
     // large part
     double H[2][(kMaxRestart + 1) * kMaxRestart];
     double cs[2][kMaxRestart], sn[2][kMaxRestart];
@@ -254,8 +254,10 @@ struct Solver {
     int guess_mode = 0;
     chm_net *net = nullptr;
     int gH = 0, gW = 0;
-    double2 *xhist = nullptr;  // state at the start of the previous step
-    bool hist = false;         // xhist holds it
+    // the last two solutions of the Krylov solve (before solvent removal):
+    // yh1 = y_{n-1}, yh2 = y_{n-2}; after chm_set_fields yh1 is the new state
+    double2 *yh1 = nullptr, *yh2 = nullptr;
+    int hist = 0;              // how many of yh1, yh2 are valid
 };
 
 // ---- util.hip

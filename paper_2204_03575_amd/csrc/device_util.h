@@ -115,8 +115,9 @@ __device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 
 // ------------------------------------------------------------------ partial-sum slots
 // kRedBlocks pairs each, in Solver::red: the inner CG uses rz (0..39) and
 // dq (40..79), the Krylov solver the right-hand-side norm (80) and the
-// residual norm (81) and the residual norm of the initial-guess candidate (82).
-constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotRg = 82, kSlots = 83;
+// residual norm (81) and the residual norms of the initial-guess candidates
+// (82 + CHM_GUESS_*: previous state, linear extrapolation, network).
+constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotGuess = 82, kSlots = 85;
 
 inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
 

@@ -30,6 +30,8 @@ constexpr int kChunk = 1024;          // pixels per block of the weight-gradient
 constexpr int kMaxBatch = 256;
 constexpr int kPtrBatch = 64;         // samples per pointer-upload launch
 constexpr double kBeta1 = 0.9, kBeta2 = 0.999, kAdamEps = 1e-8;
+constexpr int kStat = 13;             // per-sample statistics: sigma[4], mean[4], tau[4], q
+constexpr double kWeightFloor = 1e-4; // sample weight 1 / (q + floor)
 
 constexpr int w_count(int k) { return 9 * kCin[k] * kCout[k]; }
 constexpr int w_offset(int k) { return k == 0 ? 0 : w_offset(k - 1) + w_count(k - 1) + kCout[k - 1]; }
@@ -370,21 +372,49 @@ __global__ void k_grad_reduce(int nchunks, int nw, int co, const float *__restri
 }
 
 // ------------------------------------------------------------------ loss
-// masked mean square over (pixel, channel): dL/dy = 2 (y - t) / count, to
-// BF16; per-block partial sums of (y - t)^2 (FP64) in part
-__global__ void __launch_bounds__(kBlock) k_loss(long n4, const float *__restrict__ y,
+// L = (1/S) sum over samples of w_s / (4 m_s) times the sum over the 4
+// channels of [sum over masked pixels of e^2 + smooth * sum over the
+// horizontal and vertical neighbour pairs with both pixels masked of
+// (e_p - e_q)^2], e = y - t (samples are ch x cw crops, m_s their masked
+// pixels).  dL/dy_p = w_s (2 e_p + 2 smooth sum over masked neighbours q of
+// (e_p - e_q)) / (4 m_s S), rounded to BF16; per-block partial sums of the
+// loss terms (FP64, each pair counted at its left or upper pixel) in part.
+__global__ void __launch_bounds__(kBlock) k_loss(long n4, int ch, int cw, int S,
+                                                 const float *__restrict__ y,
                                                  const float *__restrict__ t,
-                                                 const uint8_t *__restrict__ mask, double count,
+                                                 const uint8_t *__restrict__ mask,
+                                                 const double *__restrict__ wts,
+                                                 const int *__restrict__ msum, double smooth,
                                                  bf16_t *__restrict__ gy, double *part)
 {
     __shared__ double2 sh[kBlock / 64];
+    const long chs = (long)ch * cw;
     double acc = 0.0;
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (long)gridDim.x * kBlock) {
         float g = 0.0f;
-        if (mask[i >> 2]) {
-            const double d = (double)y[i] - (double)t[i];
-            acc += d * d;
-            g = (float)(2.0 * d / count);
+        const long p = i >> 2;
+        if (mask[p]) {
+            const int s = (int)(p / chs), c = (int)(i & 3);
+            const long loc = p % chs;
+            const int r = (int)(loc / cw), col = (int)(loc % cw);
+            const double w = wts[s], denom = 4.0 * (double)msum[s] * (double)S;
+            const double e = (double)y[i] - (double)t[i];
+            double term = e * e, gsum = e;
+            if (smooth != 0.0) {
+                const long nb[4] = {col + 1 < cw ? p + 1 : -1, col > 0 ? p - 1 : -1,
+                                    r + 1 < ch ? p + cw : -1, r > 0 ? p - cw : -1};
+                for (int k = 0; k < 4; ++k) {
+                    const long q = nb[k];
+                    if (q < 0 || !mask[q])
+                        continue;
+                    const double eq = (double)y[q * 4 + c] - (double)t[q * 4 + c];
+                    gsum += smooth * (e - eq);
+                    if (k == 0 || k == 2)
+                        term += smooth * (eq - e) * (eq - e);
+                }
+            }
+            acc += w * term / denom;
+            g = (float)(w * (2.0 * gsum) / denom);
         }
         gy[i] = to_bf16(g);
     }
@@ -393,15 +423,24 @@ __global__ void __launch_bounds__(kBlock) k_loss(long n4, const float *__restric
         part[blockIdx.x] = s.x;
 }
 
+// sample weights 1 / (q_s + floor) from the statistics
+__global__ void k_weights(int S, const double *__restrict__ stats, double *wts)
+{
+    const int s = threadIdx.x;
+    if (s < S)
+        wts[s] = 1.0 / (stats[s * kStat + 12] + kWeightFloor);
+}
+
 // ------------------------------------------------------------------ features and guess
 struct BatchPtrs {
     const double *x2[kPtrBatch], *x1[kPtrBatch], *x0[kPtrBatch];
-    int oy[kPtrBatch], ox[kPtrBatch];
+    int oy[kPtrBatch], ox[kPtrBatch], msum[kPtrBatch];
 };
 
-// copy count samples' pointers and crop origins into the device tables at base
+// copy count samples' pointers, crop origins and masked pixel counts into the
+// device tables at base
 __global__ void k_set_batch(BatchPtrs b, int base, int count, int cap, const double **ptrs,
-                            int *crop)
+                            int *crop, int *msum)
 {
     const int i = threadIdx.x;
     if (i >= count)
@@ -411,16 +450,21 @@ __global__ void k_set_batch(BatchPtrs b, int base, int count, int cap, const dou
     ptrs[2 * cap + base + i] = b.x0[i];
     crop[base + i] = b.oy[i];
     crop[cap + base + i] = b.ox[i];
+    msum[base + i] = b.msum[i];
 }
 
 // per sample: sigma_c = RMS of x1 - x2, mean_c of x1, tau_c = RMS of x1 - mean_c
-// (stats[s][0..3], [4..7], [8..11]); one block per sample
+// (stats[s][0..3], [4..7], [8..11]) and, with x0, q = mean over channels of
+// the mean square of the target t_c = (x0 - x1 - (x1 - x2)) / sigma_c
+// (stats[s][12]; 0 without x0); one block per sample
 __global__ void __launch_bounds__(kBlock) k_stats(long n, const double *const *x2s,
-                                                  const double *const *x1s, double *stats)
+                                                  const double *const *x1s,
+                                                  const double *const *x0s, double *stats)
 {
     __shared__ double2 sh[kBlock / 64];
-    __shared__ double res[12];
+    __shared__ double res[kStat];
     const double *x2 = x2s[blockIdx.x], *x1 = x1s[blockIdx.x];
+    const double *x0 = x0s ? x0s[blockIdx.x] : nullptr;
     double sd[4] = {0.0, 0.0, 0.0, 0.0}, sm[4] = {0.0, 0.0, 0.0, 0.0};
     for (long v = threadIdx.x; v < n; v += kBlock)
         for (int c = 0; c < 4; ++c) {
@@ -436,22 +480,36 @@ __global__ void __launch_bounds__(kBlock) k_stats(long n, const double *const *x
         }
     }
     __syncthreads();
-    double st[4] = {0.0, 0.0, 0.0, 0.0};
+    double st[4] = {0.0, 0.0, 0.0, 0.0}, sq[4] = {0.0, 0.0, 0.0, 0.0};
+    double is[4];
+    for (int c = 0; c < 4; ++c)
+        is[c] = res[c] > 0.0 ? 1.0 / res[c] : 0.0;
     for (long v = threadIdx.x; v < n; v += kBlock)
         for (int c = 0; c < 4; ++c) {
-            const double e = x1[sidx(c, v, n)] - res[4 + c];
+            const long k = sidx(c, v, n);
+            const double a = x1[k];
+            const double e = a - res[4 + c];
             st[c] += e * e;
+            if (x0) {
+                const double t = (x0[k] - a - (a - x2[k])) * is[c];
+                sq[c] += t * t;
+            }
         }
+    double qsum = 0.0;   // thread 0
     for (int c = 0; c < 4; c += 2) {
         const double2 s = block_sum(d2(st[c], st[c + 1]), sh);
+        const double2 q = block_sum(d2(sq[c], sq[c + 1]), sh);
         if (threadIdx.x == 0) {
             res[8 + c] = sqrt(s.x / (double)n);
             res[9 + c] = sqrt(s.y / (double)n);
+            qsum += q.x / (double)n + q.y / (double)n;
         }
     }
+    if (threadIdx.x == 0)
+        res[12] = 0.25 * qsum;
     __syncthreads();
-    if (threadIdx.x < 12)
-        stats[blockIdx.x * 12 + threadIdx.x] = res[threadIdx.x];
+    if (threadIdx.x < kStat)
+        stats[blockIdx.x * kStat + threadIdx.x] = res[threadIdx.x];
 }
 
 __device__ inline double inv_or_zero(double s) { return s > 0.0 ? 1.0 / s : 0.0; }
@@ -472,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(int S, int H, int W, int ch, in
     const int oy = crop[s], ox = crop[cap + s];
     const long n = (long)H * W, v = (long)(oy + cy) * W + (ox + cx);
     const double *x2 = ptrs[s], *x1 = ptrs[cap + s], *x0 = ptrs[2 * cap + s];
-    const double *st = stats + 12 * s;
+    const double *st = stats + kStat * s;
     for (int c = 0; c < 4; ++c) {
         const double a = x1[sidx(c, v, n)];
         const double d = a - x2[sidx(c, v, n)];
@@ -545,7 +603,9 @@ struct chm_net {
     bf16_t *gy = nullptr, *gA = nullptr, *gB = nullptr;
     float *wpart = nullptr, *bpart = nullptr;
     double *lpart = nullptr;
-    double *stats = nullptr;
+    double *stats = nullptr;         // [kMaxBatch][kStat]
+    double *wts = nullptr;           // sample weights [kMaxBatch]
+    int *msum = nullptr;             // masked pixels per sample [kMaxBatch]
     const double **ptrs = nullptr;   // [3][kMaxBatch]
     int *crop = nullptr;             // [2][kMaxBatch]
 };
@@ -614,10 +674,12 @@ void backward(chm_net &N, hipStream_t st, int B, int H, int W)
     CHM_HIP(hipGetLastError());
 }
 
-// loss gradient into N.gy; returns the loss when want (synchronises)
-double loss_grad(chm_net &N, hipStream_t st, long npx, double count, bool want)
+// loss gradient into N.gy for S samples of ch x cw pixels (weights and masked
+// counts in N.wts, N.msum); returns the loss when want (synchronises)
+double loss_grad(chm_net &N, hipStream_t st, int S, int ch, int cw, double smooth, bool want)
 {
-    k_loss<<<kRedBlocks, kBlock, 0, st>>>(4 * npx, N.y, N.tgt, N.mask, count, N.gy, N.lpart);
+    k_loss<<<kRedBlocks, kBlock, 0, st>>>(4l * S * ch * cw, ch, cw, S, N.y, N.tgt, N.mask, N.wts,
+                                          N.msum, smooth, N.gy, N.lpart);
     CHM_HIP(hipGetLastError());
     if (!want)
         return 0.0;
@@ -627,7 +689,7 @@ double loss_grad(chm_net &N, hipStream_t st, long npx, double count, bool want)
     double s = 0.0;
     for (int i = 0; i < kRedBlocks; ++i)
         s += h[i];
-    return count > 0.0 ? s / count : 0.0;
+    return s;
 }
 
 void adam_step(chm_net &N, hipStream_t st, float lr)
@@ -644,7 +706,7 @@ void adam_step(chm_net &N, hipStream_t st, float lr)
 
 void upload_batch(chm_net &N, hipStream_t st, int S, const double *const *x2,
                   const double *const *x1, const double *const *x0, const int32_t *oy,
-                  const int32_t *ox)
+                  const int32_t *ox, const int *msum)
 {
     for (int base = 0; base < S; base += kPtrBatch) {
         BatchPtrs b{};
@@ -655,8 +717,9 @@ void upload_batch(chm_net &N, hipStream_t st, int S, const double *const *x2,
             b.x0[i] = x0 ? x0[base + i] : nullptr;
             b.oy[i] = oy ? oy[base + i] : 0;
             b.ox[i] = ox ? ox[base + i] : 0;
+            b.msum[i] = msum ? msum[base + i] : 0;
         }
-        k_set_batch<<<1, kPtrBatch, 0, st>>>(b, base, cnt, kMaxBatch, N.ptrs, N.crop);
+        k_set_batch<<<1, kPtrBatch, 0, st>>>(b, base, cnt, kMaxBatch, N.ptrs, N.crop, N.msum);
     }
     CHM_HIP(hipGetLastError());
 }
@@ -665,8 +728,8 @@ void upload_batch(chm_net &N, hipStream_t st, int S, const double *const *x2,
 void full_features(chm_net &N, hipStream_t st, int H, int W, const double *x2, const double *x1)
 {
     check_shape(N, 1, H, W);
-    upload_batch(N, st, 1, &x2, &x1, nullptr, nullptr, nullptr);
-    k_stats<<<1, kBlock, 0, st>>>((long)H * W, N.ptrs, N.ptrs + kMaxBatch, N.stats);
+    upload_batch(N, st, 1, &x2, &x1, nullptr, nullptr, nullptr, nullptr);
+    k_stats<<<1, kBlock, 0, st>>>((long)H * W, N.ptrs, N.ptrs + kMaxBatch, nullptr, N.stats);
     k_pack<<<nblk_l((long)H * W), kBlock, 0, st>>>(1, H, W, H, W, kMaxBatch, N.ptrs, N.crop, N.stats,
                                                    N.act[0], nullptr, nullptr);
     CHM_HIP(hipGetLastError());
@@ -756,7 +819,9 @@ int chm_net_create(int64_t max_pixels, void *stream, chm_net_t **out)
         N->wpart = p.get<float>((size_t)N->max_chunks * 9 * 32 * 32);
         N->bpart = p.get<float>((size_t)N->max_chunks * 32);
         N->lpart = p.get<double>(kRedBlocks);
-        N->stats = p.get<double>(12 * kMaxBatch);
+        N->stats = p.get<double>(kStat * kMaxBatch);
+        N->wts = p.get<double>(kMaxBatch);
+        N->msum = p.get<int>(kMaxBatch);
         N->ptrs = p.get<const double *>(3 * kMaxBatch);
         N->crop = p.get<int>(2 * kMaxBatch);
         hipStream_t st = N->stream;
@@ -857,26 +922,35 @@ int chm_net_forward(chm_net_t *net, int32_t batch, int32_t h, int32_t w, const f
 }
 
 int chm_net_gradients(chm_net_t *net, int32_t batch, int32_t h, int32_t w, const float *feats,
-                      const float *target, const uint8_t *mask, float *grads, double *loss)
+                      const float *target, const uint8_t *mask, const double *weights,
+                      float smooth, float *grads, double *loss)
 {
-    if (!net || !feats || !target || !mask || !grads)
+    if (!net || !feats || !target || !mask || !grads || !(smooth >= 0.0f))
         return net_fail(net, CHM_EINVAL, "chm_net_gradients: bad arguments");
     return net_guarded(net, [&]() {
         using namespace chm;
         check_shape(*net, batch, h, w);
+        if (batch > kMaxBatch)
+            throw Failure(CHM_EINVAL, "batch exceeds 256");
         hipStream_t st = net->stream;
-        const long npx = (long)batch * h * w;
+        const long chs = (long)h * w, npx = batch * chs;
         std::vector<uint8_t> hm(npx);
         CHM_HIP(hipMemcpyAsync(hm.data(), mask, npx, hipMemcpyDeviceToHost, st));
         CHM_HIP(hipStreamSynchronize(st));
-        double count = 0.0;
-        for (uint8_t m : hm)
-            count += m ? 4.0 : 0.0;
+        std::vector<int> ms(batch, 0);
+        std::vector<double> wt(batch, 1.0);
+        for (long p = 0; p < npx; ++p)
+            ms[p / chs] += hm[p] ? 1 : 0;
+        if (weights)
+            for (int s = 0; s < batch; ++s)
+                wt[s] = weights[s];
+        CHM_HIP(hipMemcpyAsync(net->msum, ms.data(), sizeof(int) * batch, hipMemcpyHostToDevice, st));
+        CHM_HIP(hipMemcpyAsync(net->wts, wt.data(), sizeof(double) * batch, hipMemcpyHostToDevice, st));
         k_f32_to_bf16<<<nblk_l(8 * npx), kBlock, 0, st>>>(8 * npx, feats, net->act[0]);
         CHM_HIP(hipMemcpyAsync(net->tgt, target, sizeof(float) * 4 * npx, hipMemcpyDeviceToDevice, st));
         CHM_HIP(hipMemcpyAsync(net->mask, mask, npx, hipMemcpyDeviceToDevice, st));
         forward(*net, st, batch, h, w);
-        const double l = loss_grad(*net, st, npx, count, true);
+        const double l = loss_grad(*net, st, batch, h, w, smooth, true);
         backward(*net, st, batch, h, w);
         CHM_HIP(hipMemcpyAsync(grads, net->grads, sizeof(float) * CHM_NET_NPARAMS,
                                hipMemcpyDeviceToHost, st));
@@ -916,9 +990,9 @@ int chm_net_guess(chm_net_t *net, int32_t H, int32_t W, const double *x2, const 
 int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int32_t crop_h,
                        int32_t crop_w, const double *const *x2, const double *const *x1,
                        const double *const *x0, const int32_t *oy, const int32_t *ox, float lr,
-                       double *loss)
+                       float smooth, double *loss)
 {
-    if (!net || !x2 || !x1 || !x0 || !oy || !ox || !(lr >= 0.0f))
+    if (!net || !x2 || !x1 || !x0 || !oy || !ox || !(lr >= 0.0f) || !(smooth >= 0.0f))
         return net_fail(net, CHM_EINVAL, "chm_net_train_step: bad arguments");
     return net_guarded(net, [&]() {
         using namespace chm;
@@ -927,7 +1001,7 @@ int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int3
         if (H < 2 || W < 2 || crop_h > H || crop_w > W)
             throw Failure(CHM_EINVAL, "crop larger than the grid");
         check_shape(*net, batch, crop_h, crop_w);
-        double count = 0.0;
+        std::vector<int> ms(batch);
         for (int i = 0; i < batch; ++i) {
             if (!x2[i] || !x1[i] || !x0[i])
                 throw Failure(CHM_EINVAL, "null state pointer");
@@ -935,18 +1009,20 @@ int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int3
                 throw Failure(CHM_EINVAL, "crop outside the grid");
             const int top = oy[i] > 0 ? kRadius : 0, bot = oy[i] + crop_h < H ? kRadius : 0;
             const int lft = ox[i] > 0 ? kRadius : 0, rgt = ox[i] + crop_w < W ? kRadius : 0;
-            count += 4.0 * std::max(0, crop_h - top - bot) * std::max(0, crop_w - lft - rgt);
+            ms[i] = std::max(0, crop_h - top - bot) * std::max(0, crop_w - lft - rgt);
         }
         hipStream_t st = net->stream;
-        upload_batch(*net, st, batch, x2, x1, x0, oy, ox);
-        k_stats<<<batch, kBlock, 0, st>>>((long)H * W, net->ptrs, net->ptrs + kMaxBatch, net->stats);
+        upload_batch(*net, st, batch, x2, x1, x0, oy, ox, ms.data());
+        k_stats<<<batch, kBlock, 0, st>>>((long)H * W, net->ptrs, net->ptrs + kMaxBatch,
+                                          net->ptrs + 2 * kMaxBatch, net->stats);
+        k_weights<<<1, kMaxBatch, 0, st>>>(batch, net->stats, net->wts);
         const long npx = (long)batch * crop_h * crop_w;
         k_pack<<<nblk_l(npx), kBlock, 0, st>>>(batch, H, W, crop_h, crop_w, kMaxBatch, net->ptrs,
                                                net->crop, net->stats, net->act[0], net->tgt,
                                                net->mask);
         CHM_HIP(hipGetLastError());
         forward(*net, st, batch, crop_h, crop_w);
-        const double l = loss_grad(*net, st, npx, count, loss != nullptr);
+        const double l = loss_grad(*net, st, batch, crop_h, crop_w, smooth, loss != nullptr);
         backward(*net, st, batch, crop_h, crop_w);
         adam_step(*net, st, lr);
         CHM_HIP(hipStreamSynchronize(st));

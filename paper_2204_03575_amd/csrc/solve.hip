@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, doubl
 }
 
 // ------------------------------------------------------------------ initial guess
-// xg = x + (x - xh): linear extrapolation of the last increment
+// xg = x + (x - xh): linear extrapolation of the last increment (x = y_{n-1}, xh = y_{n-2})
 __global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *__restrict__ xh,
                                                         const double2 *__restrict__ x, double2 *xg)
 {
@@ -479,25 +479,51 @@ __global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *
     xg[i] = d2(a.x + (a.x - h.x), a.y + (a.y - h.y));
 }
 
-// Per species, keep the candidate xg where its squared residual norm (partials
-// pg) is below the previous state's (partials px), else take x; a non-finite
-// candidate norm never wins.  Records the choice in the control block.
+// Per species, the start with the smallest residual norm among the previous
+// state x (code 0), the linear extrapolation xl (code 1; may be null) and the
+// network's guess xg (code 2; may be null), from the partial sums in
+// pg[code * kRedBlocks + g]; ties and non-finite norms keep the earlier code.
+// The chosen start goes to out (which may alias xl or xg), the codes to the
+// control block.
 __global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *__restrict__ x,
-                                                       double2 *xg, const double2 *__restrict__ pg,
-                                                       const double2 *__restrict__ px, int G, Ctl *c)
+                                                       const double2 *xl, const double2 *xg,
+                                                       const double2 *__restrict__ pg, int G,
+                                                       double2 *out, Ctl *c)
 {
-    __shared__ double2 sc[2];
-    reduce_two(pg, px, G, sc);
-    const bool ux = sc[0].x < sc[1].x, uy = sc[0].y < sc[1].y;
+    __shared__ double2 nrm[3];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (wid < 3) {
+        double2 s = d2(0.0, 0.0);
+        for (int g = lane; g < G; g += 64) {
+            const double2 q = pg[(size_t)wid * kRedBlocks + g];
+            s.x += q.x;
+            s.y += q.y;
+        }
+        s = wave_sum(s);
+        if (lane == 0)
+            nrm[wid] = s;
+    }
+    __syncthreads();
+    int cx = 0, cy = 0;
+    double bx = nrm[0].x, by = nrm[0].y;
+    if (xl) {
+        if (nrm[1].x < bx) { cx = 1; bx = nrm[1].x; }
+        if (nrm[1].y < by) { cy = 1; by = nrm[1].y; }
+    }
+    if (xg) {
+        if (nrm[2].x < bx) { cx = 2; bx = nrm[2].x; }
+        if (nrm[2].y < by) { cy = 2; by = nrm[2].y; }
+    }
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i == 0) {
-        c->guess_used[0] = ux;
-        c->guess_used[1] = uy;
+        c->guess_used[0] = cx;
+        c->guess_used[1] = cy;
     }
     if (i >= len)
         return;
-    const double2 g = xg[i], p = x[i];
-    xg[i] = d2(ux ? g.x : p.x, uy ? g.y : p.y);
+    const double2 a = x[i];
+    const double2 l = xl ? xl[i] : a, g = xg ? xg[i] : a;
+    out[i] = d2(cx == 0 ? a.x : (cx == 1 ? l.x : g.x), cy == 0 ? a.y : (cy == 1 ? l.y : g.y));
 }
 
 // ------------------------------------------------------------------ host helpers
@@ -546,7 +572,8 @@ void alloc_workspace(Solver &S)
     S.m = S.prm.restart;
     S.x = p.get<double2>(len);
     S.xk = p.get<double2>(len);
-    S.xhist = p.get<double2>(len);
+    S.yh1 = p.get<double2>(len);
+    S.yh2 = p.get<double2>(len);
     S.b = p.get<double2>(len);
     S.r = p.get<double2>(len);
     S.V = p.get<double2>(len * (S.m + 1));
@@ -654,21 +681,26 @@ int step_once(Solver &S, chm_stats_t *st_out)
     compute_rhs(S);
     k_dot<double><<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
     k_tol<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
-    if (S.guess_mode != CHM_GUESS_PREVIOUS && S.hist) {
-        // candidate start: linear extrapolation or the network's guess; each
-        // species keeps it only if its residual is smaller than the previous
-        // state's
-        if (S.guess_mode == CHM_GUESS_LINEAR)
-            k_extrapolate<<<nblk(len), kBlock, 0, st>>>(len, S.xhist, S.x, S.xk);
-        else
-            net_guess_on(S.net, st, S.gH, S.gW, reinterpret_cast<const double *>(S.xhist),
-                         reinterpret_cast<const double *>(S.x), reinterpret_cast<double *>(S.xk));
-        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b,
-                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotRg));
-        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.x, S.b,
-                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotR));
-        k_pick_guess<<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk, slot(S, kSlotRg),
-                                                   slot(S, kSlotR), Gn, S.ctl);
+    if (S.guess_mode != CHM_GUESS_PREVIOUS && S.hist >= 2) {
+        // candidate starts from the last two solutions: linear extrapolation
+        // and, in the learned mode, the network's guess; each species starts
+        // from whichever of them and the previous state has the smallest
+        // residual.  The first Krylov basis vector holds the extrapolation
+        // until the choice is made.
+        const bool learned = S.guess_mode == CHM_GUESS_LEARNED;
+        double2 *xl = S.V, *xg = learned ? S.xk : nullptr;
+        k_extrapolate<<<nblk(len), kBlock, 0, st>>>(len, S.yh2, S.yh1, xl);
+        if (learned)
+            net_guess_on(S.net, st, S.gH, S.gW, reinterpret_cast<const double *>(S.yh2),
+                         reinterpret_cast<const double *>(S.yh1), reinterpret_cast<double *>(xg));
+        const double2 *cand[3] = {S.x, xl, xg};
+        for (int k = 0; k < 3; ++k)
+            if (cand[k])
+                k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK,
+                                                      cand[k], S.b, S.r, pair(S.tau_s),
+                                                      pair(S.te_s), slot(S, kSlotGuess + k));
+        k_pick_guess<<<nblk(len), kBlock, 0, st>>>(len, S.x, xl, xg, slot(S, kSlotGuess), Gn, S.xk,
+                                                   S.ctl);
     } else {
         k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
         fill_int(S.ctl->guess_used, 0, 2, st);
@@ -677,6 +709,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
 
     int total[2] = {0, 0};
     int rc = CHM_OK;
+    bool first = true;
     double res[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0};
     for (;;) {
         k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b,
@@ -692,7 +725,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
             bn[s] = h.bnorm[s];
             finite = finite && std::isfinite(res[s]);
             act[s] = !(res[s] <= h.tol[s]);
+            if (first)
+                stats.res0[s] = bn[s] > 0.0 ? res[s] / bn[s] : res[s];
         }
+        first = false;
         if (!finite) {
             rc = CHM_ENAN;
             S.nan_where = "residual check: |r| = (" + std::to_string(res[0]) + ", " +
@@ -757,8 +793,9 @@ int step_once(Solver &S, chm_stats_t *st_out)
     stats.guess_used[0] = S.hctl->guess_used[0];
     stats.guess_used[1] = S.hctl->guess_used[1];
     if (rc == CHM_OK) {
-        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xhist);   // becomes x^{n-2}
-        S.hist = true;
+        std::swap(S.yh1, S.yh2);   // y_{n-1} becomes y_{n-2}
+        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.yh1);
+        S.hist = std::min(S.hist + 1, 2);
         k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.x);
         if (S.prm.evap_ds > 0.0 && S.step_count < S.prm.evap_steps)
             k_evaporate<<<nblk(n), kBlock, 0, st>>>(n, S.x, S.prm.evap_ds);

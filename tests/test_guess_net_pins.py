@@ -90,10 +90,10 @@ def test_backward_matches_central_differences_fp64():
 
     def loss(ps):
         _, y = G.forward(ps, feats, quantize=False)
-        return G.loss_and_grad_output(y, t, mask, quantize=False)[0]
+        return G.loss_and_grad_output(y, t, mask, [1.5, 0.5], quantize=False)[0]
 
     acts, y = G.forward(params, feats, quantize=False)
-    _, gy = G.loss_and_grad_output(y, t, mask, quantize=False)
+    _, gy = G.loss_and_grad_output(y, t, mask, [1.5, 0.5], quantize=False)
     grads = G.backward(params, acts, gy, quantize=False)
     h = 1e-6
     for k in range(4):
@@ -116,14 +116,63 @@ def test_output_gradient_matches_central_differences():
     mask = rng.integers(0, 2, (1, 3, 4)).astype(float)
     mask[0, 0, 0] = 1
     # a constant error c on the masked pixels is a mean square of c^2
-    assert np.isclose(G.loss_and_grad_output(t + 0.5, t, mask, False)[0], 0.25, rtol=1e-14)
+    assert np.isclose(G.loss_and_grad_output(t + 0.5, t, mask, quantize=False)[0], 0.25, rtol=1e-14)
     _, g = G.loss_and_grad_output(y, t, mask, quantize=False)
     for idx in [(0, 0, 0, 1), (0, 2, 3, 3), (0, 1, 2, 0)]:
         yp, ym = y.copy(), y.copy()
         yp[idx] += 1e-6
         ym[idx] -= 1e-6
-        fd = (G.loss_and_grad_output(yp, t, mask, False)[0] - G.loss_and_grad_output(ym, t, mask, False)[0]) / 2e-6
+        fd = (G.loss_and_grad_output(yp, t, mask, quantize=False)[0]
+              - G.loss_and_grad_output(ym, t, mask, quantize=False)[0]) / 2e-6
         assert abs(fd - g[idx]) <= 1e-7
+
+
+def test_weighted_loss_is_the_mean_of_per_sample_means():
+    rng = np.random.default_rng(16)
+    y = rng.standard_normal((3, 4, 5, 4))
+    t = rng.standard_normal((3, 4, 5, 4))
+    mask = np.ones((3, 4, 5))
+    mask[1, :2] = 0
+    mask[2, :, :4] = 0
+    w = np.array([2.0, 0.5, 3.0])
+    per = [float(np.sum(mask[s][..., None] * (y[s] - t[s]) ** 2) / (4 * mask[s].sum())) for s in range(3)]
+    loss, g = G.loss_and_grad_output(y, t, mask, w, quantize=False)
+    assert np.isclose(loss, np.dot(w, per) / 3, rtol=1e-13)
+    # the pair penalty on a constant error is zero; on an error alternating in
+    # sign along rows it adds smooth * (2c)^2 per masked horizontal pair
+    c = 0.3
+    assert np.isclose(G.loss_and_grad_output(t + c, t, mask, w, smooth=5.0, quantize=False)[0],
+                      np.dot(w, [c * c] * 3) / 3, rtol=1e-13)
+    alt = t + c * (-1.0) ** np.arange(5)[None, None, :, None]
+    pairs = [float((mask[s][:, 1:] * mask[s][:, :-1]).sum()) for s in range(3)]
+    ref = sum(w[s] * (4 * mask[s].sum() * c * c + 5.0 * 4 * pairs[s] * 4 * c * c) / (4 * mask[s].sum())
+              for s in range(3)) / 3
+    assert np.isclose(G.loss_and_grad_output(alt, t, mask, w, smooth=5.0, quantize=False)[0], ref,
+                      rtol=1e-12)
+    loss_s, g_s = G.loss_and_grad_output(y, t, mask, w, smooth=2.5, quantize=False)
+    for idx in [(2, 1, 4, 2), (1, 3, 0, 1), (0, 0, 0, 0)]:
+        yp, ym = y.copy(), y.copy()
+        yp[idx] += 1e-6
+        ym[idx] -= 1e-6
+        fd = (G.loss_and_grad_output(yp, t, mask, w, 2.5, quantize=False)[0]
+              - G.loss_and_grad_output(ym, t, mask, w, 2.5, quantize=False)[0]) / 2e-6
+        assert abs(fd - g_s[idx]) <= 1e-7
+    idx = (2, 1, 4, 2)
+    yp, ym = y.copy(), y.copy()
+    yp[idx] += 1e-6
+    ym[idx] -= 1e-6
+    fd = (G.loss_and_grad_output(yp, t, mask, w, quantize=False)[0]
+          - G.loss_and_grad_output(ym, t, mask, w, quantize=False)[0]) / 2e-6
+    assert abs(fd - g[idx]) <= 1e-7
+
+
+def test_sample_weight_is_inverse_mean_square_target():
+    x2, x1, x0 = states()
+    _, sigma = G.features(x2, x1)
+    t = G.target(x2, x1, x0, sigma).astype(np.float64)
+    assert np.isclose(G.sample_weight(x2, x1, x0, sigma), 1.0 / (np.mean(t * t) + 1e-4), rtol=1e-6)
+    # a pure linear extrapolation step has a zero target: the weight is the floor's inverse
+    assert G.sample_weight(x2, x1, 2 * x1 - x2, sigma) == pytest.approx(1e4, rel=1e-9)
 
 
 def test_quantized_forward_rounds_at_the_stated_boundaries():
