@@ -130,21 +130,52 @@ typedef struct {
 int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
                chm_solver_t **out);
 
-/* Set the state.  phi_p, phi_n: required, n_vertices values each.  mu_p,
- * mu_n: optional (NULL = 0); they are only the first Krylov guess of the
- * next step. */
+/* What may differ between the runs of a batch (chm_create_batch): the
+ * interaction parameters of the Flory-Huggins energy and the solvent removal
+ * (evap_ds per step for the first evap_steps steps). */
+typedef struct {
+    double chi_pn, chi_ps, chi_ns;
+    double evap_ds;
+    int32_t evap_steps;
+} chm_run_t;
+
+/* A batch of `runs` (1..64) independent runs on one mesh with one set of
+ * parameters except for run[r] (NULL: every run takes params' values).  The
+ * runs share the assembled matrices and both AMG hierarchies (none of them
+ * depends on the per-run values) and advance together: every kernel launch
+ * of a time step covers all runs, each with its own vectors, reductions,
+ * Krylov control and convergence test, so each run takes the iterates it
+ * would take alone.  chm_create is chm_create_batch with one run.  The
+ * inspection calls below (chm_vcycle ... chm_rhs) work on run 0. */
+int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t runs,
+                     const chm_run_t *run, void *stream, chm_solver_t **out);
+
+/* Number of runs of the solver (1 for chm_create). */
+int chm_batch_size(const chm_solver_t *s);
+
+/* Set the state (of run 0).  phi_p, phi_n: required, n_vertices values each.
+ * mu_p, mu_n: optional (NULL = 0); they are only the first Krylov guess of
+ * the next step. */
 int chm_set_fields(chm_solver_t *s, const double *phi_p, const double *phi_n,
                    const double *mu_p, const double *mu_n, int32_t on_device);
+/* The same for run `run` of a batch. */
+int chm_set_fields_run(chm_solver_t *s, int32_t run, const double *phi_p, const double *phi_n,
+                       const double *mu_p, const double *mu_n, int32_t on_device);
 
 /* Advance nsteps time steps (eq. FE_systems for both species, then
- * phi_s = 1 - phi_p - phi_n and the optional solvent removal).  stats may be
- * NULL or hold nsteps entries.  On CHM_ENOCONV / CHM_ENAN the state is left
- * at the last completed step and the failing step's stats are filled. */
+ * phi_s = 1 - phi_p - phi_n and the optional solvent removal) of every run.
+ * stats may be NULL or hold nsteps * runs entries (step-major: entry
+ * k * runs + r for run r of step k).  On CHM_ENOCONV / CHM_ENAN (of any run)
+ * every run is left at the last completed step and the failing step's stats
+ * are filled. */
 int chm_step(chm_solver_t *s, int32_t nsteps, chm_stats_t *stats);
 
-/* Copy out the state; any pointer may be NULL. */
+/* Copy out the state (of run 0); any pointer may be NULL. */
 int chm_get_fields(chm_solver_t *s, double *phi_p, double *phi_n, double *phi_s,
                    double *mu_p, double *mu_n, int32_t on_device);
+/* The same for run `run` of a batch. */
+int chm_get_fields_run(chm_solver_t *s, int32_t run, double *phi_p, double *phi_n, double *phi_s,
+                       double *mu_p, double *mu_n, int32_t on_device);
 
 int chm_destroy(chm_solver_t *s);
 

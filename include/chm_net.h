@@ -146,11 +146,11 @@ int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int3
  * the network's max_pixels). */
 int chm_set_guess(chm_solver_t *s, int32_t mode, chm_net_t *net, int32_t H, int32_t W);
 
-/* Copy a state vector (4 n_vertices doubles, layout above) into device
- * memory: which = 0 the current state, 1 the last solution of the solve (the
- * current state before the solvent removal of the last step; the state set by
- * chm_set_fields before the first step).  The learned guess is trained on the
- * sequence of solutions (which = 1). */
+/* Copy a state vector (4 n_vertices doubles, layout above; run 0 of a batch)
+ * into device memory: which = 0 the current state, 1 the last solution of the
+ * solve (the current state before the solvent removal of the last step; the
+ * state set by chm_set_fields before the first step).  The learned guess is
+ * trained on the sequence of solutions (which = 1). */
 int chm_get_state(chm_solver_t *s, int32_t which, double *state);
 
 #ifdef __cplusplus

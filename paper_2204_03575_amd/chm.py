@@ -30,6 +30,7 @@ ENTRY_POINTS = [
     "chm_net_create", "chm_net_destroy", "chm_net_last_error", "chm_net_set_params",
     "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
+    "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -61,6 +62,11 @@ class chm_params_t(C.Structure):
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("use_graphs", C.c_int32),
         ("precision", C.c_int32),
     ]
+
+
+class chm_run_t(C.Structure):
+    _fields_ = [("chi_pn", C.c_double), ("chi_ps", C.c_double), ("chi_ns", C.c_double),
+                ("evap_ds", C.c_double), ("evap_steps", C.c_int32)]
 
 
 class chm_stats_t(C.Structure):
@@ -117,6 +123,10 @@ def library():
                                     C.c_float, P(d)], C.c_int),
             "chm_set_guess": ([vp, i32, vp, i32, i32], C.c_int),
             "chm_get_state": ([vp, i32, vp], C.c_int),
+            "chm_create_batch": ([P(chm_mesh_t), P(chm_params_t), i32, vp, vp, P(vp)], C.c_int),
+            "chm_batch_size": ([vp], C.c_int),
+            "chm_set_fields_run": ([vp, i32, vp, vp, vp, vp, i32], C.c_int),
+            "chm_get_fields_run": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -170,10 +180,22 @@ def chm_quadrature(dim: int):
     return bary[: k * (dim + 1)].reshape(k, dim + 1).copy(), w[:k].copy()
 
 
-class Solver:
-    """One chm_solver_t on the current torch device and stream."""
+def run_from_dict(p: dict) -> chm_run_t:
+    """The per-run values of a parameter dict (chi's, solvent removal)."""
+    r = chm_run_t()
+    r.chi_pn, r.chi_ps, r.chi_ns = float(p["chi_pn"]), float(p["chi_ps"]), float(p["chi_ns"])
+    r.evap_ds = float(p.get("evap_ds", 0.0))
+    r.evap_steps = int(p.get("evap_steps", p.get("steps", 0))) if r.evap_ds > 0 else 0
+    return r
 
-    def __init__(self, coords: np.ndarray, cells: np.ndarray, params: dict, stream=None):
+
+class Solver:
+    """One chm_solver_t on the current torch device and stream.  runs: None
+    for one run, or a list of parameter dicts (one per run of a batch; only
+    their chi's and solvent removal may differ from params)."""
+
+    def __init__(self, coords: np.ndarray, cells: np.ndarray, params: dict, stream=None,
+                 runs=None):
         import torch
         self.torch = torch
         self.lib = library()
@@ -189,7 +211,14 @@ class Solver:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         h = C.c_void_p()
-        rc = self.lib.chm_create(C.byref(mesh), C.byref(self._prm), C.c_void_p(stream), C.byref(h))
+        self.nb = 1 if runs is None else len(runs)
+        if runs is None:
+            rc = self.lib.chm_create(C.byref(mesh), C.byref(self._prm), C.c_void_p(stream),
+                                     C.byref(h))
+        else:
+            rp = (chm_run_t * self.nb)(*[run_from_dict(dict(params, **r)) for r in runs])
+            rc = self.lib.chm_create_batch(C.byref(mesh), C.byref(self._prm), self.nb, rp,
+                                           C.c_void_p(stream), C.byref(h))
         if rc != CHM_OK:
             msg = self.lib.chm_last_error(None)
             raise ChmError(rc, f"chm_create: {msg.decode() if msg else ''}")
@@ -204,31 +233,35 @@ class Solver:
         self.close()
 
     # ---- state
-    def set_fields(self, phi_p, phi_n, mu_p=None, mu_n=None):
+    def set_fields(self, phi_p, phi_n, mu_p=None, mu_n=None, run: int = 0):
         torch = self.torch
         ts = [None if a is None else torch.as_tensor(np.asarray(a, dtype=np.float64)).cuda()
               for a in (phi_p, phi_n, mu_p, mu_n)]
         ptrs = [None if t is None else _dev_ptr(t) for t in ts]
-        rc = self.lib.chm_set_fields(self.h, *ptrs, 1)
+        rc = self.lib.chm_set_fields_run(self.h, run, *ptrs, 1)
         _check(self.h, rc, "chm_set_fields")
 
-    def get_fields(self) -> dict:
+    def get_fields(self, run: int = 0) -> dict:
         torch = self.torch
         out = {k: torch.empty(self.nv, dtype=torch.float64, device="cuda")
                for k in ("phi_p", "phi_n", "phi_s", "mu_p", "mu_n")}
-        rc = self.lib.chm_get_fields(self.h, *(_dev_ptr(out[k]) for k in
-                                               ("phi_p", "phi_n", "phi_s", "mu_p", "mu_n")), 1)
+        rc = self.lib.chm_get_fields_run(self.h, run, *(_dev_ptr(out[k]) for k in
+                                                        ("phi_p", "phi_n", "phi_s", "mu_p",
+                                                         "mu_n")), 1)
         _check(self.h, rc, "chm_get_fields")
         return {k: v.cpu().numpy() for k, v in out.items()}
 
     def step(self, nsteps: int = 1):
-        st = (chm_stats_t * max(1, nsteps))()
+        """Per step: a stats dict (one run) or a list of them (one per run)."""
+        nb = self.nb
+        st = (chm_stats_t * max(1, nsteps * nb))()
         rc = self.lib.chm_step(self.h, nsteps, st)
-        stats = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
-                      status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms,
-                      guess_used=(s.guess_used[0], s.guess_used[1]),
-                      res0=(s.res0[0], s.res0[1]))
-                 for s in st[:nsteps]]
+        flat = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
+                     status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms,
+                     guess_used=(s.guess_used[0], s.guess_used[1]),
+                     res0=(s.res0[0], s.res0[1]))
+                for s in st[:nsteps * nb]]
+        stats = flat if nb == 1 else [flat[k * nb:(k + 1) * nb] for k in range(nsteps)]
         if rc != CHM_OK:
             msg = self.lib.chm_last_error(self.h)
             err = ChmError(rc, f"chm_step: {msg.decode() if msg else ''}")

@@ -681,10 +681,11 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
             L.gsP = lanes_per_row(L.P);
             L.gsR = lanes_per_row(L.R);
         }
-        H.x[l] = pool.get<double2>(L.n);
-        H.xt[l] = pool.get<double2>(L.n);
-        H.b[l] = pool.get<double2>(L.n);
-        H.r[l] = pool.get<double2>(L.n);
+        const size_t len = (size_t)S.nb * L.n;   // all runs of the batch
+        H.x[l] = pool.get<double2>(len);
+        H.xt[l] = pool.get<double2>(len);
+        H.b[l] = pool.get<double2>(len);
+        H.r[l] = pool.get<double2>(len);
     }
     CHM_HIP(hipStreamSynchronize(st));
 }

@@ -98,10 +98,24 @@ extern "C" {
 int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
                chm_solver_t **out)
 {
+    return chm_create_batch(mesh, params, 1, nullptr, stream, out);
+}
+
+int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t runs,
+                     const chm_run_t *run_params, void *stream, chm_solver_t **out)
+{
     if (out)
         *out = nullptr;
     if (!mesh || !params || !out)
         return fail(nullptr, CHM_EINVAL, "chm_create: NULL argument");
+    if (runs < 1 || runs > chm::kMaxRuns)
+        return fail(nullptr, CHM_EINVAL, "chm_create: runs must be in 1..64");
+    if (run_params)
+        for (int r = 0; r < runs; ++r)
+            if (!(run_params[r].evap_ds >= 0.0) || run_params[r].evap_steps < 0 ||
+                !std::isfinite(run_params[r].chi_pn) || !std::isfinite(run_params[r].chi_ps) ||
+                !std::isfinite(run_params[r].chi_ns))
+                return fail(nullptr, CHM_EINVAL, "chm_create: bad run parameters");
     if ((mesh->dim != 2 && mesh->dim != 3) || mesh->n_vertices < 1 || mesh->n_cells < 1 ||
         !mesh->coords || !mesh->cells || mesh->n_vertices > 0x3fffffff || mesh->n_cells > 0x1fffffff)
         return fail(nullptr, CHM_EINVAL, "chm_create: bad mesh dimensions or pointers");
@@ -123,6 +137,25 @@ int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
         auto t0 = std::chrono::steady_clock::now();
         S.stream = static_cast<hipStream_t>(stream);
         S.prm = *params;
+        S.nb = runs;
+        S.nrun = 1;
+        S.runs.resize(runs);
+        for (int r = 0; r < runs; ++r) {
+            chm::RunPrm &P = S.runs[r];
+            if (run_params) {
+                P.chi_pn = run_params[r].chi_pn;
+                P.chi_ps = run_params[r].chi_ps;
+                P.chi_ns = run_params[r].chi_ns;
+                P.evap_ds = run_params[r].evap_ds;
+                P.evap_steps = run_params[r].evap_steps;
+            } else {
+                P.chi_pn = params->chi_pn;
+                P.chi_ps = params->chi_ps;
+                P.chi_ns = params->chi_ns;
+                P.evap_ds = params->evap_ds;
+                P.evap_steps = params->evap_steps;
+            }
+        }
         S.dim = mesh->dim;
         S.nv = (int)mesh->n_vertices;
         S.ncell = (int)mesh->n_cells;
@@ -168,24 +201,34 @@ int chm_create(const chm_mesh_t *mesh, const chm_params_t *params, void *stream,
 int chm_set_fields(chm_solver_t *h, const double *phi_p, const double *phi_n, const double *mu_p,
                    const double *mu_n, int32_t on_device)
 {
+    return chm_set_fields_run(h, 0, phi_p, phi_n, mu_p, mu_n, on_device);
+}
+
+int chm_set_fields_run(chm_solver_t *h, int32_t run, const double *phi_p, const double *phi_n,
+                       const double *mu_p, const double *mu_n, int32_t on_device)
+{
     if (!h)
         return fail(nullptr, CHM_EINVAL, "chm_set_fields: NULL handle");
     if (!phi_p || !phi_n)
         return fail(h, CHM_EINVAL, "chm_set_fields: phi_p and phi_n are required");
+    if (run < 0 || run >= h->s.nb)
+        return fail(h, CHM_EINVAL, "chm_set_fields: run out of range");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
         const int n = S.nv;
-        double *x = reinterpret_cast<double *>(S.x);
+        double2 *xr = S.x + (size_t)run * 2 * n;
+        double *x = reinterpret_cast<double *>(xr);
         copy_field(x, n, 0, phi_p, on_device, S.stream);
         copy_field(x, n, 1, phi_n, on_device, S.stream);
-        double *mu = reinterpret_cast<double *>(S.x + n);
+        double *mu = reinterpret_cast<double *>(xr + n);
         chm::fill_double(mu, 0.0, 2 * (size_t)n, S.stream);
         if (mu_p)
             copy_field(mu, n, 0, mu_p, on_device, S.stream);
         if (mu_n)
             copy_field(mu, n, 1, mu_n, on_device, S.stream);
-        // the new state starts the history of solutions
-        CHM_HIP(hipMemcpyAsync(S.yh1, S.x, sizeof(double2) * 2 * (size_t)n,
+        // the new state starts the history of solutions (of every run: the
+        // runs of a batch share it)
+        CHM_HIP(hipMemcpyAsync(S.yh1 + (size_t)run * 2 * n, xr, sizeof(double2) * 2 * (size_t)n,
                                hipMemcpyDeviceToDevice, S.stream));
         S.hist = 1;
         CHM_HIP(hipStreamSynchronize(S.stream));
@@ -201,7 +244,7 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
         return fail(h, CHM_EINVAL, "chm_step: nsteps < 0");
     return guarded(h, [&]() {
         for (int k = 0; k < nsteps; ++k) {
-            int rc = chm::step_once(h->s, stats ? stats + k : nullptr);
+            int rc = chm::step_once(h->s, stats ? stats + (size_t)k * h->s.nb : nullptr);
             if (rc != CHM_OK)
                 return fail(h, rc, rc == CHM_ENOCONV
                                        ? "FGMRES did not converge within max_iters"
@@ -214,13 +257,22 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
 int chm_get_fields(chm_solver_t *h, double *phi_p, double *phi_n, double *phi_s, double *mu_p,
                    double *mu_n, int32_t on_device)
 {
+    return chm_get_fields_run(h, 0, phi_p, phi_n, phi_s, mu_p, mu_n, on_device);
+}
+
+int chm_get_fields_run(chm_solver_t *h, int32_t run, double *phi_p, double *phi_n, double *phi_s,
+                       double *mu_p, double *mu_n, int32_t on_device)
+{
     if (!h)
         return fail(nullptr, CHM_EINVAL, "chm_get_fields: NULL handle");
+    if (run < 0 || run >= h->s.nb)
+        return fail(h, CHM_EINVAL, "chm_get_fields: run out of range");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
         const int n = S.nv;
-        const double *x = reinterpret_cast<const double *>(S.x);
-        const double *mu = reinterpret_cast<const double *>(S.x + n);
+        const double2 *xr = S.x + (size_t)run * 2 * n;
+        const double *x = reinterpret_cast<const double *>(xr);
+        const double *mu = reinterpret_cast<const double *>(xr + n);
         if (phi_p)
             get_field(phi_p, x, n, 0, on_device, S.stream);
         if (phi_n)
@@ -358,6 +410,7 @@ int chm_vcycle(chm_solver_t *h, int32_t hierarchy, const double *b, double *x)
         return fail(h, CHM_EINVAL, "chm_vcycle: bad arguments");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
+        S.nrun = 1;   // run 0's buffers; the caller's vectors are one run's
         chm::vcycle(S, hierarchy, reinterpret_cast<const double2 *>(b),
                     reinterpret_cast<double2 *>(x));
         CHM_HIP(hipGetLastError());
@@ -371,6 +424,7 @@ int chm_schur_solve(chm_solver_t *h, const double *b, double *x)
     if (!h || !b || !x)
         return fail(h, CHM_EINVAL, "chm_schur_solve: bad arguments");
     return guarded(h, [&]() {
+        h->s.nrun = 1;
         chm::schur_solve(h->s, reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(x));
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(h->s.stream));
@@ -383,6 +437,7 @@ int chm_apply_saddle(chm_solver_t *h, const double *x, double *y)
     if (!h || !x || !y)
         return fail(h, CHM_EINVAL, "chm_apply_saddle: bad arguments");
     return guarded(h, [&]() {
+        h->s.nrun = 1;
         chm::apply_saddle(h->s, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y));
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(h->s.stream));
@@ -395,6 +450,7 @@ int chm_apply_prec(chm_solver_t *h, const double *v, double *w)
     if (!h || !v || !w)
         return fail(h, CHM_EINVAL, "chm_apply_prec: bad arguments");
     return guarded(h, [&]() {
+        h->s.nrun = 1;
         chm::apply_prec(h->s, reinterpret_cast<const double2 *>(v), reinterpret_cast<double2 *>(w));
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(h->s.stream));
@@ -408,6 +464,7 @@ int chm_rhs(chm_solver_t *h, double *b)
         return fail(h, CHM_EINVAL, "chm_rhs: bad arguments");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
+        S.nrun = 1;
         chm::compute_rhs(S);
         CHM_HIP(hipMemcpyAsync(b, S.b, sizeof(double2) * 2 * (size_t)S.nv, hipMemcpyDeviceToDevice,
                                S.stream));
@@ -515,5 +572,7 @@ int chm_get_state(chm_solver_t *h, int32_t which, double *state)
         return CHM_OK;
     });
 }
+
+int chm_batch_size(const chm_solver_t *h) { return h ? h->s.nb : CHM_EINVAL; }
 
 }  // extern "C"

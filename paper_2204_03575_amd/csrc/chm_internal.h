@@ -31,6 +31,7 @@ constexpr int kSlice = 64;      // SELL slice height = wavefront size
 constexpr int kBlock = 256;     // threads per block for row kernels
 constexpr int kMaxLevels = 24;
 constexpr int kMaxRestart = 64;
+constexpr int kMaxRuns = 64;      // runs of one batched solver
 constexpr int kRedBlocks = 256;   // blocks of the two-stage reductions (one per CU)
 constexpr int kGsBlocks = 1024;   // blocks of the Gram-Schmidt passes (four per CU)
 
@@ -96,7 +97,7 @@ struct Sell {      // device SELL-64
 // pattern; gs = lanes per row (0: SELL-64 with one lane per row, 4..32: CSR
 // with that many lanes per row, for long or few rows).
 template <class T> struct MatView {
-    int n = 0, nnz = 0, gs = 0;
+    int n = 0, m = 0, nnz = 0, gs = 0;   // rows, columns, nonzeros, lanes per row
     const int *sptr = nullptr, *col = nullptr, *rp = nullptr, *ci = nullptr;
     const T *sval = nullptr, *cval = nullptr;
 };
@@ -126,17 +127,18 @@ struct Level {
 
 template <class T> inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, const T *sv, const T *cv)
 {
-    MatView<T> m;
-    m.n = C.n;
-    m.nnz = C.nnz;
-    m.gs = gs;
-    m.sptr = S.sptr;
-    m.col = S.col;
-    m.rp = C.rp;
-    m.ci = C.ci;
-    m.sval = sv;
-    m.cval = cv;
-    return m;
+    MatView<T> v;
+    v.n = C.n;
+    v.m = C.m;
+    v.nnz = C.nnz;
+    v.gs = gs;
+    v.sptr = S.sptr;
+    v.col = S.col;
+    v.rp = C.rp;
+    v.ci = C.ci;
+    v.sval = sv;
+    v.cval = cv;
+    return v;
 }
 template <> inline MatView<double> Level::viewA<double>() const { return make_view<double>(A, sA, gsA, sA.val, A.v); }
 template <> inline MatView<double> Level::viewP<double>() const { return make_view<double>(P, sP, gsP, sP.val, P.v); }
@@ -162,10 +164,12 @@ template <class T> struct Work;   // per-precision work vectors of the precondit
 template <> struct Work<double> {
     double2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
     double2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+    double2 *h1 = nullptr, *h2 = nullptr;     // block-vector halves of a batch
 };
 template <> struct Work<float> {
     float2 *pcg_r = nullptr, *pcg_z = nullptr, *pcg_d = nullptr, *pcg_q = nullptr;
     float2 *tmp = nullptr, *tmp2 = nullptr, *mr = nullptr, *me = nullptr;
+    float2 *h1 = nullptr, *h2 = nullptr;
     float2 *vin = nullptr, *wout = nullptr;   // block vectors at the FP64 boundary
 };
 
@@ -189,6 +193,7 @@ struct Ctl {
     double y[2][kMaxRestart];
 };
 constexpr size_t kCtlHead = offsetof(Ctl, H);
+static_assert(kCtlHead % 16 == 0, "control-block heads are packed back to back");
 
 struct Timer {
     bool on = false;
@@ -200,10 +205,25 @@ struct Timer {
     int64_t bytes = 0;             // algorithmic bytes of the timed launches
 };
 
+// what differs between the runs of a batch: the interaction parameters of
+// the free energy and the solvent removal
+struct RunPrm {
+    double chi_pn = 1.0, chi_ps = 0.3, chi_ns = 0.3;
+    double evap_ds = 0.0;
+    int evap_steps = 0;
+};
+
 struct Solver {
     Err err;
     hipStream_t stream = nullptr;
     chm_params_t prm{};
+    // Runs of the batch: nb runs share the mesh, the matrices and both AMG
+    // hierarchies; every per-run vector holds the runs back to back.  nrun is
+    // how many runs a launch covers (gridDim.y): nb for time steps, 1 for the
+    // inspection calls, which work on run 0.
+    int nb = 1, nrun = 1;
+    std::vector<RunPrm> runs;
+    void *pots = nullptr;      // device: per-run potential parameters
     int dim = 0, nv = 0, ncell = 0, nl = 0;
     Pool pool;
 
@@ -231,7 +251,8 @@ struct Solver {
     double2 *x = nullptr;      // current state as a block vector: (phi, mu)
     double2 *xk = nullptr;     // FGMRES iterate (committed to x on success)
     double2 *b = nullptr, *r = nullptr;
-    double2 *V = nullptr, *Z = nullptr;
+    double2 *V = nullptr, *Z = nullptr;   // [Krylov index][run][2n]
+    double2 *xl = nullptr;     // linear-extrapolation candidate
     double2 *f = nullptr;      // potential term of the right-hand side (pairs)
     Work<double> w64;
     Work<float> w32;
@@ -240,8 +261,9 @@ struct Solver {
     double2 *red = nullptr;    // slots of per-block partial sums (kRedBlocks each)
     double2 *gsp1 = nullptr, *gsp2 = nullptr, *gsp3 = nullptr;  // Gram-Schmidt partials
     double2 *hfin = nullptr;   // finalised Gram-Schmidt coefficients of both passes
-    Ctl *ctl = nullptr;        // device
-    Ctl *hctl = nullptr;       // pinned host mirror
+    Ctl *ctl = nullptr;        // device, one per run
+    Ctl *hctl = nullptr;       // pinned host mirror (heads), one per run
+    int *dheads = nullptr;     // device staging of the heads of a batch
     int64_t step_count = 0;
     double setup_ms = 0.0;
     Timer timer;

@@ -118,8 +118,15 @@ __device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 
 // residual norm (81) and the residual norms of the initial-guess candidates
 // (82 + CHM_GUESS_*: previous state, linear extrapolation, network).
 constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotGuess = 82, kSlots = 85;
+constexpr long kSlotStride = (long)kSlots * kRedBlocks;   // per run
 
+// run 0's slot k; run r's is kSlotStride further
 inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; }
+
+// Batched launches: blockIdx.y is the run, and every per-run array of a kernel
+// is offset by the run times its stride (elements).
+template <class P> __device__ inline P *run_at(P *p, long stride) { return p ? p + blockIdx.y * stride : p; }
+inline dim3 grid(int x, int runs) { return dim3(x, runs); }
 
 // ------------------------------------------------------------------ SpMV family (pairs)
 // SP_SET: y = A x; SP_ADD: y += A x; SP_RESID: y = b - A x
@@ -160,16 +167,21 @@ __device__ inline void spmv_store(pair_t<T> s, const pair_t<T> *__restrict__ b, 
     }
 }
 
+// per run: x advances by sx, b and y by sy
 template <int MODE, class T>
 __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
                                                  const int *__restrict__ col,
                                                  const T *__restrict__ val,
-                                                 const pair_t<T> *__restrict__ x,
-                                                 const pair_t<T> *__restrict__ b, pair_t<T> *y)
+                                                 const pair_t<T> *__restrict__ x, long sx,
+                                                 const pair_t<T> *__restrict__ b, pair_t<T> *y,
+                                                 long sy)
 {
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
+    x = run_at(x, sx);
+    b = run_at(b, sy);
+    y = run_at(y, sy);
     spmv_store<MODE, T>(sell_row<T>(sptr, col, val, x, row), b, y, row);
 }
 
@@ -202,50 +214,69 @@ template <int GS, int MODE, class T>
 __global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
                                                    const T *__restrict__ v,
-                                                   const pair_t<T> *__restrict__ x,
-                                                   const pair_t<T> *__restrict__ b, pair_t<T> *y)
+                                                   const pair_t<T> *__restrict__ x, long sx,
+                                                   const pair_t<T> *__restrict__ b, pair_t<T> *y,
+                                                   long sy)
 {
     const int t = xcd_block() * kBlock + threadIdx.x;
     const int row = t / GS, lane = t % GS;
     if (row >= n)
         return;
+    x = run_at(x, sx);
+    b = run_at(b, sy);
+    y = run_at(y, sy);
     const pair_t<T> s = row_dot<GS, T>(rp, ci, v, x, row, lane);
     if (lane == 0)
         spmv_store<MODE, T>(s, b, y, row);
 }
 
-// y = A x / y += A x / y = b - A x with the kernel shape chosen for the matrix
+// y = A x / y += A x / y = b - A x with the kernel shape chosen for the
+// matrix, for `runs` runs whose x are A.m apart and whose b, y are A.n apart
+// (or sx, sy when given)
 template <int MODE, class T>
-void spmv_op(hipStream_t st, const MatView<T> &A, const pair_t<T> *x, const pair_t<T> *b,
-             pair_t<T> *y)
+void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
+             const pair_t<T> *b, pair_t<T> *y, long sx = -1, long sy = -1)
 {
     const int n = A.n;
+    if (sx < 0)
+        sx = A.m;
+    if (sy < 0)
+        sy = A.n;
     switch (A.gs) {
     case 0:
-        k_spmv<MODE, T><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, x, b, y);
+        k_spmv<MODE, T><<<grid(nblk(n), runs), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, x, sx, b,
+                                                                y, sy);
         break;
     case 4:
-        k_spmv_v<4, MODE, T><<<nblk(4l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        k_spmv_v<4, MODE, T><<<grid(nblk(4l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x,
+                                                                          sx, b, y, sy);
         break;
     case 8:
-        k_spmv_v<8, MODE, T><<<nblk(8l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        k_spmv_v<8, MODE, T><<<grid(nblk(8l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x,
+                                                                          sx, b, y, sy);
         break;
     case 16:
-        k_spmv_v<16, MODE, T><<<nblk(16l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        k_spmv_v<16, MODE, T><<<grid(nblk(16l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval,
+                                                                            x, sx, b, y, sy);
         break;
     default:
-        k_spmv_v<32, MODE, T><<<nblk(32l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x, b, y);
+        k_spmv_v<32, MODE, T><<<grid(nblk(32l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval,
+                                                                            x, sx, b, y, sy);
         break;
     }
 }
 
 // ------------------------------------------------------------------ vector kernels
-// per-block partial sums of the two species' dot products, accumulated in FP64
+// per-block partial sums of the two species' dot products, accumulated in
+// FP64; per run, a and b advance by n and part by one run's slots
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restrict__ a,
                                                 const pair_t<T> *__restrict__ b, double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
+    a = run_at(a, n);
+    b = run_at(b, n);
+    part = run_at(part, kSlotStride);
     double2 acc = d2(0.0, 0.0);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const pair_t<T> x = a[i], y = b[i];
@@ -257,12 +288,13 @@ __global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restri
         part[blockIdx.x] = s;
 }
 
+// per run, a and b advance by n
 template <class P>
 __global__ void __launch_bounds__(kBlock) k_copy(int n, const P *__restrict__ a, P *b)
 {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row < n)
-        b[row] = a[row];
+        run_at(b, n)[row] = run_at(a, n)[row];
 }
 
 }  // namespace

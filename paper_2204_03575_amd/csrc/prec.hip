@@ -4,6 +4,9 @@
 // preconditioned by one V-cycle.  Both species run through every kernel
 // together (pair vectors), each with its own CG scalars.
 //
+// Batches: every launch covers S.nrun runs (gridDim.y), all vectors of a
+// level holding the runs back to back (run r of an n-row vector at r n).
+//
 // All of it is templated on the value type T.  T = double is the FP64 path.
 // T = float is the mixed-precision preconditioner: FP32 matrix values, work
 // vectors, smoothing, restriction, prolongation and the product with M inside
@@ -53,6 +56,9 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
+    b = run_at(b, n);
+    xk = run_at(xk, n);
+    xprev = run_at(xprev, n);
     const pair_t<T> s = sell_row<T>(sptr, col, val, xk, row);
     xprev[row] = cheb_update<T>(s, b, xk, dinv, xprev, row, c1, c2, prev);
 }
@@ -70,6 +76,9 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
     const int row = t / GS, lane = t % GS;
     if (row >= n)
         return;
+    b = run_at(b, n);
+    xk = run_at(xk, n);
+    xprev = run_at(xprev, n);
     const pair_t<T> s = row_dot<GS, T>(rp, ci, v, xk, row, lane);
     if (lane != 0)
         return;
@@ -85,9 +94,9 @@ __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ d
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    const pair_t<T> bb = b[row];
+    const pair_t<T> bb = run_at(b, n)[row];
     const T di = dinv[row];
-    x[row] = mk<T>(c2 * (di * bb.x), c2 * (di * bb.y));
+    run_at(x, n)[row] = mk<T>(c2 * (di * bb.x), c2 * (di * bb.y));
 }
 
 // coarsest level: x = A^-1 b with the FP64 inverse stored row-major.  One
@@ -101,6 +110,8 @@ __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restric
     __shared__ double2 sh[kBlock / 64];
     const int row = blockIdx.x;
     const double *a = inv + (size_t)row * n;
+    b = run_at(b, n);
+    x = run_at(x, n);
     double2 acc = d2(0.0, 0.0);
     for (int j = threadIdx.x; j < n; j += kBlock) {
         const double v = a[j];
@@ -120,6 +131,8 @@ __global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const pair_t<T> *__r
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n)
         return;
+    e = run_at(e, n);
+    x = run_at(x, n);
     const pair_t<T> a = x[row], b = e[row];
     x[row] = mk<T>(a.x + b.x, a.y + b.y);
 }
@@ -142,10 +155,15 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, pair_t<T> *x, pair_t<T
                                                    int first)
 {
     __shared__ double2 sc[2];
-    reduce_two(rz_part, dq_part, G, sc);
+    reduce_two(run_at(rz_part, kSlotStride), run_at(dq_part, kSlotStride), G, sc);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
+    x = run_at(x, n);
+    r = run_at(r, n);
+    b = run_at(b, n);
+    d = run_at(d, n);
+    q = run_at(q, n);
     const double2 al = ratio_or_zero(sc[0], sc[1]);
     const T ax = T(al.x), ay = T(al.y);
     const pair_t<T> dv = d[i], qv = q[i];
@@ -169,10 +187,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const pair_t<T> *__re
 {
     __shared__ double2 sc[2];
     if (!first)
-        reduce_two(new_part, old_part, G, sc);
+        reduce_two(run_at(new_part, kSlotStride), run_at(old_part, kSlotStride), G, sc);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
+    z = run_at(z, n);
+    d = run_at(d, n);
     const pair_t<T> zv = z[i];
     if (first) {
         d[i] = zv;
@@ -184,14 +204,35 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const pair_t<T> *__re
     d[i] = mk<T>(zv.x + bx * dv.x, zv.y + by * dv.y);
 }
 
+// ------------------------------------------------------------------ batch layout
+// per run: out[0..n) = in[run * stride + 0..n) (a half of a block vector into
+// a contiguous work vector) and back
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_gather_half(int n, const pair_t<T> *__restrict__ in,
+                                                        long stride, pair_t<T> *out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        run_at(out, n)[i] = run_at(in, stride)[i];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_scatter_half(int n, const pair_t<T> *__restrict__ in,
+                                                         pair_t<T> *out, long stride)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        run_at(out, stride)[i] = run_at(in, n)[i];
+}
+
 // ------------------------------------------------------------------ precision boundary
 __global__ void __launch_bounds__(kBlock) k_narrow_pairs(int n, const double2 *__restrict__ a,
                                                          float2 *b)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
-        const double2 v = a[i];
-        b[i] = make_float2(float(v.x), float(v.y));
+        const double2 v = run_at(a, n)[i];
+        run_at(b, n)[i] = make_float2(float(v.x), float(v.y));
     }
 }
 
@@ -200,8 +241,8 @@ __global__ void __launch_bounds__(kBlock) k_widen_pairs(int n, const float2 *__r
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
-        const float2 v = a[i];
-        b[i] = make_double2(double(v.x), double(v.y));
+        const float2 v = run_at(a, n)[i];
+        run_at(b, n)[i] = make_double2(double(v.x), double(v.y));
     }
 }
 
@@ -246,36 +287,37 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     const MatView<T> A = L.viewA<T>();
     const T *dinv = L.dinv_t<T>();
     const T c1 = T(c1d), c2 = T(c2d);
-    const int n = L.n;
+    const int n = L.n, R = S.nrun;
     hipStream_t st = S.stream;
     switch (A.gs) {
     case 0:
-        k_cheb<T><<<nblk(n), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b, xk, xprev, c1, c2,
-                                              prev);
+        k_cheb<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b, xk, xprev,
+                                                       c1, c2, prev);
         break;
     case 4:
-        k_cheb_v<4, T><<<nblk(4l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk, xprev,
-                                                        c1, c2, prev);
+        k_cheb_v<4, T><<<grid(nblk(4l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
+                                                                 xprev, c1, c2, prev);
         break;
     case 8:
-        k_cheb_v<8, T><<<nblk(8l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk, xprev,
-                                                        c1, c2, prev);
+        k_cheb_v<8, T><<<grid(nblk(8l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
+                                                                 xprev, c1, c2, prev);
         break;
     case 16:
-        k_cheb_v<16, T><<<nblk(16l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
-                                                          xprev, c1, c2, prev);
+        k_cheb_v<16, T><<<grid(nblk(16l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b,
+                                                                   xk, xprev, c1, c2, prev);
         break;
     default:
-        k_cheb_v<32, T><<<nblk(32l * n), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
-                                                          xprev, c1, c2, prev);
+        k_cheb_v<32, T><<<grid(nblk(32l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b,
+                                                                   xk, xprev, c1, c2, prev);
         break;
     }
     if (timed_level(S, H, l)) {
-        // algorithmic bytes: column index + value per nonzero; per row x_k
-        // (gathered once), b, D^-1, x_{k-1} (when read) and the written x_{k+1}
+        // algorithmic bytes: column index + value per nonzero (once per
+        // launch); per row and run x_k (gathered once), b, D^-1, x_{k-1}
+        // (when read) and the written x_{k+1}
         S.timer.count += 1;
         S.timer.bytes += (long long)(sizeof(int) + sizeof(T)) * L.A.nnz +
-                         (long long)(prev ? 9 : 7) * sizeof(T) * L.n;
+                         (long long)R * (prev ? 9 : 7) * sizeof(T) * L.n;
     }
 }
 
@@ -284,8 +326,9 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
 {
     const Level &L = H.lev[l];
     hipStream_t st = S.stream;
+    const int R = S.nrun;
     if (l == H.nlev - 1) {
-        k_dense<T><<<L.n, kBlock, 0, st>>>(L.n, L.inv, b, x);
+        k_dense<T><<<grid(L.n, R), kBlock, 0, st>>>(L.n, L.inv, b, x);
         return;
     }
     const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
@@ -295,7 +338,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     // Pre-smoothing from zero.  Every step after the first writes the buffer
     // not holding the current iterate; 2 deg - 1 such steps follow the first,
     // so starting in xt leaves the result in x.
-    k_cheb0<T><<<nblk(L.n), kBlock, 0, st>>>(L.n, L.dinv_t<T>(), b, V.xt, T(c2(1)));
+    k_cheb0<T><<<grid(nblk(L.n), R), kBlock, 0, st>>>(L.n, L.dinv_t<T>(), b, V.xt, T(c2(1)));
     pair_t<T> *cur = V.xt, *oth = x;
     const bool timed = timed_level(S, H, l);
     if (timed && deg >= 2)
@@ -306,10 +349,10 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     }
     if (timed && deg >= 2)
         timer_mark(S, false);
-    spmv_op<SP_RESID, T>(st, L.viewA<T>(), cur, b, V.r);
-    spmv_op<SP_SET, T>(st, L.viewR<T>(), V.r, nullptr, Vc.b);
+    spmv_op<SP_RESID, T>(st, R, L.viewA<T>(), cur, b, V.r);
+    spmv_op<SP_SET, T>(st, R, L.viewR<T>(), V.r, nullptr, Vc.b);
     vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
-    spmv_op<SP_ADD, T>(st, L.viewP<T>(), Vc.x, nullptr, cur);
+    spmv_op<SP_ADD, T>(st, R, L.viewP<T>(), Vc.x, nullptr, cur);
     if (timed)
         timer_mark(S, true);
     for (int k = 1; k <= deg; ++k) {
@@ -329,9 +372,9 @@ void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
     const int n = L0.n;
     vcycle_level<T>(S, H, 0, b, x);
     for (int c = 1; c < S.prm.amg_cycles; ++c) {
-        spmv_op<SP_RESID, T>(S.stream, L0.viewA<T>(), x, b, W.mr);
+        spmv_op<SP_RESID, T>(S.stream, S.nrun, L0.viewA<T>(), x, b, W.mr);
         vcycle_level<T>(S, H, 0, W.mr, W.me);
-        k_axpy_add<T><<<nblk(n), kBlock, 0, S.stream>>>(n, W.me, x);
+        k_axpy_add<T><<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, W.me, x);
     }
 }
 
@@ -350,46 +393,63 @@ void schur_solve_t(Solver &S, const pair_t<T> *b, pair_t<T> *x)
     Work<T> &W = work<T>(S);
     const MatView<T> A = H.lev[0].viewA<T>();
     pair_t<T> *r = W.pcg_r, *z = W.pcg_z, *d = W.pcg_d, *q = W.pcg_q;
-    const int G = red_blocks(n);
+    const int G = red_blocks(n), R = S.nrun;
     vcycle_level<T>(S, H, 0, b, z);                                    // z = V(b), r = b
-    k_dot<T><<<G, kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
-    k_pcg_dir<T><<<nblk(n), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
+    k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
+    k_pcg_dir<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
     for (int it = 1; it <= k; ++it) {
-        spmv_op<SP_SET, T>(st, A, d, nullptr, q);
-        k_dot<T><<<G, kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
-        k_pcg_xr<T><<<nblk(n), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
-                                                slot(S, kSlotDq + it), G, it == 1);
+        spmv_op<SP_SET, T>(st, R, A, d, nullptr, q);
+        k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
+        k_pcg_xr<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
+                                                         slot(S, kSlotDq + it), G, it == 1);
         if (it == k)
             break;
         vcycle_level<T>(S, H, 0, r, z);
-        k_dot<T><<<G, kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
-        k_pcg_dir<T><<<nblk(n), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
-                                                 slot(S, kSlotRz + it - 1), G, 0);
+        k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
+        k_pcg_dir<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
+                                                          slot(S, kSlotRz + it - 1), G, 0);
     }
 }
 
-// Algorithm 1 on a block vector: w1 = AMG(M) v1; w2 = As^-1 M As^-1 v2
+// Algorithm 1 on a block vector: w1 = AMG(M) v1; w2 = As^-1 M As^-1 v2.
+// A batch holds its runs' block vectors back to back (2n apart); the two
+// halves go through contiguous per-run work vectors (n apart), since the
+// V-cycles take their runs n apart.
 template <class T>
 void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
 {
     Work<T> &W = work<T>(S);
-    const int n = S.nv;
-    stationary<T>(S, S.hM, v, w);
-    schur_solve_t<T>(S, v + n, W.tmp);
-    k_spmv<SP_SET, T><<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col,
-                                                         mass_sell_values<T>(S), W.tmp, nullptr,
-                                                         W.tmp2);
-    schur_solve_t<T>(S, W.tmp2, w + n);
+    const int n = S.nv, R = S.nrun;
+    hipStream_t st = S.stream;
+    const long len = 2l * n;
+    if (R == 1) {
+        stationary<T>(S, S.hM, v, w);
+        schur_solve_t<T>(S, v + n, W.tmp);
+        k_spmv<SP_SET, T><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, mass_sell_values<T>(S),
+                                                       W.tmp, n, nullptr, W.tmp2, n);
+        schur_solve_t<T>(S, W.tmp2, w + n);
+        return;
+    }
+    k_gather_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, v, len, W.h1);
+    stationary<T>(S, S.hM, W.h1, W.h2);
+    k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w, len);
+    k_gather_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, v + n, len, W.h1);
+    schur_solve_t<T>(S, W.h1, W.tmp);
+    k_spmv<SP_SET, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col,
+                                                            mass_sell_values<T>(S), W.tmp, n,
+                                                            nullptr, W.tmp2, n);
+    schur_solve_t<T>(S, W.tmp2, W.h2);
+    k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w + n, len);
 }
 
 void narrow(Solver &S, int n, const double2 *a, float2 *b)
 {
-    k_narrow_pairs<<<nblk(n), kBlock, 0, S.stream>>>(n, a, b);
+    k_narrow_pairs<<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, a, b);
 }
 
 void widen(Solver &S, int n, const float2 *a, double2 *b)
 {
-    k_widen_pairs<<<nblk(n), kBlock, 0, S.stream>>>(n, a, b);
+    k_widen_pairs<<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, a, b);
 }
 
 float *narrow_copy(Pool &pool, hipStream_t st, const double *a, long n)
@@ -418,10 +478,11 @@ void narrow_hierarchy(Solver &S, Hierarchy &H)
     hipStream_t st = S.stream;
     for (int l = 0; l < H.nlev; ++l) {
         Level &L = H.lev[l];
-        H.fx[l] = pool.get<float2>(L.n);
-        H.fxt[l] = pool.get<float2>(L.n);
-        H.fb[l] = pool.get<float2>(L.n);
-        H.fr[l] = pool.get<float2>(L.n);
+        const size_t len = (size_t)S.nb * L.n;
+        H.fx[l] = pool.get<float2>(len);
+        H.fxt[l] = pool.get<float2>(len);
+        H.fb[l] = pool.get<float2>(len);
+        H.fr[l] = pool.get<float2>(len);
         // A on every level: the fine one also serves the inner CG and the
         // stationary cycles when it is the coarsest
         narrow_matrix(pool, st, L.A, L.sA, L.gsA, L.fA_s, L.fA_c);
@@ -461,29 +522,33 @@ void timer_mark(Solver &S, bool begin)
 void prec_setup(Solver &S)
 {
     Pool &p = S.pool;
-    const int n = S.nv;
+    const size_t n = S.nv, nb = S.nb;   // every work vector holds all runs
     Work<double> &D = S.w64;
-    D.pcg_r = p.get<double2>(n);
-    D.pcg_z = p.get<double2>(n);
-    D.pcg_d = p.get<double2>(n);
-    D.pcg_q = p.get<double2>(n);
-    D.tmp = p.get<double2>(n);
-    D.tmp2 = p.get<double2>(n);
-    D.mr = p.get<double2>(n);
-    D.me = p.get<double2>(n);
+    D.pcg_r = p.get<double2>(nb * n);
+    D.pcg_z = p.get<double2>(nb * n);
+    D.pcg_d = p.get<double2>(nb * n);
+    D.pcg_q = p.get<double2>(nb * n);
+    D.tmp = p.get<double2>(nb * n);
+    D.tmp2 = p.get<double2>(nb * n);
+    D.mr = p.get<double2>(nb * n);
+    D.me = p.get<double2>(nb * n);
+    D.h1 = p.get<double2>(nb * n);
+    D.h2 = p.get<double2>(nb * n);
     if (!S.mixed)
         return;
     Work<float> &F = S.w32;
-    F.pcg_r = p.get<float2>(n);
-    F.pcg_z = p.get<float2>(n);
-    F.pcg_d = p.get<float2>(n);
-    F.pcg_q = p.get<float2>(n);
-    F.tmp = p.get<float2>(n);
-    F.tmp2 = p.get<float2>(n);
-    F.mr = p.get<float2>(n);
-    F.me = p.get<float2>(n);
-    F.vin = p.get<float2>(2 * (size_t)n);
-    F.wout = p.get<float2>(2 * (size_t)n);
+    F.pcg_r = p.get<float2>(nb * n);
+    F.pcg_z = p.get<float2>(nb * n);
+    F.pcg_d = p.get<float2>(nb * n);
+    F.pcg_q = p.get<float2>(nb * n);
+    F.tmp = p.get<float2>(nb * n);
+    F.tmp2 = p.get<float2>(nb * n);
+    F.mr = p.get<float2>(nb * n);
+    F.me = p.get<float2>(nb * n);
+    F.h1 = p.get<float2>(nb * n);
+    F.h2 = p.get<float2>(nb * n);
+    F.vin = p.get<float2>(2 * nb * n);
+    F.wout = p.get<float2>(2 * nb * n);
     S.fsM = narrow_copy(p, S.stream, S.sM.val, (long)S.sM.stored);
     narrow_hierarchy(S, S.hM);
     narrow_hierarchy(S, S.hA);

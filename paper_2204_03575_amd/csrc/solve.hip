@@ -41,6 +41,7 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
     y1 = d2(t.x * k0x - te.x * m1x, t.y * k0y - te.y * m1y);
 }
 
+// per run, x and y advance by 2n
 __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict__ sptr,
                                                    const int *__restrict__ col,
                                                    const double *__restrict__ vm,
@@ -51,6 +52,8 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
+    x = run_at(x, 2l * n);
+    y = run_at(y, 2l * n);
     double2 y0, y1;
     saddle_row(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
     y[row] = y0;
@@ -58,6 +61,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
 }
 
 // y = b - A x over a grid-stride loop, and partial sums of |y|^2 per species
+// (per run: vectors advance by 2n, part by one run's slots)
 __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
                                                          const int *__restrict__ col,
                                                          const double *__restrict__ vm,
@@ -67,6 +71,10 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
                                                          double2 t, double2 te, double2 *part)
 {
     __shared__ double2 sh[kBlock / 64];
+    x = run_at(x, 2l * n);
+    b = run_at(b, 2l * n);
+    y = run_at(y, 2l * n);
+    part = run_at(part, kSlotStride);
     double2 nrm = d2(0.0, 0.0);
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
         double2 y0, y1;
@@ -88,18 +96,24 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
 // MODE 0: partials of V_i . w;  MODE 1: w -= sum_i V_i h[i] with the
 // finalised MODE-0 results h, then partials of V_i . w;  MODE 2: the same
 // update with the MODE-1 results, then partials of w . w.  All per species;
-// len = 2n.  The grid (up to kGsBlocks blocks) keeps several blocks per CU.
+// len = 2n.  The grid (up to kGsBlocks blocks per run) keeps several blocks
+// per CU.  The Krylov vectors are [index][run][len] (index stride ks = runs
+// len); per run, w advances by len, h by hs and the partials by ps.
 constexpr int kChunk = 8;
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restrict__ V, int nvec,
-                                               double2 *w, const double2 *__restrict__ hin,
-                                               double2 *part)
+__global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *__restrict__ V,
+                                               int nvec, double2 *w, const double2 *__restrict__ hin,
+                                               long hs, double2 *part, long ps)
 {
     __shared__ double2 sh[kBlock / 64];
     __shared__ double2 h[kMaxRestart + 1];
     const int G = gridDim.x;
     const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
+    V = run_at(V, len);
+    w = run_at(w, len);
+    hin = run_at(hin, hs);
+    part = run_at(part, ps);
     if (MODE > 0) {
         for (int v = threadIdx.x; v < nvec; v += kBlock)
             h[v] = hin[v];
@@ -107,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
         for (int i = start; i < len; i += stride) {
             double2 wv = w[i];
             for (int v = 0; v < nvec; ++v) {
-                const double2 hv = h[v], vv = V[(size_t)v * len + i];
+                const double2 hv = h[v], vv = V[(size_t)v * ks + i];
                 wv.x -= hv.x * vv.x;
                 wv.y -= hv.y * vv.y;
             }
@@ -135,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
 #pragma unroll
             for (int c = 0; c < kChunk; ++c) {
                 if (v0 + c < nvec) {
-                    const double2 vv = V[(size_t)(v0 + c) * len + i];
+                    const double2 vv = V[(size_t)(v0 + c) * ks + i];
                     acc[c].x += vv.x * wv.x;
                     acc[c].y += vv.y * wv.y;
                 }
@@ -150,11 +164,14 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, const double2 *__restric
 }
 
 // out[v] = sum of the G partials of vector v; block v handles vector v
-// (thread t adds g = t, t + 256, ... in order, then a fixed block tree)
-__global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ part, int G,
-                                                  double2 *out)
+// (thread t adds g = t, t + 256, ... in order, then a fixed block tree);
+// per run, part advances by ps and out by hs
+__global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ part, long ps, int G,
+                                                  double2 *out, long hs)
 {
     __shared__ double2 sh[kBlock / 64];
+    part = run_at(part, ps);
+    out = run_at(out, hs);
     const int v = blockIdx.x;
     double2 s = d2(0.0, 0.0);
     for (int g = threadIdx.x; g < G; g += kBlock) {
@@ -167,13 +184,17 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double2 *__restrict__ p
         out[v] = s;
 }
 
-// ------------------------------------------------------------------ FGMRES control (one block)
+// ------------------------------------------------------------------ FGMRES control (one block per run)
+// The control kernels run one block per run (blockIdx.y); c points at run
+// 0's control block.
+
 // ||b||^2 from partials; tol = rtol ||b|| per species
 __global__ void __launch_bounds__(kBlock) k_tol(Ctl *c, const double2 *__restrict__ part, int G,
                                                 double rtol)
 {
     __shared__ double2 r[1];
-    reduce_parts(part, 1, G, r);
+    c += blockIdx.y;
+    reduce_parts(run_at(part, kSlotStride), 1, G, r);
     if (threadIdx.x < 2) {
         const int s = threadIdx.x;
         const double nb = s == 0 ? r[0].x : r[0].y;
@@ -188,55 +209,91 @@ __global__ void __launch_bounds__(kBlock) k_tol(Ctl *c, const double2 *__restric
 __global__ void __launch_bounds__(kBlock) k_nrm(Ctl *c, const double2 *__restrict__ part, int G)
 {
     __shared__ double2 r[1];
-    reduce_parts(part, 1, G, r);
+    c += blockIdx.y;
+    reduce_parts(run_at(part, kSlotStride), 1, G, r);
     if (threadIdx.x < 2)
         c->nrm[threadIdx.x] = threadIdx.x == 0 ? r[0].x : r[0].y;
 }
 
+// per-species flags of every run, from the host (2 per run)
+struct Flags {
+    int a[2 * kMaxRuns];
+};
+
 // start of a cycle: g = (||r||, 0, ...), active flags from the host, k = 0
-__global__ void k_cycle_init(Ctl *c, int act0, int act1)
+__global__ void k_cycle_init(Ctl *c, Flags act)
 {
     const int s = threadIdx.x;
     if (s >= 2)
         return;
-    c->active[s] = s == 0 ? act0 : act1;
+    c += blockIdx.y;
+    c->active[s] = act.a[2 * blockIdx.y + s];
     c->k[s] = 0;
     c->g[s][0] = sqrt(c->nrm[s]);
 }
 
 // keep only the species the host still lets iterate
-__global__ void k_deactivate(Ctl *c, int act0, int act1)
+__global__ void k_deactivate(Ctl *c, Flags act)
 {
     const int s = threadIdx.x;
-    if (s < 2)
-        c->active[s] = c->active[s] && (s == 0 ? act0 : act1);
+    if (s < 2) {
+        c += blockIdx.y;
+        c->active[s] = c->active[s] && act.a[2 * blockIdx.y + s];
+    }
 }
 
-// v0 = r / ||r|| for active species, 0 otherwise
+// the heads of the runs' control blocks, back to back, for one copy to the host
+__global__ void k_pack_heads(const Ctl *__restrict__ c, int *out)
+{
+    constexpr int words = (int)(kCtlHead / sizeof(int));
+    const int *src = reinterpret_cast<const int *>(c + blockIdx.y);
+    for (int i = threadIdx.x; i < words; i += blockDim.x)
+        out[blockIdx.y * words + i] = src[i];
+}
+
+// the counters of a step: clamps, non-finite flag, starts used
+__global__ void k_ctl_reset(Ctl *c)
+{
+    c += blockIdx.y;
+    if (threadIdx.x == 0) {
+        c->clamped = 0;
+        c->nan = 0;
+        c->guess_used[0] = 0;
+        c->guess_used[1] = 0;
+    }
+}
+
+// v0 = r / ||r|| for active species, 0 otherwise (per run, r and v advance by len)
 __global__ void __launch_bounds__(kBlock) k_scale_first(int len, const double2 *__restrict__ r,
                                                         double2 *v, const Ctl *__restrict__ c)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
         return;
+    c += blockIdx.y;
     const double s0 = (c->active[0] && c->nrm[0] > 0.0) ? 1.0 / sqrt(c->nrm[0]) : 0.0;
     const double s1 = (c->active[1] && c->nrm[1] > 0.0) ? 1.0 / sqrt(c->nrm[1]) : 0.0;
-    const double2 rv = r[i];
-    v[i] = d2(rv.x * s0, rv.y * s1);
+    const double2 rv = run_at(r, len)[i];
+    run_at(v, len)[i] = d2(rv.x * s0, rv.y * s1);
 }
 
 // Column j of the Hessenberg matrix from the two Gram-Schmidt passes, the
 // previous rotations applied, a new rotation that zeroes H[j+1][j], the
-// residual estimate |g[j+1]|, and the convergence test against tol.
+// residual estimate |g[j+1]|, and the convergence test against tol.  Per
+// run, h1 and h2 advance by hs and p3 by ps.
 __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
                                                    const double2 *__restrict__ h1,
-                                                   const double2 *__restrict__ h2,
-                                                   const double2 *__restrict__ p3, int G)
+                                                   const double2 *__restrict__ h2, long hs,
+                                                   const double2 *__restrict__ p3, long ps, int G)
 {
     // the column and the previous rotations are staged in LDS by the whole
     // block, so the sequential rotation loop below touches no global memory
     __shared__ double2 nn[1];
     __shared__ double col[2][kMaxRestart + 1], csl[2][kMaxRestart], snl[2][kMaxRestart];
+    c += blockIdx.y;
+    h1 = run_at(h1, hs);
+    h2 = run_at(h2, hs);
+    p3 = run_at(p3, ps);
     for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock) {
         const int s = t / (j + 1), i = t % (j + 1);
         col[s][i] = s == 0 ? h1[i].x + h2[i].x : h1[i].y + h2[i].y;
@@ -287,12 +344,14 @@ __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
     }
 }
 
-// v_{j+1} = w / ||w|| for species still active, 0 otherwise
+// v_{j+1} = w / ||w|| for species still active, 0 otherwise (per run, v advances by len)
 __global__ void __launch_bounds__(kBlock) k_scale_next(int len, double2 *v, const Ctl *__restrict__ c)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
         return;
+    c += blockIdx.y;
+    v = run_at(v, len);
     const double s0 = (c->active[0] && c->hn[0] > 0.0) ? 1.0 / c->hn[0] : 0.0;
     const double s1 = (c->active[1] && c->hn[1] > 0.0) ? 1.0 / c->hn[1] : 0.0;
     const double2 vv = v[i];
@@ -305,6 +364,7 @@ __global__ void k_trisolve(Ctl *c, int m)
     const int s = threadIdx.x;
     if (s >= 2)
         return;
+    c += blockIdx.y;
     const int k = c->k[s];
     const double *H = c->H[s];
     for (int i = k - 1; i >= 0; --i) {
@@ -317,16 +377,21 @@ __global__ void k_trisolve(Ctl *c, int m)
         c->y[s][i] = 0.0;
 }
 
-// x += sum_{i < kmax} Z_i y_i, per species
-__global__ void __launch_bounds__(kBlock) k_update_x(int len, double2 *x, const double2 *__restrict__ Z,
-                                                     int kmax, const Ctl *__restrict__ c)
+// x += sum_{i < kmax} Z_i y_i, per species (Z is [index][run][len], index
+// stride ks; per run x advances by len)
+__global__ void __launch_bounds__(kBlock) k_update_x(int len, long ks, double2 *x,
+                                                     const double2 *__restrict__ Z, int kmax,
+                                                     const Ctl *__restrict__ c)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
         return;
+    c += blockIdx.y;
+    x = run_at(x, len);
+    Z = run_at(Z, len);
     double2 xv = x[i];
     for (int t = 0; t < kmax; ++t) {
-        const double2 z = Z[(size_t)t * len + i];
+        const double2 z = Z[(size_t)t * ks + i];
         xv.x += c->y[0][t] * z.x;
         xv.y += c->y[1][t] * z.y;
     }
@@ -338,9 +403,9 @@ __global__ void __launch_bounds__(kBlock) k_finite(int len, const double2 *__res
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
         return;
-    const double2 v = x[i];
+    const double2 v = run_at(x, len)[i];
     if (!isfinite(v.x) || !isfinite(v.y))
-        c->nan = 1;
+        c[blockIdx.y].nan = 1;
 }
 
 // ------------------------------------------------------------------ right-hand side
@@ -379,19 +444,26 @@ __device__ inline void dpot(const Pot &P, double p, double q, double &fp, double
 }
 
 // f[v] += sum over the quadrature of f'(phi_h) lambda_v |T| for the cells of
-// one colour (no two share a vertex, so the += are race free)
+// one colour (no two share a vertex, so the += are race free).  Per run: the
+// state x (phi is its first half) advances by 2n, f by n, and the run has its
+// own potential parameters and clamp counter.
 template <int NL>
 __global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ list, int count,
                                                       const int *__restrict__ cells,
                                                       const double *__restrict__ vol,
                                                       const double *__restrict__ qb,
-                                                      const double *__restrict__ qw, int nq,
-                                                      const double2 *__restrict__ phi, Pot P,
-                                                      double2 *f, int *clamped)
+                                                      const double *__restrict__ qw, int nq, int n,
+                                                      const double2 *__restrict__ phi,
+                                                      const Pot *__restrict__ pots, double2 *f,
+                                                      Ctl *ctl)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= count)
         return;
+    phi = run_at(phi, 2l * n);
+    f = run_at(f, (long)n);
+    const Pot P = pots[blockIdx.y];
+    int *clamped = &ctl[blockIdx.y].clamped;
     const int c = list[t];
     int vtx[NL];
     double2 ph[NL], acc[NL];
@@ -430,30 +502,41 @@ __global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ li
         atomicAdd(clamped, clamps);
 }
 
-// b1 = -(tau'/eps) f
+// b1 = -(tau'/eps) f (per run: f advances by n, b1, the second half of the
+// right-hand side, by 2n)
 __global__ void __launch_bounds__(kBlock) k_rhs_second(int n, const double2 *__restrict__ f,
                                                        double2 *b1, double2 te)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
-    const double2 v = f[i];
-    b1[i] = d2(-te.x * v.x, -te.y * v.y);
+    const double2 v = run_at(f, (long)n)[i];
+    run_at(b1, 2l * n)[i] = d2(-te.x * v.x, -te.y * v.y);
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero(int n, double2 *v)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n)
-        v[i] = d2(0.0, 0.0);
+        run_at(v, (long)n)[i] = d2(0.0, 0.0);
 }
 
-// solvent removal after a step: phi_i += ds phi_i / (phi_p + phi_n), equal halves if the sum is <= 0
-__global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, double ds)
+// solvent removed per run in this step (0: none)
+struct Evap {
+    double ds[kMaxRuns];
+};
+
+// solvent removal after a step: phi_i += ds phi_i / (phi_p + phi_n), equal
+// halves if the sum is <= 0 (per run: the state advances by 2n)
+__global__ void __launch_bounds__(kBlock) k_evaporate(int n, double2 *phi, Evap e)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
+    const double ds = e.ds[blockIdx.y];
+    if (ds == 0.0)
+        return;
+    phi = run_at(phi, 2l * n);
     double2 v = phi[i];
     const double sum = v.x + v.y;
     if (sum > 0.0) {
@@ -475,8 +558,8 @@ __global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
         return;
-    const double2 a = x[i], h = xh[i];
-    xg[i] = d2(a.x + (a.x - h.x), a.y + (a.y - h.y));
+    const double2 a = run_at(x, len)[i], h = run_at(xh, len)[i];
+    run_at(xg, len)[i] = d2(a.x + (a.x - h.x), a.y + (a.y - h.y));
 }
 
 // Per species, the start with the smallest residual norm among the previous
@@ -492,6 +575,12 @@ __global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *_
 {
     __shared__ double2 nrm[3];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    pg = run_at(pg, kSlotStride);
+    c += blockIdx.y;
+    x = run_at(x, len);
+    xl = run_at(xl, len);
+    xg = run_at(xg, len);
+    out = run_at(out, len);
     if (wid < 3) {
         double2 s = d2(0.0, 0.0);
         for (int g = lane; g < G; g += 64) {
@@ -529,38 +618,47 @@ __global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *_
 // ------------------------------------------------------------------ host helpers
 inline double2 pair(const double *a) { return make_double2(a[0], a[1]); }
 
+// the control-block head of run r in the pinned host mirror
+inline const Ctl &head(const Solver &S, int r)
+{
+    return *reinterpret_cast<const Ctl *>(reinterpret_cast<const char *>(S.hctl) + r * kCtlHead);
+}
+
 }  // namespace
 
 void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
     const int n = S.nv;
-    k_saddle<<<nblk(n), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, y,
-                                               pair(S.tau_s), pair(S.te_s));
+    k_saddle<<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
+                                                             S.sK, x, y, pair(S.tau_s),
+                                                             pair(S.te_s));
 }
 
-// b = (M phi, -(tau'/eps) f) for the current state
+// b = (M phi, -(tau'/eps) f) for the current state of every run
 void compute_rhs(Solver &S)
 {
-    const int n = S.nv;
+    const int n = S.nv, R = S.nrun;
+    const long len = 2l * n;
     hipStream_t st = S.stream;
-    Pot P{S.prm.potential, S.prm.Np, S.prm.Nn, S.prm.Ns,
-          S.prm.chi_pn,    S.prm.chi_ps, S.prm.chi_ns, S.prm.log_floor};
-    k_zero<<<nblk(n), kBlock, 0, st>>>(n, S.f);
-    fill_int(&S.ctl->clamped, 0, 1, st);
+    const Pot *pots = static_cast<const Pot *>(S.pots);
+    k_zero<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f);
     for (int c = 0; c < S.ncolors; ++c) {
         const int cnt = S.color_ptr[c + 1] - S.color_ptr[c];
         if (!cnt)
             continue;
         const int *list = S.color_cells + S.color_ptr[c];
         if (S.nl == 3)
-            k_rhs_color<3><<<nblk(cnt), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb, S.qw, S.nq,
-                                                         S.x, P, S.f, &S.ctl->clamped);
+            k_rhs_color<3><<<grid(nblk(cnt), R), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb,
+                                                                  S.qw, S.nq, n, S.x, pots, S.f,
+                                                                  S.ctl);
         else
-            k_rhs_color<4><<<nblk(cnt), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb, S.qw, S.nq,
-                                                         S.x, P, S.f, &S.ctl->clamped);
+            k_rhs_color<4><<<grid(nblk(cnt), R), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb,
+                                                                  S.qw, S.nq, n, S.x, pots, S.f,
+                                                                  S.ctl);
     }
-    k_spmv<SP_SET, double><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.x, nullptr, S.b);
-    k_rhs_second<<<nblk(n), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
+    k_spmv<SP_SET, double><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
+                                                                S.x, len, nullptr, S.b, len);
+    k_rhs_second<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());
 }
 
@@ -568,61 +666,89 @@ void alloc_workspace(Solver &S)
 {
     Pool &p = S.pool;
     const int n = S.nv;
-    const size_t len = 2 * (size_t)n;
+    const size_t len = 2 * (size_t)n, nb = S.nb;
     S.m = S.prm.restart;
-    S.x = p.get<double2>(len);
-    S.xk = p.get<double2>(len);
-    S.yh1 = p.get<double2>(len);
-    S.yh2 = p.get<double2>(len);
-    S.b = p.get<double2>(len);
-    S.r = p.get<double2>(len);
-    S.V = p.get<double2>(len * (S.m + 1));
-    S.Z = p.get<double2>(len * S.m);
-    S.f = p.get<double2>(n);
-    S.red = p.get<double2>((size_t)kSlots * kRedBlocks);
-    S.gsp1 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
-    S.gsp2 = p.get<double2>((size_t)(kMaxRestart + 1) * kGsBlocks);
-    S.gsp3 = p.get<double2>(kGsBlocks);
-    S.hfin = p.get<double2>(2 * (kMaxRestart + 1));
-    S.ctl = p.get<Ctl>(1);
-    fill_int(reinterpret_cast<int *>(S.ctl), 0, sizeof(Ctl) / sizeof(int), S.stream);
-    CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), sizeof(Ctl), hipHostMallocDefault));
-    k_zero<<<nblk(len), kBlock, 0, S.stream>>>((int)len, S.x);
+    S.x = p.get<double2>(nb * len);
+    S.xk = p.get<double2>(nb * len);
+    S.xl = p.get<double2>(nb * len);
+    S.yh1 = p.get<double2>(nb * len);
+    S.yh2 = p.get<double2>(nb * len);
+    S.b = p.get<double2>(nb * len);
+    S.r = p.get<double2>(nb * len);
+    S.V = p.get<double2>(nb * len * (S.m + 1));
+    S.Z = p.get<double2>(nb * len * S.m);
+    S.f = p.get<double2>(nb * n);
+    S.red = p.get<double2>(nb * kSlotStride);
+    S.gsp1 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
+    S.gsp2 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
+    S.gsp3 = p.get<double2>(nb * kGsBlocks);
+    S.hfin = p.get<double2>(nb * 2 * (kMaxRestart + 1));
+    S.ctl = p.get<Ctl>(nb);
+    fill_int(reinterpret_cast<int *>(S.ctl), 0, nb * sizeof(Ctl) / sizeof(int), S.stream);
+    std::vector<Pot> pots(nb);
+    for (size_t r = 0; r < nb; ++r)
+        pots[r] = Pot{S.prm.potential, S.prm.Np, S.prm.Nn, S.prm.Ns, S.runs[r].chi_pn,
+                      S.runs[r].chi_ps, S.runs[r].chi_ns, S.prm.log_floor};
+    Pot *dp = p.get<Pot>(nb);
+    CHM_HIP(hipMemcpyAsync(dp, pots.data(), nb * sizeof(Pot), hipMemcpyHostToDevice, S.stream));
+    S.pots = dp;
+    CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), nb * kCtlHead, hipHostMallocDefault));
+    S.dheads = p.get<int>(nb * kCtlHead / sizeof(int));
+    k_zero<<<grid(nblk(len), (int)nb), kBlock, 0, S.stream>>>((int)len, S.x);
     CHM_HIP(hipStreamSynchronize(S.stream));
 }
 
 namespace {
 
+constexpr long kGsStride = (long)(kMaxRestart + 1) * kGsBlocks;   // per run
+constexpr long kHStride = 2 * (kMaxRestart + 1);                  // per run
+
+// the heads of the runs' control blocks into the pinned mirror (one run:
+// directly; a batch: packed on the device first, then one copy)
+void copy_heads(Solver &S, hipStream_t st)
+{
+    if (S.nrun == 1) {
+        CHM_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlHead, hipMemcpyDeviceToHost, st));
+        return;
+    }
+    k_pack_heads<<<grid(1, S.nrun), 64, 0, st>>>(S.ctl, S.dheads);
+    CHM_HIP(hipMemcpyAsync(S.hctl, S.dheads, S.nrun * kCtlHead, hipMemcpyDeviceToHost, st));
+}
+
 void read_ctl(Solver &S)
 {
-    CHM_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlHead, hipMemcpyDeviceToHost, S.stream));
+    copy_heads(S, S.stream);
     CHM_HIP(hipStreamSynchronize(S.stream));
 }
 
-// One Arnoldi step j of FGMRES for both species: z_j = Prec(v_j) (Algorithm 1),
-// w = A z_j, two Gram-Schmidt passes, the Givens update and v_{j+1} = w/|w|,
-// then the head of the control block is copied to pinned host memory.
-// Everything is enqueued on S.stream without host synchronisation, so the
-// sequence can be captured as a graph.
+// One Arnoldi step j of FGMRES for both species of every run: z_j =
+// Prec(v_j) (Algorithm 1), w = A z_j, two Gram-Schmidt passes, the Givens
+// update and v_{j+1} = w/|w|, then the heads of the control blocks are copied
+// to pinned host memory.  Everything is enqueued on S.stream without host
+// synchronisation, so the sequence can be captured as a graph.
 void iteration_body(Solver &S, int j)
 {
-    const int len = 2 * S.nv, m = S.m;
+    const int len = 2 * S.nv, m = S.m, R = S.nrun;
+    const long ks = (long)R * len;   // Krylov index stride: [index][run][len]
     hipStream_t st = S.stream;
     const int Gg = (int)std::min<long>(kGsBlocks, nblk(len));
-    double2 *vj = S.V + (size_t)j * len, *zj = S.Z + (size_t)j * len;
-    double2 *w = S.V + (size_t)(j + 1) * len;
+    double2 *vj = S.V + (size_t)j * ks, *zj = S.Z + (size_t)j * ks;
+    double2 *w = S.V + (size_t)(j + 1) * ks;
     apply_prec(S, vj, zj);
     apply_saddle(S, zj, w);
     double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
-    k_gs<0><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, nullptr, S.gsp1);
-    k_finish<<<j + 1, kBlock, 0, st>>>(S.gsp1, Gg, h1);
-    k_gs<1><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h1, S.gsp2);
-    k_finish<<<j + 1, kBlock, 0, st>>>(S.gsp2, Gg, h2);
-    k_gs<2><<<Gg, kBlock, 0, st>>>(len, S.V, j + 1, w, h2, S.gsp3);
-    k_givens<<<1, kBlock, 0, st>>>(S.ctl, j, m, h1, h2, S.gsp3, Gg);
-    k_scale_next<<<nblk(len), kBlock, 0, st>>>(len, w, S.ctl);
+    k_gs<0><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, nullptr, kHStride, S.gsp1,
+                                            kGsStride);
+    k_finish<<<grid(j + 1, R), kBlock, 0, st>>>(S.gsp1, kGsStride, Gg, h1, kHStride);
+    k_gs<1><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride, S.gsp2,
+                                            kGsStride);
+    k_finish<<<grid(j + 1, R), kBlock, 0, st>>>(S.gsp2, kGsStride, Gg, h2, kHStride);
+    k_gs<2><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h2, kHStride, S.gsp3,
+                                            kGsBlocks);
+    k_givens<<<grid(1, R), kBlock, 0, st>>>(S.ctl, j, m, h1, h2, kHStride, S.gsp3, kGsBlocks, Gg);
+    k_scale_next<<<grid(nblk(len), R), kBlock, 0, st>>>(len, w, S.ctl);
     CHM_HIP(hipGetLastError());
-    CHM_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlHead, hipMemcpyDeviceToHost, st));
+    copy_heads(S, st);
 }
 
 // Run iteration_body(j), as a HIP graph when enabled (captured once per j on
@@ -667,151 +793,205 @@ void run_iteration(Solver &S, int j)
     CHM_HIP(hipStreamSynchronize(S.stream));
 }
 
+std::string pair_str(double a, double b)
+{
+    return "(" + std::to_string(a) + ", " + std::to_string(b) + ")";
+}
+
 }  // namespace
 
-// One time step: right-hand side, FGMRES for both species, commit and solvent removal.
+// One time step of every run of the batch: right-hand side, FGMRES for both
+// species, commit and solvent removal.  The runs' Arnoldi steps advance
+// together; each species of each run has its own flags, iteration count and
+// convergence test, so each run follows the same iterates as it would alone.
+// A step that fails for any run commits no run.  st_out: nb entries.
 int step_once(Solver &S, chm_stats_t *st_out)
 {
-    const int n = S.nv, len = 2 * n, m = S.m;
+    const int n = S.nv, len = 2 * n, m = S.m, R = S.nb;
+    S.nrun = R;
+    const long ks = (long)R * len;
     hipStream_t st = S.stream;
     const int Gv = red_blocks(len), Gn = red_blocks(n);
     auto t0 = std::chrono::steady_clock::now();
-    chm_stats_t stats{};
+    std::vector<chm_stats_t> stats(R);
 
+    k_ctl_reset<<<grid(1, R), 64, 0, st>>>(S.ctl);
     compute_rhs(S);
-    k_dot<double><<<Gv, kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
-    k_tol<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
+    k_dot<double><<<grid(Gv, R), kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
+    k_tol<<<grid(1, R), kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
     if (S.guess_mode != CHM_GUESS_PREVIOUS && S.hist >= 2) {
         // candidate starts from the last two solutions: linear extrapolation
         // and, in the learned mode, the network's guess; each species starts
         // from whichever of them and the previous state has the smallest
-        // residual.  The first Krylov basis vector holds the extrapolation
-        // until the choice is made.
+        // residual
         const bool learned = S.guess_mode == CHM_GUESS_LEARNED;
-        double2 *xl = S.V, *xg = learned ? S.xk : nullptr;
-        k_extrapolate<<<nblk(len), kBlock, 0, st>>>(len, S.yh2, S.yh1, xl);
+        double2 *xg = learned ? S.xk : nullptr;
+        k_extrapolate<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.yh2, S.yh1, S.xl);
         if (learned)
-            net_guess_on(S.net, st, S.gH, S.gW, reinterpret_cast<const double *>(S.yh2),
-                         reinterpret_cast<const double *>(S.yh1), reinterpret_cast<double *>(xg));
-        const double2 *cand[3] = {S.x, xl, xg};
+            for (int r = 0; r < R; ++r)
+                net_guess_on(S.net, st, S.gH, S.gW,
+                             reinterpret_cast<const double *>(S.yh2 + (size_t)r * len),
+                             reinterpret_cast<const double *>(S.yh1 + (size_t)r * len),
+                             reinterpret_cast<double *>(xg + (size_t)r * len));
+        const double2 *cand[3] = {S.x, S.xl, xg};
         for (int k = 0; k < 3; ++k)
             if (cand[k])
-                k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK,
-                                                      cand[k], S.b, S.r, pair(S.tau_s),
-                                                      pair(S.te_s), slot(S, kSlotGuess + k));
-        k_pick_guess<<<nblk(len), kBlock, 0, st>>>(len, S.x, xl, xg, slot(S, kSlotGuess), Gn, S.xk,
-                                                   S.ctl);
+                k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
+                                                               S.sK, cand[k], S.b, S.r,
+                                                               pair(S.tau_s), pair(S.te_s),
+                                                               slot(S, kSlotGuess + k));
+        k_pick_guess<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xl, xg, slot(S, kSlotGuess),
+                                                            Gn, S.xk, S.ctl);
     } else {
-        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.x, S.xk);
-        fill_int(S.ctl->guess_used, 0, 2, st);
+        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xk);
     }
-    fill_int(&S.ctl->nan, 0, 1, st);
 
-    int total[2] = {0, 0};
+    std::vector<int> total(2 * R, 0), act(2 * R, 0);
+    std::vector<double> res(2 * R, 0.0), bn(2 * R, 0.0);
     int rc = CHM_OK;
     bool first = true;
-    double res[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0};
+    Flags flags{};
     for (;;) {
-        k_saddle_resid<<<Gn, kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk, S.b,
-                                              S.r, pair(S.tau_s), pair(S.te_s), slot(S, kSlotR));
-        k_nrm<<<1, kBlock, 0, st>>>(S.ctl, slot(S, kSlotR), Gn);
+        k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk,
+                                                       S.b, S.r, pair(S.tau_s), pair(S.te_s),
+                                                       slot(S, kSlotR));
+        k_nrm<<<grid(1, R), kBlock, 0, st>>>(S.ctl, slot(S, kSlotR), Gn);
         CHM_HIP(hipGetLastError());
         read_ctl(S);
-        const Ctl &h = *S.hctl;
-        int act[2];
-        bool finite = true;
-        for (int s = 0; s < 2; ++s) {
-            res[s] = std::sqrt(h.nrm[s]);
-            bn[s] = h.bnorm[s];
-            finite = finite && std::isfinite(res[s]);
-            act[s] = !(res[s] <= h.tol[s]);
-            if (first)
-                stats.res0[s] = bn[s] > 0.0 ? res[s] / bn[s] : res[s];
+        bool finite = true, any = false, over = false;
+        for (int r = 0; r < R; ++r) {
+            const Ctl &h = head(S, r);
+            for (int s = 0; s < 2; ++s) {
+                const int q = 2 * r + s;
+                res[q] = std::sqrt(h.nrm[s]);
+                bn[q] = h.bnorm[s];
+                finite = finite && std::isfinite(res[q]);
+                act[q] = !(res[q] <= h.tol[s]);
+                if (first)
+                    stats[r].res0[s] = bn[q] > 0.0 ? res[q] / bn[q] : res[q];
+                any = any || act[q];
+                over = over || (act[q] && total[q] >= S.prm.max_iters);
+            }
         }
         first = false;
         if (!finite) {
             rc = CHM_ENAN;
-            S.nan_where = "residual check: |r| = (" + std::to_string(res[0]) + ", " +
-                          std::to_string(res[1]) + "), |b| = (" + std::to_string(bn[0]) + ", " +
-                          std::to_string(bn[1]) + "), iterations (" + std::to_string(total[0]) +
-                          ", " + std::to_string(total[1]) + ")";
+            for (int r = 0; r < R; ++r)
+                if (!std::isfinite(res[2 * r]) || !std::isfinite(res[2 * r + 1])) {
+                    S.nan_where = "residual check, run " + std::to_string(r) + ": |r| = " +
+                                  pair_str(res[2 * r], res[2 * r + 1]) + ", |b| = " +
+                                  pair_str(bn[2 * r], bn[2 * r + 1]) + ", iterations " +
+                                  pair_str(total[2 * r], total[2 * r + 1]);
+                    break;
+                }
             break;
         }
-        if (!act[0] && !act[1])
+        if (!any)
             break;
-        if ((act[0] && total[0] >= S.prm.max_iters) || (act[1] && total[1] >= S.prm.max_iters)) {
+        if (over) {
             rc = CHM_ENOCONV;
             break;
         }
-        k_cycle_init<<<1, 64, 0, st>>>(S.ctl, act[0], act[1]);
-        k_scale_first<<<nblk(len), kBlock, 0, st>>>(len, S.r, S.V, S.ctl);
+        for (int q = 0; q < 2 * R; ++q)
+            flags.a[q] = act[q];
+        k_cycle_init<<<grid(1, R), 64, 0, st>>>(S.ctl, flags);
+        k_scale_first<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.r, S.V, S.ctl);
         int kmax = 0;
         for (int j = 0; j < m; ++j) {
             run_iteration(S, j);
-            for (int s = 0; s < 2; ++s)
-                total[s] += act[s];
-            kmax = std::max(S.hctl->k[0], S.hctl->k[1]);
-            bool any = false, capped = false;
-            for (int s = 0; s < 2; ++s) {
-                act[s] = S.hctl->active[s];
-                if (act[s] && total[s] >= S.prm.max_iters) {
-                    act[s] = 0;   // iteration budget spent: the cycle ends for this species
-                    capped = true;
+            for (int q = 0; q < 2 * R; ++q)
+                total[q] += act[q];
+            bool anyact = false, capped = false, nan = false;
+            for (int r = 0; r < R; ++r) {
+                const Ctl &h = head(S, r);
+                kmax = std::max(kmax, std::max(h.k[0], h.k[1]));
+                nan = nan || h.nan;
+                for (int s = 0; s < 2; ++s) {
+                    const int q = 2 * r + s;
+                    act[q] = h.active[s];
+                    if (act[q] && total[q] >= S.prm.max_iters) {
+                        act[q] = 0;   // iteration budget spent: the cycle ends for this species
+                        capped = true;
+                    }
+                    anyact = anyact || act[q];
                 }
-                any = any || act[s];
             }
-            if (capped)
-                k_deactivate<<<1, 64, 0, st>>>(S.ctl, act[0], act[1]);
-            if (S.hctl->nan) {
+            if (capped) {
+                for (int q = 0; q < 2 * R; ++q)
+                    flags.a[q] = act[q];
+                k_deactivate<<<grid(1, R), 64, 0, st>>>(S.ctl, flags);
+            }
+            if (nan) {
                 rc = CHM_ENAN;
-                S.nan_where = "Arnoldi step " + std::to_string(j) + ": estimates (" +
-                              std::to_string(S.hctl->resest[0]) + ", " +
-                              std::to_string(S.hctl->resest[1]) + "), |w| (" +
-                              std::to_string(S.hctl->hn[0]) + ", " + std::to_string(S.hctl->hn[1]) +
-                              "), iterations (" + std::to_string(total[0]) + ", " +
-                              std::to_string(total[1]) + ")";
+                for (int r = 0; r < R; ++r) {
+                    const Ctl &h = head(S, r);
+                    if (h.nan) {
+                        S.nan_where = "Arnoldi step " + std::to_string(j) + ", run " +
+                                      std::to_string(r) + ": estimates " +
+                                      pair_str(h.resest[0], h.resest[1]) + ", |w| " +
+                                      pair_str(h.hn[0], h.hn[1]) + ", iterations " +
+                                      pair_str(total[2 * r], total[2 * r + 1]);
+                        break;
+                    }
+                }
                 break;
             }
-            if (!any)
+            if (!anyact)
                 break;
         }
         if (rc)
             break;
-        k_trisolve<<<1, 64, 0, st>>>(S.ctl, m);
-        k_update_x<<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.Z, kmax, S.ctl);
+        k_trisolve<<<grid(1, R), 64, 0, st>>>(S.ctl, m);
+        k_update_x<<<grid(nblk(len), R), kBlock, 0, st>>>(len, ks, S.xk, S.Z, kmax, S.ctl);
         CHM_HIP(hipGetLastError());
     }
     if (rc == CHM_OK) {
-        k_finite<<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.ctl);
+        k_finite<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.ctl);
         read_ctl(S);
-        if (S.hctl->nan) {
-            rc = CHM_ENAN;
-            S.nan_where = "final iterate";
-        }
+        for (int r = 0; r < R; ++r)
+            if (head(S, r).nan) {
+                rc = CHM_ENAN;
+                S.nan_where = "final iterate, run " + std::to_string(r);
+                break;
+            }
     }
-    stats.clamped = S.hctl->clamped;
-    stats.guess_used[0] = S.hctl->guess_used[0];
-    stats.guess_used[1] = S.hctl->guess_used[1];
+    for (int r = 0; r < R; ++r) {
+        const Ctl &h = head(S, r);
+        stats[r].clamped = h.clamped;
+        stats[r].guess_used[0] = h.guess_used[0];
+        stats[r].guess_used[1] = h.guess_used[1];
+    }
     if (rc == CHM_OK) {
         std::swap(S.yh1, S.yh2);   // y_{n-1} becomes y_{n-2}
-        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.yh1);
+        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.yh1);
         S.hist = std::min(S.hist + 1, 2);
-        k_copy<double2><<<nblk(len), kBlock, 0, st>>>(len, S.xk, S.x);
-        if (S.prm.evap_ds > 0.0 && S.step_count < S.prm.evap_steps)
-            k_evaporate<<<nblk(n), kBlock, 0, st>>>(n, S.x, S.prm.evap_ds);
+        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.x);
+        Evap e{};
+        bool evap = false;
+        for (int r = 0; r < R; ++r) {
+            const RunPrm &P = S.runs[r];
+            e.ds[r] = (P.evap_ds > 0.0 && S.step_count < P.evap_steps) ? P.evap_ds : 0.0;
+            evap = evap || e.ds[r] > 0.0;
+        }
+        if (evap)
+            k_evaporate<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.x, e);
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(st));
         S.step_count++;
     }
-    for (int s = 0; s < 2; ++s) {
-        stats.iters[s] = total[s];
-        stats.relres[s] = bn[s] > 0.0 ? res[s] / bn[s] : res[s];
-    }
-    stats.status = rc;
-    stats.t_step_ms =
+    const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (st_out)
-        *st_out = stats;
+    for (int r = 0; r < R; ++r) {
+        for (int s = 0; s < 2; ++s) {
+            const int q = 2 * r + s;
+            stats[r].iters[s] = total[q];
+            stats[r].relres[s] = bn[q] > 0.0 ? res[q] / bn[q] : res[q];
+        }
+        stats[r].status = rc;
+        stats[r].t_step_ms = ms;
+        if (st_out)
+            st_out[r] = stats[r];
+    }
     return rc;
 }
 

@@ -1,0 +1,136 @@
+"""GPU: batched solvers (several runs on one mesh sharing matrices and AMG
+hierarchies, every launch covering all runs).
+
+Each run of a batch performs, per run, exactly the operations of a solver
+that holds that run alone (same kernels, same per-run partial-sum grids and
+summation orders, its own Krylov control), so its trajectory must equal the
+single-run trajectory bitwise: fields, iteration counts and residuals.  The
+single-run solver is itself checked against the oracle elsewhere; one batched
+run is also compared with the oracle directly here (1e-10, equal iterations).
+"""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi_p", "phi_n", "mu_p", "mu_n")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_available():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_03575_amd import library
+    library()
+
+
+def case(name, **kw):
+    print(f"\n[case] {name} {kw}", flush=True)
+
+
+def run_list(k, seed=5):
+    rng = np.random.default_rng(seed)
+    return [dict(chi_pn=float(rng.uniform(0.6, 1.4)), evap_ds=float(rng.uniform(1e-3, 5e-3)),
+                 evap_steps=int(rng.integers(1, 4))) for _ in range(k)]
+
+
+def initial(nv, r, p):
+    return S.initial_fractions(nv, p["mean_p"], p["mean_n"], seed=S.BASE_SEED + 100 + r)[:2]
+
+
+@pytest.mark.parametrize("runs,precision,guess", [(1, "fp64", "previous"), (5, "fp64", "previous"),
+                                                  (7, "fp32", "previous"), (4, "fp64", "linear")],
+                         ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear"])
+def test_batch_runs_equal_single_runs_bitwise(runs, precision, guess):
+    case("batch vs single runs", runs=runs, precision=precision, guess=guess)
+    from paper_2204_03575_amd import Solver
+    p = dict(S.preset("square32", n=(24, 20)), precision=precision)
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    rl = run_list(runs)
+    steps = 4
+    b = Solver(co, ce, p, runs=rl)
+    for r in range(runs):
+        b.set_fields(*initial(nv, r, p), run=r)
+    b.set_guess(guess, None, 21, 25)
+    bst = b.step(steps)
+    for r in range(runs):
+        s = Solver(co, ce, dict(p, **rl[r]))
+        s.set_fields(*initial(nv, r, p))
+        s.set_guess(guess, None, 21, 25)
+        sst = s.step(steps)
+        for k in range(steps):
+            got = bst[k] if runs == 1 else bst[k][r]
+            for key in ("iters", "relres", "res0", "guess_used", "status"):
+                assert got[key] == sst[k][key], (r, k, key, got[key], sst[k][key])
+        fb, fs = b.get_fields(run=r), s.get_fields()
+        for f in FIELDS:
+            assert np.array_equal(fb[f], fs[f]), (r, f)
+        print(f"run {r}: iterations {[x['iters'] for x in sst]}", flush=True)
+        del s
+
+
+def test_batched_run_matches_oracle():
+    case("one run of a batch of 3 against the oracle")
+    from paper_2204_03575_amd import Solver
+    p = S.preset("square32", n=(20, 18))
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    rl = [dict(chi_pn=0.8, evap_ds=0.0), dict(chi_pn=1.3, evap_ds=0.002, evap_steps=5),
+          dict(chi_pn=1.0, evap_ds=0.0)]
+    b = Solver(co, ce, p, runs=rl)
+    for r in range(3):
+        b.set_fields(*initial(nv, r, p), run=r)
+    o = Oracle(co, ce, dict(p, **rl[1]))
+    php, phn = initial(nv, 1, p)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(nv), mu_n=np.zeros(nv))
+    for k in range(3):
+        bs = b.step(1)[0][1]
+        st = o.step(st)
+        got = b.get_fields(run=1)
+        assert bs["iters"] == st["stats"]["iters"], (k, bs, st["stats"])
+        for f in FIELDS:
+            e = np.linalg.norm(got[f] - st[f]) / np.linalg.norm(st[f])
+            assert e <= 1e-10, (k, f, e)
+
+
+def test_nan_in_one_run_commits_no_run():
+    case("a NaN in one run of four")
+    from paper_2204_03575_amd import ChmError, Solver
+    p = S.preset("square32", n=(12, 10))
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    b = Solver(co, ce, p, runs=run_list(4))
+    for r in range(4):
+        php, phn = initial(nv, r, p)
+        if r == 2:
+            php = php.copy()
+            php[7] = np.nan
+        b.set_fields(php, phn, run=r)
+    before = [b.get_fields(run=r) for r in range(4)]
+    with pytest.raises(ChmError) as e:
+        b.step(1)
+    assert "run 2" in str(e.value)
+    for r in range(4):
+        after = b.get_fields(run=r)
+        for f in ("phi_p", "phi_n"):
+            assert np.array_equal(after[f], before[r][f], equal_nan=True)
+
+
+def test_batch_argument_checks():
+    case("batch argument checks")
+    from paper_2204_03575_amd import ChmError, Solver
+    p = S.preset("square32", n=(6, 6))
+    co, ce = S.make_mesh(p)
+    with pytest.raises(ChmError):
+        Solver(co, ce, p, runs=[{}] * 65)
+    with pytest.raises(ChmError):
+        Solver(co, ce, p, runs=[dict(evap_ds=-1.0)])
+    b = Solver(co, ce, p, runs=[{}, {}])
+    with pytest.raises(ChmError):
+        b.set_fields(np.zeros(49), np.zeros(49), run=2)
+    assert b.lib.chm_batch_size(b.h) == 2
