@@ -1,6 +1,8 @@
 """Benchmark: time steps of the 512x512 P1 workload on one MI355X (or, with
 --workload box96, of the 96x96x48 tetrahedral box; with --workload guess256,
-500-step runs on a 256x256 square comparing the starts of the Krylov solve).
+500-step runs on a 256x256 square comparing the starts of the Krylov solve;
+with --workload sweep64, 64 independent runs of uneven mesh sizes, batched by
+size and autotuned, against the same runs one at a time).
 
 One timed "step" is one time step of the whole per-step path: right-hand side
 (coloured quadrature of f' and M phi), FGMRES to 1e-8 relative residual for
@@ -53,7 +55,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("square512", "box96", "guess256"), default="square512")
+    ap.add_argument("--workload", choices=("square512", "box96", "guess256", "sweep64"),
+                    default="square512")
+    ap.add_argument("--no-tune", action="store_true", help="sweep64: skip the autotuner")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2204_03575_amd", "weights",
                                                       "guess256.npy"),
                     help="trained guess network (guess256 workload)")
@@ -183,6 +187,83 @@ def guess_main(args):
     print(json.dumps(out), flush=True)
 
 
+def sweep_main(args):
+    """64 runs (sizes 128^2..512^2, chi_pn and solvent removal drawn per run),
+    FP32 preconditioner: batched by mesh size with autotuned settings, then
+    batched with the default settings, then one solver per run; `steps` time
+    steps of every run after one warm-up step."""
+    import torch
+
+    from paper_2204_03575_amd import Solver
+    from paper_2204_03575_amd import sweep as W
+    import synthetic as S
+    torch.cuda.init()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    runs = W.draw_runs(64)
+    G = W.groups(runs)
+    base = dict(precision="fp32")
+    steps = args.steps
+    tuned = {}
+    if not args.no_tune:
+        for n, rs in G.items():
+            log(f"# autotune {n}x{n} ({len(rs)} runs)")
+            tuned[n] = W.autotune(n, rs, base, log=log)
+    out_modes = {}
+    for label, settings in (("batched+tuned", tuned), ("batched", {})):
+        if label == "batched+tuned" and not tuned:
+            continue
+        total_t, total_it, dof_it, per = 0.0, 0, 0.0, {}
+        for n, rs in G.items():
+            cfg = dict(base, **settings.get(n, {}))
+            g, nv = W.make_group(n, rs, cfg)
+            g.step(1)
+            dt, st = W.timed_steps(g, steps)
+            it = W.iters_of(st, g.nb > 1)
+            total_t += dt
+            total_it += it
+            dof_it += 2 * nv * it
+            per[f"{n}x{n}"] = {"runs": len(rs), "ms_per_step": 1e3 * dt / steps,
+                               "settings": settings.get(n, "default"),
+                               "iters_per_species_step": it / (2 * len(rs) * steps)}
+            log(f"# {label} {n}x{n}: {per[f'{n}x{n}']}")
+            del g
+        out_modes[label] = {"run_steps_per_s": len(runs) * steps / total_t, "seconds": total_t,
+                            "dof_iters_per_s": dof_it / total_t, "groups": per}
+    total_t, dof_it, total_it = 0.0, 0.0, 0
+    for k, r in enumerate(runs):
+        p = dict(S.preset("square512", n=(r["n"], r["n"])), precision="fp32", chi_pn=r["chi_pn"],
+                 evap_ds=r["evap_ds"], evap_steps=r["evap_steps"])
+        co, ce = S.make_mesh(p)
+        g = Solver(co, ce, p)
+        php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"], seed=r["seed"])
+        g.set_fields(php, phn)
+        g.step(1)
+        dt, st = W.timed_steps(g, steps)
+        it = W.iters_of(st, False)
+        total_t += dt
+        total_it += it
+        dof_it += 2 * co.shape[0] * it
+        del g
+        if k % 16 == 15:
+            log(f"# one at a time: {k + 1}/64 runs, {total_t:.2f} s")
+    out_modes["one_at_a_time"] = {"run_steps_per_s": len(runs) * steps / total_t,
+                                  "seconds": total_t, "dof_iters_per_s": dof_it / total_t}
+    best = out_modes.get("batched+tuned", out_modes["batched"])
+    out = {"metric": METRIC, "value": best["run_steps_per_s"], "unit": "run time steps/s",
+           "n_gpus": 1, "steps": steps, "warmup": 1,
+           "ms_per_step": 1e3 * best["seconds"] / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32 preconditioner",
+           "data": "synthetic",
+           "config": {"workload": "64 independent 2D unit-square runs, sizes "
+                                  + ", ".join(f"{n}x{n}: {len(rs)}" for n, rs in G.items())
+                                  + ", chi_pn in [0.6, 1.4], solvent removal in [1e-3, 5e-3] "
+                                    "per step, FGMRES rtol 1e-8, FP32 preconditioner",
+                      "global_batch": 64, "parallelism": "batched by mesh size"},
+           "speedup_vs_one_at_a_time": best["run_steps_per_s"] / out_modes["one_at_a_time"]["run_steps_per_s"],
+           "modes": out_modes}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -192,6 +273,9 @@ def main():
         sys.exit(2)
     if args.workload == "guess256":
         guess_main(args)
+        return
+    if args.workload == "sweep64":
+        sweep_main(args)
         return
     import numpy as np
     import torch

@@ -1,0 +1,89 @@
+"""Parameter sweep of many independent 2D runs on one GPU.
+
+Runs are grouped by mesh size; each group is one batched solver
+(chm_create_batch): its runs share the assembled matrices and both AMG
+hierarchies, and every kernel launch of a time step covers all of them.  An
+autotuner picks, per group, the preconditioner settings (Chebyshev degree of
+the As hierarchy, CG steps per As solve, HIP graphs or eager launches) with
+the shortest time per step measured on the group itself, from the same state,
+at the same residual tolerance.  All computation runs in the library; this
+module only schedules it.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SIZES = (128, 192, 256, 384, 512)
+TUNE_SPACE = [dict(cheb_degree=d, schur_pcg=k, use_graphs=g)
+              for d in (3, 4) for k in (2, 3) for g in (1, 0)]
+
+
+def draw_runs(count: int = 64, seed: int = 20220700):
+    """count runs: mesh size uniform in SIZES, chi_pn uniform in [0.6, 1.4], solvent
+    removal uniform in [1e-3, 5e-3] per step until the solvent fraction has dropped
+    by 0.5, initial-noise seed per run."""
+    sys.path.insert(0, ROOT)
+    import synthetic as S
+    u = S.uniform01(seed, 3 * count).reshape(count, 3)
+    runs = []
+    for k in range(count):
+        n = SIZES[min(int(u[k, 0] * len(SIZES)), len(SIZES) - 1)]
+        evap = 1e-3 + 4e-3 * u[k, 2]
+        runs.append(dict(n=n, chi_pn=0.6 + 0.8 * u[k, 1], evap_ds=evap,
+                         evap_steps=int(round(0.5 / evap)), seed=seed + 1 + k))
+    return runs
+
+
+def groups(runs):
+    out = {}
+    for r in runs:
+        out.setdefault(r["n"], []).append(r)
+    return dict(sorted(out.items()))
+
+
+def make_group(n: int, runs, base: dict):
+    import synthetic as S
+    from .chm import Solver
+    p = dict(S.preset("square512", n=(n, n)), **base)
+    co, ce = S.make_mesh(p)
+    rl = [dict(chi_pn=r["chi_pn"], evap_ds=r["evap_ds"], evap_steps=r["evap_steps"]) for r in runs]
+    g = Solver(co, ce, p, runs=rl)
+    for i, r in enumerate(runs):
+        php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"], seed=r["seed"])
+        g.set_fields(php, phn, run=i)
+    return g, co.shape[0]
+
+
+def timed_steps(g, steps: int):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
+
+
+def autotune(n: int, runs, base: dict, steps: int = 2, log=print):
+    """The TUNE_SPACE entry with the shortest time per step for this group
+    (one warm-up step, then `steps` timed ones, from the group's initial state)."""
+    best, best_t = None, float("inf")
+    for cand in TUNE_SPACE:
+        g, _ = make_group(n, runs, dict(base, **cand))
+        g.step(1)
+        dt, _ = timed_steps(g, steps)
+        del g
+        log(f"#   {n}x{n} {cand}: {1e3 * dt / steps:.2f} ms/step")
+        if dt < best_t:
+            best, best_t = cand, dt
+    return best
+
+
+def iters_of(stats, batched: bool):
+    flat = [s for step in stats for s in (step if batched else [step])]
+    return sum(s["iters"][0] + s["iters"][1] for s in flat)
