@@ -244,13 +244,20 @@ static void gauss_jacobi3(double alpha, double *u, double *w)
 int orc_quadrature(int dim, int *npts, double *bary, double *w)
 {
     double u[3][3], wu[3][3];
-    if (dim != 2 && dim != 3)
+    if (dim < 1 || dim > 3)
         return ORC_EINVAL;
     for (int k = 0; k < dim; ++k)
         gauss_jacobi3((double)(dim - 1 - k), u[k], wu[k]);
     int q = 0;
     double vol = 1.0 / factorial(dim);
-    if (dim == 2) {
+    if (dim == 1) {   /* Gauss-Legendre on an edge (weight (1-u)^0) */
+        for (int a = 0; a < 3; ++a) {
+            bary[q * 2 + 1] = u[0][a];
+            bary[q * 2 + 0] = 1.0 - u[0][a];
+            w[q] = wu[0][a];
+            ++q;
+        }
+    } else if (dim == 2) {
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
                 double x = u[0][a];
@@ -1129,7 +1136,111 @@ static int fgmres(const orc_solver_t *s, int sp, const double *b, double *x, int
 }
 
 /* ------------------------------------------------------------------ */
-/* Right-hand side (eq. saddle_point_system): b1 = M phi^k,             */
+/* Boundary terms of eq. chternary:2 (Section 2; the coefficients of     */
+/* Section 4).  A facet of a cell (the cell without one of its           */
+/* vertices) lies on the top boundary when all its vertices have the     */
+/* largest second coordinate of the mesh, on the bottom when all have    */
+/* the smallest.  On the top, solvent evaporation enters as an inflow of */
+/* polymer and acceptor, g_i = k phi_i phi_s; on the bottom, the         */
+/* substrate flux g_i = p_i(x) (g_i + 2 h_i phi_i) with p_p = 1 on the   */
+/* first, third and fifth sixth of the bottom and p_n = 1 on the others  */
+/* (or p = 1 without patterning).  G_j = integral of g_i lambda_j over   */
+/* the boundary facets, by the degree-5 rule of the facet's dimension.   */
+
+static double facet_measure(int d, const double *xv, int dim)
+{
+    /* d = number of facet vertices (2: edge, 3: triangle); xv: d points */
+    double e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) {
+        e1[k] = xv[dim + k] - xv[k];
+        if (d == 3)
+            e2[k] = xv[2 * dim + k] - xv[k];
+    }
+    if (d == 2)
+        return sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    double c0 = e1[1] * e2[2] - e1[2] * e2[1], c1 = e1[2] * e2[0] - e1[0] * e2[2],
+           c2 = e1[0] * e2[1] - e1[1] * e2[0];
+    return 0.5 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+}
+
+int orc_boundary(orc_solver_t *s, const double *php, const double *phn, double *gp, double *gn)
+{
+    if (!s || !php || !phn || !gp || !gn)
+        return ORC_EINVAL;
+    const int n = s->nv, dim = s->dim, nl = dim + 1, d = dim;
+    const orc_params_t *p = &s->prm;
+    for (int i = 0; i < n; ++i)
+        gp[i] = gn[i] = 0.0;
+    if (!p->boundary)
+        return ORC_OK;
+    double ymin = INFINITY, ymax = -INFINITY, xmin = INFINITY, xmax = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        ymin = fmin(ymin, s->coords[(size_t)i * dim + 1]);
+        ymax = fmax(ymax, s->coords[(size_t)i * dim + 1]);
+        xmin = fmin(xmin, s->coords[(size_t)i * dim]);
+        xmax = fmax(xmax, s->coords[(size_t)i * dim]);
+    }
+    const double tol = 1e-12 * (ymax - ymin);
+    int nq;
+    double qb[64 * 4], qw[64];
+    orc_quadrature(d - 1, &nq, qb, qw);
+    for (int c = 0; c < s->ncell; ++c) {
+        const int *v = s->cells + (size_t)c * nl;
+        for (int omit = 0; omit < nl; ++omit) {
+            int fv[3], k = 0;
+            for (int a = 0; a < nl; ++a)
+                if (a != omit)
+                    fv[k++] = v[a];
+            int top = 1, bot = 1;
+            for (int a = 0; a < d; ++a) {
+                const double y = s->coords[(size_t)fv[a] * dim + 1];
+                top = top && fabs(y - ymax) <= tol;
+                bot = bot && fabs(y - ymin) <= tol;
+            }
+            if (!top && !bot)
+                continue;
+            double xv[9];
+            for (int a = 0; a < d; ++a)
+                for (int k2 = 0; k2 < dim; ++k2)
+                    xv[a * dim + k2] = s->coords[(size_t)fv[a] * dim + k2];
+            const double meas = facet_measure(d, xv, dim);
+            for (int q = 0; q < nq; ++q) {
+                const double *lam = qb + q * d;
+                double pp = 0.0, pn = 0.0, x = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    pp += lam[a] * php[fv[a]];
+                    pn += lam[a] * phn[fv[a]];
+                    x += lam[a] * xv[a * dim];
+                }
+                double fp_, fn_;
+                if (top) {
+                    const double ps = 1.0 - pp - pn;
+                    fp_ = p->bc_k * pp * ps;
+                    fn_ = p->bc_k * pn * ps;
+                } else {
+                    double wp = 1.0, wn = 1.0;
+                    if (p->bc_pattern) {
+                        int six = (int)floor(6.0 * (x - xmin) / (xmax - xmin));
+                        six = six < 0 ? 0 : (six > 5 ? 5 : six);
+                        wp = (six % 2 == 0) ? 1.0 : 0.0;
+                        wn = 1.0 - wp;
+                    }
+                    fp_ = wp * (p->bc_g[0] + 2.0 * p->bc_h[0] * pp);
+                    fn_ = wn * (p->bc_g[1] + 2.0 * p->bc_h[1] * pn);
+                }
+                for (int a = 0; a < d; ++a) {
+                    gp[fv[a]] += meas * qw[q] * fp_ * lam[a];
+                    gn[fv[a]] += meas * qw[q] * fn_ * lam[a];
+                }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Right-hand side (eq. saddle_point_system): b1 = M phi^k (+ tau G,    */
+/* the boundary vector, when the boundary terms are on),                */
 /* b2 = -(tau'/eps) f^k, f^k_j = sum over cells of the quadrature of     */
 /* f'(phi_h^k) lambda_j.                                                */
 
@@ -1164,6 +1275,25 @@ static int rhs_both(orc_solver_t *s, const double *php, const double *phn, doubl
     }
     csr_mv(&s->M, php, bp);
     csr_mv(&s->M, phn, bn);
+    if (s->prm.boundary) {
+        /* the boundary flux enters the first block row times tau (the flux
+         * value already contains the mobility) */
+        double *gp = malloc(sizeof(double) * n), *gn = malloc(sizeof(double) * n);
+        if (!gp || !gn) {
+            free(gp);
+            free(gn);
+            free(fp);
+            free(fn);
+            return ORC_ENOMEM;
+        }
+        orc_boundary(s, php, phn, gp, gn);
+        for (int i = 0; i < n; ++i) {
+            bp[i] += s->prm.tau * gp[i];
+            bn[i] += s->prm.tau * gn[i];
+        }
+        free(gp);
+        free(gn);
+    }
     double cp = tau_s(&s->prm, 0) / s->prm.eps[0], cn = tau_s(&s->prm, 1) / s->prm.eps[1];
     for (int i = 0; i < n; ++i) {
         bp[n + i] = -cp * fp[i];

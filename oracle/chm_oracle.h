@@ -66,6 +66,15 @@ typedef struct {
     double cheb_ratio_mass;
     int32_t coarse_max;  /* stop coarsening at or below this many rows */
     int32_t max_levels;  /* at most this many levels */
+    /* boundary terms of eq. chternary:2 (Section 2), explicit in time: the
+     * top facets (largest second coordinate) take the solvent evaporation as
+     * an inflow k phi_i phi_s of polymer and acceptor, the bottom facets
+     * (smallest second coordinate) the substrate flux d f_s / d phi_i =
+     * p_i(x) (g_i + 2 h_i phi_i) of eq. surfenergy; elsewhere no flux */
+    int32_t boundary;    /* 0: no flux everywhere; 1: the two terms above */
+    double bc_k;         /* evaporation rate k */
+    double bc_g[2], bc_h[2]; /* substrate coefficients g_i, h_i */
+    int32_t bc_pattern;  /* 1: p_p, p_n alternate on sixths of the bottom (Section 4); 0: p = 1 */
 } orc_params_t;
 
 typedef struct {
@@ -79,8 +88,12 @@ typedef struct orc_solver orc_solver_t;
 
 /* element matrices of one simplex: xv = (dim+1) vertices x dim coords */
 int orc_element_matrices(int dim, const double *xv, double *MT, double *KT, double *vol);
-/* quadrature rule on the reference simplex: barycentric points [npts][dim+1], weights sum to 1 */
+/* quadrature rule on the reference simplex: barycentric points [npts][dim+1], weights sum to 1
+ * (dim 1: three-point Gauss-Legendre on an edge; 2, 3: degree 5) */
 int orc_quadrature(int dim, int *npts, double *bary, double *w);
+/* the boundary vector G of eq. chternary:2: G_j = integral over the top and
+ * bottom facets of the flux g_i(phi_h) lambda_j, per species (gp, gn: n_vertices) */
+int orc_boundary(orc_solver_t *s, const double *php, const double *phn, double *gp, double *gn);
 /* potential and its derivatives at one point */
 int orc_potential(const orc_params_t *p, double php, double phn, double *f, double *fp, double *fn);
 

@@ -40,6 +40,8 @@ class orc_params_t(C.Structure):
         ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
         ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+        ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
+        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32),
     ]
 
 
@@ -89,6 +91,7 @@ def load_library():
         lib.orc_apply_saddle.argtypes = [vp, C.c_int, vp, vp]
         lib.orc_apply_prec.argtypes = [vp, C.c_int, vp, vp]
         lib.orc_rhs.argtypes = [vp, vp, vp, vp, vp]
+        lib.orc_boundary.argtypes = [vp, vp, vp, vp, vp]
         lib.orc_fgmres.argtypes = [vp, C.c_int, vp, vp, P(i32), P(d)]
         lib.orc_step.argtypes = [vp, vp, vp, vp, vp, P(orc_stats_t)]
         lib.orc_energy.argtypes = [vp, vp, vp]
@@ -123,6 +126,13 @@ def oracle_params(p: dict) -> orc_params_t:
     s.smoother = SMOOTHERS[p["smoother"]]
     s.cheb_ratio = p["cheb_ratio"]
     s.cheb_ratio_mass = p["cheb_ratio_mass"]
+    s.boundary = int(p.get("boundary", 0))
+    s.bc_k = float(p.get("bc_k", 0.0))
+    g = p.get("bc_g", (0.0, 0.0))
+    h = p.get("bc_h", (0.0, 0.0))
+    s.bc_g[0], s.bc_g[1] = g
+    s.bc_h[0], s.bc_h[1] = h
+    s.bc_pattern = int(p.get("bc_pattern", 0))
     return s
 
 
@@ -141,6 +151,7 @@ def element_matrices(xv: np.ndarray):
 
 
 def quadrature(dim: int):
+    """The rule on the reference simplex of dimension dim (1: edges)."""
     lib = load_library()
     bary = np.zeros((64, dim + 1))
     w = np.zeros(64)
@@ -290,6 +301,16 @@ class Oracle:
         if rc:
             raise OracleError(rc, "orc_rhs")
         return bp, bn
+
+    def boundary(self, php: np.ndarray, phn: np.ndarray):
+        """The boundary vectors (G_p, G_n) of eq. chternary:2 for the state."""
+        php = np.ascontiguousarray(php, dtype=np.float64)
+        phn = np.ascontiguousarray(phn, dtype=np.float64)
+        gp, gn = np.zeros(self.nv), np.zeros(self.nv)
+        rc = self.lib.orc_boundary(self.h, _ptr(php), _ptr(phn), _ptr(gp), _ptr(gn))
+        if rc:
+            raise OracleError(rc, "orc_boundary")
+        return gp, gn
 
     def fgmres(self, species: int, b: np.ndarray, x0: np.ndarray):
         b = np.ascontiguousarray(b, dtype=np.float64)
