@@ -107,6 +107,20 @@ typedef struct {
     int32_t use_graphs;    /* 1: each FGMRES iteration runs as a captured HIP graph
                               (the same kernels, bitwise the same results); 0: eager */
     int32_t precision;     /* CHM_PREC_*: arithmetic of the preconditioner */
+    /* Boundary terms of eq. chternary:2 (Section 2, coefficients of Section
+     * 4), explicit in time, added to the first block row of the right-hand
+     * side times tau: on the top facets (all vertices at the largest second
+     * coordinate) the solvent evaporation as an inflow bc_k phi_i phi_s of
+     * polymer and acceptor; on the bottom facets (smallest second
+     * coordinate) the substrate flux p_i(x) (bc_g[i] + 2 bc_h[i] phi_i),
+     * p_p = 1 on the first, third and fifth sixth of the bottom in x and
+     * p_n = 1 on the others when bc_pattern = 1, p = 1 otherwise; no flux
+     * elsewhere.  boundary = 0: no flux everywhere (the other fields are
+     * ignored). */
+    int32_t boundary;
+    double bc_k;
+    double bc_g[2], bc_h[2];
+    int32_t bc_pattern;
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -207,6 +221,9 @@ int chm_apply_saddle(chm_solver_t *s, const double *x, double *y);
 int chm_apply_prec(chm_solver_t *s, const double *v, double *w);
 /* right-hand side of the current state into a device block vector b */
 int chm_rhs(chm_solver_t *s, double *b);
+/* the boundary vector G of the current state (run 0) into a device pair
+ * vector g (double2[n]); zero without boundary terms */
+int chm_boundary(chm_solver_t *s, double *g);
 
 /* Host-only: the quadrature rule of the right-hand side (barycentric points
  * [npts][dim+1], weights summing to 1); bary and w hold at least 64 points. */

@@ -31,6 +31,7 @@ ENTRY_POINTS = [
     "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
+    "chm_boundary",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -61,6 +62,8 @@ class chm_params_t(C.Structure):
         ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("use_graphs", C.c_int32),
         ("precision", C.c_int32),
+        ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
+        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32),
     ]
 
 
@@ -127,6 +130,7 @@ def library():
             "chm_batch_size": ([vp], C.c_int),
             "chm_set_fields_run": ([vp, i32, vp, vp, vp, vp, i32], C.c_int),
             "chm_get_fields_run": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
+            "chm_boundary": ([vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -155,6 +159,11 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.smoother = SMOOTHERS[p["smoother"]]
     s.use_graphs = int(p.get("use_graphs", 1))
     s.precision = {"fp64": 0, "fp32": 1}[p.get("precision", "fp64")]
+    s.boundary = int(p.get("boundary", 0))
+    s.bc_k = float(p.get("bc_k", 0.0))
+    s.bc_g[0], s.bc_g[1] = p.get("bc_g", (0.0, 0.0))
+    s.bc_h[0], s.bc_h[1] = p.get("bc_h", (0.0, 0.0))
+    s.bc_pattern = int(p.get("bc_pattern", 0))
     return s
 
 
@@ -273,6 +282,13 @@ class Solver:
         rc = self.lib.chm_set_guess(self.h, GUESS_MODES[mode], net.h if net is not None else None,
                                     H, W)
         _check(self.h, rc, "chm_set_guess")
+
+    def boundary(self):
+        """The boundary vectors (G_p, G_n) of the current state (run 0)."""
+        g = self.torch.empty(2 * self.nv, dtype=self.torch.float64, device="cuda")
+        _check(self.h, self.lib.chm_boundary(self.h, _dev_ptr(g)), "chm_boundary")
+        g = g.cpu().numpy()
+        return g[0::2].copy(), g[1::2].copy()
 
     def get_state(self, solution: bool = False):
         """The state vector (4 n doubles, solver block layout) as a CUDA tensor;

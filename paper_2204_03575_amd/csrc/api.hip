@@ -70,6 +70,12 @@ const char *check_params(const chm_params_t &p)
         return "evaporation settings must be non-negative";
     if (p.precision != CHM_PREC_FP64 && p.precision != CHM_PREC_FP32)
         return "unknown precision";
+    if (p.boundary != 0 && p.boundary != 1)
+        return "boundary must be 0 or 1";
+    if (p.boundary && (!(p.bc_k >= 0.0) || !std::isfinite(p.bc_k) || !std::isfinite(p.bc_g[0]) ||
+                       !std::isfinite(p.bc_g[1]) || !std::isfinite(p.bc_h[0]) ||
+                       !std::isfinite(p.bc_h[1]) || (p.bc_pattern != 0 && p.bc_pattern != 1)))
+        return "bad boundary coefficients";
     return nullptr;
 }
 
@@ -171,6 +177,7 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         CHM_HIP(hipMemcpyAsync(S.cells, mesh->cells, sizeof(int) * (size_t)S.ncell * nl,
                                hipMemcpyHostToDevice, S.stream));
         chm::mesh_setup(S);
+        chm::boundary_setup(S);
         S.hM.degree = S.prm.cheb_degree_mass;
         S.hM.ratio = S.prm.cheb_ratio_mass;
         S.hM.jacobi = S.prm.smoother == CHM_SMOOTH_JACOBI;
@@ -574,5 +581,18 @@ int chm_get_state(chm_solver_t *h, int32_t which, double *state)
 }
 
 int chm_batch_size(const chm_solver_t *h) { return h ? h->s.nb : CHM_EINVAL; }
+
+int chm_boundary(chm_solver_t *h, double *g)
+{
+    if (!h || !g)
+        return fail(h, CHM_EINVAL, "chm_boundary: bad arguments");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        S.nrun = 1;
+        chm::boundary_rhs(S, reinterpret_cast<double2 *>(g));
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
 
 }  // extern "C"

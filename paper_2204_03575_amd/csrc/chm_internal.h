@@ -213,6 +213,18 @@ struct RunPrm {
     int evap_steps = 0;
 };
 
+// boundary facets of eq. chternary:2 (boundary.hip)
+struct Boundary {
+    int nf = 0, D = 0, nq = 0;       // facets, vertices per facet, quadrature points
+    int *fv = nullptr;               // [nf][D] vertices
+    int *ftype = nullptr;            // 1 top, 2 bottom
+    double *fmeas = nullptr;         // length or area
+    double2 *fpat = nullptr;         // [nf][nq] patterning weights (p_p, p_n)
+    double *qb = nullptr, *qw = nullptr;   // facet rule: [nq][D] barycentric, [nq]
+    int *inc_ptr = nullptr, *inc = nullptr;   // vertex -> facet slots f D + a, ascending
+    double2 *slot = nullptr;         // [runs][nf D] per-slot values of a step
+};
+
 struct Solver {
     Err err;
     hipStream_t stream = nullptr;
@@ -245,6 +257,7 @@ struct Solver {
     double tau_s[2], te_s[2];
 
     Hierarchy hM, hA;
+    Boundary bc;
 
     // state and Krylov workspace
     int m = 30;
@@ -304,6 +317,11 @@ void prec_setup(Solver &S);   // FP32 copies and work vectors (mixed precision)
 void vcycle(Solver &S, int hier, const double2 *b, double2 *x);
 void schur_solve(Solver &S, const double2 *b, double2 *x);
 void apply_prec(Solver &S, const double2 *v, double2 *w);
+
+// ---- boundary.hip
+void boundary_setup(Solver &S);
+// b1 += tau G for every run's state, or G of run 0 into g when g != nullptr
+void boundary_rhs(Solver &S, double2 *g);
 
 // ---- net.hip
 long long net_max_pixels(const chm_net *net);

@@ -378,9 +378,16 @@ void build_quadrature(int dim, std::vector<double> &bary, std::vector<double> &w
             wu[k][q] = wt[q] * std::pow(0.5, alpha + 1.0);
         }
     }
-    double fact = (dim == 2) ? 2.0 : 6.0;   // 1 / volume of the reference simplex
     bary.clear();
     w.clear();
+    if (dim == 1) {   // edges: Gauss-Legendre (weight (1-u)^0), weights summing to 1
+        for (int a = 0; a < 3; ++a) {
+            bary.insert(bary.end(), {1.0 - u[0][a], u[0][a]});
+            w.push_back(wu[0][a]);
+        }
+        return;
+    }
+    double fact = (dim == 2) ? 2.0 : 6.0;   // 1 / volume of the reference simplex
     int n3 = (dim == 2) ? 1 : 3;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)

@@ -634,7 +634,8 @@ void apply_saddle(Solver &S, const double2 *x, double2 *y)
                                                              pair(S.te_s));
 }
 
-// b = (M phi, -(tau'/eps) f) for the current state of every run
+// b = (M phi + tau G, -(tau'/eps) f) for the current state of every run
+// (G: the boundary vector, zero without boundary terms)
 void compute_rhs(Solver &S)
 {
     const int n = S.nv, R = S.nrun;
@@ -658,6 +659,7 @@ void compute_rhs(Solver &S)
     }
     k_spmv<SP_SET, double><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
                                                                 S.x, len, nullptr, S.b, len);
+    boundary_rhs(S, nullptr);
     k_rhs_second<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());
 }
