@@ -1322,7 +1322,9 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
     if (!(prm->tau > 0.0) || !(prm->eps[0] > 0.0) || !(prm->eps[1] > 0.0)
         || !(prm->mobility[0] > 0.0) || !(prm->mobility[1] > 0.0) || prm->restart < 1
         || !(prm->cheb_ratio > 1.0) || !(prm->cheb_ratio_mass > 1.0) || prm->cheb_degree < 1
-        || prm->cheb_degree_mass < 1 || prm->amg_cycles < 1 || prm->schur_pcg < 0)
+        || prm->cheb_degree_mass < 1 || prm->amg_cycles < 1 || prm->schur_pcg < 0
+        || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
+        || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0))
         return ORC_EINVAL;
     for (int64_t i = 0; i < nc * (dim + 1); ++i)
         if (cells[i] < 0 || cells[i] >= nv)
@@ -1512,6 +1514,134 @@ int orc_apply_prec(const orc_solver_t *s, int species, const double *v, double *
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* Preconditioned MINRES (Paige and Saunders 1975) for the symmetric     */
+/* saddle-point matrix with the symmetric positive definite Algorithm 1  */
+/* of stationary V-cycles: the Lanczos process on P^-1 A in the P inner  */
+/* product (three-term recurrence with the vectors r1, r2 and their      */
+/* preconditioned images), the QR factorisation of its tridiagonal       */
+/* matrix by Givens rotations, and the iterate updated along the         */
+/* directions w.  phibar, the residual in the P^-1 norm, comes from the  */
+/* rotations; the method stops when it is at most rtol times the P^-1    */
+/* norm of b.  relres reports the true 2-norm residual relative to b.    */
+
+static int minres(const orc_solver_t *s, int sp, const double *b, double *x, int32_t *iters,
+                  double *relres)
+{
+    const orc_params_t *p = &s->prm;
+    const int n2 = 2 * s->nv;
+    double *r1 = malloc(sizeof(double) * n2), *r2 = malloc(sizeof(double) * n2);
+    double *y = malloc(sizeof(double) * n2), *v = malloc(sizeof(double) * n2);
+    double *w1 = calloc((size_t)n2, sizeof(double)), *w2 = calloc((size_t)n2, sizeof(double));
+    double *pb = malloc(sizeof(double) * n2);
+    int rc = ORC_OK, k = 0;
+    if (!r1 || !r2 || !y || !v || !w1 || !w2 || !pb) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    prec(s, sp, b, pb);
+    const double bnp2 = dot(n2, b, pb);
+    if (!(bnp2 >= 0.0)) {
+        rc = ORC_ENAN;   /* an indefinite (or non-finite) preconditioner */
+        goto out;
+    }
+    const double tol = p->rtol * sqrt(bnp2);
+    saddle(s, sp, x, r1);
+    for (int i = 0; i < n2; ++i)
+        r1[i] = b[i] - r1[i];
+    prec(s, sp, r1, y);
+    double beta = dot(n2, r1, y);
+    if (!(beta >= 0.0)) {
+        rc = ORC_ENAN;
+        goto out;
+    }
+    beta = sqrt(beta);
+    memcpy(r2, r1, sizeof(double) * n2);
+    double oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta, cs = -1.0, sn = 0.0;
+    while (phibar > tol) {
+        if (k >= p->max_iters) {
+            rc = ORC_ENOCONV;
+            break;
+        }
+        ++k;
+        for (int i = 0; i < n2; ++i)
+            v[i] = y[i] / beta;
+        saddle(s, sp, v, y);
+        if (k >= 2)
+            for (int i = 0; i < n2; ++i)
+                y[i] -= (beta / oldb) * r1[i];
+        const double alfa = dot(n2, v, y);
+        for (int i = 0; i < n2; ++i)
+            y[i] -= (alfa / beta) * r2[i];
+        memcpy(r1, r2, sizeof(double) * n2);
+        memcpy(r2, y, sizeof(double) * n2);
+        prec(s, sp, r2, y);
+        oldb = beta;
+        beta = dot(n2, r2, y);
+        if (!(beta >= 0.0)) {
+            rc = ORC_ENAN;
+            break;
+        }
+        beta = sqrt(beta);
+        const double oldeps = epsln;
+        const double delta = cs * dbar + sn * alfa;
+        const double gbar = sn * dbar - cs * alfa;
+        epsln = sn * beta;
+        dbar = -cs * beta;
+        double gamma = sqrt(gbar * gbar + beta * beta);
+        if (gamma == 0.0)
+            gamma = 1e-300;
+        cs = gbar / gamma;
+        sn = beta / gamma;
+        const double phi = cs * phibar;
+        phibar = sn * phibar;
+        for (int i = 0; i < n2; ++i) {
+            const double wn = (v[i] - oldeps * w1[i] - delta * w2[i]) / gamma;
+            w1[i] = w2[i];
+            w2[i] = wn;
+            x[i] += phi * wn;
+        }
+        if (!isfinite(phibar)) {
+            rc = ORC_ENAN;
+            break;
+        }
+    }
+    saddle(s, sp, x, r1);
+    for (int i = 0; i < n2; ++i)
+        r1[i] = b[i] - r1[i];
+    {
+        const double bn = sqrt(dot(n2, b, b)), rn = sqrt(dot(n2, r1, r1));
+        *relres = bn > 0.0 ? rn / bn : rn;
+    }
+out:
+    *iters = k;
+    free(r1);
+    free(r2);
+    free(y);
+    free(v);
+    free(w1);
+    free(w2);
+    free(pb);
+    return rc;
+}
+
+int orc_minres(const orc_solver_t *s, int species, const double *b, double *x, int32_t *iters,
+               double *relres)
+{
+    if (!s || species < 0 || species > 1 || !b || !x || !iters || !relres)
+        return ORC_EINVAL;
+    return minres(s, species, b, x, iters, relres);
+}
+
+/* the Krylov method of the parameters */
+static int krylov(const orc_solver_t *s, int sp, const double *b, double *x, int32_t *iters,
+                  double *relres)
+{
+    if (s->prm.krylov == ORC_KRYLOV_MINRES)
+        return minres(s, sp, b, x, iters, relres);
+    return fgmres(s, sp, b, x, iters, relres);
+}
+
 int orc_fgmres(const orc_solver_t *s, int species, const double *b, double *x, int32_t *iters,
                double *relres)
 {
@@ -1540,13 +1670,13 @@ int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun
     memcpy(xn, phn, sizeof(double) * n);
     memcpy(xn + n, mun, sizeof(double) * n);
     loc.clamped = clamped;
-    rc = fgmres(s, 0, bp, xp, &loc.iters[0], &loc.relres[0]);
+    rc = krylov(s, 0, bp, xp, &loc.iters[0], &loc.relres[0]);
     if (!rc)
-        rc = fgmres(s, 1, bn, xn, &loc.iters[1], &loc.relres[1]);
+        rc = krylov(s, 1, bn, xn, &loc.iters[1], &loc.relres[1]);
     else {
         int32_t it;
         double rr;
-        fgmres(s, 1, bn, xn, &it, &rr);
+        krylov(s, 1, bn, xn, &it, &rr);
         loc.iters[1] = it;
         loc.relres[1] = rr;
     }

@@ -75,7 +75,15 @@ typedef struct {
     double bc_k;         /* evaporation rate k */
     double bc_g[2], bc_h[2]; /* substrate coefficients g_i, h_i */
     int32_t bc_pattern;  /* 1: p_p, p_n alternate on sixths of the bottom (Section 4); 0: p = 1 */
+    int32_t krylov;      /* ORC_KRYLOV_*: the Krylov method of each time step */
 } orc_params_t;
+
+/* FGMRES (right preconditioned, any Algorithm 1), or preconditioned MINRES
+ * as in the paper's experiments, which needs the symmetric positive
+ * definite Algorithm 1 of stationary V-cycles (schur_pcg = 0) and stops on
+ * the residual in the preconditioner's inverse norm relative to that of b */
+#define ORC_KRYLOV_FGMRES 0
+#define ORC_KRYLOV_MINRES 1
 
 typedef struct {
     int32_t iters[2];
@@ -122,6 +130,9 @@ int orc_apply_saddle(const orc_solver_t *s, int species, const double *x, double
 int orc_apply_prec(const orc_solver_t *s, int species, const double *v, double *w);
 int orc_rhs(orc_solver_t *s, const double *php, const double *phn, double *bp, double *bn);
 int orc_fgmres(const orc_solver_t *s, int species, const double *b, double *x,
+               int32_t *iters, double *relres);
+/* preconditioned MINRES; relres = the true ||b - A x||_2 / ||b||_2 at the end */
+int orc_minres(const orc_solver_t *s, int species, const double *b, double *x,
                int32_t *iters, double *relres);
 int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun,
              orc_stats_t *st);

@@ -41,7 +41,7 @@ class orc_params_t(C.Structure):
         ("cheb_degree_mass", C.c_int32), ("cheb_ratio_mass", C.c_double),
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
-        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32),
+        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
     ]
 
 
@@ -92,6 +92,7 @@ def load_library():
         lib.orc_apply_prec.argtypes = [vp, C.c_int, vp, vp]
         lib.orc_rhs.argtypes = [vp, vp, vp, vp, vp]
         lib.orc_boundary.argtypes = [vp, vp, vp, vp, vp]
+        lib.orc_minres.argtypes = [vp, C.c_int, vp, vp, P(i32), P(d)]
         lib.orc_fgmres.argtypes = [vp, C.c_int, vp, vp, P(i32), P(d)]
         lib.orc_step.argtypes = [vp, vp, vp, vp, vp, P(orc_stats_t)]
         lib.orc_energy.argtypes = [vp, vp, vp]
@@ -133,6 +134,7 @@ def oracle_params(p: dict) -> orc_params_t:
     s.bc_g[0], s.bc_g[1] = g
     s.bc_h[0], s.bc_h[1] = h
     s.bc_pattern = int(p.get("bc_pattern", 0))
+    s.krylov = {"fgmres": 0, "minres": 1}[p.get("krylov", "fgmres")]
     return s
 
 
@@ -311,6 +313,18 @@ class Oracle:
         if rc:
             raise OracleError(rc, "orc_boundary")
         return gp, gn
+
+    def minres(self, species: int, b: np.ndarray, x0: np.ndarray, allow_noconv: bool = False):
+        """MINRES from x0; with allow_noconv the iterate after max_iters is
+        returned instead of an error."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64, copy=True)
+        it = C.c_int32()
+        rr = C.c_double()
+        rc = self.lib.orc_minres(self.h, species, _ptr(b), _ptr(x), C.byref(it), C.byref(rr))
+        if rc and not (allow_noconv and rc == -4):
+            raise OracleError(rc, "orc_minres")
+        return x, it.value, rr.value
 
     def fgmres(self, species: int, b: np.ndarray, x0: np.ndarray):
         b = np.ascontiguousarray(b, dtype=np.float64)

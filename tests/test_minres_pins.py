@@ -1,0 +1,99 @@
+"""Pins of the oracle's MINRES (the paper's Krylov method): the symmetric
+positive definite Algorithm 1 it needs (stationary V-cycles), its solution
+against sparse LU, and the defining optimality: after k steps the iterate
+minimises the residual in the preconditioner's inverse norm over the Krylov
+space, checked against a dense least-squares solve."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.linalg import splu
+
+import synthetic as S
+from oracle import Oracle, OracleError
+
+MINRES = dict(krylov="minres", schur_pcg=0, amg_cycles=2, coarse_max=6)
+
+
+def setup(n=(6, 5), **kw):
+    p = S.preset("square32", n=n, **dict(MINRES, **kw))
+    co, ce = S.make_mesh(p)
+    return p, co, ce, Oracle(co, ce, p)
+
+
+def dense_prec(o, sp_):
+    N = 2 * o.nv
+    return np.column_stack([o.apply_prec(sp_, e) for e in np.eye(N)])
+
+
+def saddle_matrix(o, p, s):
+    M, K = o.scipy_matrix("M"), o.scipy_matrix("K")
+    t = p["tau"] * p["mobility"]
+    te = t / p["eps"]
+    return sp.bmat([[M, t * K], [t * K, -te * M]]).tocsc()
+
+
+def test_preconditioner_is_symmetric_positive_definite():
+    p, co, ce, o = setup()
+    for s in (0, 1):
+        P = dense_prec(o, s)
+        assert np.allclose(P, P.T, rtol=0, atol=1e-12 * np.abs(P).max())
+        assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+
+
+def test_minres_requires_the_stationary_preconditioner():
+    p = S.preset("square32", n=(4, 4), krylov="minres", schur_pcg=3)
+    co, ce = S.make_mesh(p)
+    with pytest.raises(OracleError):
+        Oracle(co, ce, p)
+
+
+def test_minres_solution_matches_sparse_lu():
+    p, co, ce, o = setup(rtol=1e-13, max_iters=500)
+    rng = np.random.default_rng(1)
+    A = saddle_matrix(o, p, 0)
+    b = rng.standard_normal(2 * o.nv)
+    x, it, rr = o.minres(0, b, np.zeros(2 * o.nv))
+    ref = splu(A).solve(b)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert rr <= 1e-11
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 7])
+def test_minres_iterate_minimises_the_preconditioned_residual(k):
+    p, co, ce, o = setup(max_iters=k)
+    rng = np.random.default_rng(2)
+    A = saddle_matrix(o, p, 1).toarray()
+    P = dense_prec(o, 1)
+    P = 0.5 * (P + P.T)
+    b = rng.standard_normal(2 * o.nv)
+    x0 = 0.1 * rng.standard_normal(2 * o.nv)
+    x, it, _ = o.minres(1, b, x0, allow_noconv=True)
+    assert it == k
+    # Krylov space K_k(P A, P r0), orthonormalised; minimise ||b - A x||_{P}
+    # (P = the preconditioner's action, i.e. the inverse of its matrix)
+    r0 = b - A @ x0
+    basis = [P @ r0]
+    for _ in range(k - 1):
+        basis.append(P @ (A @ basis[-1]))
+    Q, _ = np.linalg.qr(np.column_stack(basis))
+    L = np.linalg.cholesky(P)            # ||r||_P^2 = |L^T r|^2
+    c, *_ = np.linalg.lstsq(L.T @ (A @ Q), L.T @ r0, rcond=None)
+    xref = x0 + Q @ c
+    nrm = lambda r: np.sqrt(r @ P @ r)
+    assert abs(nrm(b - A @ x) - nrm(b - A @ xref)) <= 1e-8 * nrm(r0)
+    assert np.linalg.norm(x - xref) <= 1e-6 * np.linalg.norm(xref - x0) + 1e-12
+
+
+def test_minres_step_matches_sparse_lu_and_conserves_mass():
+    p, co, ce, o = setup(n=(8, 8), rtol=1e-12, max_iters=500)
+    nv = co.shape[0]
+    php, phn, _ = S.initial_fractions(nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(nv), mu_n=np.zeros(nv))
+    new = o.step(st)
+    b0, b1 = o.rhs(php, phn)
+    for s, (b, ph, mu) in enumerate(((b0, "phi_p", "mu_p"), (b1, "phi_n", "mu_n"))):
+        ref = splu(saddle_matrix(o, p, s)).solve(b)
+        got = np.concatenate([new[ph], new[mu]])
+        assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
+    M = o.scipy_matrix("M")
+    assert abs(np.ones(nv) @ (M @ (new["phi_p"] - php))) <= 1e-10
