@@ -43,7 +43,7 @@ extern "C" {
 #define CHM_EINVAL (-1)   /* bad argument or unsupported configuration */
 #define CHM_ENOMEM (-2)   /* device allocation failed */
 #define CHM_EHIP (-3)     /* a HIP runtime call failed */
-#define CHM_ENOCONV (-4)  /* FGMRES did not reach rtol within max_iters */
+#define CHM_ENOCONV (-4)  /* the Krylov method did not reach rtol within max_iters */
 #define CHM_ENAN (-5)     /* a non-finite value appeared */
 
 #define CHM_POT_FLORY_HUGGINS 0 /* eq. logarithmicpotential (Section 2) */
@@ -62,6 +62,17 @@ extern "C" {
  * FP64 in both settings. */
 #define CHM_PREC_FP64 0
 #define CHM_PREC_FP32 1
+
+/* Krylov method of the time step (Section 3).  FGMRES: restarted, with the
+ * preconditioner applied on the right, stopped on the true 2-norm residual.
+ * MINRES (the method of the paper's experiments): the symmetric saddle-point
+ * matrix with Algorithm 1 as a symmetric positive definite preconditioner,
+ * which needs schur_pcg = 0 (the As solves are then amg_cycles stationary
+ * V-cycles, a fixed symmetric operator); it stops when the residual in the
+ * P^-1 norm that its rotations give is at most rtol times the P^-1 norm of
+ * b, and relres still reports the true 2-norm residual. */
+#define CHM_KRYLOV_FGMRES 0
+#define CHM_KRYLOV_MINRES 1
 
 typedef struct chm_solver chm_solver_t;
 
@@ -92,9 +103,9 @@ typedef struct {
     double log_floor;      /* log arguments below this are clamped to it */
     double evap_ds;        /* solvent fraction removed per step (0 = off) */
     int32_t evap_steps;    /* steps, counted from creation, that remove solvent */
-    double rtol;           /* FGMRES: ||b - A x||_2 <= rtol ||b||_2 per species */
+    double rtol;           /* FGMRES: ||b - A x||_2 <= rtol ||b||_2 per species (MINRES: see above) */
     int32_t restart;       /* FGMRES restart length m, 1..64 */
-    int32_t max_iters;     /* FGMRES iterations allowed per species and step */
+    int32_t max_iters;     /* Krylov iterations allowed per species and step */
     int32_t amg_cycles;    /* V-cycles per mass-matrix solve */
     int32_t schur_pcg;     /* CG steps (one V-cycle each) per As solve; 0 = amg_cycles V-cycles */
     int32_t smoother;      /* CHM_SMOOTH_* */
@@ -121,11 +132,12 @@ typedef struct {
     double bc_k;
     double bc_g[2], bc_h[2];
     int32_t bc_pattern;
+    int32_t krylov;        /* CHM_KRYLOV_* */
 } chm_params_t;
 
 /* Per-step statistics. */
 typedef struct {
-    int32_t iters[2];      /* FGMRES iterations per species */
+    int32_t iters[2];      /* Krylov iterations per species */
     double relres[2];      /* final true residual / ||b|| per species */
     int32_t status;        /* CHM_OK or the step's error code */
     int32_t clamped;       /* clamped log arguments in the right-hand side */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchm.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["util.hip", "mesh_setup.hip", "amg_setup.hip", "prec.hip", "solve.hip", "boundary.hip", "net.hip", "api.hip"]
+SOURCES = ["util.hip", "mesh_setup.hip", "amg_setup.hip", "prec.hip", "solve.hip", "boundary.hip", "minres.hip", "net.hip", "api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

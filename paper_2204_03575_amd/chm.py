@@ -63,7 +63,7 @@ class chm_params_t(C.Structure):
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("use_graphs", C.c_int32),
         ("precision", C.c_int32),
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
-        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32),
+        ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
     ]
 
 
@@ -164,6 +164,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.bc_g[0], s.bc_g[1] = p.get("bc_g", (0.0, 0.0))
     s.bc_h[0], s.bc_h[1] = p.get("bc_h", (0.0, 0.0))
     s.bc_pattern = int(p.get("bc_pattern", 0))
+    s.krylov = {"fgmres": 0, "minres": 1}[p.get("krylov", "fgmres")]
     return s
 
 

@@ -76,6 +76,10 @@ const char *check_params(const chm_params_t &p)
                        !std::isfinite(p.bc_g[1]) || !std::isfinite(p.bc_h[0]) ||
                        !std::isfinite(p.bc_h[1]) || (p.bc_pattern != 0 && p.bc_pattern != 1)))
         return "bad boundary coefficients";
+    if (p.krylov != CHM_KRYLOV_FGMRES && p.krylov != CHM_KRYLOV_MINRES)
+        return "unknown Krylov method";
+    if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
+        return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
 }
 
@@ -189,6 +193,8 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         S.mixed = S.prm.precision == CHM_PREC_FP32;
         chm::prec_setup(S);
         chm::alloc_workspace(S);
+        if (S.prm.krylov == CHM_KRYLOV_MINRES)
+            chm::minres_alloc(S);
         CHM_HIP(hipStreamSynchronize(S.stream));
         S.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return CHM_OK;
@@ -198,6 +204,8 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
         if (h->s.hctl)
             (void)hipHostFree(h->s.hctl);
+        if (h->s.hmrctl)
+            (void)hipHostFree(h->s.hmrctl);
         delete h;
         return rc;
     }
@@ -320,6 +328,8 @@ int chm_destroy(chm_solver_t *h)
         (void)hipStreamDestroy(h->s.cap_stream);
     if (h->s.hctl)
         (void)hipHostFree(h->s.hctl);
+    if (h->s.hmrctl)
+        (void)hipHostFree(h->s.hmrctl);
     delete h;
     return CHM_OK;
 }

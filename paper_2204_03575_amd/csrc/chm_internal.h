@@ -293,6 +293,10 @@ struct Solver {
     // yh1 = y_{n-1}, yh2 = y_{n-2}; after chm_set_fields yh1 is the new state
     double2 *yh1 = nullptr, *yh2 = nullptr;
     int hist = 0;              // how many of yh1, yh2 are valid
+    // MINRES (krylov = CHM_KRYLOV_MINRES): six block vectors per run (r1, r2,
+    // y, v, w1, w2) and the per-run recurrence scalars, with a pinned mirror
+    double2 *mr = nullptr;
+    void *mrctl = nullptr, *hmrctl = nullptr;
 };
 
 // ---- util.hip
@@ -335,5 +339,11 @@ void apply_saddle(Solver &S, const double2 *x, double2 *y);
 void compute_rhs(Solver &S);
 int step_once(Solver &S, chm_stats_t *st);
 void timer_mark(Solver &S, bool begin);
+
+// ---- minres.hip
+void minres_alloc(Solver &S);
+// MINRES from S.xk for right-hand side S.b given S.r = b - A xk (every run);
+// adds each species' iterations to total (2 per run)
+int minres_solve(Solver &S, std::vector<int> &total);
 
 }  // namespace chm

@@ -116,7 +116,8 @@ __device__ inline void reduce_two(const double2 *__restrict__ pa, const double2 
 // kRedBlocks pairs each, in Solver::red: the inner CG uses rz (0..39) and
 // dq (40..79), the Krylov solver the right-hand-side norm (80) and the
 // residual norm (81) and the residual norms of the initial-guess candidates
-// (82 + CHM_GUESS_*: previous state, linear extrapolation, network).
+// (82 + CHM_GUESS_*: previous state, linear extrapolation, network); MINRES
+// takes slot 82 for its inner products once the start is chosen.
 constexpr int kSlotRz = 0, kSlotDq = 40, kSlotB = 80, kSlotR = 81, kSlotGuess = 82, kSlots = 85;
 constexpr long kSlotStride = (long)kSlots * kRedBlocks;   // per run
 

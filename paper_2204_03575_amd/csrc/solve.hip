@@ -802,8 +802,8 @@ std::string pair_str(double a, double b)
 
 }  // namespace
 
-// One time step of every run of the batch: right-hand side, FGMRES for both
-// species, commit and solvent removal.  The runs' Arnoldi steps advance
+// One time step of every run of the batch: right-hand side, the Krylov
+// method (FGMRES or MINRES) for both species, commit and solvent removal.  The runs' Arnoldi steps advance
 // together; each species of each run has its own flags, iteration count and
 // convergence test, so each run follows the same iterates as it would alone.
 // A step that fails for any run commits no run.  st_out: nb entries.
@@ -852,6 +852,8 @@ int step_once(Solver &S, chm_stats_t *st_out)
     std::vector<double> res(2 * R, 0.0), bn(2 * R, 0.0);
     int rc = CHM_OK;
     bool first = true;
+    const bool minres = S.prm.krylov == CHM_KRYLOV_MINRES;
+    bool mr_done = false;
     Flags flags{};
     for (;;) {
         k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk,
@@ -887,6 +889,17 @@ int step_once(Solver &S, chm_stats_t *st_out)
                     break;
                 }
             break;
+        }
+        if (minres) {
+            // one MINRES solve from the chosen start (its own stopping rule in
+            // the P^-1 norm), then one more pass for the true residual
+            if (mr_done)
+                break;
+            rc = minres_solve(S, total);
+            if (rc)
+                break;
+            mr_done = true;
+            continue;
         }
         if (!any)
             break;

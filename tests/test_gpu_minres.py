@@ -1,0 +1,136 @@
+"""GPU: MINRES, the Krylov method of the paper's experiments (Section 3),
+with the symmetric positive definite Algorithm 1 (stationary V-cycles in both
+blocks), against the oracle's MINRES: equal iteration counts and fields to
+1e-10 per step, in 2D (with a ragged mesh), on the paper's 10 x 2.5 film with
+its boundary terms, and in 3D; a batch against single runs (bitwise); the
+FP32 preconditioner against FP64; the argument check."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi_p", "phi_n", "mu_p", "mu_n")
+MINRES = dict(krylov="minres", schur_pcg=0, amg_cycles=2)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_available():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_03575_amd import library
+    library()
+
+
+def case(name, **kw):
+    print(f"\n[case] {name} {kw}", flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def compare_steps(p, steps=3, seed=None):
+    from paper_2204_03575_amd import Solver
+    co, ce = S.make_mesh(p)
+    g = Solver(co, ce, p)
+    o = Oracle(co, ce, p)
+    kw = {} if seed is None else dict(seed=seed)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"], **kw)
+    g.set_fields(php, phn)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros_like(php), mu_n=np.zeros_like(php))
+    out = []
+    for k in range(steps):
+        gs = g.step(1)[0]
+        st = o.step(st)
+        got = g.get_fields()
+        print(f"step {k}: {gs['iters']} oracle {st['stats']['iters']} relres {gs['relres']}",
+              flush=True)
+        assert gs["iters"] == st["stats"]["iters"], (k, gs, st["stats"])
+        assert gs["iters"][0] > 0 and gs["iters"][1] > 0
+        for f in FIELDS:
+            assert rel(got[f], st[f]) <= 1e-10, (k, f, rel(got[f], st[f]))
+        for s in (0, 1):
+            # the true residual of the same iterate up to rounding: relres
+            # (near rtol) agrees to a percent
+            o_rr = st["stats"]["relres"][s]
+            assert abs(gs["relres"][s] - o_rr) <= 1e-2 * o_rr + 1e-13, (k, s, gs["relres"], o_rr)
+        out.append(gs)
+    return out
+
+
+@pytest.mark.parametrize("kw", [dict(n=(24, 20)), dict(n=(37, 29), tau=1e-5)],
+                         ids=["24x20", "37x29-tau1e-5"])
+def test_minres_steps_match_oracle_2d(kw):
+    case("MINRES steps, unit square", **kw)
+    compare_steps(S.preset("square32", **dict(MINRES, **kw)))
+
+
+def test_minres_steps_match_oracle_paper_film_with_boundary_terms():
+    case("MINRES steps, 10 x 2.5 film with boundary terms")
+    compare_steps(S.preset("paper2d", n=(40, 10), **MINRES))
+
+
+def test_minres_steps_match_oracle_3d():
+    case("MINRES steps, 3D box")
+    compare_steps(S.preset("square32", dim=3, n=(6, 5, 4), extent=(1.0, 1.0, 1.0), **MINRES))
+
+
+def test_minres_batch_equals_single_runs_bitwise():
+    case("MINRES batch of 3 vs single runs")
+    from paper_2204_03575_amd import Solver
+    p = S.preset("square32", n=(20, 16), **MINRES)
+    co, ce = S.make_mesh(p)
+    nv = co.shape[0]
+    rl = [dict(chi_pn=0.7, evap_ds=0.002, evap_steps=2), dict(chi_pn=1.2), dict(chi_pn=1.4)]
+    inits = [S.initial_fractions(nv, 0.1, 0.1, seed=S.BASE_SEED + 70 + r)[:2] for r in range(3)]
+    b = Solver(co, ce, p, runs=rl)
+    for r in range(3):
+        b.set_fields(*inits[r], run=r)
+    bst = b.step(3)
+    for r in range(3):
+        s = Solver(co, ce, dict(p, **rl[r]))
+        s.set_fields(*inits[r])
+        sst = s.step(3)
+        for k in range(3):
+            for key in ("iters", "relres", "res0", "status"):
+                assert bst[k][r][key] == sst[k][key], (r, k, key)
+        fb, fs = b.get_fields(run=r), s.get_fields()
+        for f in FIELDS:
+            assert np.array_equal(fb[f], fs[f]), (r, f)
+
+
+def test_minres_fp32_preconditioner_converges_to_fp64_solution():
+    case("MINRES with the FP32 preconditioner")
+    from paper_2204_03575_amd import Solver
+    p = S.preset("square32", n=(48, 48), **MINRES)
+    co, ce = S.make_mesh(p)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
+    res = {}
+    for prec in ("fp64", "fp32"):
+        g = Solver(co, ce, dict(p, precision=prec))
+        g.set_fields(php, phn)
+        st = g.step(3)
+        res[prec] = (g.get_fields(), st)
+        print(prec, [x["iters"] for x in st], [x["relres"] for x in st], flush=True)
+    for k in range(3):
+        i64, i32 = res["fp64"][1][k]["iters"], res["fp32"][1][k]["iters"]
+        for s in (0, 1):
+            assert abs(i32[s] - i64[s]) <= 2
+            assert res["fp32"][1][k]["relres"][s] <= 10 * p["rtol"]
+    for f in FIELDS:
+        # both solve to rtol; the fields agree to a few times rtol
+        assert rel(res["fp32"][0][f], res["fp64"][0][f]) <= 1e-5, f
+
+
+def test_minres_needs_the_symmetric_preconditioner():
+    case("MINRES argument check")
+    from paper_2204_03575_amd import ChmError, Solver
+    p = S.preset("square32", n=(6, 6), krylov="minres", schur_pcg=3)
+    co, ce = S.make_mesh(p)
+    with pytest.raises(ChmError):
+        Solver(co, ce, p)
