@@ -913,8 +913,9 @@ static void vcycle(const orc_params_t *prm, const hier_t *h, int l, const double
     free(e);
 }
 
-/* Stationary AMG solve: amg_cycles V-cycles from a zero guess,         */
-/* x <- x + V(b - A x).                                                 */
+/* Stationary AMG solve: V-cycles from a zero guess, x <- x + V(b - A x): */
+/* amg_cycles of them, or with amg_tol > 0 until the residual norm is at  */
+/* most amg_tol ||b|| (at least one cycle, at most amg_cycles).           */
 static void amg_stationary(const orc_params_t *prm, const hier_t *h, const double *b, double *x)
 {
     int n = h->lev[0].n;
@@ -923,10 +924,13 @@ static void amg_stationary(const orc_params_t *prm, const hier_t *h, const doubl
         return;
     double *r = malloc(sizeof(double) * (size_t)n);
     double *e = malloc(sizeof(double) * (size_t)n);
+    const double bnorm = prm->amg_tol > 0.0 ? sqrt(dot(n, b, b)) : 0.0;
     for (int c = 1; c < prm->amg_cycles; ++c) {
         csr_mv(&h->lev[0].A, x, r);
         for (int i = 0; i < n; ++i)
             r[i] = b[i] - r[i];
+        if (prm->amg_tol > 0.0 && sqrt(dot(n, r, r)) <= prm->amg_tol * bnorm)
+            break;
         vcycle(prm, h, 0, r, e);
         for (int i = 0; i < n; ++i)
             x[i] += e[i];
@@ -1324,7 +1328,8 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
         || !(prm->cheb_ratio > 1.0) || !(prm->cheb_ratio_mass > 1.0) || prm->cheb_degree < 1
         || prm->cheb_degree_mass < 1 || prm->amg_cycles < 1 || prm->schur_pcg < 0
         || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
-        || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0))
+        || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0)
+        || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol))
         return ORC_EINVAL;
     for (int64_t i = 0; i < nc * (dim + 1); ++i)
         if (cells[i] < 0 || cells[i] >= nv)

@@ -57,7 +57,7 @@ typedef struct {
     double rtol;         /* FGMRES relative residual tolerance (2-norm, relative to ||b||) */
     int32_t restart;     /* FGMRES restart length m */
     int32_t max_iters;   /* total FGMRES iterations allowed per solve */
-    int32_t amg_cycles;  /* V-cycles per stationary AMG solve (mass solves) */
+    int32_t amg_cycles;  /* V-cycles per stationary AMG solve (mass solves); the cap when amg_tol > 0 */
     int32_t schur_pcg;   /* CG steps (one V-cycle each) per As solve; 0 = stationary */
     int32_t smoother;    /* ORC_SMOOTH_* */
     int32_t cheb_degree; /* As hierarchies: Chebyshev degree (pre and post) or Jacobi sweeps */
@@ -76,6 +76,12 @@ typedef struct {
     double bc_g[2], bc_h[2]; /* substrate coefficients g_i, h_i */
     int32_t bc_pattern;  /* 1: p_p, p_n alternate on sixths of the bottom (Section 4); 0: p = 1 */
     int32_t krylov;      /* ORC_KRYLOV_*: the Krylov method of each time step */
+    /* Inner tolerance of the stationary AMG solves (the paper runs its AMG
+     * preconditioner to a tolerance of 1e-4, Section 4): 0 gives exactly
+     * amg_cycles V-cycles; amg_tol > 0 stops as soon as the 2-norm
+     * residual of the block is at most amg_tol times the norm of its
+     * right-hand side, after at least one and at most amg_cycles cycles. */
+    double amg_tol;
 } orc_params_t;
 
 /* FGMRES (right preconditioned, any Algorithm 1), or preconditioned MINRES

@@ -97,3 +97,66 @@ def test_minres_step_matches_sparse_lu_and_conserves_mass():
         assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
     M = o.scipy_matrix("M")
     assert abs(np.ones(nv) @ (M @ (new["phi_p"] - php))) <= 1e-10
+
+
+# ---- the inner tolerance of the stationary AMG solves (Section 4 runs its
+# AMG preconditioner to a relative tolerance of 1e-4)
+
+def level0(o, hier):
+    lv = o.level(hier, 0)
+    rp, ci, v = lv["A"]
+    return sp.csr_matrix((v, ci, rp), shape=(lv["n"], lv["n"]))
+
+
+@pytest.mark.parametrize("hier", [0, 1])
+def test_inner_tolerance_stops_at_the_first_cycle_that_meets_it(hier):
+    """The solve to amg_tol equals the fixed-cycle solve with k cycles, k the
+    smallest count whose residual (computed here with scipy) meets the
+    tolerance: this pins both the test and where it is taken."""
+    tol = 1e-4
+    base = dict(n=(14, 11), coarse_max=6)
+    fixed = {}
+    for k in range(1, 16):
+        fixed[k] = setup(**base, amg_cycles=k)[3]
+    _, _, _, ot = setup(**base, amg_cycles=40, amg_tol=tol)
+    A = level0(ot, hier)
+    rng = np.random.default_rng(11 + hier)
+    b = rng.standard_normal(A.shape[0])
+    x = ot.amg_solve(hier, b)
+    xs = {k: fixed[k].amg_solve(hier, b) for k in fixed}
+    res = {k: np.linalg.norm(b - A @ xs[k]) / np.linalg.norm(b) for k in xs}
+    kstar = min(k for k in res if res[k] <= tol)
+    assert kstar >= 2, res                      # the test is not vacuous
+    assert res[kstar - 1] > tol
+    assert np.array_equal(x, xs[kstar])
+    # the residuals the fixed solves reach fall monotonically (a convergent
+    # stationary iteration), so the first crossing is the only one
+    assert all(res[k + 1] < res[k] for k in range(1, kstar))
+
+
+def test_inner_tolerance_caps_at_amg_cycles_and_keeps_zero():
+    _, _, _, ot = setup(n=(10, 9), coarse_max=6, amg_cycles=2, amg_tol=1e-14)
+    _, _, _, o2 = setup(n=(10, 9), coarse_max=6, amg_cycles=2)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(ot.nv)
+    assert np.array_equal(ot.amg_solve(0, b), o2.amg_solve(0, b))
+    assert not np.any(ot.amg_solve(1, np.zeros(ot.nv)))
+
+
+def test_minres_with_inner_tolerance_solves_the_step():
+    """MINRES with the paper's inner tolerance (a slightly variable
+    preconditioner) still reaches the solution of the step (sparse LU)."""
+    p, co, ce, o = setup(n=(9, 8), rtol=1e-10, max_iters=500, amg_cycles=30, amg_tol=1e-4)
+    nv = co.shape[0]
+    php, phn, _ = S.initial_fractions(nv, 0.1, 0.1)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(nv), mu_n=np.zeros(nv))
+    new = o.step(st)
+    b0, _ = o.rhs(php, phn)
+    ref = splu(saddle_matrix(o, p, 0)).solve(b0)
+    got = np.concatenate([new["phi_p"], new["mu_p"]])
+    assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
+def test_negative_inner_tolerance_is_rejected():
+    with pytest.raises(OracleError):
+        setup(amg_tol=-1.0)
