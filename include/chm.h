@@ -133,6 +133,14 @@ typedef struct {
     double bc_g[2], bc_h[2];
     int32_t bc_pattern;
     int32_t krylov;        /* CHM_KRYLOV_* */
+    /* Inner tolerance of the stationary AMG solves (Section 4 runs its AMG
+     * preconditioner to 1e-4): 0 = exactly amg_cycles V-cycles; > 0 = per
+     * species, stop at the first cycle whose residual norm is at most amg_tol
+     * times the norm of the block's right-hand side (at least one cycle, at
+     * most amg_cycles).  The preconditioner then varies slightly from one
+     * application to the next; the cycle counts are decided on the host, so
+     * these runs use no HIP graphs. */
+    double amg_tol;
 } chm_params_t;
 
 /* Per-step statistics. */

@@ -78,6 +78,8 @@ const char *check_params(const chm_params_t &p)
         return "bad boundary coefficients";
     if (p.krylov != CHM_KRYLOV_FGMRES && p.krylov != CHM_KRYLOV_MINRES)
         return "unknown Krylov method";
+    if (!(p.amg_tol >= 0.0) || !std::isfinite(p.amg_tol))
+        return "amg_tol must be finite and non-negative";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -206,6 +208,8 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
             (void)hipHostFree(h->s.hctl);
         if (h->s.hmrctl)
             (void)hipHostFree(h->s.hmrctl);
+        if (h->s.hamg_act)
+            (void)hipHostFree(h->s.hamg_act);
         delete h;
         return rc;
     }
@@ -330,6 +334,8 @@ int chm_destroy(chm_solver_t *h)
         (void)hipHostFree(h->s.hctl);
     if (h->s.hmrctl)
         (void)hipHostFree(h->s.hmrctl);
+    if (h->s.hamg_act)
+        (void)hipHostFree(h->s.hamg_act);
     delete h;
     return CHM_OK;
 }

@@ -297,6 +297,9 @@ struct Solver {
     // y, v, w1, w2) and the per-run recurrence scalars, with a pinned mirror
     double2 *mr = nullptr;
     void *mrctl = nullptr, *hmrctl = nullptr;
+    // stationary AMG solves to amg_tol: per run, which species go on (device
+    // and pinned host mirror)
+    int2 *amg_act = nullptr, *hamg_act = nullptr;
 };
 
 // ---- util.hip

@@ -137,6 +137,38 @@ __global__ void __launch_bounds__(kBlock) k_axpy_add(int n, const pair_t<T> *__r
     x[row] = mk<T>(a.x + b.x, a.y + b.y);
 }
 
+// ------------------------------------------------------------------ inner tolerance
+// Per run (blockIdx.y) and species: whether the stationary solve goes on,
+// from the partials of b.b and r.r: it stops once ||r|| <= tol ||b|| (and
+// stays stopped: the iterate no longer changes).
+__global__ void __launch_bounds__(kBlock) k_amg_flags(const double2 *__restrict__ pb,
+                                                      const double2 *__restrict__ pr, int G,
+                                                      double tol, int2 *act, int first)
+{
+    __shared__ double2 sh[2];
+    reduce_two(run_at(pb, kSlotStride), run_at(pr, kSlotStride), G, sh);
+    if (threadIdx.x == 0) {
+        const int2 a = first ? make_int2(1, 1) : act[blockIdx.y];
+        const double bx = sqrt(sh[0].x), by = sqrt(sh[0].y);
+        const double rx = sqrt(sh[1].x), ry = sqrt(sh[1].y);
+        act[blockIdx.y] = make_int2(a.x && !(rx <= tol * bx), a.y && !(ry <= tol * by));
+    }
+}
+
+// the residual of a stopped species is set to zero, so its V-cycle
+// correction is exactly zero and its iterate stays as it is
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_amg_mask(int n, pair_t<T> *r, const int2 *__restrict__ act)
+{
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    const int2 a = act[blockIdx.y];
+    r = run_at(r, n);
+    const pair_t<T> v = r[row];
+    r[row] = mk<T>(a.x ? v.x : T(0), a.y ? v.y : T(0));
+}
+
 // ------------------------------------------------------------------ inner CG for As
 __device__ inline double2 ratio_or_zero(double2 num, double2 den)
 {
@@ -363,18 +395,39 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
         timer_mark(S, false);
 }
 
-// stationary AMG solve: x = V(b), then x += V(b - A x) for the further cycles
+// stationary AMG solve: x = V(b), then x += V(b - A x) for the further
+// cycles: amg_cycles in all, or with amg_tol > 0 until each species' residual
+// norm is at most amg_tol times that of its b (at most amg_cycles; the host
+// reads the flags after each residual, so this mode runs eagerly)
 template <class T>
 void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
 {
     Work<T> &W = work<T>(S);
     const Level &L0 = H.lev[0];
-    const int n = L0.n;
+    const int n = L0.n, R = S.nrun, G = red_blocks(n);
+    const double tol = S.prm.amg_tol;
+    hipStream_t st = S.stream;
     vcycle_level<T>(S, H, 0, b, x);
+    if (tol > 0.0 && S.prm.amg_cycles > 1)
+        k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, b, slot(S, kSlotRz));
     for (int c = 1; c < S.prm.amg_cycles; ++c) {
-        spmv_op<SP_RESID, T>(S.stream, S.nrun, L0.viewA<T>(), x, b, W.mr);
+        spmv_op<SP_RESID, T>(st, R, L0.viewA<T>(), x, b, W.mr);
+        if (tol > 0.0) {
+            k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, W.mr, W.mr, slot(S, kSlotRz + 1));
+            k_amg_flags<<<grid(1, R), kBlock, 0, st>>>(slot(S, kSlotRz), slot(S, kSlotRz + 1), G,
+                                                       tol, S.amg_act, c == 1);
+            CHM_HIP(hipMemcpyAsync(S.hamg_act, S.amg_act, sizeof(int2) * R, hipMemcpyDeviceToHost,
+                                   st));
+            CHM_HIP(hipStreamSynchronize(st));
+            bool any = false;
+            for (int r = 0; r < R; ++r)
+                any = any || S.hamg_act[r].x || S.hamg_act[r].y;
+            if (!any)
+                break;
+            k_amg_mask<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.mr, S.amg_act);
+        }
         vcycle_level<T>(S, H, 0, W.mr, W.me);
-        k_axpy_add<T><<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, W.me, x);
+        k_axpy_add<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.me, x);
     }
 }
 
@@ -534,6 +587,9 @@ void prec_setup(Solver &S)
     D.me = p.get<double2>(nb * n);
     D.h1 = p.get<double2>(nb * n);
     D.h2 = p.get<double2>(nb * n);
+    S.amg_act = p.get<int2>(nb);
+    CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hamg_act), nb * sizeof(int2),
+                          hipHostMallocDefault));
     if (!S.mixed)
         return;
     Work<float> &F = S.w32;

@@ -758,7 +758,7 @@ void iteration_body(Solver &S, int j)
 // The event timer records around kernels, so timed runs stay eager.
 void run_iteration(Solver &S, int j)
 {
-    if (!S.prm.use_graphs || S.timer.on) {
+    if (!S.prm.use_graphs || S.timer.on || S.prm.amg_tol > 0.0) {
         iteration_body(S, j);
         CHM_HIP(hipStreamSynchronize(S.stream));
         return;

@@ -3,7 +3,9 @@ with the symmetric positive definite Algorithm 1 (stationary V-cycles in both
 blocks), against the oracle's MINRES: equal iteration counts and fields to
 1e-10 per step, in 2D (with a ragged mesh), on the paper's 10 x 2.5 film with
 its boundary terms, and in 3D; a batch against single runs (bitwise); the
-FP32 preconditioner against FP64; the argument check."""
+FP32 preconditioner against FP64; the argument check.  Then the paper's
+inner tolerance (AMG solves stopped at a relative residual of 1e-4, Section
+4): the preconditioner, MINRES and FGMRES steps and a batch, the same way."""
 import numpy as np
 import pytest
 
@@ -14,6 +16,8 @@ pytestmark = pytest.mark.gpu
 
 FIELDS = ("phi_p", "phi_n", "mu_p", "mu_n")
 MINRES = dict(krylov="minres", schur_pcg=0, amg_cycles=2)
+# the paper's setting: AMG solves to a relative residual of 1e-4
+PAPER = dict(krylov="minres", schur_pcg=0, amg_cycles=30, amg_tol=1e-4)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -80,14 +84,13 @@ def test_minres_steps_match_oracle_3d():
     compare_steps(S.preset("square32", dim=3, n=(6, 5, 4), extent=(1.0, 1.0, 1.0), **MINRES))
 
 
-def test_minres_batch_equals_single_runs_bitwise():
-    case("MINRES batch of 3 vs single runs")
+def batch_vs_single(p, seed_off):
     from paper_2204_03575_amd import Solver
-    p = S.preset("square32", n=(20, 16), **MINRES)
     co, ce = S.make_mesh(p)
     nv = co.shape[0]
     rl = [dict(chi_pn=0.7, evap_ds=0.002, evap_steps=2), dict(chi_pn=1.2), dict(chi_pn=1.4)]
-    inits = [S.initial_fractions(nv, 0.1, 0.1, seed=S.BASE_SEED + 70 + r)[:2] for r in range(3)]
+    inits = [S.initial_fractions(nv, 0.1, 0.1, seed=S.BASE_SEED + seed_off + r)[:2]
+             for r in range(3)]
     b = Solver(co, ce, p, runs=rl)
     for r in range(3):
         b.set_fields(*inits[r], run=r)
@@ -102,6 +105,11 @@ def test_minres_batch_equals_single_runs_bitwise():
         fb, fs = b.get_fields(run=r), s.get_fields()
         for f in FIELDS:
             assert np.array_equal(fb[f], fs[f]), (r, f)
+
+
+def test_minres_batch_equals_single_runs_bitwise():
+    case("MINRES batch of 3 vs single runs")
+    batch_vs_single(S.preset("square32", n=(20, 16), **MINRES), 70)
 
 
 def test_minres_fp32_preconditioner_converges_to_fp64_solution():
@@ -134,3 +142,30 @@ def test_minres_needs_the_symmetric_preconditioner():
     co, ce = S.make_mesh(p)
     with pytest.raises(ChmError):
         Solver(co, ce, p)
+
+
+def test_preconditioner_with_inner_tolerance_matches_oracle():
+    case("Algorithm 1 with AMG solves to 1e-4")
+    from paper_2204_03575_amd import Solver
+    p = S.preset("square32", n=(29, 23), **PAPER)
+    co, ce = S.make_mesh(p)
+    g, o = Solver(co, ce, p), Oracle(co, ce, p)
+    one = Solver(co, ce, dict(p, amg_cycles=1, amg_tol=0.0))
+    rng = np.random.default_rng(8)
+    v0, v1 = rng.standard_normal(2 * o.nv), rng.standard_normal(2 * o.nv)
+    w0, w1 = g.apply_prec(v0, v1)
+    assert rel(w0, o.apply_prec(0, v0)) <= 1e-12
+    assert rel(w1, o.apply_prec(1, v1)) <= 1e-12
+    u0, _ = one.apply_prec(v0, v1)
+    assert rel(w0, u0) > 1e-6        # the tolerance took more than one cycle
+
+
+@pytest.mark.parametrize("krylov", ["minres", "fgmres"])
+def test_steps_with_inner_tolerance_match_oracle(krylov):
+    case("steps with AMG solves to 1e-4, 10 x 2.5 film", krylov=krylov)
+    compare_steps(S.preset("paper2d", n=(40, 10), **dict(PAPER, krylov=krylov, rtol=1e-7)))
+
+
+def test_batch_with_inner_tolerance_equals_single_runs_bitwise():
+    case("batch of 3 with AMG solves to 1e-4 vs single runs")
+    batch_vs_single(S.preset("square32", n=(18, 15), **PAPER), 90)
