@@ -85,22 +85,52 @@ const char *check_params(const chm_params_t &p)
     return nullptr;
 }
 
-void copy_field(double *dst_dev_pair, int n, int comp, const double *src, bool on_device,
-                hipStream_t st)
+// one field into component `comp` of a pair vector, and back out: comp 0
+// or 1, or 2 for phi_s = 1 - phi_p - phi_n (Section 2)
+__global__ void k_field_in(int n, const double *__restrict__ src, double2 *dst, int comp)
 {
-    // scatter one field into component `comp` of a pair vector
-    CHM_HIP(hipMemcpy2DAsync(reinterpret_cast<char *>(dst_dev_pair) + comp * sizeof(double),
-                             2 * sizeof(double), src, sizeof(double), sizeof(double), n,
-                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    double2 v = dst[i];
+    if (comp == 0)
+        v.x = src[i];
+    else
+        v.y = src[i];
+    dst[i] = v;
 }
 
-void get_field(double *dst, const double *src_dev_pair, int n, int comp, bool on_device,
-               hipStream_t st)
+__global__ void k_field_out(int n, const double2 *__restrict__ src, double *dst, int comp)
 {
-    CHM_HIP(hipMemcpy2DAsync(dst, sizeof(double),
-                             reinterpret_cast<const char *>(src_dev_pair) + comp * sizeof(double),
-                             2 * sizeof(double), sizeof(double), n,
-                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const double2 v = src[i];
+    dst[i] = comp == 0 ? v.x : (comp == 1 ? v.y : 1.0 - v.x - v.y);
+}
+
+inline int blocks256(int n) { return n > 0 ? (n + 255) / 256 : 1; }
+
+// src: device or host (through the solver's staging vector)
+void copy_field(chm::Solver &S, double2 *dst, int comp, const double *src, bool on_device)
+{
+    const int n = S.nv;
+    if (!on_device) {
+        CHM_HIP(hipMemcpyAsync(S.stage, src, sizeof(double) * n, hipMemcpyHostToDevice, S.stream));
+        src = S.stage;
+    }
+    k_field_in<<<blocks256(n), 256, 0, S.stream>>>(n, src, dst, comp);
+    CHM_HIP(hipGetLastError());
+}
+
+void get_field(chm::Solver &S, double *dst, const double2 *src, int comp, bool on_device)
+{
+    const int n = S.nv;
+    double *out = on_device ? dst : S.stage;
+    k_field_out<<<blocks256(n), 256, 0, S.stream>>>(n, src, out, comp);
+    CHM_HIP(hipGetLastError());
+    if (!on_device)
+        CHM_HIP(hipMemcpyAsync(dst, S.stage, sizeof(double) * n, hipMemcpyDeviceToHost, S.stream));
 }
 
 }  // namespace
@@ -236,15 +266,13 @@ int chm_set_fields_run(chm_solver_t *h, int32_t run, const double *phi_p, const 
         chm::Solver &S = h->s;
         const int n = S.nv;
         double2 *xr = S.x + (size_t)run * 2 * n;
-        double *x = reinterpret_cast<double *>(xr);
-        copy_field(x, n, 0, phi_p, on_device, S.stream);
-        copy_field(x, n, 1, phi_n, on_device, S.stream);
-        double *mu = reinterpret_cast<double *>(xr + n);
-        chm::fill_double(mu, 0.0, 2 * (size_t)n, S.stream);
+        copy_field(S, xr, 0, phi_p, on_device);
+        copy_field(S, xr, 1, phi_n, on_device);
+        chm::fill_double(reinterpret_cast<double *>(xr + n), 0.0, 2 * (size_t)n, S.stream);
         if (mu_p)
-            copy_field(mu, n, 0, mu_p, on_device, S.stream);
+            copy_field(S, xr + n, 0, mu_p, on_device);
         if (mu_n)
-            copy_field(mu, n, 1, mu_n, on_device, S.stream);
+            copy_field(S, xr + n, 1, mu_n, on_device);
         // the new state starts the history of solutions (of every run: the
         // runs of a batch share it)
         CHM_HIP(hipMemcpyAsync(S.yh1 + (size_t)run * 2 * n, xr, sizeof(double2) * 2 * (size_t)n,
@@ -266,7 +294,7 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
             int rc = chm::step_once(h->s, stats ? stats + (size_t)k * h->s.nb : nullptr);
             if (rc != CHM_OK)
                 return fail(h, rc, rc == CHM_ENOCONV
-                                       ? "FGMRES did not converge within max_iters"
+                                       ? "the Krylov method did not converge within max_iters"
                                        : "non-finite value in the solve (" + h->s.nan_where + ")");
         }
         return CHM_OK;
@@ -290,30 +318,17 @@ int chm_get_fields_run(chm_solver_t *h, int32_t run, double *phi_p, double *phi_
         chm::Solver &S = h->s;
         const int n = S.nv;
         const double2 *xr = S.x + (size_t)run * 2 * n;
-        const double *x = reinterpret_cast<const double *>(xr);
-        const double *mu = reinterpret_cast<const double *>(xr + n);
         if (phi_p)
-            get_field(phi_p, x, n, 0, on_device, S.stream);
+            get_field(S, phi_p, xr, 0, on_device);
         if (phi_n)
-            get_field(phi_n, x, n, 1, on_device, S.stream);
+            get_field(S, phi_n, xr, 1, on_device);
+        if (phi_s)
+            get_field(S, phi_s, xr, 2, on_device);
         if (mu_p)
-            get_field(mu_p, mu, n, 0, on_device, S.stream);
+            get_field(S, mu_p, xr + n, 0, on_device);
         if (mu_n)
-            get_field(mu_n, mu, n, 1, on_device, S.stream);
+            get_field(S, mu_n, xr + n, 1, on_device);
         CHM_HIP(hipStreamSynchronize(S.stream));
-        if (phi_s) {
-            // phi_s = 1 - phi_p - phi_n (Section 2), formed from the copied fields
-            std::vector<double> a(n), b(n);
-            get_field(a.data(), x, n, 0, false, S.stream);
-            get_field(b.data(), x, n, 1, false, S.stream);
-            CHM_HIP(hipStreamSynchronize(S.stream));
-            std::vector<double> s(n);
-            for (int i = 0; i < n; ++i)
-                s[i] = 1.0 - a[i] - b[i];
-            CHM_HIP(hipMemcpyAsync(phi_s, s.data(), sizeof(double) * n,
-                                   on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, S.stream));
-            CHM_HIP(hipStreamSynchronize(S.stream));
-        }
         return CHM_OK;
     });
 }

@@ -300,6 +300,7 @@ struct Solver {
     // stationary AMG solves to amg_tol: per run, which species go on (device
     // and pinned host mirror)
     int2 *amg_act = nullptr, *hamg_act = nullptr;
+    double *stage = nullptr;   // one field, for host-side set/get of fields
 };
 
 // ---- util.hip

@@ -680,6 +680,7 @@ void alloc_workspace(Solver &S)
     S.V = p.get<double2>(nb * len * (S.m + 1));
     S.Z = p.get<double2>(nb * len * S.m);
     S.f = p.get<double2>(nb * n);
+    S.stage = p.get<double>(n);
     S.red = p.get<double2>(nb * kSlotStride);
     S.gsp1 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
     S.gsp2 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
