@@ -29,19 +29,30 @@ namespace {
 // d_{k-1} = x_k - x_{k-1}.  x_{k+1} overwrites x_{k-1} row by row; with
 // prev = 0 the previous iterate is taken as zero (start from x = 0) or is not
 // needed (c1 = 0).
+// the row's operands of the update, loaded apart from the product so that a
+// kernel can issue them before the gathers of A x_k
+template <class T> struct ChebRow {
+    pair_t<T> bb, xi, xp;
+    T di;
+};
+
 template <class T>
-__device__ inline pair_t<T> cheb_update(pair_t<T> s, const pair_t<T> *__restrict__ b,
-                                        const pair_t<T> *__restrict__ xk,
-                                        const T *__restrict__ dinv, const pair_t<T> *xprev,
-                                        int row, T c1, T c2, int prev)
+__device__ inline ChebRow<T> cheb_row(const pair_t<T> *__restrict__ b, const pair_t<T> *__restrict__ xk,
+                                      const T *__restrict__ dinv, const pair_t<T> *xprev, int row,
+                                      int prev)
 {
-    const pair_t<T> bb = b[row], xi = xk[row];
-    const T di = dinv[row];
-    pair_t<T> xp = mk<T>(0, 0);
-    if (prev)
-        xp = xprev[row];
-    return mk<T>(xi.x + c1 * (xi.x - xp.x) + c2 * (di * (bb.x - s.x)),
-                 xi.y + c1 * (xi.y - xp.y) + c2 * (di * (bb.y - s.y)));
+    ChebRow<T> o;
+    o.bb = b[row];
+    o.xi = xk[row];
+    o.di = dinv[row];
+    o.xp = prev ? xprev[row] : mk<T>(0, 0);
+    return o;
+}
+
+template <class T> __device__ inline pair_t<T> cheb_apply(pair_t<T> s, const ChebRow<T> &o, T c1, T c2)
+{
+    return mk<T>(o.xi.x + c1 * (o.xi.x - o.xp.x) + c2 * (o.di * (o.bb.x - s.x)),
+                 o.xi.y + c1 * (o.xi.y - o.xp.y) + c2 * (o.di * (o.bb.y - s.y)));
 }
 
 template <class T>
@@ -59,8 +70,9 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     b = run_at(b, n);
     xk = run_at(xk, n);
     xprev = run_at(xprev, n);
+    const ChebRow<T> o = cheb_row<T>(b, xk, dinv, xprev, row, prev);
     const pair_t<T> s = sell_row<T>(sptr, col, val, xk, row);
-    xprev[row] = cheb_update<T>(s, b, xk, dinv, xprev, row, c1, c2, prev);
+    xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
 template <int GS, class T>
@@ -82,7 +94,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
     const pair_t<T> s = row_dot<GS, T>(rp, ci, v, xk, row, lane);
     if (lane != 0)
         return;
-    xprev[row] = cheb_update<T>(s, b, xk, dinv, xprev, row, c1, c2, prev);
+    xprev[row] = cheb_apply<T>(s, cheb_row<T>(b, xk, dinv, xprev, row, prev), c1, c2);
 }
 
 // first smoothing step from x = 0: x = c2 D^-1 b
@@ -100,28 +112,45 @@ __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ d
 }
 
 // coarsest level: x = A^-1 b with the FP64 inverse stored row-major.  One
-// block per row: thread t takes columns t, t + 256, ... (coalesced reads of the
-// row; b stays in L2), then a fixed wave-shuffle and LDS tree; FP64 sums in
-// both precisions.
+// wave per row (four rows per block): lane l takes columns l, l + 64, ...,
+// four of them per pass into separate accumulators, so each lane keeps four
+// loads of the row in flight (the inverse streams from the last-level cache;
+// b stays in L2); the accumulators are added in a fixed order and the wave
+// with a fixed shuffle tree.  FP64 sums in both precisions.
+constexpr int kDenseRows = kBlock / 64;
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
                                                   const pair_t<T> *__restrict__ b, pair_t<T> *x)
 {
-    __shared__ double2 sh[kBlock / 64];
-    const int row = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * kDenseRows + (threadIdx.x >> 6);
+    if (row >= n)
+        return;   // the whole wave: row depends on the wave only
     const double *a = inv + (size_t)row * n;
     b = run_at(b, n);
-    x = run_at(x, n);
-    double2 acc = d2(0.0, 0.0);
-    for (int j = threadIdx.x; j < n; j += kBlock) {
+    double2 acc[4] = {d2(0.0, 0.0), d2(0.0, 0.0), d2(0.0, 0.0), d2(0.0, 0.0)};
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double v = a[j + 64 * u];
+            const pair_t<T> bv = b[j + 64 * u];
+            acc[u].x += v * double(bv.x);
+            acc[u].y += v * double(bv.y);
+        }
+    }
+    for (; j < n; j += 64) {
         const double v = a[j];
         const pair_t<T> bv = b[j];
-        acc.x += v * double(bv.x);
-        acc.y += v * double(bv.y);
+        acc[0].x += v * double(bv.x);
+        acc[0].y += v * double(bv.y);
     }
-    const double2 s = block_sum(acc, sh);
-    if (threadIdx.x == 0)
-        x[row] = mk<T>(T(s.x), T(s.y));
+    double2 s = d2((acc[0].x + acc[1].x) + (acc[2].x + acc[3].x),
+                   (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y));
+    s = wave_sum(s);
+    if (lane == 0)
+        run_at(x, n)[row] = mk<T>(T(s.x), T(s.y));
 }
 
 template <class T>
@@ -360,7 +389,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     hipStream_t st = S.stream;
     const int R = S.nrun;
     if (l == H.nlev - 1) {
-        k_dense<T><<<grid(L.n, R), kBlock, 0, st>>>(L.n, L.inv, b, x);
+        k_dense<T><<<grid(nblk(L.n, kDenseRows), R), kBlock, 0, st>>>(L.n, L.inv, b, x);
         return;
     }
     const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
