@@ -671,15 +671,25 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
             cap *= 2;
         return std::min(want, cap);
     };
+    // entries per CSR lane and pass: about the average row length over the
+    // lanes, so short rows do not load padding and long rows keep four loads
+    // in flight per lane
+    auto unroll = [](const Csr &A, int gs) {
+        const double per_lane = (gs > 0 && A.n > 0) ? double(A.nnz) / A.n / gs : 1.0;
+        return per_lane > 2.0 ? 4 : (per_lane > 1.0 ? 2 : 1);
+    };
     for (int l = 0; l < H.nlev; ++l) {
         Level &L = H.lev[l];
         csr_to_sell(L.A, L.sA, pool, st);
         L.gsA = lanes_per_row(L.A);
+        L.uA = unroll(L.A, L.gsA);
         if (l + 1 < H.nlev) {
             csr_to_sell(L.P, L.sP, pool, st);
             csr_to_sell(L.R, L.sR, pool, st);
             L.gsP = lanes_per_row(L.P);
             L.gsR = lanes_per_row(L.R);
+            L.uP = unroll(L.P, L.gsP);
+            L.uR = unroll(L.R, L.gsR);
         }
         const size_t len = (size_t)S.nb * L.n;   // all runs of the batch
         H.x[l] = pool.get<double2>(len);

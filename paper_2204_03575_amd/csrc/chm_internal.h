@@ -95,9 +95,10 @@ struct Sell {      // device SELL-64
 // One matrix of a level as the solve kernels see it, in value type T: the
 // SELL-64 layout (sptr, col, sval) and the CSR layout (rp, ci, cval) share the
 // pattern; gs = lanes per row (0: SELL-64 with one lane per row, 4..32: CSR
-// with that many lanes per row, for long or few rows).
+// with that many lanes per row, for long or few rows); u = entries a CSR lane
+// loads per pass (1, 2 or 4: about the row length over gs).
 template <class T> struct MatView {
-    int n = 0, m = 0, nnz = 0, gs = 0;   // rows, columns, nonzeros, lanes per row
+    int n = 0, m = 0, nnz = 0, gs = 0, u = 1;   // rows, columns, nonzeros, lanes per row, unroll
     const int *sptr = nullptr, *col = nullptr, *rp = nullptr, *ci = nullptr;
     const T *sval = nullptr, *cval = nullptr;
 };
@@ -107,6 +108,7 @@ struct Level {
     Csr A, P, R;
     Sell sA, sP, sR;
     int gsA = 0, gsP = 0, gsR = 0;   // lanes per row (see MatView)
+    int uA = 1, uP = 1, uR = 1;      // CSR entries per lane and pass (see MatView)
     double *dinv = nullptr;
     double rho = 0.0;
     int *agg = nullptr;
@@ -125,9 +127,11 @@ struct Level {
     template <class T> const T *dinv_t() const;
 };
 
-template <class T> inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, const T *sv, const T *cv)
+template <class T>
+inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, int u, const T *sv, const T *cv)
 {
     MatView<T> v;
+    v.u = u;
     v.n = C.n;
     v.m = C.m;
     v.nnz = C.nnz;
@@ -140,12 +144,12 @@ template <class T> inline MatView<T> make_view(const Csr &C, const Sell &S, int 
     v.cval = cv;
     return v;
 }
-template <> inline MatView<double> Level::viewA<double>() const { return make_view<double>(A, sA, gsA, sA.val, A.v); }
-template <> inline MatView<double> Level::viewP<double>() const { return make_view<double>(P, sP, gsP, sP.val, P.v); }
-template <> inline MatView<double> Level::viewR<double>() const { return make_view<double>(R, sR, gsR, sR.val, R.v); }
-template <> inline MatView<float> Level::viewA<float>() const { return make_view<float>(A, sA, gsA, fA_s, fA_c); }
-template <> inline MatView<float> Level::viewP<float>() const { return make_view<float>(P, sP, gsP, fP_s, fP_c); }
-template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, fR_s, fR_c); }
+template <> inline MatView<double> Level::viewA<double>() const { return make_view<double>(A, sA, gsA, uA, sA.val, A.v); }
+template <> inline MatView<double> Level::viewP<double>() const { return make_view<double>(P, sP, gsP, uP, sP.val, P.v); }
+template <> inline MatView<double> Level::viewR<double>() const { return make_view<double>(R, sR, gsR, uR, sR.val, R.v); }
+template <> inline MatView<float> Level::viewA<float>() const { return make_view<float>(A, sA, gsA, uA, fA_s, fA_c); }
+template <> inline MatView<float> Level::viewP<float>() const { return make_view<float>(P, sP, gsP, uP, fP_s, fP_c); }
+template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, uR, fR_s, fR_c); }
 template <> inline const double *Level::dinv_t<double>() const { return dinv; }
 template <> inline const float *Level::dinv_t<float>() const { return fdinv; }
 

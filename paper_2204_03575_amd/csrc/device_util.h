@@ -223,19 +223,37 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
 // The same with a group of GS lanes per row (CSR), for matrices with long rows
 // or few rows: lane l of the group takes entries l, l + GS, ... of the row and
 // the group adds its lanes with a fixed shuffle tree.  Whole groups share a
-// row, so they exit together.
-template <int GS, class T>
+// row, so they exit together.  A lane takes U of its entries per pass,
+// loading all their indices and values, then all their gathers, before the
+// products (entries past the row end repeat its last entry with a zero
+// coefficient), so a pass costs two dependent memory round trips.
+template <int GS, int U, class T>
 __device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
                                     const T *__restrict__ v, const pair_t<T> *__restrict__ x,
                                     int row, int lane)
 {
     T ax = 0, ay = 0;
-    const int e = rp[row + 1];
-    for (int k = rp[row] + lane; k < e; k += GS) {
-        const T a = v[k];
-        const pair_t<T> xv = x[ci[k]];
-        ax += a * xv.x;
-        ay += a * xv.y;
+    const int s = rp[row], e = rp[row + 1];
+    for (int k0 = s + lane; k0 < e; k0 += GS * U) {
+        int c[U];
+        T a[U];
+        pair_t<T> xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * GS;
+            const int kk = k < e ? k : e - 1;
+            c[u] = ci[kk];
+            const T val = v[kk];
+            a[u] = k < e ? val : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ax += a[u] * xv[u].x;
+            ay += a[u] * xv[u].y;
+        }
     }
 #pragma unroll
     for (int off = GS / 2; off > 0; off >>= 1) {
@@ -245,7 +263,7 @@ __device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__res
     return mk<T>(ax, ay);
 }
 
-template <int GS, int MODE, class T>
+template <int GS, int U, int MODE, class T>
 __global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
                                                    const T *__restrict__ v,
@@ -260,9 +278,23 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(int n, const int *__restrict_
     x = run_at(x, sx);
     b = run_at(b, sy);
     y = run_at(y, sy);
-    const pair_t<T> s = row_dot<GS, T>(rp, ci, v, x, row, lane);
+    const pair_t<T> s = row_dot<GS, U, T>(rp, ci, v, x, row, lane);
     if (lane == 0)
         spmv_store<MODE, T>(s, b, y, row);
+}
+
+// the CSR-vector launch for the matrix's entries per lane and pass
+template <int GS, int MODE, class T>
+void spmv_v_u(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
+              const pair_t<T> *b, pair_t<T> *y, long sx, long sy)
+{
+    const dim3 g = grid(nblk((long)GS * A.n), runs);
+    if (A.u >= 4)
+        k_spmv_v<GS, 4, MODE, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, x, sx, b, y, sy);
+    else if (A.u == 2)
+        k_spmv_v<GS, 2, MODE, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, x, sx, b, y, sy);
+    else
+        k_spmv_v<GS, 1, MODE, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, x, sx, b, y, sy);
 }
 
 // y = A x / y += A x / y = b - A x with the kernel shape chosen for the
@@ -277,26 +309,23 @@ void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
         sx = A.m;
     if (sy < 0)
         sy = A.n;
-    switch (A.gs) {
-    case 0:
+    if (A.gs == 0) {
         k_spmv<MODE, T><<<grid(nblk(n), runs), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, x, sx, b,
                                                                 y, sy);
-        break;
+        return;
+    }
+    switch (A.gs) {
     case 4:
-        k_spmv_v<4, MODE, T><<<grid(nblk(4l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x,
-                                                                          sx, b, y, sy);
+        spmv_v_u<4, MODE, T>(st, runs, A, x, b, y, sx, sy);
         break;
     case 8:
-        k_spmv_v<8, MODE, T><<<grid(nblk(8l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, x,
-                                                                          sx, b, y, sy);
+        spmv_v_u<8, MODE, T>(st, runs, A, x, b, y, sx, sy);
         break;
     case 16:
-        k_spmv_v<16, MODE, T><<<grid(nblk(16l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval,
-                                                                            x, sx, b, y, sy);
+        spmv_v_u<16, MODE, T>(st, runs, A, x, b, y, sx, sy);
         break;
     default:
-        k_spmv_v<32, MODE, T><<<grid(nblk(32l * n), runs), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval,
-                                                                            x, sx, b, y, sy);
+        spmv_v_u<32, MODE, T>(st, runs, A, x, b, y, sx, sy);
         break;
     }
 }

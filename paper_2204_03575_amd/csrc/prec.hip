@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
-template <int GS, class T>
+template <int GS, int U, class T>
 __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
                                                    const T *__restrict__ v,
@@ -91,10 +91,11 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
     b = run_at(b, n);
     xk = run_at(xk, n);
     xprev = run_at(xprev, n);
-    const pair_t<T> s = row_dot<GS, T>(rp, ci, v, xk, row, lane);
+    const ChebRow<T> o = cheb_row<T>(b, xk, dinv, xprev, row, prev);   // the group's lanes share these lines
+    const pair_t<T> s = row_dot<GS, U, T>(rp, ci, v, xk, row, lane);
     if (lane != 0)
         return;
-    xprev[row] = cheb_apply<T>(s, cheb_row<T>(b, xk, dinv, xprev, row, prev), c1, c2);
+    xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
 // first smoothing step from x = 0: x = c2 D^-1 b
@@ -339,6 +340,23 @@ bool timed_level(const Solver &S, const Hierarchy &H, int l)
     return S.timer.on && S.timer.kind == 0 && &H == &S.hA && l == 0;
 }
 
+// the CSR-vector smoothing launch for the matrix's entries per lane and pass
+template <int GS, class T>
+void cheb_v_u(hipStream_t st, int R, const MatView<T> &A, const T *dinv, const pair_t<T> *b,
+              const pair_t<T> *xk, pair_t<T> *xprev, T c1, T c2, int prev)
+{
+    const dim3 g = grid(nblk((long)GS * A.n), R);
+    if (A.u >= 4)
+        k_cheb_v<GS, 4, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, xk, xprev, c1, c2,
+                                                 prev);
+    else if (A.u == 2)
+        k_cheb_v<GS, 2, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, xk, xprev, c1, c2,
+                                                 prev);
+    else
+        k_cheb_v<GS, 1, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, xk, xprev, c1, c2,
+                                                 prev);
+}
+
 // one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
 template <class T>
 void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_t<T> *xk,
@@ -356,20 +374,16 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
                                                        c1, c2, prev);
         break;
     case 4:
-        k_cheb_v<4, T><<<grid(nblk(4l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
-                                                                 xprev, c1, c2, prev);
+        cheb_v_u<4, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
         break;
     case 8:
-        k_cheb_v<8, T><<<grid(nblk(8l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b, xk,
-                                                                 xprev, c1, c2, prev);
+        cheb_v_u<8, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
         break;
     case 16:
-        k_cheb_v<16, T><<<grid(nblk(16l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b,
-                                                                   xk, xprev, c1, c2, prev);
+        cheb_v_u<16, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
         break;
     default:
-        k_cheb_v<32, T><<<grid(nblk(32l * n), R), kBlock, 0, st>>>(n, A.rp, A.ci, A.cval, dinv, b,
-                                                                   xk, xprev, c1, c2, prev);
+        cheb_v_u<32, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
         break;
     }
     if (timed_level(S, H, l)) {
