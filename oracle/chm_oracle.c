@@ -1019,7 +1019,13 @@ static void prec(const orc_solver_t *s, int sp, const double *v, double *w)
 {
     int n = s->nv;
     double *t = malloc(sizeof(double) * (size_t)n), *u = malloc(sizeof(double) * (size_t)n);
-    amg_stationary(&s->prm, &s->hM, v, w);
+    if (s->prm.mass_solver == ORC_MASS_CHEBYSHEV) {
+        /* w1 = the Chebyshev semi-iteration on M from zero (t, u as work) */
+        memset(w, 0, sizeof(double) * (size_t)n);
+        smooth(&s->prm, &s->hM, &s->hM.lev[0], v, w, t, u);
+    } else {
+        amg_stationary(&s->prm, &s->hM, v, w);
+    }
     amg_schur(&s->prm, &s->hA[sp], v + n, t);
     csr_mv(&s->M, t, u);
     amg_schur(&s->prm, &s->hA[sp], u, w + n);
@@ -1329,7 +1335,8 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
         || prm->cheb_degree_mass < 1 || prm->amg_cycles < 1 || prm->schur_pcg < 0
         || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
         || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0)
-        || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol))
+        || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol)
+        || (prm->mass_solver != ORC_MASS_AMG && prm->mass_solver != ORC_MASS_CHEBYSHEV))
         return ORC_EINVAL;
     for (int64_t i = 0; i < nc * (dim + 1); ++i)
         if (cells[i] < 0 || cells[i] >= nv)

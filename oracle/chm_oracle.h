@@ -82,6 +82,13 @@ typedef struct {
      * residual of the block is at most amg_tol times the norm of its
      * right-hand side, after at least one and at most amg_cycles cycles. */
     double amg_tol;
+    /* The mass block of Algorithm 1 (an approximation of M^-1, Section 3):
+     * ORC_MASS_AMG, amg_cycles stationary V-cycles of the mass hierarchy;
+     * ORC_MASS_CHEBYSHEV, the Chebyshev semi-iteration the paper names as
+     * the alternative (Wathen and Rees): cheb_degree_mass steps on D^-1 M
+     * over [rho/cheb_ratio_mass, rho] from zero, no coarse levels (the
+     * mass hierarchy's fine-level smoother applied once). */
+    int32_t mass_solver;
 } orc_params_t;
 
 /* FGMRES (right preconditioned, any Algorithm 1), or preconditioned MINRES
@@ -90,6 +97,8 @@ typedef struct {
  * the residual in the preconditioner's inverse norm relative to that of b */
 #define ORC_KRYLOV_FGMRES 0
 #define ORC_KRYLOV_MINRES 1
+#define ORC_MASS_AMG 0
+#define ORC_MASS_CHEBYSHEV 1
 
 typedef struct {
     int32_t iters[2];
