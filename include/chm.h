@@ -74,6 +74,9 @@ extern "C" {
 #define CHM_KRYLOV_FGMRES 0
 #define CHM_KRYLOV_MINRES 1
 
+#define CHM_MASS_AMG 0
+#define CHM_MASS_CHEBYSHEV 1
+
 typedef struct chm_solver chm_solver_t;
 
 /* A conforming simplex mesh: triangles (dim 2) or tetrahedra (dim 3).
@@ -141,6 +144,15 @@ typedef struct {
      * application to the next; the cycle counts are decided on the host, so
      * these runs use no HIP graphs. */
     double amg_tol;
+    /* The mass block of Algorithm 1, an approximation of M^-1 (Section 3
+     * names AMG and, after Wathen and Rees, a Chebyshev semi-iteration):
+     * CHM_MASS_AMG, amg_cycles stationary V-cycles of the mass hierarchy
+     * (smoother degree cheb_degree_mass); CHM_MASS_CHEBYSHEV,
+     * cheb_degree_mass Chebyshev steps on D^-1 M over
+     * [rho/cheb_ratio_mass, rho] from zero, with no coarse levels (damped
+     * Jacobi sweeps with the Jacobi smoother).  Both are fixed symmetric
+     * positive definite operators. */
+    int32_t mass_solver;
 } chm_params_t;
 
 /* Per-step statistics. */

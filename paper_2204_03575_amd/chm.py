@@ -64,7 +64,7 @@ class chm_params_t(C.Structure):
         ("precision", C.c_int32),
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
-        ("amg_tol", C.c_double),
+        ("amg_tol", C.c_double), ("mass_solver", C.c_int32),
     ]
 
 
@@ -167,6 +167,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.bc_pattern = int(p.get("bc_pattern", 0))
     s.krylov = {"fgmres": 0, "minres": 1}[p.get("krylov", "fgmres")]
     s.amg_tol = float(p.get("amg_tol", 0.0))
+    s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
     return s
 
 

@@ -80,6 +80,8 @@ const char *check_params(const chm_params_t &p)
         return "unknown Krylov method";
     if (!(p.amg_tol >= 0.0) || !std::isfinite(p.amg_tol))
         return "amg_tol must be finite and non-negative";
+    if (p.mass_solver != CHM_MASS_AMG && p.mass_solver != CHM_MASS_CHEBYSHEV)
+        return "unknown mass solver";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;

@@ -396,6 +396,33 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     }
 }
 
+// The level's smoother from x = 0: deg steps (Chebyshev over the level's
+// interval, or damped Jacobi) on b, the first into `first`, each further step
+// into the other buffer.  Returns the buffer holding the result (first when
+// deg is odd).
+template <class T>
+pair_t<T> *presmooth(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> *first,
+                     pair_t<T> *other)
+{
+    const Level &L = H.lev[l];
+    const int deg = H.degree, R = S.nrun;
+    auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
+    auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
+    k_cheb0<T><<<grid(nblk(L.n), R), kBlock, 0, S.stream>>>(L.n, L.dinv_t<T>(), b, first,
+                                                             T(c2(1)));
+    pair_t<T> *cur = first, *oth = other;
+    const bool timed = timed_level(S, H, l);
+    if (timed && deg >= 2)
+        timer_mark(S, true);
+    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
+        launch_cheb<T>(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
+        std::swap(cur, oth);
+    }
+    if (timed && deg >= 2)
+        timer_mark(S, false);
+    return cur;
+}
+
 template <class T>
 void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> *x)
 {
@@ -413,17 +440,9 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     // Pre-smoothing from zero.  Every step after the first writes the buffer
     // not holding the current iterate; 2 deg - 1 such steps follow the first,
     // so starting in xt leaves the result in x.
-    k_cheb0<T><<<grid(nblk(L.n), R), kBlock, 0, st>>>(L.n, L.dinv_t<T>(), b, V.xt, T(c2(1)));
-    pair_t<T> *cur = V.xt, *oth = x;
+    pair_t<T> *cur = presmooth<T>(S, H, l, b, V.xt, x);
+    pair_t<T> *oth = cur == x ? V.xt : x;
     const bool timed = timed_level(S, H, l);
-    if (timed && deg >= 2)
-        timer_mark(S, true);
-    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
-        launch_cheb<T>(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
-        std::swap(cur, oth);
-    }
-    if (timed && deg >= 2)
-        timer_mark(S, false);
     spmv_op<SP_RESID, T>(st, R, L.viewA<T>(), cur, b, V.r);
     spmv_op<SP_SET, T>(st, R, L.viewR<T>(), V.r, nullptr, Vc.b);
     vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
@@ -441,7 +460,9 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
 // stationary AMG solve: x = V(b), then x += V(b - A x) for the further
 // cycles: amg_cycles in all, or with amg_tol > 0 until each species' residual
 // norm is at most amg_tol times that of its b (at most amg_cycles; the host
-// reads the flags after each residual, so this mode runs eagerly)
+// reads the flags after each residual, so this mode runs eagerly).  The mass
+// block with mass_solver = CHM_MASS_CHEBYSHEV is a Chebyshev semi-iteration
+// instead (Section 3 names it as the alternative to AMG for M).
 template <class T>
 void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
 {
@@ -450,6 +471,14 @@ void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
     const int n = L0.n, R = S.nrun, G = red_blocks(n);
     const double tol = S.prm.amg_tol;
     hipStream_t st = S.stream;
+    if (&H == &S.hM && S.prm.mass_solver == CHM_MASS_CHEBYSHEV) {
+        // the Chebyshev semi-iteration on M instead of V-cycles: the mass
+        // hierarchy's fine-level smoother from zero, landing in x
+        pair_t<T> *xt = vecs<T>(H, 0).xt;
+        const bool odd = H.degree % 2 == 1;
+        presmooth<T>(S, H, 0, b, odd ? x : xt, odd ? xt : x);
+        return;
+    }
     vcycle_level<T>(S, H, 0, b, x);
     if (tol > 0.0 && S.prm.amg_cycles > 1)
         k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, b, slot(S, kSlotRz));

@@ -181,7 +181,12 @@ def test_square32_free_running_trajectory():
     dict(restart=5),                                  # forces restarts
     dict(tau=1e-6, eps=1e-2, mobility=2.0),
     dict(potential="none"),
-], ids=["poly", "jacobi", "stationary", "restart5", "tau-eps-mob", "nopot"])
+    dict(mass_solver="chebyshev", cheb_degree_mass=5),
+    dict(mass_solver="chebyshev", cheb_degree_mass=4, smoother="jacobi", cheb_degree=3),
+    dict(mass_solver="chebyshev", cheb_degree_mass=5, krylov="minres", schur_pcg=0,
+         amg_cycles=2),
+], ids=["poly", "jacobi", "stationary", "restart5", "tau-eps-mob", "nopot", "mass-cheb",
+        "mass-jacobi", "mass-cheb-minres"])
 def test_step_variants(variant):
     v = dict(variant)
     mean = v.pop("mean", (0.1, 0.1))
@@ -191,10 +196,23 @@ def test_step_variants(variant):
     run_pair(p, co, ce, g, o, 2, php, phn)
 
 
-def test_3d_box_steps():
-    case("3d box 6x6x4, 2 steps")
-    p, co, ce, g, o = make(n=(6, 6, 4), dim=3, extent=(1.0, 1.0, 0.5))
+@pytest.mark.parametrize("mass", ["amg", "chebyshev"])
+def test_3d_box_steps(mass):
+    case("3d box 6x6x4, 2 steps", mass_solver=mass)
+    p, co, ce, g, o = make(n=(6, 6, 4), dim=3, extent=(1.0, 1.0, 0.5), mass_solver=mass,
+                           cheb_degree_mass=5 if mass == "chebyshev" else 2)
     run_pair(p, co, ce, g, o, 2)
+
+
+@pytest.mark.parametrize("mass", ["chebyshev"])
+def test_preconditioner_with_chebyshev_mass_matches(mass):
+    case("Algorithm 1 with the Chebyshev mass solve")
+    p, co, ce, g, o = make(n=(23, 19), mass_solver=mass, cheb_degree_mass=5)
+    rng = np.random.default_rng(12)
+    v0, v1 = rng.standard_normal(2 * o.nv), rng.standard_normal(2 * o.nv)
+    w0, w1 = g.apply_prec(v0, v1)
+    assert relerr(w0, o.apply_prec(0, v0)) <= 1e-12
+    assert relerr(w1, o.apply_prec(1, v1)) <= 1e-12
 
 
 def test_evaporation_steps():
