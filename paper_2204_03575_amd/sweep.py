@@ -3,10 +3,10 @@
 Runs are grouped by mesh size; each group is one batched solver
 (chm_create_batch): its runs share the assembled matrices and both AMG
 hierarchies, and every kernel launch of a time step covers all of them.  An
-autotuner picks, per group, the preconditioner settings (Chebyshev degree of
-the As hierarchy, CG steps per As solve, HIP graphs or eager launches) with
-the shortest time per step measured on the group itself, from the same state,
-at the same residual tolerance.  All computation runs in the library; this
+autotuner picks, per group, the preconditioner settings (Chebyshev degree and
+interval of the As hierarchy, CG steps per As solve, HIP graphs or eager
+launches) with the shortest time per step measured on the group itself, from
+the same state, at the same residual tolerance.  All computation runs in the library; this
 module only schedules it.
 """
 from __future__ import annotations
@@ -20,8 +20,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SIZES = (128, 192, 256, 384, 512)
-TUNE_SPACE = [dict(cheb_degree=d, schur_pcg=k, use_graphs=g)
-              for d in (3, 4) for k in (2, 3) for g in (1, 0)]
+TUNE_SPACE = [dict(cheb_degree=d, schur_pcg=k, cheb_ratio=r, use_graphs=g)
+              for (d, k, r) in ((6, 2, 5.0), (5, 2, 8.0), (4, 2, 15.0), (4, 3, 30.0))
+              for g in (1, 0)]
 
 
 def draw_runs(count: int = 64, seed: int = 20220700):

@@ -164,12 +164,15 @@ PRESETS = {
     "square32": dict(_COMMON, dim=2, n=(32, 32), extent=(1.0, 1.0),
                      mean_p=0.1, mean_n=0.1, steps=5, evap_ds=0.0, evap_stop=0.0),
     # 2D unit square, 512x512 squares, 200 steps, solvent lowered linearly
-    # from 0.8 to 0.3 (0.0025 per step).  The mass block of Algorithm 1 is a
+    # from 0.8 to 0.3 (0.0025 per step).  Preconditioner settings measured
+    # fastest per time step on this mesh: the mass block of Algorithm 1 is a
     # degree-5 Chebyshev semi-iteration (as accurate as the mass V-cycle here,
-    # with no coarse levels).
+    # with no coarse levels); each As solve is 2 CG steps with V-cycles whose
+    # degree-6 Chebyshev smoother covers [rho/5, rho].
     "square512": dict(_COMMON, dim=2, n=(512, 512), extent=(1.0, 1.0), coarse_max=2048,
                       mean_p=0.1, mean_n=0.1, steps=200, evap_ds=0.0025, evap_stop=0.3,
-                      mass_solver="chebyshev", cheb_degree_mass=5),
+                      mass_solver="chebyshev", cheb_degree_mass=5,
+                      cheb_degree=6, cheb_ratio=5.0, schur_pcg=2),
     # The paper's 2D experiment (Section 4): a 10 x 2.5 film (y is the height),
     # polynomial potential, phi_p = phi_n = 0.35 +- 0.01, solvent evaporation
     # through the top (k = 5e-3) and a patterned substrate at the bottom
@@ -178,10 +181,12 @@ PRESETS = {
                     mean_p=0.35, mean_n=0.35, steps=5, evap_ds=0.0, evap_stop=0.0,
                     boundary=1, bc_k=5e-3, bc_g=(0.01, 0.01), bc_h=(0.0, 0.0), bc_pattern=1),
     # 3D box of 96x96x48 cubes, Kuhn tetrahedra, 50 steps; the mass block as
-    # for square512.
+    # for square512, each As solve one CG step (a V-cycle with the optimal
+    # scaling): the outer iteration count hardly depends on the As accuracy
+    # here, so the cheapest As solve is the fastest.
     "box96": dict(_COMMON, dim=3, n=(96, 96, 48), extent=(1.0, 1.0, 0.5), coarse_max=2048,
                   mean_p=0.1, mean_n=0.1, steps=50, evap_ds=0.0, evap_stop=0.0,
-                  mass_solver="chebyshev", cheb_degree_mass=5),
+                  mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=1),
 }
 
 
