@@ -136,12 +136,42 @@ enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
 // row of a SELL-64 matrix (one lane per row, columns of a slice stored
 // column-major so that the 64 lanes read consecutive words).  A wave is one
 // slice (64 consecutive rows, 64-aligned), so the slice bounds are scalar
-// loads.  Slices up to kSellUnroll wide (the fine levels of P1 meshes) take a
-// fully unrolled path that issues every column and value load of the row,
-// then every gather of x, before the first product: two dependent memory
-// round trips instead of one per group of entries.  The products are added
-// in column order either way.
+// loads.  Slices up to kSellUnroll wide (the fine levels of P1 meshes), or
+// twice that, take a fully unrolled path that issues every column and value
+// load of the row, then every gather of x, before the first product: two
+// dependent memory round trips instead of one per group of entries.  The
+// products are added in column order either way.
 constexpr int kSellUnroll = 8;
+
+// the unrolled row product for slices at most W wide (width >= 1)
+template <int W, class T>
+__device__ inline pair_t<T> sell_row_w(int base, int width, int lane, const int *__restrict__ col,
+                                       const T *__restrict__ val, const pair_t<T> *__restrict__ x)
+{
+    // entries past the slice width repeat the last column with a zero
+    // coefficient: every load is unconditional (no branch between the
+    // loads and the gathers) and hits the cache line just read
+    int c[W];
+    T a[W];
+    pair_t<T> xv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+        c[k] = col[idx];
+        const T v = val[idx];
+        a[k] = k < width ? v : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        xv[k] = x[c[k]];
+    T ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        ax += a[k] * xv[k].x;
+        ay += a[k] * xv[k].y;
+    }
+    return mk<T>(ax, ay);
+}
 
 template <class T>
 __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
@@ -150,33 +180,13 @@ __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const int *__
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    if (width == 0)
+        return mk<T>(0, 0);
+    if (width <= kSellUnroll)
+        return sell_row_w<kSellUnroll, T>(base, width, lane, col, val, x);
+    if (width <= 2 * kSellUnroll)
+        return sell_row_w<2 * kSellUnroll, T>(base, width, lane, col, val, x);
     T ax = 0, ay = 0;
-    if (width <= kSellUnroll) {
-        if (width == 0)
-            return mk<T>(ax, ay);
-        // entries past the slice width repeat the last column with a zero
-        // coefficient: every load is unconditional (no branch between the
-        // loads and the gathers) and hits the cache line just read
-        int c[kSellUnroll];
-        T a[kSellUnroll];
-        pair_t<T> xv[kSellUnroll];
-#pragma unroll
-        for (int k = 0; k < kSellUnroll; ++k) {
-            const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
-            c[k] = col[idx];
-            const T v = val[idx];
-            a[k] = k < width ? v : T(0);
-        }
-#pragma unroll
-        for (int k = 0; k < kSellUnroll; ++k)
-            xv[k] = x[c[k]];
-#pragma unroll
-        for (int k = 0; k < kSellUnroll; ++k) {
-            ax += a[k] * xv[k].x;
-            ay += a[k] * xv[k].y;
-        }
-        return mk<T>(ax, ay);
-    }
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
         const int idx = base + k * kSlice + lane;
