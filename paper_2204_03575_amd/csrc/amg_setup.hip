@@ -655,13 +655,14 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
     }
 
     // SELL copies, kernel shapes and work vectors
-    // One lane per row (SELL-64) for short rows when there are enough rows to
-    // fill the chip; otherwise a power-of-two group of lanes per row, enough to
-    // reach about 128k threads but no wider than the rows.
+    // One lane per row (SELL-64) for rows the unrolled SELL path covers (up to
+    // 16 entries: the fine levels of P1 meshes in 2D and 3D) when there are
+    // enough rows to fill the chip; otherwise a power-of-two group of lanes
+    // per row, enough to reach about 128k threads but no wider than the rows.
     auto lanes_per_row = [](const Csr &A) {
         const double avg = A.n > 0 ? double(A.nnz) / A.n : 0.0;
         const long target = 131072;
-        if (avg < 12.0 && A.n >= target)
+        if (avg < 16.0 && A.n >= target)
             return 0;
         int want = 4;
         while (want < 32 && (long)want * A.n < target)
