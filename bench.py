@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for a 512 MB elementwise copy (FETCH_SIZE x 2.000,
 # WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Keyed by workload and
 # precision; None where the counters were not taken (or the kernel changed since).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 40.45e6, ("square512", "fp32"): 23.95e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 40.47e6, ("square512", "fp32"): 23.97e6}
 
 
 def parse():
