@@ -12,11 +12,15 @@
  *   where M, K are the P1 mass and stiffness matrices and
  *   f_i^k = integral of (d f / d phi_i)(phi_h^k) times each hat function
  *   (the explicit part of the IMEX scheme eq. chternary_space), by
- *   right-preconditioned flexible GMRES with the block-diagonal preconditioner
- *   of Algorithm 1 (mass block by AMG; Schur block by the matching
- *   approximation (tau' K + sqrt(tau'/eps) M) M^-1 (tau' K + sqrt(tau'/eps) M)
- *   justified by Lemma 1), then set phi_s = 1 - phi_p - phi_n (Section 2).
- *   The AMG is smoothed aggregation with Chebyshev or Jacobi smoothing.
+ *   right-preconditioned flexible GMRES (or, as in the paper's experiments,
+ *   MINRES: krylov) with the block-diagonal preconditioner of Algorithm 1
+ *   (mass block by AMG or a Chebyshev semi-iteration: mass_solver; Schur
+ *   block by the matching approximation
+ *   (tau' K + sqrt(tau'/eps) M) M^-1 (tau' K + sqrt(tau'/eps) M) justified by
+ *   Lemma 1), then set phi_s = 1 - phi_p - phi_n (Section 2).  Optional
+ *   boundary terms of eq. chternary:2 (boundary) add to the first block of
+ *   the right-hand side.  The AMG is smoothed aggregation with Chebyshev or
+ *   Jacobi smoothing.
  *
  * Conventions
  *   - Every call returns CHM_OK (0) or a negative CHM_E* code; no exception
