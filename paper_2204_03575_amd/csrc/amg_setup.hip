@@ -333,6 +333,69 @@ __global__ void k_rows_sort_count(const int *off, int n, uint64_t *keys, int *ro
     rowlen[i] = u;
 }
 
+// Rows of a product with at most kDenseCols columns (the coarse levels, whose
+// expanded rows can hold 10^5 entries): one block per row.  Every thread
+// scans the row's entries in position order and accumulates those of its own
+// columns (c mod kBlock) in LDS, so each column is summed in position order,
+// exactly as the sorting path sums it.  phase 0 counts the row's distinct
+// columns; phase 1 (after the scan of the counts) writes the row in column
+// order.
+constexpr int kDenseCols = 4096;
+
+__global__ void __launch_bounds__(kBlock) k_rows_dense(const int *__restrict__ off,
+                                                       const uint64_t *__restrict__ keys,
+                                                       const double *__restrict__ vals, int ncols,
+                                                       int phase, int *rowlen,
+                                                       const int *__restrict__ crp, int *cci,
+                                                       double *cv)
+{
+    __shared__ double acc[kDenseCols];
+    __shared__ unsigned char present[kDenseCols];
+    __shared__ int part[kBlock];
+    const int i = blockIdx.x, t = threadIdx.x;
+    for (int c = t; c < ncols; c += kBlock)
+        present[c] = 0;
+    __syncthreads();
+    const int b = off[i], e = off[i + 1];
+#pragma unroll 8
+    for (int k = b; k < e; ++k) {
+        const int c = (int)(keys[k] >> 32);
+        if (c % kBlock == t) {
+            if (present[c])
+                acc[c] += vals[k];
+            else
+                acc[c] = vals[k];
+            present[c] = 1;
+        }
+    }
+    __syncthreads();
+    // thread t takes the columns [t ch, (t + 1) ch) for the count and the output
+    const int ch = (ncols + kBlock - 1) / kBlock, c0 = min(t * ch, ncols), c1 = min(c0 + ch, ncols);
+    int cnt = 0;
+    for (int c = c0; c < c1; ++c)
+        cnt += present[c];
+    part[t] = cnt;
+    __syncthreads();
+    if (phase == 0) {
+        if (t == 0) {
+            int tot = 0;
+            for (int k = 0; k < kBlock; ++k)
+                tot += part[k];
+            rowlen[i] = tot;
+        }
+        return;
+    }
+    int o = crp[i];
+    for (int k = 0; k < t; ++k)
+        o += part[k];
+    for (int c = c0; c < c1; ++c)
+        if (present[c]) {
+            cci[o] = c;
+            cv[o] = acc[c];
+            ++o;
+        }
+}
+
 // sum equal columns in position order and write the row
 __global__ void k_rows_compress(const int *off, int n, const uint64_t *keys, const double *vals,
                                 const int *crp, int *cci, double *cv)
@@ -370,24 +433,48 @@ __global__ void k_t_fill(const int *rp, const int *ci, const double *v, int n, i
     }
 }
 
+// heap sort of (key, value) pairs by key (the keys of a segment are distinct,
+// so the order is unique)
+__device__ void heap_sort_pairs(int *key, double *val, int n)
+{
+    auto sift = [&](int root, int end) {
+        for (;;) {
+            int child = 2 * root + 1;
+            if (child >= end)
+                break;
+            if (child + 1 < end && key[child + 1] > key[child])
+                ++child;
+            if (key[root] >= key[child])
+                break;
+            const int tk = key[root];
+            key[root] = key[child];
+            key[child] = tk;
+            const double tv = val[root];
+            val[root] = val[child];
+            val[child] = tv;
+            root = child;
+        }
+    };
+    for (int start = n / 2 - 1; start >= 0; --start)
+        sift(start, n);
+    for (int end = n - 1; end > 0; --end) {
+        const int tk = key[0];
+        key[0] = key[end];
+        key[end] = tk;
+        const double tv = val[0];
+        val[0] = val[end];
+        val[end] = tv;
+        sift(0, end);
+    }
+}
+
 __global__ void k_sort_pairs_segments(int *key, double *val, const int *ptr, int n)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n)
         return;
-    int b = ptr[s], e = ptr[s + 1];
-    for (int k = b + 1; k < e; ++k) {
-        int kk = key[k];
-        double vv = val[k];
-        int j = k - 1;
-        while (j >= b && key[j] > kk) {
-            key[j + 1] = key[j];
-            val[j + 1] = val[j];
-            --j;
-        }
-        key[j + 1] = kk;
-        val[j + 1] = vv;
-    }
+    const int b = ptr[s];
+    heap_sort_pairs(key + b, val + b, ptr[s + 1] - b);
 }
 
 // ---- coarsest level: Gauss-Jordan inverse of an SPD matrix (no pivoting) ----
@@ -460,13 +547,22 @@ void finish_rows(int n, int ncols, Scratch &sc, Csr &C, Pool &pool, hipStream_t 
     C.n = n;
     C.m = ncols;
     C.rp = pool.get<int>(n + 1);
-    k_rows_sort_count<<<nblk(n), kBlock, 0, st>>>(sc.off, n, sc.keys, C.rp);
+    const bool dense = ncols <= kDenseCols && n > 0;
+    if (dense)
+        k_rows_dense<<<n, kBlock, 0, st>>>(sc.off, sc.keys, sc.vals, ncols, 0, C.rp, nullptr,
+                                           nullptr, nullptr);
+    else
+        k_rows_sort_count<<<nblk(n), kBlock, 0, st>>>(sc.off, n, sc.keys, C.rp);
     CHM_HIP(hipGetLastError());
     scan_exclusive(C.rp, n, C.rp + n, pool, st);
     C.nnz = read_int(C.rp + n, st);
     C.ci = pool.get<int>(C.nnz);
     C.v = pool.get<double>(C.nnz);
-    k_rows_compress<<<nblk(n), kBlock, 0, st>>>(sc.off, n, sc.keys, sc.vals, C.rp, C.ci, C.v);
+    if (dense)
+        k_rows_dense<<<n, kBlock, 0, st>>>(sc.off, sc.keys, sc.vals, ncols, 1, nullptr, C.rp,
+                                           C.ci, C.v);
+    else
+        k_rows_compress<<<nblk(n), kBlock, 0, st>>>(sc.off, n, sc.keys, sc.vals, C.rp, C.ci, C.v);
     CHM_HIP(hipGetLastError());
 }
 
