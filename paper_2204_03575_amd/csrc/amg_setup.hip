@@ -492,37 +492,126 @@ __global__ void k_dense_from_csr(const int *rp, const int *ci, const double *v, 
 
 constexpr int kGJMax = 2048;
 
-// Gauss-Jordan inverse of an SPD matrix, one pivot per pair of launches (no
-// pivoting is needed: every pivot of an SPD matrix is positive).
-// Pivot k: rowk = row k of [A | I] divided by its pivot, colk = column k.
-__global__ void k_gj_pivot(int n, const double *aug, int k, double *rowk, double *colk, int *bad)
+// ---- blocked Gauss-Jordan on [A | I] (n x 2n, row-major) in steps of kGB
+// pivots: the pivot block's inverse Dinv (one workgroup, in LDS), the new
+// pivot rows Rb = Dinv [A | I](pivot rows), and the rank-kGB update of every
+// other row, [A | I](i, :) -= C(i, :) Rb with C the pivot columns before the
+// step, on FP64 matrix cores (16x16x4 MFMA tiles).  No pivoting: every pivot
+// block of an SPD matrix is SPD.
+constexpr int kGB = 32;
+
+__global__ void __launch_bounds__(kBlock) k_bgj_diag(int n, const double *__restrict__ aug, int k0,
+                                                     int kb, double *dinv, int *bad)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int w = 2 * n;
-    const double piv = aug[(size_t)k * w + k];
-    if (!(piv > 0.0)) {
-        if (t == 0)
-            atomicAdd(bad, 1);
-        return;
+    __shared__ double a[kGB][2 * kGB];
+    constexpr int kPer = kGB * 2 * kGB / kBlock;   // elements per thread
+    const int w = 2 * n, t = threadIdx.x;
+    for (int idx = t; idx < kGB * 2 * kGB; idx += kBlock) {
+        const int r = idx / (2 * kGB), c = idx % (2 * kGB);
+        double v = 0.0;
+        if (r < kb && c < kb)
+            v = aug[(size_t)(k0 + r) * w + k0 + c];
+        else if (r < kb && c >= kGB && c - kGB < kb)
+            v = (c - kGB == r) ? 1.0 : 0.0;
+        a[r][c] = v;
     }
-    if (t < w)
-        rowk[t] = aug[(size_t)k * w + t] / piv;
-    if (t < n)
-        colk[t] = aug[(size_t)t * w + k];
+    __syncthreads();
+    int badp = 0;
+    for (int p = 0; p < kb; ++p) {
+        double piv = a[p][p];
+        if (!(piv > 0.0)) {
+            badp = 1;
+            piv = 1.0;
+        }
+        double nv[kPer];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = t + e * kBlock, r = idx / (2 * kGB), c = idx % (2 * kGB);
+            const double rowp = a[p][c] / piv;
+            nv[e] = r == p ? rowp : a[r][c] - a[r][p] * rowp;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = t + e * kBlock;
+            a[idx / (2 * kGB)][idx % (2 * kGB)] = nv[e];
+        }
+        __syncthreads();
+    }
+    if (badp && t == 0)
+        atomicAdd(bad, 1);
+    for (int idx = t; idx < kGB * kGB; idx += kBlock) {
+        const int r = idx / kGB, c = idx % kGB;
+        dinv[idx] = (r < kb && c < kb) ? a[r][kGB + c] : 0.0;
+    }
 }
 
-// eliminate column k from every other row; row k becomes rowk
-__global__ void k_gj_update(int n, double *aug, int k, const double *rowk, const double *colk)
+// Rb (kGB x w) = Dinv times the pivot rows (rows past kb are zero); C (n x kGB)
+// = the pivot columns of every row before the step (columns past kb zero)
+__global__ void __launch_bounds__(kBlock) k_bgj_rows(int n, const double *__restrict__ aug, int k0,
+                                                     int kb, const double *__restrict__ dinv,
+                                                     double *rb, double *cc)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int w = 2 * n;
-    if (idx >= (long)n * w)
-        return;
-    const int i = (int)(idx / w), j = (int)(idx % w);
-    if (i == k)
-        aug[idx] = rowk[j];
-    else
-        aug[idx] -= colk[i] * rowk[j];
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < w) {
+        const int j = (int)t;
+        double col[kGB];
+#pragma unroll
+        for (int s = 0; s < kGB; ++s)
+            col[s] = s < kb ? aug[(size_t)(k0 + s) * w + j] : 0.0;
+        for (int r = 0; r < kGB; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < kGB; ++s)
+                acc += dinv[r * kGB + s] * col[s];
+            rb[(size_t)r * w + j] = acc;
+        }
+    }
+    if (t < (long)n * kGB) {
+        const int i = (int)(t / kGB), s = (int)(t % kGB);
+        cc[t] = s < kb ? aug[(size_t)i * w + k0 + s] : 0.0;
+    }
+}
+
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+// one wave per 16 x 16 tile of [A | I]: rows outside the pivot block take
+// aug - C Rb (8 MFMA steps of K = 4), the pivot rows take Rb.  Lane l holds
+// C(i0 + l % 16, 4 q + l / 16), Rb(4 q + l / 16, j0 + l % 16) and the results
+// (i0 + 4 e + l / 16, j0 + l % 16), e = 0..3.
+__global__ void __launch_bounds__(kBlock) k_bgj_update(int n, double *aug, int k0, int kb,
+                                                       const double *__restrict__ rb,
+                                                       const double *__restrict__ cc)
+{
+    const int w = 2 * n, lane = threadIdx.x & 63;
+    const int ct = (w + 15) / 16, rt = (n + 15) / 16;
+    const long tile = (long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (tile >= (long)rt * ct)
+        return;   // the whole wave
+    const int i0 = (int)(tile / ct) * 16, j0 = (int)(tile % ct) * 16;
+    const int lr = lane % 16, lq = lane / 16, col = j0 + lr;
+    mfma_f64x4 acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = i0 + 4 * e + lq;
+        acc[e] = (row < n && col < w) ? aug[(size_t)row * w + col] : 0.0;
+    }
+    const int arow = i0 + lr;
+#pragma unroll
+    for (int q = 0; q < kGB / 4; ++q) {
+        const int s = 4 * q + lq;
+        const double av = arow < n ? -cc[(size_t)arow * kGB + s] : 0.0;
+        const double bv = col < w ? rb[(size_t)s * w + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int row = i0 + 4 * e + lq;
+        if (row < n && col < w)
+            aug[(size_t)row * w + col] =
+                (row >= k0 && row < k0 + kb) ? rb[(size_t)(row - k0) * w + col] : acc[e];
+    }
 }
 
 // inverse, row-major: inv[i * n + j] = (A^-1)[i][j]
@@ -736,11 +825,16 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         double *aug = tmp.get<double>((size_t)nc * 2 * nc);
         k_dense_from_csr<<<nblk(nc), kBlock, 0, st>>>(Lc.A.rp, Lc.A.ci, Lc.A.v, nc, aug);
         fill_int(flags + 3, 0, 1, st);
-        double *rowk = tmp.get<double>(2 * (size_t)nc), *colk = tmp.get<double>(nc);
-        const long cells = (long)nc * 2 * nc;
-        for (int k = 0; k < nc; ++k) {
-            k_gj_pivot<<<nblk(2l * nc), kBlock, 0, st>>>(nc, aug, k, rowk, colk, flags + 3);
-            k_gj_update<<<nblk(cells), kBlock, 0, st>>>(nc, aug, k, rowk, colk);
+        double *dinv = tmp.get<double>(kGB * kGB);
+        double *rb = tmp.get<double>((size_t)kGB * 2 * nc), *cc = tmp.get<double>((size_t)nc * kGB);
+        const long tiles = (long)((nc + 15) / 16) * ((2 * nc + 15) / 16);
+        const long rows_threads = std::max<long>(2l * nc, (long)nc * kGB);
+        for (int k0 = 0; k0 < nc; k0 += kGB) {
+            const int kb = std::min(kGB, nc - k0);
+            k_bgj_diag<<<1, kBlock, 0, st>>>(nc, aug, k0, kb, dinv, flags + 3);
+            k_bgj_rows<<<nblk(rows_threads), kBlock, 0, st>>>(nc, aug, k0, kb, dinv, rb, cc);
+            k_bgj_update<<<(int)((tiles + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(
+                nc, aug, k0, kb, rb, cc);
         }
         Lc.inv = pool.get<double>((size_t)nc * nc);
         k_extract_inverse<<<nblk((long)nc * nc), kBlock, 0, st>>>(aug, nc, Lc.inv);
