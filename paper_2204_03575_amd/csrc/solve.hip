@@ -60,15 +60,17 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
     y[n + row] = y1;
 }
 
-// y = b - A x over a grid-stride loop, and partial sums of |y|^2 per species
-// (per run: vectors advance by 2n, part by one run's slots)
+// y = b - A x over a grid-stride loop, and partial sums of |y1|^2 + w2 |y2|^2
+// per species (y1, y2: the two block rows; w2 = 1 gives the 2-norm; per run:
+// vectors advance by 2n, part by one run's slots)
 __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
                                                          const int *__restrict__ col,
                                                          const double *__restrict__ vm,
                                                          const double *__restrict__ vk,
                                                          const double2 *__restrict__ x,
                                                          const double2 *__restrict__ b, double2 *y,
-                                                         double2 t, double2 te, double2 *part)
+                                                         double2 t, double2 te, double2 *part,
+                                                         double w2)
 {
     __shared__ double2 sh[kBlock / 64];
     x = run_at(x, 2l * n);
@@ -82,8 +84,8 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
         const double2 b0 = b[row], b1 = b[n + row];
         y0 = d2(b0.x - y0.x, b0.y - y0.y);
         y1 = d2(b1.x - y1.x, b1.y - y1.y);
-        nrm.x += y0.x * y0.x + y1.x * y1.x;
-        nrm.y += y0.y * y0.y + y1.y * y1.y;
+        nrm.x += y0.x * y0.x + w2 * (y1.x * y1.x);
+        nrm.y += y0.y * y0.y + w2 * (y1.y * y1.y);
         y[row] = y0;
         y[n + row] = y1;
     }
@@ -562,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *
     run_at(xg, len)[i] = d2(a.x + (a.x - h.x), a.y + (a.y - h.y));
 }
 
-// Per species, the start with the smallest residual norm among the previous
+// Per species, the start with the smallest norm (first block row) among the previous
 // state x (code 0), the linear extrapolation xl (code 1; may be null) and the
 // network's guess xg (code 2; may be null), from the partial sums in
 // pg[code * kRedBlocks + g]; ties and non-finite norms keep the earlier code.
@@ -826,7 +828,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
         // candidate starts from the last two solutions: linear extrapolation
         // and, in the learned mode, the network's guess; each species starts
         // from whichever of them and the previous state has the smallest
-        // residual
+        // residual in the first block row (the mass balance).  The second
+        // row's residual is dominated by a spatially constant error in mu,
+        // which the preconditioned iteration removes almost at once, so its
+        // 2-norm does not rank the starts by their cost.
         const bool learned = S.guess_mode == CHM_GUESS_LEARNED;
         double2 *xg = learned ? S.xk : nullptr;
         k_extrapolate<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.yh2, S.yh1, S.xl);
@@ -842,7 +847,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
                 k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
                                                                S.sK, cand[k], S.b, S.r,
                                                                pair(S.tau_s), pair(S.te_s),
-                                                               slot(S, kSlotGuess + k));
+                                                               slot(S, kSlotGuess + k), 0.0);
         k_pick_guess<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xl, xg, slot(S, kSlotGuess),
                                                             Gn, S.xk, S.ctl);
     } else {
@@ -859,7 +864,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
     for (;;) {
         k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk,
                                                        S.b, S.r, pair(S.tau_s), pair(S.te_s),
-                                                       slot(S, kSlotR));
+                                                       slot(S, kSlotR), 1.0);
         k_nrm<<<grid(1, R), kBlock, 0, st>>>(S.ctl, slot(S, kSlotR), Gn);
         CHM_HIP(hipGetLastError());
         read_ctl(S);
