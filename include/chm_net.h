@@ -138,8 +138,9 @@ int chm_net_train_step(chm_net_t *net, int32_t batch, int32_t H, int32_t W, int3
  * chm_set_fields starts from the previous state.  LINEAR offers the linear
  * extrapolation 2 y_{n-1} - y_{n-2}, LEARNED that and the network's guess;
  * each species starts from whichever of the offered candidates and the
- * previous state has the smallest residual norm (ties: the simpler one;
- * chm_stats_t.guess_used and .res0 report the choice).
+ * previous state has the smallest residual 2-norm in the first block row of
+ * the saddle-point system (ties: the simpler one; chm_stats_t.guess_used and
+ * .res0, the start's full relative residual, report the choice).
  * LEARNED needs net (used on the solver's stream, kept by the caller until
  * replaced or the solver is destroyed) and a structured mesh with
  * H * W = n_vertices in the vertex order described above (H, W >= 2, at most
