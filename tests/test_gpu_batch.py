@@ -42,13 +42,20 @@ def initial(nv, r, p):
     return S.initial_fractions(nv, p["mean_p"], p["mean_n"], seed=S.BASE_SEED + 100 + r)[:2]
 
 
-@pytest.mark.parametrize("runs,precision,guess", [(1, "fp64", "previous"), (5, "fp64", "previous"),
-                                                  (7, "fp32", "previous"), (4, "fp64", "linear")],
-                         ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear"])
-def test_batch_runs_equal_single_runs_bitwise(runs, precision, guess):
-    case("batch vs single runs", runs=runs, precision=precision, guess=guess)
+# the preconditioner settings of the 512x512 workload (Chebyshev mass solve,
+# 2 CG steps of degree-6 V-cycles over [rho/5, rho])
+W512 = dict(mass_solver="chebyshev", cheb_degree_mass=5, cheb_degree=6, cheb_ratio=5.0,
+            schur_pcg=2)
+
+
+@pytest.mark.parametrize("runs,precision,guess,extra", [
+    (1, "fp64", "previous", {}), (5, "fp64", "previous", {}), (7, "fp32", "previous", {}),
+    (4, "fp64", "linear", {}), (3, "fp32", "linear", W512)],
+    ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear", "3-fp32-linear-w512"])
+def test_batch_runs_equal_single_runs_bitwise(runs, precision, guess, extra):
+    case("batch vs single runs", runs=runs, precision=precision, guess=guess, **extra)
     from paper_2204_03575_amd import Solver
-    p = dict(S.preset("square32", n=(24, 20)), precision=precision)
+    p = dict(S.preset("square32", n=(24, 20)), precision=precision, **extra)
     co, ce = S.make_mesh(p)
     nv = co.shape[0]
     rl = run_list(runs)
