@@ -92,6 +92,33 @@ def cpu_baseline(p, co, ce, php, phn):
                       f"{dt:.1f} s"}
 
 
+def stream_bandwidth(mib=1024, reps=10):
+    """Bandwidth (GB/s) of two plain streaming kernels on this GPU over `mib`
+    MiB of FP64: a copy y = 1.0 * x (every byte read and written once) and a
+    sum of x (read only); the practical ceilings of an HBM-bound kernel,
+    beside the published peak."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    nbytes = src.numel() * 8
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    copy = 2.0 * nbytes / timed(lambda: torch.mul(src, 1.0, out=dst)) / 1e9
+    read = nbytes / timed(lambda: torch.sum(src)) / 1e9
+    del src, dst
+    return copy, read
+
+
 def describe(p, nv):
     shape = "x".join(map(str, p["n"]))
     dom = ("2D unit square" if p["dim"] == 2 else
@@ -359,6 +386,11 @@ def main():
                            "bytes_per_launch": per_launch,
                            "timing": f"HIP events around each run of back-to-back launches in "
                                      f"{args.kernel_steps} further time steps (eager)"}
+        copy_gbs, read_gbs = stream_bandwidth()
+        out["roofline"]["stream_gbs"] = {"copy": copy_gbs, "read": read_gbs,
+                                         "kernels": "torch.mul(x, 1.0) and torch.sum(x), "
+                                                    "1 GiB FP64, HIP events"}
+        out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
