@@ -46,8 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
 # scaled by what the same counters read for a 512 MB elementwise copy (FETCH_SIZE x 2.000,
 # WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Keyed by workload and
-# precision; None where the counters were not taken (or the kernel changed since).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 40.47e6, ("square512", "fp32"): 23.97e6}
+# precision, for the default 16-bit SELL column offsets; None where the counters were not
+# taken (or the kernel changed since, or with --wide-index).
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 36.77e6, ("square512", "fp32"): 20.28e6}
 
 
 def parse():
@@ -64,6 +65,9 @@ def parse():
     ap.add_argument("--n", type=int, default=512,
                     help="squares per side of the unit square (square512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wide-index", action="store_true",
+                    help="keep 32-bit SELL column indices (the comparison run for the 16-bit "
+                         "column offsets; bitwise the same results)")
     ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
     ap.add_argument("--kernel-steps", type=int, default=2,
                     help="time steps of the event-timed pass of the dominant kernel")
@@ -314,6 +318,8 @@ def main():
         p = S.preset("square512", n=(args.n, args.n))
     else:
         p = S.preset("box96")
+    if args.wide_index:
+        p["wide_index"] = 1
     co, ce = S.make_mesh(p)
     nv = co.shape[0]
     php, phn, _ = S.initial_fractions(nv, p["mean_p"], p["mean_n"])
@@ -364,7 +370,7 @@ def main():
             avg_s = ms * 1e-3 / max(1, launches)
             achieved = nbytes / max(1, launches) / avg_s / 1e9 if avg_s > 0 else 0.0
             traffic = (TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, "fp32"))
-                       if args.n == 512 else None)
+                       if args.n == 512 and not args.wide_index else None)
             out["mixed"]["k_cheb_fp32"] = {"achieved": achieved, "unit": "GB/s",
                                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                                            "avg_us": avg_s * 1e6, "launches": launches,
@@ -378,7 +384,8 @@ def main():
         avg_s = ms * 1e-3 / max(1, launches)
         per_launch = nbytes / max(1, launches)
         achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-        traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, "fp64")) if args.n == 512 else None
+        traffic = (TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, "fp64"))
+                   if args.n == 512 and not args.wide_index else None)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": "k_cheb (fine level, As hierarchy)",

@@ -157,6 +157,13 @@ typedef struct {
      * Jacobi sweeps with the Jacobi smoother).  Both are fixed symmetric
      * positive definite operators. */
     int32_t mass_solver;
+    /* Column indices of the SELL-64 matrices (one lane per row: the fine
+     * levels and the products with M, K and As): 0, the default, stores each
+     * column of a square matrix as a 16-bit offset from its row when every
+     * offset of the matrix fits (|col - row| <= 32767; 2 B per entry instead
+     * of 4 in the kernels' traffic); 1 keeps 32-bit columns everywhere.  The
+     * results are bitwise the same. */
+    int32_t wide_index;
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -244,6 +251,14 @@ int chm_get_matrix(chm_solver_t *s, int32_t which, int32_t *rowptr, int32_t *col
 int chm_num_levels(const chm_solver_t *s, int32_t hierarchy);
 int chm_level_info(const chm_solver_t *s, int32_t hierarchy, int32_t level, int64_t *n,
                    int64_t *nnz_a, int64_t *nnz_p, double *rho);
+/* How the solve kernels read a matrix: hierarchy 0 (mass) or 1 (As) with
+ * its level's A, or hierarchy -1 for the solver's own M, K, As (one
+ * pattern; level ignored).  *lanes_per_row: 0 for the SELL-64 layout (one
+ * lane per row), else the lanes that share a CSR row; *index_bytes: bytes per
+ * column index the kernels load, 2 for 16-bit offsets from the row (the
+ * wide_index parameter), else 4.  Either pointer may be NULL. */
+int chm_level_layout(const chm_solver_t *s, int32_t hierarchy, int32_t level,
+                     int32_t *lanes_per_row, int32_t *index_bytes);
 /* Host buffers; agg/P arrays are left untouched on the coarsest level. */
 int chm_level_get(chm_solver_t *s, int32_t hierarchy, int32_t level, int32_t *a_rowptr,
                   int32_t *a_col, double *a_val, int32_t *agg, int32_t *p_rowptr,

@@ -31,7 +31,7 @@ ENTRY_POINTS = [
     "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
-    "chm_boundary",
+    "chm_boundary", "chm_level_layout",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -64,7 +64,7 @@ class chm_params_t(C.Structure):
         ("precision", C.c_int32),
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
-        ("amg_tol", C.c_double), ("mass_solver", C.c_int32),
+        ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
     ]
 
 
@@ -102,6 +102,7 @@ def library():
             "chm_get_matrix": ([vp, i32, vp, vp, vp], C.c_int),
             "chm_num_levels": ([vp, i32], C.c_int),
             "chm_level_info": ([vp, i32, i32, P(i64), P(i64), P(i64), P(d)], C.c_int),
+            "chm_level_layout": ([vp, i32, i32, P(i32), P(i32)], C.c_int),
             "chm_level_get": ([vp, i32, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "chm_vcycle": ([vp, i32, vp, vp], C.c_int),
             "chm_schur_solve": ([vp, vp, vp], C.c_int),
@@ -168,6 +169,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.krylov = {"fgmres": 0, "minres": 1}[p.get("krylov", "fgmres")]
     s.amg_tol = float(p.get("amg_tol", 0.0))
     s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
+    s.wide_index = int(p.get("wide_index", 0))
     return s
 
 
@@ -319,6 +321,14 @@ class Solver:
 
     def num_levels(self, hier: int) -> int:
         return self.lib.chm_num_levels(self.h, hier)
+
+    def layout(self, hier: int, lev: int = 0) -> tuple:
+        """(lanes per row, bytes per column index) of a level's A as the solve
+        kernels read it; hier = -1 for the solver's M, K, As."""
+        lanes, ib = C.c_int32(), C.c_int32()
+        rc = self.lib.chm_level_layout(self.h, hier, lev, C.byref(lanes), C.byref(ib))
+        _check(self.h, rc, "chm_level_layout")
+        return lanes.value, ib.value
 
     def level(self, hier: int, lev: int) -> dict:
         n, na, npp = C.c_int64(), C.c_int64(), C.c_int64()

@@ -871,12 +871,13 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
     };
     for (int l = 0; l < H.nlev; ++l) {
         Level &L = H.lev[l];
-        csr_to_sell(L.A, L.sA, pool, st);
+        const bool o16 = S.prm.wide_index == 0;
+        csr_to_sell(L.A, L.sA, pool, st, o16);
         L.gsA = lanes_per_row(L.A);
         L.uA = unroll(L.A, L.gsA);
         if (l + 1 < H.nlev) {
-            csr_to_sell(L.P, L.sP, pool, st);
-            csr_to_sell(L.R, L.sR, pool, st);
+            csr_to_sell(L.P, L.sP, pool, st, o16);
+            csr_to_sell(L.R, L.sR, pool, st, o16);
             L.gsP = lanes_per_row(L.P);
             L.gsR = lanes_per_row(L.R);
             L.uP = unroll(L.P, L.gsP);

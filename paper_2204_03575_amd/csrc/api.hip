@@ -82,6 +82,8 @@ const char *check_params(const chm_params_t &p)
         return "amg_tol must be finite and non-negative";
     if (p.mass_solver != CHM_MASS_AMG && p.mass_solver != CHM_MASS_CHEBYSHEV)
         return "unknown mass solver";
+    if (p.wide_index != 0 && p.wide_index != 1)
+        return "wide_index must be 0 or 1";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -411,6 +413,28 @@ int chm_level_info(const chm_solver_t *h, int32_t hierarchy, int32_t level, int6
         *nnz_p = (level + 1 < H->nlev) ? L.P.nnz : 0;
     if (rho)
         *rho = L.rho;
+    return CHM_OK;
+}
+
+int chm_level_layout(const chm_solver_t *h, int32_t hierarchy, int32_t level,
+                     int32_t *lanes_per_row, int32_t *index_bytes)
+{
+    int lanes = 0;
+    const int16_t *ocol = nullptr;
+    if (h && hierarchy == -1) {
+        ocol = h->s.sM.ocol;
+    } else {
+        const chm::Hierarchy *H = hier_of(h, hierarchy);
+        if (!H || level < 0 || level >= H->nlev)
+            return CHM_EINVAL;
+        const chm::Level &L = H->lev[level];
+        lanes = L.gsA;
+        ocol = L.sA.ocol;
+    }
+    if (lanes_per_row)
+        *lanes_per_row = lanes;
+    if (index_bytes)
+        *index_bytes = (lanes == 0 && ocol) ? 2 : 4;
     return CHM_OK;
 }
 

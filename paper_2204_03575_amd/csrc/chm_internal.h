@@ -90,6 +90,9 @@ struct Sell {      // device SELL-64
     int *sptr = nullptr;  // nslices + 1 offsets
     int *col = nullptr;
     double *val = nullptr;
+    // col - row as 16 bits, for a square matrix whose offsets all fit (the
+    // solve kernels then read these instead of col); else null
+    int16_t *ocol = nullptr;
 };
 
 // One matrix of a level as the solve kernels see it, in value type T: the
@@ -100,6 +103,7 @@ struct Sell {      // device SELL-64
 template <class T> struct MatView {
     int n = 0, m = 0, nnz = 0, gs = 0, u = 1;   // rows, columns, nonzeros, lanes per row, unroll
     const int *sptr = nullptr, *col = nullptr, *rp = nullptr, *ci = nullptr;
+    const int16_t *ocol = nullptr;              // SELL column offsets (see Sell), or null
     const T *sval = nullptr, *cval = nullptr;
 };
 
@@ -138,6 +142,7 @@ inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, int u, const T 
     v.gs = gs;
     v.sptr = S.sptr;
     v.col = S.col;
+    v.ocol = S.ocol;
     v.rp = C.rp;
     v.ci = C.ci;
     v.sval = sv;
@@ -313,7 +318,9 @@ void fill_int(int *p, int v, size_t n, hipStream_t s);
 void fill_double(double *p, double v, size_t n, hipStream_t s);
 int read_int(const int *d, hipStream_t s);
 double reduce_max_host(const double *d, int n, Pool &pool, hipStream_t s);
-void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s);
+// offsets16: also store the 16-bit column offsets (Sell::ocol) when A is
+// square and every offset fits
+void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s, bool offsets16);
 void sell_values(const Csr &A, const Sell &S, const double *csr_vals, double *sell_vals, hipStream_t s);
 
 // ---- mesh_setup.hip

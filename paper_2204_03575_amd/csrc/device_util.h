@@ -143,10 +143,21 @@ enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
 // products are added in column order either way.
 constexpr int kSellUnroll = 8;
 
+// Column of SELL entry idx, which belongs to row `row`: stored as a 32-bit
+// column (I = int), or as a 16-bit offset from the row (I = int16_t; square
+// matrices whose entries all lie within 32767 of the diagonal, 2 B per entry
+// instead of 4).
+__device__ inline int sell_col(const int *__restrict__ col, int idx, int) { return col[idx]; }
+__device__ inline int sell_col(const int16_t *__restrict__ col, int idx, int row)
+{
+    return row + (int)col[idx];
+}
+
 // the unrolled row product for slices at most W wide (width >= 1)
-template <int W, class T>
-__device__ inline pair_t<T> sell_row_w(int base, int width, int lane, const int *__restrict__ col,
-                                       const T *__restrict__ val, const pair_t<T> *__restrict__ x)
+template <int W, class I, class T>
+__device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
+                                       const I *__restrict__ col, const T *__restrict__ val,
+                                       const pair_t<T> *__restrict__ x)
 {
     // entries past the slice width repeat the last column with a zero
     // coefficient: every load is unconditional (no branch between the
@@ -157,7 +168,7 @@ __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, const int 
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
-        c[k] = col[idx];
+        c[k] = sell_col(col, idx, row);
         const T v = val[idx];
         a[k] = k < width ? v : T(0);
     }
@@ -173,8 +184,8 @@ __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, const int 
     return mk<T>(ax, ay);
 }
 
-template <class T>
-__device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
+template <class I, class T>
+__device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__restrict__ col,
                                      const T *__restrict__ val, const pair_t<T> *__restrict__ x,
                                      int row)
 {
@@ -183,15 +194,15 @@ __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const int *__
     if (width == 0)
         return mk<T>(0, 0);
     if (width <= kSellUnroll)
-        return sell_row_w<kSellUnroll, T>(base, width, lane, col, val, x);
+        return sell_row_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x);
     if (width <= 2 * kSellUnroll)
-        return sell_row_w<2 * kSellUnroll, T>(base, width, lane, col, val, x);
+        return sell_row_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x);
     T ax = 0, ay = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
         const int idx = base + k * kSlice + lane;
         const T a = val[idx];
-        const pair_t<T> xv = x[col[idx]];
+        const pair_t<T> xv = x[sell_col(col, idx, row)];
         ax += a * xv.x;
         ay += a * xv.y;
     }
@@ -213,9 +224,9 @@ __device__ inline void spmv_store(pair_t<T> s, const pair_t<T> *__restrict__ b, 
 }
 
 // per run: x advances by sx, b and y by sy
-template <int MODE, class T>
+template <int MODE, class I, class T>
 __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
-                                                 const int *__restrict__ col,
+                                                 const I *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const pair_t<T> *__restrict__ x, long sx,
                                                  const pair_t<T> *__restrict__ b, pair_t<T> *y,
@@ -227,7 +238,19 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
     x = run_at(x, sx);
     b = run_at(b, sy);
     y = run_at(y, sy);
-    spmv_store<MODE, T>(sell_row<T>(sptr, col, val, x, row), b, y, row);
+    spmv_store<MODE, T>(sell_row<I, T>(sptr, col, val, x, row), b, y, row);
+}
+
+// k_spmv over a SELL matrix of n rows, on its 16-bit column offsets when it
+// has them (ocol), else on its columns
+template <int MODE, class T>
+void sell_spmv(hipStream_t st, dim3 g, int n, const int *sptr, const int *col, const int16_t *ocol,
+               const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y, long sy)
+{
+    if (ocol)
+        k_spmv<MODE, int16_t, T><<<g, kBlock, 0, st>>>(n, sptr, ocol, val, x, sx, b, y, sy);
+    else
+        k_spmv<MODE, int, T><<<g, kBlock, 0, st>>>(n, sptr, col, val, x, sx, b, y, sy);
 }
 
 // The same with a group of GS lanes per row (CSR), for matrices with long rows
@@ -320,8 +343,8 @@ void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
     if (sy < 0)
         sy = A.n;
     if (A.gs == 0) {
-        k_spmv<MODE, T><<<grid(nblk(n), runs), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, x, sx, b,
-                                                                y, sy);
+        sell_spmv<MODE, T>(st, grid(nblk(n), runs), n, A.sptr, A.col, A.ocol, A.sval, x, sx, b, y,
+                           sy);
         return;
     }
     switch (A.gs) {

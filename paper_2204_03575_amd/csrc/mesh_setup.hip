@@ -506,7 +506,7 @@ void mesh_setup(Solver &S)
     CHM_HIP(hipGetLastError());
 
     // SELL-64 copies for the solve (one pattern, three value arrays)
-    csr_to_sell(M, S.sM, pool, st);
+    csr_to_sell(M, S.sM, pool, st, S.prm.wide_index == 0);
     S.sK = pool.get<double>(S.sM.stored);
     S.sAs = pool.get<double>(S.sM.stored);
     sell_values(M, S.sM, S.K.v, S.sK, st);

@@ -55,9 +55,9 @@ template <class T> __device__ inline pair_t<T> cheb_apply(pair_t<T> s, const Che
                  o.xi.y + c1 * (o.xi.y - o.xp.y) + c2 * (o.di * (o.bb.y - s.y)));
 }
 
-template <class T>
+template <class I, class T>
 __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ sptr,
-                                                 const int *__restrict__ col,
+                                                 const I *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ dinv,
                                                  const pair_t<T> *__restrict__ b,
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     xk = run_at(xk, n);
     xprev = run_at(xprev, n);
     const ChebRow<T> o = cheb_row<T>(b, xk, dinv, xprev, row, prev);
-    const pair_t<T> s = sell_row<T>(sptr, col, val, xk, row);
+    const pair_t<T> s = sell_row<I, T>(sptr, col, val, xk, row);
     xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
@@ -370,8 +370,12 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     hipStream_t st = S.stream;
     switch (A.gs) {
     case 0:
-        k_cheb<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b, xk, xprev,
-                                                       c1, c2, prev);
+        if (A.ocol)
+            k_cheb<int16_t, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.ocol, A.sval, dinv,
+                                                                    b, xk, xprev, c1, c2, prev);
+        else
+            k_cheb<int, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b,
+                                                                xk, xprev, c1, c2, prev);
         break;
     case 4:
         cheb_v_u<4, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
@@ -387,11 +391,12 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
         break;
     }
     if (timed_level(S, H, l)) {
-        // algorithmic bytes: column index + value per nonzero (once per
-        // launch); per row and run x_k (gathered once), b, D^-1, x_{k-1}
-        // (when read) and the written x_{k+1}
+        // algorithmic bytes: column index (2 B as a SELL offset, else 4) +
+        // value per nonzero (once per launch); per row and run x_k (gathered
+        // once), b, D^-1, x_{k-1} (when read) and the written x_{k+1}
+        const long long ib = (A.gs == 0 && A.ocol) ? 2 : 4;
         S.timer.count += 1;
-        S.timer.bytes += (long long)(sizeof(int) + sizeof(T)) * L.A.nnz +
+        S.timer.bytes += (ib + (long long)sizeof(T)) * L.A.nnz +
                          (long long)R * (prev ? 9 : 7) * sizeof(T) * L.n;
     }
 }
@@ -550,8 +555,8 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
     if (R == 1) {
         stationary<T>(S, S.hM, v, w);
         schur_solve_t<T>(S, v + n, W.tmp);
-        k_spmv<SP_SET, T><<<nblk(n), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, mass_sell_values<T>(S),
-                                                       W.tmp, n, nullptr, W.tmp2, n);
+        sell_spmv<SP_SET, T>(st, grid(nblk(n), 1), n, S.sM.sptr, S.sM.col, S.sM.ocol,
+                             mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
         schur_solve_t<T>(S, W.tmp2, w + n);
         return;
     }
@@ -560,9 +565,8 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
     k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w, len);
     k_gather_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, v + n, len, W.h1);
     schur_solve_t<T>(S, W.h1, W.tmp);
-    k_spmv<SP_SET, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col,
-                                                            mass_sell_values<T>(S), W.tmp, n,
-                                                            nullptr, W.tmp2, n);
+    sell_spmv<SP_SET, T>(st, grid(nblk(n), R), n, S.sM.sptr, S.sM.col, S.sM.ocol,
+                         mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
     schur_solve_t<T>(S, W.tmp2, W.h2);
     k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w + n, len);
 }

@@ -15,8 +15,9 @@ namespace {
 
 // ------------------------------------------------------------------ saddle-point operator
 // y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
+template <class I>
 __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
-                                  const int *__restrict__ col, const double *__restrict__ vm,
+                                  const I *__restrict__ col, const double *__restrict__ vm,
                                   const double *__restrict__ vk, const double2 *__restrict__ x,
                                   double2 t, double2 te, double2 &y0, double2 &y1)
 {
@@ -25,7 +26,7 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
     double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
     for (int k = 0; k < width; ++k) {
         const int idx = base + k * kSlice + lane;
-        const int c = col[idx];
+        const int c = sell_col(col, idx, row);
         const double am = vm[idx], ak = vk[idx];
         const double2 x0 = x[c], x1 = x[n + c];
         m0x += am * x0.x;
@@ -42,8 +43,9 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
 }
 
 // per run, x and y advance by 2n
+template <class I>
 __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict__ sptr,
-                                                   const int *__restrict__ col,
+                                                   const I *__restrict__ col,
                                                    const double *__restrict__ vm,
                                                    const double *__restrict__ vk,
                                                    const double2 *__restrict__ x, double2 *y,
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
     x = run_at(x, 2l * n);
     y = run_at(y, 2l * n);
     double2 y0, y1;
-    saddle_row(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+    saddle_row<I>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
     y[row] = y0;
     y[n + row] = y1;
 }
@@ -63,8 +65,9 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
 // y = b - A x over a grid-stride loop, and partial sums of |y1|^2 + w2 |y2|^2
 // per species (y1, y2: the two block rows; w2 = 1 gives the 2-norm; per run:
 // vectors advance by 2n, part by one run's slots)
+template <class I>
 __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
-                                                         const int *__restrict__ col,
+                                                         const I *__restrict__ col,
                                                          const double *__restrict__ vm,
                                                          const double *__restrict__ vk,
                                                          const double2 *__restrict__ x,
@@ -80,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
     double2 nrm = d2(0.0, 0.0);
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
         double2 y0, y1;
-        saddle_row(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+        saddle_row<I>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
         const double2 b0 = b[row], b1 = b[n + row];
         y0 = d2(b0.x - y0.x, b0.y - y0.y);
         y1 = d2(b1.x - y1.x, b1.y - y1.y);
@@ -631,9 +634,27 @@ inline const Ctl &head(const Solver &S, int r)
 void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
     const int n = S.nv;
-    k_saddle<<<grid(nblk(n), S.nrun), kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
-                                                             S.sK, x, y, pair(S.tau_s),
-                                                             pair(S.te_s));
+    const dim3 g = grid(nblk(n), S.nrun);
+    if (S.sM.ocol)
+        k_saddle<int16_t><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, y,
+                                                      pair(S.tau_s), pair(S.te_s));
+    else
+        k_saddle<int><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, y,
+                                                  pair(S.tau_s), pair(S.te_s));
+}
+
+// y = b - A x and the partials of its norms (k_saddle_resid) on M's pattern
+static void saddle_resid(Solver &S, dim3 g, const double2 *x, double2 *y, double2 *part, double w2)
+{
+    const int n = S.nv;
+    if (S.sM.ocol)
+        k_saddle_resid<int16_t><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK,
+                                                            x, S.b, y, pair(S.tau_s),
+                                                            pair(S.te_s), part, w2);
+    else
+        k_saddle_resid<int><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
+                                                        S.b, y, pair(S.tau_s), pair(S.te_s), part,
+                                                        w2);
 }
 
 // b = (M phi + tau G, -(tau'/eps) f) for the current state of every run
@@ -659,8 +680,8 @@ void compute_rhs(Solver &S)
                                                                   S.qw, S.nq, n, S.x, pots, S.f,
                                                                   S.ctl);
     }
-    k_spmv<SP_SET, double><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
-                                                                S.x, len, nullptr, S.b, len);
+    sell_spmv<SP_SET, double>(st, grid(nblk(n), R), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val,
+                              S.x, len, nullptr, S.b, len);
     boundary_rhs(S, nullptr);
     k_rhs_second<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());
@@ -844,10 +865,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
         const double2 *cand[3] = {S.x, S.xl, xg};
         for (int k = 0; k < 3; ++k)
             if (cand[k])
-                k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val,
-                                                               S.sK, cand[k], S.b, S.r,
-                                                               pair(S.tau_s), pair(S.te_s),
-                                                               slot(S, kSlotGuess + k), 0.0);
+                saddle_resid(S, grid(Gn, R), cand[k], S.r, slot(S, kSlotGuess + k), 0.0);
         k_pick_guess<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xl, xg, slot(S, kSlotGuess),
                                                             Gn, S.xk, S.ctl);
     } else {
@@ -862,9 +880,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
     bool mr_done = false;
     Flags flags{};
     for (;;) {
-        k_saddle_resid<<<grid(Gn, R), kBlock, 0, st>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, S.xk,
-                                                       S.b, S.r, pair(S.tau_s), pair(S.te_s),
-                                                       slot(S, kSlotR), 1.0);
+        saddle_resid(S, grid(Gn, R), S.xk, S.r, slot(S, kSlotR), 1.0);
         k_nrm<<<grid(1, R), kBlock, 0, st>>>(S.ctl, slot(S, kSlotR), Gn);
         CHM_HIP(hipGetLastError());
         read_ctl(S);

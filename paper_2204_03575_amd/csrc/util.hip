@@ -143,6 +143,30 @@ __global__ void k_check_cols(const int *col, int64_t stored, int ncols, int *bad
         atomicAdd(bad, 1);
 }
 
+// col - row of every stored entry of the real rows as 16 bits (padding rows
+// past n get 0 and are never read); bad is set when an offset does not fit
+__global__ void k_sell_offsets(const int *sptr, const int *col, int n, int nslices,
+                               int16_t *ocol, int *bad)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nslices * kSlice)
+        return;
+    const int s = row / kSlice, lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        int d = 0;
+        if (row < n) {
+            d = col[idx] - row;
+            if (d < -32767 || d > 32767) {
+                bad[0] = 1;
+                d = 0;
+            }
+        }
+        ocol[idx] = (int16_t)d;
+    }
+}
+
 }  // namespace
 
 void scan_exclusive(int *d, int n, int *d_total, Pool &pool, hipStream_t s)
@@ -207,7 +231,7 @@ double reduce_max_host(const double *d, int n, Pool &pool, hipStream_t s)
     return m;
 }
 
-void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s)
+void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s, bool offsets16)
 {
     S.n = A.n;
     S.nslices = (A.n + kSlice - 1) / kSlice;
@@ -234,6 +258,16 @@ void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s)
         CHM_HIP(hipGetLastError());
         if (read_int(bad, s))
             throw Failure(CHM_EINVAL, "SELL conversion produced a column outside the matrix");
+    }
+    S.ocol = nullptr;
+    if (offsets16 && A.n == A.m && S.stored > 0) {
+        int16_t *oc = pool.get<int16_t>(S.stored);
+        int *bad = pool.get<int>(1);
+        fill_int(bad, 0, 1, s);
+        k_sell_offsets<<<(rows + 255) / 256, 256, 0, s>>>(S.sptr, S.col, A.n, S.nslices, oc, bad);
+        CHM_HIP(hipGetLastError());
+        if (!read_int(bad, s))
+            S.ocol = oc;
     }
 }
 
