@@ -153,11 +153,13 @@ __device__ inline int sell_col(const int16_t *__restrict__ col, int idx, int row
     return row + (int)col[idx];
 }
 
-// the unrolled row product for slices at most W wide (width >= 1)
+// the unrolled row product for slices at most W wide (width >= 1); diag
+// receives the row's nonzero diagonal entry (0 if it has none; the padding
+// of a short row may repeat the diagonal column, with value 0)
 template <int W, class I, class T>
 __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
                                        const I *__restrict__ col, const T *__restrict__ val,
-                                       const pair_t<T> *__restrict__ x)
+                                       const pair_t<T> *__restrict__ x, T &diag)
 {
     // entries past the slice width repeat the last column with a zero
     // coefficient: every load is unconditional (no branch between the
@@ -175,37 +177,45 @@ __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
 #pragma unroll
     for (int k = 0; k < W; ++k)
         xv[k] = x[c[k]];
-    T ax = 0, ay = 0;
+    T ax = 0, ay = 0, d = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         ax += a[k] * xv[k].x;
         ay += a[k] * xv[k].y;
+        d = (c[k] == row && a[k] != T(0)) ? a[k] : d;   // not the zero padding
     }
+    diag = d;
     return mk<T>(ax, ay);
 }
 
+// the row product of a SELL-64 matrix; diag receives the row's diagonal
+// entry (0 if it has none; callers that do not use it lose the selects)
 template <class I, class T>
 __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__restrict__ col,
                                      const T *__restrict__ val, const pair_t<T> *__restrict__ x,
-                                     int row)
+                                     int row, T &diag)
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    diag = 0;
     if (width == 0)
         return mk<T>(0, 0);
     if (width <= kSellUnroll)
-        return sell_row_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x);
+        return sell_row_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x, diag);
     if (width <= 2 * kSellUnroll)
-        return sell_row_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x);
-    T ax = 0, ay = 0;
+        return sell_row_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x, diag);
+    T ax = 0, ay = 0, d = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
         const int idx = base + k * kSlice + lane;
         const T a = val[idx];
-        const pair_t<T> xv = x[sell_col(col, idx, row)];
+        const int c = sell_col(col, idx, row);
+        const pair_t<T> xv = x[c];
         ax += a * xv.x;
         ay += a * xv.y;
+        d = (c == row && a != T(0)) ? a : d;
     }
+    diag = d;
     return mk<T>(ax, ay);
 }
 
@@ -238,7 +248,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
     x = run_at(x, sx);
     b = run_at(b, sy);
     y = run_at(y, sy);
-    spmv_store<MODE, T>(sell_row<I, T>(sptr, col, val, x, row), b, y, row);
+    T diag;
+    spmv_store<MODE, T>(sell_row<I, T>(sptr, col, val, x, row, diag), b, y, row);
 }
 
 // k_spmv over a SELL matrix of n rows, on its 16-bit column offsets when it

@@ -44,7 +44,7 @@ __device__ inline ChebRow<T> cheb_row(const pair_t<T> *__restrict__ b, const pai
     ChebRow<T> o;
     o.bb = b[row];
     o.xi = xk[row];
-    o.di = dinv[row];
+    o.di = dinv ? dinv[row] : T(0);
     o.xp = prev ? xprev[row] : mk<T>(0, 0);
     return o;
 }
@@ -70,8 +70,15 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     b = run_at(b, n);
     xk = run_at(xk, n);
     xprev = run_at(xprev, n);
-    const ChebRow<T> o = cheb_row<T>(b, xk, dinv, xprev, row, prev);
-    const pair_t<T> s = sell_row<I, T>(sptr, col, val, xk, row);
+    // FP64: D^-1 of the row is 1 / a_ii of the entries just read, the value
+    // the setup stored (the same IEEE division), so it is not loaded; the
+    // FP32 path loads its rounded copy
+    constexpr bool own = std::is_same<T, double>::value;
+    ChebRow<T> o = cheb_row<T>(b, xk, own ? nullptr : dinv, xprev, row, prev);
+    T diag;
+    const pair_t<T> s = sell_row<I, T>(sptr, col, val, xk, row, diag);
+    if (own)
+        o.di = T(1) / diag;
     xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
@@ -392,12 +399,16 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     }
     if (timed_level(S, H, l)) {
         // algorithmic bytes: column index (2 B as a SELL offset, else 4) +
-        // value per nonzero (once per launch); per row and run x_k (gathered
-        // once), b, D^-1, x_{k-1} (when read) and the written x_{k+1}
+        // value per nonzero (once per launch); per row D^-1 (except the FP64
+        // SELL kernel, which takes it from the diagonal entry) and per row
+        // and run x_k (gathered once), b, x_{k-1} (when read) and the
+        // written x_{k+1}
         const long long ib = (A.gs == 0 && A.ocol) ? 2 : 4;
+        const bool own = A.gs == 0 && std::is_same<T, double>::value;
         S.timer.count += 1;
         S.timer.bytes += (ib + (long long)sizeof(T)) * L.A.nnz +
-                         (long long)R * (prev ? 9 : 7) * sizeof(T) * L.n;
+                         (own ? 0ll : (long long)sizeof(T) * L.n) +
+                         (long long)R * (prev ? 8 : 6) * sizeof(T) * L.n;
     }
 }
 
