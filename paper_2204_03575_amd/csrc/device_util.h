@@ -271,10 +271,16 @@ void sell_spmv(hipStream_t st, dim3 g, int n, const int *sptr, const int *col, c
 // loading all their indices and values, then all their gathers, before the
 // products (entries past the row end repeat its last entry with a zero
 // coefficient), so a pass costs two dependent memory round trips.
-template <int GS, int U, class T>
-__device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
-                                    const T *__restrict__ v, const pair_t<T> *__restrict__ x,
-                                    int row, int lane)
+// The entries of x the row product gathers, x[j] by default; a kernel may
+// form them on the fly instead (G: a callable taking the column).
+template <class T> struct Gather {
+    const pair_t<T> *__restrict__ x;
+    __device__ pair_t<T> operator()(int j) const { return x[j]; }
+};
+
+template <int GS, int U, class T, class G>
+__device__ inline pair_t<T> row_dot_g(const int *__restrict__ rp, const int *__restrict__ ci,
+                                      const T *__restrict__ v, const G &x, int row, int lane)
 {
     T ax = 0, ay = 0;
     const int s = rp[row], e = rp[row + 1];
@@ -292,7 +298,7 @@ __device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__res
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            xv[u] = x[c[u]];
+            xv[u] = x(c[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             ax += a[u] * xv[u].x;
@@ -305,6 +311,14 @@ __device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__res
         ay += __shfl_down(ay, off, GS);
     }
     return mk<T>(ax, ay);
+}
+
+template <int GS, int U, class T>
+__device__ inline pair_t<T> row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                    const T *__restrict__ v, const pair_t<T> *__restrict__ x,
+                                    int row, int lane)
+{
+    return row_dot_g<GS, U, T>(rp, ci, v, Gather<T>{x}, row, lane);
 }
 
 template <int GS, int U, int MODE, class T>

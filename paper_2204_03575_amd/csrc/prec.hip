@@ -82,6 +82,134 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
+// The first two smoothing steps from x = 0 in one launch (SELL levels):
+// x_1 = c2' D^-1 b is formed on the fly for the row and for every column it
+// gathers, by the expression of k_cheb0 (so with its bits), and the row's
+// x_2 = x_1 + c1 x_1 + c2 D^-1 (b - A x_1) follows as in k_cheb.  Both are
+// stored (step 3 reads x_1 as its previous iterate).  The launch reads b and
+// D^-1 where k_cheb0 + k_cheb read b and D^-1 twice and x_1 once more.
+template <class T> struct FirstIter {
+    const pair_t<T> *__restrict__ b;
+    const T *__restrict__ dinv;
+    T c2;
+    __device__ pair_t<T> operator()(int j) const
+    {
+        const pair_t<T> bb = b[j];
+        const T di = dinv[j];
+        return mk<T>(c2 * (di * bb.x), c2 * (di * bb.y));
+    }
+};
+
+// the row's operands of step 2 with x_1 formed on the fly
+template <class T> __device__ inline ChebRow<T> first_row(const FirstIter<T> &x1, int row)
+{
+    ChebRow<T> o;
+    o.bb = x1.b[row];
+    o.di = x1.dinv[row];
+    o.xi = mk<T>(x1.c2 * (o.di * o.bb.x), x1.c2 * (o.di * o.bb.y));
+    o.xp = mk<T>(0, 0);
+    return o;
+}
+
+// A x_1 over one SELL row, entries added in column order; slices at most W
+// wide take the unrolled path of sell_row_w (all column and value loads,
+// then all gathers, then the products)
+template <int W, class I, class T>
+__device__ inline pair_t<T> sell_row_first_w(int base, int width, int lane, int row,
+                                             const I *__restrict__ col, const T *__restrict__ val,
+                                             const FirstIter<T> &x1)
+{
+    int c[W];
+    T a[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+        c[k] = sell_col(col, idx, row);
+        const T v = val[idx];
+        a[k] = k < width ? v : T(0);
+    }
+    pair_t<T> bv[W];
+    T dv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        bv[k] = x1.b[c[k]];
+        dv[k] = x1.dinv[c[k]];
+    }
+    T ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        ax += a[k] * (x1.c2 * (dv[k] * bv[k].x));
+        ay += a[k] * (x1.c2 * (dv[k] * bv[k].y));
+    }
+    return mk<T>(ax, ay);
+}
+
+template <class I, class T>
+__device__ inline pair_t<T> sell_row_first(const int *__restrict__ sptr, const I *__restrict__ col,
+                                           const T *__restrict__ val, const FirstIter<T> &x1,
+                                           int row)
+{
+    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    if (width == 0)
+        return mk<T>(0, 0);
+    if (width <= kSellUnroll)
+        return sell_row_first_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x1);
+    if (width <= 2 * kSellUnroll)
+        return sell_row_first_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x1);
+    T ax = 0, ay = 0;
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        const T a = val[idx];
+        const pair_t<T> xv = x1(sell_col(col, idx, row));
+        ax += a * xv.x;
+        ay += a * xv.y;
+    }
+    return mk<T>(ax, ay);
+}
+
+template <class I, class T>
+__global__ void __launch_bounds__(kBlock) k_cheb_first(int n, const int *__restrict__ sptr,
+                                                       const I *__restrict__ col,
+                                                       const T *__restrict__ val,
+                                                       const T *__restrict__ dinv,
+                                                       const pair_t<T> *__restrict__ b,
+                                                       pair_t<T> *x1out, pair_t<T> *x2, T c2first,
+                                                       T c1, T c2)
+{
+    const int row = xcd_block() * kBlock + threadIdx.x;
+    if (row >= n)
+        return;
+    const FirstIter<T> x1{run_at(b, n), dinv, c2first};
+    const ChebRow<T> o = first_row(x1, row);
+    const pair_t<T> s = sell_row_first<I, T>(sptr, col, val, x1, row);
+    run_at(x1out, n)[row] = o.xi;
+    run_at(x2, n)[row] = cheb_apply<T>(s, o, c1, c2);
+}
+
+// the same for a CSR level with a group of GS lanes per row
+template <int GS, int U, class T>
+__global__ void __launch_bounds__(kBlock) k_cheb_v_first(int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci,
+                                                         const T *__restrict__ v,
+                                                         const T *__restrict__ dinv,
+                                                         const pair_t<T> *__restrict__ b,
+                                                         pair_t<T> *x1out, pair_t<T> *x2,
+                                                         T c2first, T c1, T c2)
+{
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    const FirstIter<T> x1{run_at(b, n), dinv, c2first};
+    const ChebRow<T> o = first_row(x1, row);   // the group's lanes share these lines
+    const pair_t<T> s = row_dot_g<GS, U, T>(rp, ci, v, x1, row, lane);
+    if (lane != 0)
+        return;
+    run_at(x1out, n)[row] = o.xi;
+    run_at(x2, n)[row] = cheb_apply<T>(s, o, c1, c2);
+}
+
 template <int GS, int U, class T>
 __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
@@ -364,6 +492,58 @@ void cheb_v_u(hipStream_t st, int R, const MatView<T> &A, const T *dinv, const p
                                                  prev);
 }
 
+template <int GS, class T>
+void cheb_first_v_u(hipStream_t st, int R, const MatView<T> &A, const T *dinv, const pair_t<T> *b,
+                    pair_t<T> *x1, pair_t<T> *x2, T c2f, T c1, T c2)
+{
+    const dim3 g = grid(nblk((long)GS * A.n), R);
+    if (A.u >= 4)
+        k_cheb_v_first<GS, 4, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, x1, x2,
+                                                       c2f, c1, c2);
+    else if (A.u == 2)
+        k_cheb_v_first<GS, 2, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, x1, x2,
+                                                       c2f, c1, c2);
+    else
+        k_cheb_v_first<GS, 1, T><<<g, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.cval, dinv, b, x1, x2,
+                                                       c2f, c1, c2);
+}
+
+// smoothing steps 1 and 2 from x = 0 on level l in one launch: x1 <- x_1,
+// x2 <- x_2 (step 1 with c2f, step 2 with c1, c2)
+template <class T>
+void launch_cheb_first(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> *x1,
+                       pair_t<T> *x2, double c2fd, double c1d, double c2d)
+{
+    const Level &L = H.lev[l];
+    const MatView<T> A = L.viewA<T>();
+    const T *dinv = L.dinv_t<T>();
+    const T c2f = T(c2fd), c1 = T(c1d), c2 = T(c2d);
+    const int n = L.n, R = S.nrun;
+    hipStream_t st = S.stream;
+    switch (A.gs) {
+    case 0:
+        if (A.ocol)
+            k_cheb_first<int16_t, T><<<grid(nblk(n), R), kBlock, 0, st>>>(
+                n, A.sptr, A.ocol, A.sval, dinv, b, x1, x2, c2f, c1, c2);
+        else
+            k_cheb_first<int, T><<<grid(nblk(n), R), kBlock, 0, st>>>(
+                n, A.sptr, A.col, A.sval, dinv, b, x1, x2, c2f, c1, c2);
+        break;
+    case 4:
+        cheb_first_v_u<4, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
+        break;
+    case 8:
+        cheb_first_v_u<8, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
+        break;
+    case 16:
+        cheb_first_v_u<16, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
+        break;
+    default:
+        cheb_first_v_u<32, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
+        break;
+    }
+}
+
 // one smoothing step on level l: xprev <- x_{k+1} from xk (and xprev when prev = 1)
 template <class T>
 void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_t<T> *xk,
@@ -424,17 +604,26 @@ pair_t<T> *presmooth(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<
     const int deg = H.degree, R = S.nrun;
     auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
-    k_cheb0<T><<<grid(nblk(L.n), R), kBlock, 0, S.stream>>>(L.n, L.dinv_t<T>(), b, first,
-                                                             T(c2(1)));
     pair_t<T> *cur = first, *oth = other;
+    int k0 = 2;   // the first step k_cheb handles
+    if (deg >= 2) {
+        // steps 1 and 2 in one launch; x_1 and x_2 land where the two
+        // launches would put them
+        launch_cheb_first<T>(S, H, l, b, cur, oth, c2(1), c1(2), c2(2));
+        std::swap(cur, oth);
+        k0 = 3;
+    } else {
+        k_cheb0<T><<<grid(nblk(L.n), R), kBlock, 0, S.stream>>>(L.n, L.dinv_t<T>(), b, first,
+                                                                 T(c2(1)));
+    }
     const bool timed = timed_level(S, H, l);
-    if (timed && deg >= 2)
+    if (timed && deg >= k0)
         timer_mark(S, true);
-    for (int k = 2; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
+    for (int k = k0; k <= deg; ++k) {   // x_0 = 0: the previous iterate is zero at k = 2
         launch_cheb<T>(S, H, l, b, cur, oth, c1(k), c2(k), k > 2 && !H.jacobi);
         std::swap(cur, oth);
     }
-    if (timed && deg >= 2)
+    if (timed && deg >= k0)
         timer_mark(S, false);
     return cur;
 }
