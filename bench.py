@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Keyed by workload and
 # precision, for the default 16-bit SELL column offsets; None where the counters were not
 # taken (or the kernel changed since, or with --wide-index).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 34.67e6, ("square512", "fp32"): 20.28e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.08e6, ("square512", "fp32"): 20.48e6}
 
 
 def parse():
