@@ -341,7 +341,8 @@ __device__ inline double2 ratio_or_zero(double2 num, double2 den)
 }
 
 // alpha = rz / dq from partials; first == 1: x = alpha d, r = b - alpha q
-// (x = 0 and r = b before the step), else x += alpha d, r -= alpha q
+// (x = 0 and r = b before the step), else x += alpha d, r -= alpha q; with
+// want_r = 0 (the last step) r is left alone
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, pair_t<T> *x, pair_t<T> *r,
                                                    const pair_t<T> *__restrict__ b,
@@ -349,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, pair_t<T> *x, pair_t<T
                                                    const pair_t<T> *__restrict__ q,
                                                    const double2 *__restrict__ rz_part,
                                                    const double2 *__restrict__ dq_part, int G,
-                                                   int first)
+                                                   int first, int want_r)
 {
     __shared__ double2 sc[2];
     reduce_two(run_at(rz_part, kSlotStride), run_at(dq_part, kSlotStride), G, sc);
@@ -363,38 +364,35 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, pair_t<T> *x, pair_t<T
     q = run_at(q, n);
     const double2 al = ratio_or_zero(sc[0], sc[1]);
     const T ax = T(al.x), ay = T(al.y);
-    const pair_t<T> dv = d[i], qv = q[i];
+    const pair_t<T> dv = d[i];
     pair_t<T> xv = first ? mk<T>(0, 0) : x[i];
-    pair_t<T> rv = first ? b[i] : r[i];
     xv.x += ax * dv.x;
     xv.y += ay * dv.y;
+    x[i] = xv;
+    if (!want_r)
+        return;
+    const pair_t<T> qv = q[i];
+    pair_t<T> rv = first ? b[i] : r[i];
     rv.x -= ax * qv.x;
     rv.y -= ay * qv.y;
-    x[i] = xv;
     r[i] = rv;
 }
 
-// d = z + beta d with beta = rz_new / rz_old (0 where rz_old == 0); first: d = z
+// d = z + beta d with beta = rz_new / rz_old (0 where rz_old == 0)
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_dir(int n, const pair_t<T> *__restrict__ z,
                                                     pair_t<T> *d,
                                                     const double2 *__restrict__ new_part,
-                                                    const double2 *__restrict__ old_part, int G,
-                                                    int first)
+                                                    const double2 *__restrict__ old_part, int G)
 {
     __shared__ double2 sc[2];
-    if (!first)
-        reduce_two(run_at(new_part, kSlotStride), run_at(old_part, kSlotStride), G, sc);
+    reduce_two(run_at(new_part, kSlotStride), run_at(old_part, kSlotStride), G, sc);
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
     z = run_at(z, n);
     d = run_at(d, n);
     const pair_t<T> zv = z[i];
-    if (first) {
-        d[i] = zv;
-        return;
-    }
     const double2 be = ratio_or_zero(sc[0], sc[1]);
     const T bx = T(be.x), by = T(be.y);
     const pair_t<T> dv = d[i];
@@ -722,22 +720,26 @@ void schur_solve_t(Solver &S, const pair_t<T> *b, pair_t<T> *x)
     }
     Work<T> &W = work<T>(S);
     const MatView<T> A = H.lev[0].viewA<T>();
-    pair_t<T> *r = W.pcg_r, *z = W.pcg_z, *d = W.pcg_d, *q = W.pcg_q;
+    pair_t<T> *r = W.pcg_r, *q = W.pcg_q;
     const int G = red_blocks(n), R = S.nrun;
-    vcycle_level<T>(S, H, 0, b, z);                                    // z = V(b), r = b
-    k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, z, slot(S, kSlotRz));
-    k_pcg_dir<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, z, d, nullptr, nullptr, G, 1);   // d = z
+    // the first direction is z itself (no copy); each later z goes to the
+    // buffer not holding the direction, which k_pcg_dir then updates in place
+    pair_t<T> *d = W.pcg_z;
+    vcycle_level<T>(S, H, 0, b, d);                                    // z = V(b), r = b
+    k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, d, slot(S, kSlotRz));
     for (int it = 1; it <= k; ++it) {
         spmv_op<SP_SET, T>(st, R, A, d, nullptr, q);
         k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
         k_pcg_xr<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
-                                                         slot(S, kSlotDq + it), G, it == 1);
+                                                         slot(S, kSlotDq + it), G, it == 1,
+                                                         it < k);
         if (it == k)
             break;
+        pair_t<T> *z = d == W.pcg_z ? W.pcg_d : W.pcg_z;
         vcycle_level<T>(S, H, 0, r, z);
         k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, r, z, slot(S, kSlotRz + it));
         k_pcg_dir<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, z, d, slot(S, kSlotRz + it),
-                                                          slot(S, kSlotRz + it - 1), G, 0);
+                                                          slot(S, kSlotRz + it - 1), G);
     }
 }
 
