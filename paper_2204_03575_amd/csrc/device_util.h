@@ -390,7 +390,9 @@ void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
 
 // ------------------------------------------------------------------ vector kernels
 // per-block partial sums of the two species' dot products, accumulated in
-// FP64; per run, a and b advance by n and part by one run's slots
+// FP64; per run, a and b advance by n and part by one run's slots.  A thread
+// adds its elements i, i + stride, ... in that order; it loads four of them
+// at a time, so a pass costs one memory round trip, not four.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restrict__ a,
                                                 const pair_t<T> *__restrict__ b, double2 *part)
@@ -400,7 +402,22 @@ __global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restri
     b = run_at(b, n);
     part = run_at(part, kSlotStride);
     double2 acc = d2(0.0, 0.0);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const int stride = gridDim.x * kBlock;
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        pair_t<T> x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = a[i + u * stride];
+            y[u] = b[i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc.x += double(x[u].x) * double(y[u].x);
+            acc.y += double(x[u].y) * double(y[u].y);
+        }
+    }
+    for (; i < n; i += stride) {
         const pair_t<T> x = a[i], y = b[i];
         acc.x += double(x.x) * double(y.x);
         acc.y += double(x.y) * double(y.y);
