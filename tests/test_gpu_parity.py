@@ -185,8 +185,10 @@ def test_square32_free_running_trajectory():
     dict(mass_solver="chebyshev", cheb_degree_mass=4, smoother="jacobi", cheb_degree=3),
     dict(mass_solver="chebyshev", cheb_degree_mass=5, krylov="minres", schur_pcg=0,
          amg_cycles=2),
+    dict(cheb_degree=1, cheb_degree_mass=1),          # one smoothing step: no fused first steps
+    dict(cheb_degree=2, cheb_degree_mass=2, mass_solver="chebyshev"),   # the fused steps only
 ], ids=["poly", "jacobi", "stationary", "restart5", "tau-eps-mob", "nopot", "mass-cheb",
-        "mass-jacobi", "mass-cheb-minres"])
+        "mass-jacobi", "mass-cheb-minres", "degree1", "degree2"])
 def test_step_variants(variant):
     v = dict(variant)
     mean = v.pop("mean", (0.1, 0.1))
