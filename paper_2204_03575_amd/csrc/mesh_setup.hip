@@ -102,11 +102,6 @@ __global__ void k_pattern(const int *cells, int nl, const int *inc_ptr, const in
     }
 }
 
-// One synchronous round of Jones-Plassmann colouring of the cell conflict
-// graph (cells conflict when they share a vertex).  A cell uncoloured at the
-// start of the round whose (hash, index) beats every uncoloured neighbour
-// takes the smallest colour absent among its coloured neighbours.  Reads
-// col_in, writes col_out, so decisions depend on the previous round only.
 // one atomic per wave: lane 0 adds the number of lanes with pred set (every
 // lane of the wave must reach the call)
 __device__ inline void count_in_wave(int *counter, bool pred)
@@ -116,55 +111,108 @@ __device__ inline void count_in_wave(int *counter, bool pred)
         atomicAdd(counter, __popcll(m));
 }
 
-__global__ void k_jp_round(const int *cells, int nl, int ncell, const int *inc_ptr, const int *inc,
-                           const int *col_in, int *col_out, int *remaining, int *maxcolor,
-                           int *overflow)
+// priority of a cell in the colouring (a fixed hash; ties broken by index)
+__device__ inline uint64_t cell_prio(int c)
+{
+    return mix_hash(0x632BE59BD9B4E019ull + (uint64_t)c * 0x9E3779B97F4A7C15ull);
+}
+__device__ inline bool beats(int e, uint64_t he, int c, uint64_t hc)
+{
+    return he > hc || (he == hc && e > c);
+}
+
+// Speculative colouring of the cell conflict graph (cells conflict when they
+// share a vertex), in synchronous rounds of two kernels.  Pick: every cell
+// uncoloured at the start of the round tentatively takes the smallest colour
+// absent among its coloured neighbours (col_in -> col_try).  Resolve: a
+// tentative colour that a tentatively coloured neighbour of higher priority
+// also took is dropped (col_in, col_try -> col_out); the others become final.
+// The highest-priority uncoloured cell always keeps its colour, so every
+// round colours at least one cell, and a final colour never repeats among
+// neighbours.  Decisions depend on the previous round only.
+__global__ void k_color_pick(const int *cells, int nl, int ncell, const int *inc_ptr,
+                             const int *inc, const int *col_in, int *col_try, int *overflow)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool waiting = false;
+    if (c >= ncell)
+        return;
+    const int mine = col_in[c];
+    if (mine >= 0) {
+        col_try[c] = mine;
+        return;
+    }
+    uint64_t used0 = 0, used1 = 0;
+    for (int a = 0; a < nl; ++a) {
+        const int v = cells[(size_t)c * nl + a];
+        for (int k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+            const int ce = col_in[inc[k]];
+            if (ce >= 0 && ce < 64)
+                used0 |= 1ull << ce;
+            else if (ce >= 64)
+                used1 |= 1ull << (ce - 64);
+        }
+    }
+    int pick = -1;
+    if (~used0)
+        pick = __ffsll((unsigned long long)~used0) - 1;
+    else if (~used1)
+        pick = 64 + __ffsll((unsigned long long)~used1) - 1;
+    if (pick < 0)
+        atomicAdd(overflow, 1);
+    col_try[c] = pick;
+}
+
+__global__ void k_color_resolve(const int *cells, int nl, int ncell, const int *inc_ptr,
+                                const int *inc, const int *col_in, const int *col_try,
+                                int *col_out, int *remaining, int *maxcolor)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool dropped = false;
     if (c < ncell) {
-        const int mine = col_in[c];
-        col_out[c] = mine;
-        if (mine < 0) {
-            const uint64_t hc = mix_hash(0x632BE59BD9B4E019ull + (uint64_t)c * 0x9E3779B97F4A7C15ull);
-            uint64_t used0 = 0, used1 = 0;
-            for (int a = 0; a < nl && !waiting; ++a) {
+        const int t = col_try[c];
+        if (col_in[c] >= 0 || t < 0) {
+            col_out[c] = t;   // final before this round, or no colour left (overflow)
+        } else {
+            const uint64_t hc = cell_prio(c);
+            for (int a = 0; a < nl && !dropped; ++a) {
                 const int v = cells[(size_t)c * nl + a];
                 for (int k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
                     const int e = inc[k];
-                    if (e == c)
-                        continue;
-                    const int ce = col_in[e];
-                    if (ce < 0) {
-                        const uint64_t he =
-                            mix_hash(0x632BE59BD9B4E019ull + (uint64_t)e * 0x9E3779B97F4A7C15ull);
-                        if (he > hc || (he == hc && e > c)) {
-                            waiting = true;
-                            break;
-                        }
-                    } else if (ce < 64) {
-                        used0 |= 1ull << ce;
-                    } else {
-                        used1 |= 1ull << (ce - 64);
+                    if (e != c && col_in[e] < 0 && col_try[e] == t && beats(e, cell_prio(e), c, hc)) {
+                        dropped = true;
+                        break;
                     }
                 }
             }
-            if (!waiting) {
-                int pick = -1;
-                if (~used0)
-                    pick = __ffsll((unsigned long long)~used0) - 1;
-                else if (~used1)
-                    pick = 64 + __ffsll((unsigned long long)~used1) - 1;
-                if (pick < 0) {
-                    atomicAdd(overflow, 1);
-                } else {
-                    col_out[c] = pick;
-                    atomicMax(maxcolor, pick);
+            col_out[c] = dropped ? -1 : t;
+            if (!dropped)
+                atomicMax(maxcolor, t);
+        }
+    }
+    count_in_wave(remaining, dropped);
+}
+
+// cells that share a vertex with a cell of the same colour (must be none)
+__global__ void k_color_check(const int *cells, int nl, int ncell, const int *inc_ptr,
+                              const int *inc, const int *col, int *bad)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool clash = false;
+    if (c < ncell) {
+        const int mine = col[c];
+        clash = mine < 0;
+        for (int a = 0; a < nl && !clash; ++a) {
+            const int v = cells[(size_t)c * nl + a];
+            for (int k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+                const int e = inc[k];
+                if (e != c && col[e] == mine) {
+                    clash = true;
+                    break;
                 }
             }
         }
     }
-    count_in_wave(remaining, waiting);
+    count_in_wave(bad, clash);
 }
 
 __global__ void k_color_count(const int *color, int ncell, int *cnt)
@@ -440,23 +488,32 @@ void mesh_setup(Solver &S)
                                                  flags);
     CHM_HIP(hipGetLastError());
 
-    // Jones-Plassmann colouring of the cells
-    int *colA = pool.get<int>(ncell), *colB = pool.get<int>(ncell);
+    // speculative colouring of the cells; a cell is uncoloured after a round
+    // only if a neighbour of higher priority took its tentative colour
+    int *colA = pool.get<int>(ncell), *colB = pool.get<int>(ncell), *colT = pool.get<int>(ncell);
     fill_int(colA, -1, ncell, st);
     for (int round = 0;; ++round) {
         fill_int(flags + 1, 0, 1, st);
-        k_jp_round<<<blocks_for(ncell), kBlock, 0, st>>>(S.cells, nl, ncell, inc_ptr, inc, colA,
-                                                         colB, flags + 1, flags + 2, flags);
+        k_color_pick<<<blocks_for(ncell), kBlock, 0, st>>>(S.cells, nl, ncell, inc_ptr, inc, colA,
+                                                           colT, flags);
+        k_color_resolve<<<blocks_for(ncell), kBlock, 0, st>>>(S.cells, nl, ncell, inc_ptr, inc,
+                                                              colA, colT, colB, flags + 1,
+                                                              flags + 2);
         CHM_HIP(hipGetLastError());
         std::swap(colA, colB);
-        int rem = read_int(flags + 1, st);
         if (read_int(flags, st))
             throw Failure(CHM_EINVAL, "cell colouring needs more than 128 colours");
-        if (rem == 0)
+        if (read_int(flags + 1, st) == 0)
             break;
-        if (round > 100000)
+        if (round > ncell)
             throw Failure(CHM_EINVAL, "cell colouring did not terminate");
     }
+    fill_int(flags + 1, 0, 1, st);
+    k_color_check<<<blocks_for(ncell), kBlock, 0, st>>>(S.cells, nl, ncell, inc_ptr, inc, colA,
+                                                        flags + 1);
+    CHM_HIP(hipGetLastError());
+    if (read_int(flags + 1, st))
+        throw Failure(CHM_EINVAL, "cell colouring left two cells that share a vertex in one colour");
     S.ncolors = read_int(flags + 2, st) + 1;
     int *ccount = pool.get<int>(kMaxColors + 1);
     fill_int(ccount, 0, kMaxColors + 1, st);
