@@ -168,6 +168,64 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *
     }
 }
 
+// MODE 1 for nvec <= NV basis vectors with the thread's V_i entries held in
+// registers: each element's entries are loaded once, for the update and for
+// the partials, which the MODE-1 kernel above loads twice.  The update runs
+// over i = 0, 1, ... and each partial over the thread's elements in the same
+// order as there, so the results are bitwise the same.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gs1_reg(int len, long ks, const double2 *__restrict__ V,
+                                                    int nvec, double2 *w,
+                                                    const double2 *__restrict__ hin, long hs,
+                                                    double2 *part, long ps)
+{
+    __shared__ double2 sh[kBlock / 64];
+    __shared__ double2 h[NV];
+    const int G = gridDim.x;
+    const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
+    V = run_at(V, len);
+    w = run_at(w, len);
+    hin = run_at(hin, hs);
+    part = run_at(part, ps);
+    for (int v = threadIdx.x; v < nvec; v += kBlock)
+        h[v] = hin[v];
+    __syncthreads();
+    double2 acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        acc[v] = d2(0.0, 0.0);
+#pragma unroll 1
+    for (int i = start; i < len; i += stride) {
+        double2 vv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)   // slots past nvec repeat the last vector; unused
+            vv[v] = V[(size_t)(v < nvec ? v : nvec - 1) * ks + i];
+        double2 wv = w[i];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v < nvec) {
+                const double2 hv = h[v];
+                wv.x -= hv.x * vv[v].x;
+                wv.y -= hv.y * vv[v].y;
+            }
+        }
+        w[i] = wv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc[v].x += vv[v].x * wv.x;
+            acc[v].y += vv[v].y * wv.y;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nvec) {
+            const double2 t = block_sum(acc[v], sh);
+            if (threadIdx.x == 0)
+                part[(size_t)v * G + blockIdx.x] = t;
+        }
+    }
+}
+
 // out[v] = sum of the G partials of vector v; block v handles vector v
 // (thread t adds g = t, t + 256, ... in order, then a fixed block tree);
 // per run, part advances by ps and out by hs
@@ -766,8 +824,15 @@ void iteration_body(Solver &S, int j)
     k_gs<0><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, nullptr, kHStride, S.gsp1,
                                             kGsStride);
     k_finish<<<grid(j + 1, R), kBlock, 0, st>>>(S.gsp1, kGsStride, Gg, h1, kHStride);
-    k_gs<1><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride, S.gsp2,
-                                            kGsStride);
+    if (j + 1 <= 8)
+        k_gs1_reg<8><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride, S.gsp2,
+                                                     kGsStride);
+    else if (j + 1 <= 16)
+        k_gs1_reg<16><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride,
+                                                      S.gsp2, kGsStride);
+    else
+        k_gs<1><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride, S.gsp2,
+                                                kGsStride);
     k_finish<<<grid(j + 1, R), kBlock, 0, st>>>(S.gsp2, kGsStride, Gg, h2, kHStride);
     k_gs<2><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h2, kHStride, S.gsp3,
                                             kGsBlocks);
