@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
 // ------------------------------------------------------------------ Gram-Schmidt passes
 // MODE 0: partials of V_i . w;  MODE 1: w -= sum_i V_i h[i] with the
 // finalised MODE-0 results h, then partials of V_i . w;  MODE 2: the same
-// update with the MODE-1 results, then partials of w . w.  All per species;
+// update with the MODE-1 results and, in the same loop, partials of w . w.  All per species;
 // len = 2n.  The grid (up to kGsBlocks blocks per run) keeps several blocks
 // per CU.  The Krylov vectors are [index][run][len] (index stride ks = runs
 // len); per run, w advances by len, h by hs and the partials by ps.
@@ -119,6 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *
     w = run_at(w, len);
     hin = run_at(hin, hs);
     part = run_at(part, ps);
+    double2 nrm = d2(0.0, 0.0);   // MODE 2: w . w of the updated elements, in element order
     if (MODE > 0) {
         for (int v = threadIdx.x; v < nvec; v += kBlock)
             h[v] = hin[v];
@@ -131,16 +132,14 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *
                 wv.y -= hv.y * vv.y;
             }
             w[i] = wv;
+            if (MODE == 2) {
+                nrm.x += wv.x * wv.x;
+                nrm.y += wv.y * wv.y;
+            }
         }
     }
     if (MODE == 2) {
-        double2 acc = d2(0.0, 0.0);
-        for (int i = start; i < len; i += stride) {
-            const double2 wv = w[i];
-            acc.x += wv.x * wv.x;
-            acc.y += wv.y * wv.y;
-        }
-        const double2 s = block_sum(acc, sh);
+        const double2 s = block_sum(nrm, sh);
         if (threadIdx.x == 0)
             part[blockIdx.x] = s;
         return;
