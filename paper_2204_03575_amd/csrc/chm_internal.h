@@ -87,6 +87,7 @@ struct Csr {       // device CSR
 struct Sell {      // device SELL-64
     int n = 0, nslices = 0;
     int64_t stored = 0;   // padded entry count
+    int wmax = 0;         // entries in the widest slice
     int *sptr = nullptr;  // nslices + 1 offsets
     int *col = nullptr;
     double *val = nullptr;

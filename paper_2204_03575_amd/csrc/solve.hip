@@ -15,35 +15,69 @@ namespace {
 
 // ------------------------------------------------------------------ saddle-point operator
 // y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
-template <class I>
+// U8: every slice of the pattern is at most kSellUnroll wide (2D meshes); the
+// row then takes the unrolled form of the loop: every column and value load,
+// then every gather, then the products in column order (slots past the slice
+// width repeat its last column with zero values)
+template <class I, bool U8>
 __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
                                   const I *__restrict__ col, const double *__restrict__ vm,
                                   const double *__restrict__ vk, const double2 *__restrict__ x,
                                   double2 t, double2 te, double2 &y0, double2 &y1)
 {
-    const int s = row / kSlice, lane = row % kSlice;
+    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
     double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const int c = sell_col(col, idx, row);
-        const double am = vm[idx], ak = vk[idx];
-        const double2 x0 = x[c], x1 = x[n + c];
-        m0x += am * x0.x;
-        m0y += am * x0.y;
-        k1x += ak * x1.x;
-        k1y += ak * x1.y;
-        k0x += ak * x0.x;
-        k0y += ak * x0.y;
-        m1x += am * x1.x;
-        m1y += am * x1.y;
+    if (U8 && width > 0) {
+        int c[kSellUnroll];
+        double am[kSellUnroll], ak[kSellUnroll];
+#pragma unroll
+        for (int k = 0; k < kSellUnroll; ++k) {
+            const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+            c[k] = sell_col(col, idx, row);
+            const double vmk = vm[idx], vkk = vk[idx];
+            am[k] = k < width ? vmk : 0.0;
+            ak[k] = k < width ? vkk : 0.0;
+        }
+        double2 x0[kSellUnroll], x1[kSellUnroll];
+#pragma unroll
+        for (int k = 0; k < kSellUnroll; ++k) {
+            x0[k] = x[c[k]];
+            x1[k] = x[n + c[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kSellUnroll; ++k) {
+            m0x += am[k] * x0[k].x;
+            m0y += am[k] * x0[k].y;
+            k1x += ak[k] * x1[k].x;
+            k1y += ak[k] * x1[k].y;
+            k0x += ak[k] * x0[k].x;
+            k0y += ak[k] * x0[k].y;
+            m1x += am[k] * x1[k].x;
+            m1y += am[k] * x1[k].y;
+        }
+    } else {
+        for (int k = 0; k < width; ++k) {
+            const int idx = base + k * kSlice + lane;
+            const int c = sell_col(col, idx, row);
+            const double am = vm[idx], ak = vk[idx];
+            const double2 x0 = x[c], x1 = x[n + c];
+            m0x += am * x0.x;
+            m0y += am * x0.y;
+            k1x += ak * x1.x;
+            k1y += ak * x1.y;
+            k0x += ak * x0.x;
+            k0y += ak * x0.y;
+            m1x += am * x1.x;
+            m1y += am * x1.y;
+        }
     }
     y0 = d2(m0x + t.x * k1x, m0y + t.y * k1y);
     y1 = d2(t.x * k0x - te.x * m1x, t.y * k0y - te.y * m1y);
 }
 
 // per run, x and y advance by 2n
-template <class I>
+template <class I, bool U8>
 __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict__ sptr,
                                                    const I *__restrict__ col,
                                                    const double *__restrict__ vm,
@@ -57,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
     x = run_at(x, 2l * n);
     y = run_at(y, 2l * n);
     double2 y0, y1;
-    saddle_row<I>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+    saddle_row<I, U8>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
     y[row] = y0;
     y[n + row] = y1;
 }
@@ -65,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
 // y = b - A x over a grid-stride loop, and partial sums of |y1|^2 + w2 |y2|^2
 // per species (y1, y2: the two block rows; w2 = 1 gives the 2-norm; per run:
 // vectors advance by 2n, part by one run's slots)
-template <class I>
+template <class I, bool U8>
 __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
                                                          const I *__restrict__ col,
                                                          const double *__restrict__ vm,
@@ -83,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__res
     double2 nrm = d2(0.0, 0.0);
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
         double2 y0, y1;
-        saddle_row<I>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+        saddle_row<I, U8>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
         const double2 b0 = b[row], b1 = b[n + row];
         y0 = d2(b0.x - y0.x, b0.y - y0.y);
         y1 = d2(b1.x - y1.x, b1.y - y1.y);
@@ -692,26 +726,39 @@ void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
     const int n = S.nv;
     const dim3 g = grid(nblk(n), S.nrun);
-    if (S.sM.ocol)
-        k_saddle<int16_t><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, y,
-                                                      pair(S.tau_s), pair(S.te_s));
+    const bool u8 = S.sM.wmax <= kSellUnroll;
+    if (S.sM.ocol && u8)
+        k_saddle<int16_t, true><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK,
+                                                            x, y, pair(S.tau_s), pair(S.te_s));
+    else if (S.sM.ocol)
+        k_saddle<int16_t, false><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val,
+                                                             S.sK, x, y, pair(S.tau_s),
+                                                             pair(S.te_s));
+    else if (u8)
+        k_saddle<int, true><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
+                                                        y, pair(S.tau_s), pair(S.te_s));
     else
-        k_saddle<int><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, y,
-                                                  pair(S.tau_s), pair(S.te_s));
+        k_saddle<int, false><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
+                                                         y, pair(S.tau_s), pair(S.te_s));
 }
 
 // y = b - A x and the partials of its norms (k_saddle_resid) on M's pattern
 static void saddle_resid(Solver &S, dim3 g, const double2 *x, double2 *y, double2 *part, double w2)
 {
     const int n = S.nv;
-    if (S.sM.ocol)
-        k_saddle_resid<int16_t><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK,
-                                                            x, S.b, y, pair(S.tau_s),
-                                                            pair(S.te_s), part, w2);
+    const bool u8 = S.sM.wmax <= kSellUnroll;
+    if (S.sM.ocol && u8)
+        k_saddle_resid<int16_t, true><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+    else if (S.sM.ocol)
+        k_saddle_resid<int16_t, false><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+    else if (u8)
+        k_saddle_resid<int, true><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
     else
-        k_saddle_resid<int><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
-                                                        S.b, y, pair(S.tau_s), pair(S.te_s), part,
-                                                        w2);
+        k_saddle_resid<int, false><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
 }
 
 // b = (M phi + tau G, -(tau'/eps) f) for the current state of every run

@@ -241,7 +241,16 @@ void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s, bool offsets1
         CHM_HIP(hipGetLastError());
     }
     scan_exclusive(S.sptr, S.nslices, S.sptr + S.nslices, pool, s);
-    S.stored = read_int(S.sptr + S.nslices, s);
+    {
+        std::vector<int> hp(S.nslices + 1);
+        CHM_HIP(hipMemcpyAsync(hp.data(), S.sptr, sizeof(int) * hp.size(), hipMemcpyDeviceToHost,
+                               s));
+        CHM_HIP(hipStreamSynchronize(s));
+        S.stored = hp[S.nslices];
+        S.wmax = 0;
+        for (int k = 0; k < S.nslices; ++k)
+            S.wmax = std::max(S.wmax, (hp[k + 1] - hp[k]) / kSlice);
+    }
     S.col = pool.get<int>(S.stored);
     S.val = pool.get<double>(S.stored);
     int rows = S.nslices * kSlice;
