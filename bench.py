@@ -45,10 +45,12 @@ HBM_PEAK_GBS = 8000.0
 # Memory traffic of the timed kernel per launch (L2 <-> HBM/Infinity Cache) from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
 # scaled by what the same counters read for a 512 MB elementwise copy (FETCH_SIZE x 2.000,
-# WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md.  Keyed by workload and
+# WRITE_SIZE x 1.000); see profiles/k_cheb_square512_counters.md and
+# profiles/k_cheb_box96_counters.md.  Keyed by workload and
 # precision, for the default 16-bit SELL column offsets; None where the counters were not
 # taken (or the kernel changed since, or with --wide-index).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.08e6, ("square512", "fp32"): 20.48e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.08e6, ("square512", "fp32"): 20.48e6,
+                            ("box96", "fp64"): 99.87e6, ("box96", "fp32"): 58.55e6}
 
 
 def parse():
