@@ -8,7 +8,8 @@ wide_index = 1: checked over two time steps in FP64 and FP32 on a mesh large
 enough for the fine levels to take the SELL layout (400 x 400, 160,801
 vertices).  A mesh whose vertex numbering is shuffled has offsets beyond
 16 bits; the library keeps 32-bit columns for it, and a step matches the
-oracle as every other step does."""
+oracle as every other step does.  Strips whose largest offset is exactly
+32767 and 32768 pin the limit."""
 import numpy as np
 import pytest
 
@@ -84,6 +85,28 @@ def test_offsets_that_do_not_fit_keep_wide_columns():
     co, ce = shuffled_mesh(p, 5)
     g, o = Solver(co, ce, p), Oracle(co, ce, p)
     assert g.layout(-1) == (0, 4)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
+    g.set_fields(php, phn)
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros_like(php), mu_n=np.zeros_like(php))
+    gs = g.step(1)[0]
+    st = o.step(st)
+    assert gs["iters"] == st["stats"]["iters"], (gs, st["stats"])
+    got = g.get_fields()
+    for f in FIELDS:
+        assert relerr(got[f], st[f]) <= 1e-10, f
+
+
+@pytest.mark.parametrize("nx,fits", [(32765, True), (32766, False)])
+def test_offsets_at_the_16_bit_limit(nx, fits):
+    """A strip of nx x 1 unit squares: its largest column offset is nx + 2,
+    32767 (the largest that fits) or 32768 (the first that does not)."""
+    case("strip at the 16-bit offset limit", nx=nx)
+    from paper_2204_03575_amd import Solver
+    p = S.preset("square32", n=(nx, 1), extent=(float(nx), 1.0))
+    co, ce = S.make_mesh(p)
+    assert np.abs(ce[:, :, None] - ce[:, None, :]).max() == (32767 if fits else 32768)
+    g, o = Solver(co, ce, p), Oracle(co, ce, p)
+    assert g.layout(-1) == (0, 2 if fits else 4)
     php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
     g.set_fields(php, phn)
     st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros_like(php), mu_n=np.zeros_like(php))
