@@ -215,18 +215,45 @@ __global__ void k_color_check(const int *cells, int nl, int ncell, const int *in
     count_in_wave(bad, clash);
 }
 
+// cells per colour: a histogram per block in LDS, then one global atomic per
+// block and colour (a global atomic per cell serialises on the few counters)
 __global__ void k_color_count(const int *color, int ncell, int *cnt)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int h[kMaxColors];
+    for (int t = threadIdx.x; t < kMaxColors; t += blockDim.x)
+        h[t] = 0;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < ncell)
-        atomicAdd(&cnt[color[c]], 1);
+        atomicAdd(&h[color[c]], 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kMaxColors; t += blockDim.x)
+        if (h[t])
+            atomicAdd(&cnt[t], h[t]);
 }
 
+// the cells of each colour listed from cursor[colour] on: each block takes
+// one range per colour it holds (the order within a colour is free: its
+// cells share no vertex, so the scatter's sums do not depend on it)
 __global__ void k_color_fill(const int *color, int ncell, int *cursor, int *list)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int h[kMaxColors], base[kMaxColors];
+    for (int t = threadIdx.x; t < kMaxColors; t += blockDim.x)
+        h[t] = 0;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int col = -1, pos = 0;
+    if (c < ncell) {
+        col = color[c];
+        pos = atomicAdd(&h[col], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kMaxColors; t += blockDim.x)
+        if (h[t])
+            base[t] = atomicAdd(&cursor[t], h[t]);
+    __syncthreads();
     if (c < ncell)
-        list[atomicAdd(&cursor[color[c]], 1)] = c;
+        list[base[col] + pos] = c;
 }
 
 // element geometry: gradients of the barycentric coordinates and the volume
