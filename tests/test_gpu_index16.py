@@ -119,9 +119,13 @@ def test_offsets_at_the_16_bit_limit(nx, fits):
 
 
 def test_wide_index_argument_check():
-    case("wide_index must be 0 or 1")
+    case("wide_index must be 0 or 1; layout of a level that does not exist")
     from paper_2204_03575_amd import ChmError, Solver
     p = S.preset("square32", n=(4, 4), wide_index=2)
     co, ce = S.make_mesh(p)
     with pytest.raises(ChmError):
         Solver(co, ce, p)
+    g = Solver(co, ce, dict(p, wide_index=0))
+    for hier, lev in ((2, 0), (1, g.num_levels(1)), (0, -1)):
+        with pytest.raises(ChmError):
+            g.layout(hier, lev)
