@@ -234,6 +234,24 @@ int chm_get_fields(chm_solver_t *s, double *phi_p, double *phi_n, double *phi_s,
 int chm_get_fields_run(chm_solver_t *s, int32_t run, double *phi_p, double *phi_n, double *phi_s,
                        double *mu_p, double *mu_n, int32_t on_device);
 
+/* Exact checkpoint and resume.  Besides the fields of chm_get_fields_run,
+ * two things carry from one time step to the next: the history of solutions
+ * of the solve that the extrapolating starts use (chm_set_guess in chm_net.h:
+ * y1 = y_{n-1}, y2 = y_{n-2}, each a state vector of 4 n_vertices doubles in
+ * the layout of chm_get_state, with `valid` = how many of them exist, 0..2),
+ * and the run's count of completed time steps, which decides whether a step
+ * removes solvent (evap_steps).  chm_get_history copies them out (y1, y2 may
+ * be NULL; a vector past `valid` is left untouched).  chm_set_history,
+ * called after chm_set_fields_run (which starts a history of one, the new
+ * state), replaces them; a solver restored this way takes, from its next
+ * chm_step on, the iterates the uninterrupted solver would take, bit for
+ * bit.  y1 (valid >= 1) and y2 (valid = 2) are required by the set call;
+ * steps_done >= 0.  on_device: as for the fields. */
+int chm_get_history(chm_solver_t *s, int32_t run, double *y1, double *y2, int32_t *valid,
+                    int64_t *steps_done, int32_t on_device);
+int chm_set_history(chm_solver_t *s, int32_t run, const double *y1, const double *y2,
+                    int32_t valid, int64_t steps_done, int32_t on_device);
+
 int chm_destroy(chm_solver_t *s);
 
 /* Message of the last failed call on s (s = NULL: of the last failed

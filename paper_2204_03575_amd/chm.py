@@ -31,7 +31,7 @@ ENTRY_POINTS = [
     "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
-    "chm_boundary", "chm_level_layout",
+    "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -133,6 +133,8 @@ def library():
             "chm_set_fields_run": ([vp, i32, vp, vp, vp, vp, i32], C.c_int),
             "chm_get_fields_run": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
             "chm_boundary": ([vp, vp], C.c_int),
+            "chm_get_history": ([vp, i32, vp, vp, P(i32), P(i64), i32], C.c_int),
+            "chm_set_history": ([vp, i32, vp, vp, i32, i64, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -283,6 +285,27 @@ class Solver:
             err.stats = stats
             raise err
         return stats
+
+    def get_history(self, run: int = 0) -> dict:
+        """Checkpoint data beyond the fields: the last two solutions of the
+        solve (CUDA tensors, state-vector layout; None past `valid`), how
+        many are valid, and the run's completed steps."""
+        torch = self.torch
+        y1 = torch.empty(4 * self.nv, dtype=torch.float64, device="cuda")
+        y2 = torch.empty_like(y1)
+        valid, steps = C.c_int32(), C.c_int64()
+        rc = self.lib.chm_get_history(self.h, run, _dev_ptr(y1), _dev_ptr(y2), C.byref(valid),
+                                      C.byref(steps), 1)
+        _check(self.h, rc, "chm_get_history")
+        return dict(y1=y1 if valid.value >= 1 else None, y2=y2 if valid.value >= 2 else None,
+                    valid=valid.value, steps=steps.value)
+
+    def set_history(self, hist: dict, run: int = 0):
+        """Restore what get_history returned (after set_fields)."""
+        ptr = lambda t: None if t is None else _dev_ptr(t)
+        rc = self.lib.chm_set_history(self.h, run, ptr(hist["y1"]), ptr(hist["y2"]),
+                                      int(hist["valid"]), int(hist["steps"]), 1)
+        _check(self.h, rc, "chm_set_history")
 
     def set_guess(self, mode: str, net=None, H: int = 0, W: int = 0):
         rc = self.lib.chm_set_guess(self.h, GUESS_MODES[mode], net.h if net is not None else None,

@@ -186,6 +186,8 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         S.nb = runs;
         S.nrun = 1;
         S.runs.resize(runs);
+        S.hist.assign(runs, 0);
+        S.steps.assign(runs, 0);
         for (int r = 0; r < runs; ++r) {
             chm::RunPrm &P = S.runs[r];
             if (run_params) {
@@ -277,11 +279,10 @@ int chm_set_fields_run(chm_solver_t *h, int32_t run, const double *phi_p, const 
             copy_field(S, xr + n, 0, mu_p, on_device);
         if (mu_n)
             copy_field(S, xr + n, 1, mu_n, on_device);
-        // the new state starts the history of solutions (of every run: the
-        // runs of a batch share it)
+        // the new state starts this run's history of solutions
         CHM_HIP(hipMemcpyAsync(S.yh1 + (size_t)run * 2 * n, xr, sizeof(double2) * 2 * (size_t)n,
                                hipMemcpyDeviceToDevice, S.stream));
-        S.hist = 1;
+        S.hist[run] = 1;
         CHM_HIP(hipStreamSynchronize(S.stream));
         return CHM_OK;
     });
@@ -333,6 +334,56 @@ int chm_get_fields_run(chm_solver_t *h, int32_t run, double *phi_p, double *phi_
         if (mu_n)
             get_field(S, mu_n, xr + n, 1, on_device);
         CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_get_history(chm_solver_t *h, int32_t run, double *y1, double *y2, int32_t *valid,
+                    int64_t *steps_done, int32_t on_device)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_get_history: NULL handle");
+    if (run < 0 || run >= h->s.nb)
+        return fail(h, CHM_EINVAL, "chm_get_history: run out of range");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        const size_t bytes = sizeof(double2) * 2 * (size_t)S.nv;
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        const int have = S.hist[run];
+        if (y1 && have >= 1)
+            CHM_HIP(hipMemcpyAsync(y1, S.yh1 + (size_t)run * 2 * S.nv, bytes, kind, S.stream));
+        if (y2 && have >= 2)
+            CHM_HIP(hipMemcpyAsync(y2, S.yh2 + (size_t)run * 2 * S.nv, bytes, kind, S.stream));
+        if (valid)
+            *valid = have;
+        if (steps_done)
+            *steps_done = S.steps[run];
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        return CHM_OK;
+    });
+}
+
+int chm_set_history(chm_solver_t *h, int32_t run, const double *y1, const double *y2,
+                    int32_t valid, int64_t steps_done, int32_t on_device)
+{
+    if (!h)
+        return fail(nullptr, CHM_EINVAL, "chm_set_history: NULL handle");
+    if (run < 0 || run >= h->s.nb)
+        return fail(h, CHM_EINVAL, "chm_set_history: run out of range");
+    if (valid < 0 || valid > 2 || steps_done < 0 || (valid >= 1 && !y1) || (valid == 2 && !y2))
+        return fail(h, CHM_EINVAL, "chm_set_history: need 0 <= valid <= 2 with y1 (and y2) "
+                                   "given, and steps_done >= 0");
+    return guarded(h, [&]() {
+        chm::Solver &S = h->s;
+        const size_t bytes = sizeof(double2) * 2 * (size_t)S.nv;
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        if (valid >= 1)
+            CHM_HIP(hipMemcpyAsync(S.yh1 + (size_t)run * 2 * S.nv, y1, bytes, kind, S.stream));
+        if (valid >= 2)
+            CHM_HIP(hipMemcpyAsync(S.yh2 + (size_t)run * 2 * S.nv, y2, bytes, kind, S.stream));
+        CHM_HIP(hipStreamSynchronize(S.stream));
+        S.hist[run] = valid;
+        S.steps[run] = steps_done;
         return CHM_OK;
     });
 }
@@ -628,7 +679,7 @@ int chm_get_state(chm_solver_t *h, int32_t which, double *state)
         return fail(h, CHM_EINVAL, "chm_get_state: bad arguments");
     return guarded(h, [&]() {
         chm::Solver &S = h->s;
-        if (which == 1 && S.hist < 1)
+        if (which == 1 && S.hist[0] < 1)
             throw chm::Failure(CHM_EINVAL, "chm_get_state: no solution yet");
         CHM_HIP(hipMemcpyAsync(state, which == 0 ? S.x : S.yh1, sizeof(double2) * 2 * (size_t)S.nv,
                                hipMemcpyDeviceToDevice, S.stream));

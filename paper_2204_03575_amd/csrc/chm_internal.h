@@ -287,7 +287,7 @@ struct Solver {
     Ctl *ctl = nullptr;        // device, one per run
     Ctl *hctl = nullptr;       // pinned host mirror (heads), one per run
     int *dheads = nullptr;     // device staging of the heads of a batch
-    int64_t step_count = 0;
+    std::vector<int64_t> steps;   // per run: completed time steps (the solvent removal counts them)
     double setup_ms = 0.0;
     Timer timer;
     std::string nan_where;     // where the last CHM_ENAN was detected
@@ -302,7 +302,7 @@ struct Solver {
     // the last two solutions of the Krylov solve (before solvent removal):
     // yh1 = y_{n-1}, yh2 = y_{n-2}; after chm_set_fields yh1 is the new state
     double2 *yh1 = nullptr, *yh2 = nullptr;
-    int hist = 0;              // how many of yh1, yh2 are valid
+    std::vector<int> hist;     // per run: how many of yh1, yh2 are valid
     // MINRES (krylov = CHM_KRYLOV_MINRES): six block vectors per run (r1, r2,
     // y, v, w1, w2) and the per-run recurrence scalars, with a pinned mirror
     double2 *mr = nullptr;

@@ -662,12 +662,18 @@ __global__ void __launch_bounds__(kBlock) k_extrapolate(int len, const double2 *
 // state x (code 0), the linear extrapolation xl (code 1; may be null) and the
 // network's guess xg (code 2; may be null), from the partial sums in
 // pg[code * kRedBlocks + g]; ties and non-finite norms keep the earlier code.
+// A run without two solutions in its history (mask) keeps code 0.
 // The chosen start goes to out (which may alias xl or xg), the codes to the
 // control block.
+// runs whose history holds two solutions (the others start from the previous state)
+struct RunMask {
+    int ok[kMaxRuns];
+};
+
 __global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *__restrict__ x,
                                                        const double2 *xl, const double2 *xg,
                                                        const double2 *__restrict__ pg, int G,
-                                                       double2 *out, Ctl *c)
+                                                       double2 *out, Ctl *c, RunMask mask)
 {
     __shared__ double2 nrm[3];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -691,6 +697,10 @@ __global__ void __launch_bounds__(kBlock) k_pick_guess(int len, const double2 *_
     __syncthreads();
     int cx = 0, cy = 0;
     double bx = nrm[0].x, by = nrm[0].y;
+    if (!mask.ok[blockIdx.y]) {
+        xl = nullptr;
+        xg = nullptr;
+    }
     if (xl) {
         if (nrm[1].x < bx) { cx = 1; bx = nrm[1].x; }
         if (nrm[1].y < by) { cy = 1; by = nrm[1].y; }
@@ -956,7 +966,13 @@ int step_once(Solver &S, chm_stats_t *st_out)
     compute_rhs(S);
     k_dot<double><<<grid(Gv, R), kBlock, 0, st>>>(len, S.b, S.b, slot(S, kSlotB));
     k_tol<<<grid(1, R), kBlock, 0, st>>>(S.ctl, slot(S, kSlotB), Gv, S.prm.rtol);
-    if (S.guess_mode != CHM_GUESS_PREVIOUS && S.hist >= 2) {
+    RunMask mask{};
+    bool any_hist = false;
+    for (int r = 0; r < R; ++r) {
+        mask.ok[r] = S.hist[r] >= 2;
+        any_hist = any_hist || mask.ok[r];
+    }
+    if (S.guess_mode != CHM_GUESS_PREVIOUS && any_hist) {
         // candidate starts from the last two solutions: linear extrapolation
         // and, in the learned mode, the network's guess; each species starts
         // from whichever of them and the previous state has the smallest
@@ -969,7 +985,8 @@ int step_once(Solver &S, chm_stats_t *st_out)
         k_extrapolate<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.yh2, S.yh1, S.xl);
         if (learned)
             for (int r = 0; r < R; ++r)
-                net_guess_on(S.net, st, S.gH, S.gW,
+                if (mask.ok[r])
+                    net_guess_on(S.net, st, S.gH, S.gW,
                              reinterpret_cast<const double *>(S.yh2 + (size_t)r * len),
                              reinterpret_cast<const double *>(S.yh1 + (size_t)r * len),
                              reinterpret_cast<double *>(xg + (size_t)r * len));
@@ -978,7 +995,7 @@ int step_once(Solver &S, chm_stats_t *st_out)
             if (cand[k])
                 saddle_resid(S, grid(Gn, R), cand[k], S.r, slot(S, kSlotGuess + k), 0.0);
         k_pick_guess<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xl, xg, slot(S, kSlotGuess),
-                                                            Gn, S.xk, S.ctl);
+                                                            Gn, S.xk, S.ctl, mask);
     } else {
         k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.x, S.xk);
     }
@@ -1112,20 +1129,22 @@ int step_once(Solver &S, chm_stats_t *st_out)
     if (rc == CHM_OK) {
         std::swap(S.yh1, S.yh2);   // y_{n-1} becomes y_{n-2}
         k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.yh1);
-        S.hist = std::min(S.hist + 1, 2);
+        for (int r = 0; r < R; ++r)
+            S.hist[r] = std::min(S.hist[r] + 1, 2);
         k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.x);
         Evap e{};
         bool evap = false;
         for (int r = 0; r < R; ++r) {
             const RunPrm &P = S.runs[r];
-            e.ds[r] = (P.evap_ds > 0.0 && S.step_count < P.evap_steps) ? P.evap_ds : 0.0;
+            e.ds[r] = (P.evap_ds > 0.0 && S.steps[r] < P.evap_steps) ? P.evap_ds : 0.0;
             evap = evap || e.ds[r] > 0.0;
         }
         if (evap)
             k_evaporate<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.x, e);
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(st));
-        S.step_count++;
+        for (int r = 0; r < R; ++r)
+            S.steps[r]++;
     }
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
