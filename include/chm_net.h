@@ -118,6 +118,24 @@ int chm_net_adam(chm_net_t *net, const float *grads, float lr);
 int chm_net_guess(chm_net_t *net, int32_t H, int32_t W, const double *x2, const double *x1,
                   double *guess);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the guess
+ * of chm_net_guess with every work buffer (frame statistics, features,
+ * hidden activations, network output) in one fixed device array that the
+ * library holds on each GPU it runs on until the process ends (about 11 MB),
+ * instead of the network's own buffers.  The same kernels in the same order,
+ * so the same bits as chm_net_guess.  The network's max_pixels does not
+ * limit it; H * W must be at most CHM_NET_NOALLOC_MAX_PIXELS (a 257 x 257
+ * vertex grid), else CHM_EINVAL.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  The work is enqueued on the network's stream and the
+ * call returns without waiting for it (synchronise the stream before
+ * reading guess).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (from any network, stream or thread) race, so the
+ * caller serialises them. */
+#define CHM_NET_NOALLOC_MAX_PIXELS 66049
+int chm_net_guess_noalloc(chm_net_t *net, int32_t H, int32_t W, const double *x2,
+                          const double *x1, double *guess);
+
 /* One training step on a batch of crops: sample i takes the device state
  * vectors x2[i], x1[i], x0[i] (steps n-2, n-1, n of one run on the H x W
  * grid; the arrays of pointers are host arrays), the crop of crop_h x crop_w

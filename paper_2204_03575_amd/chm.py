@@ -32,6 +32,7 @@ ENTRY_POINTS = [
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
     "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history",
+    "chm_net_guess_noalloc",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -124,6 +125,7 @@ def library():
                                   C.c_int),
             "chm_net_adam": ([vp, vp, C.c_float], C.c_int),
             "chm_net_guess": ([vp, i32, i32, vp, vp, vp], C.c_int),
+            "chm_net_guess_noalloc": ([vp, i32, i32, vp, vp, vp], C.c_int),
             "chm_net_train_step": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, C.c_float,
                                     C.c_float, P(d)], C.c_int),
             "chm_set_guess": ([vp, i32, vp, i32, i32], C.c_int),
@@ -555,6 +557,13 @@ class Net:
         out = self.torch.empty_like(x1)
         self._check(self.lib.chm_net_guess(self.h, H, W, _dev_ptr(x2), _dev_ptr(x1), _dev_ptr(out)),
                     "chm_net_guess")
+        return out
+
+    def guess_noalloc(self, H: int, W: int, x2, x1, out):
+        """chm_net_guess_noalloc into the caller's tensor `out`; enqueued on
+        the network's stream (the caller synchronises)."""
+        self._check(self.lib.chm_net_guess_noalloc(self.h, H, W, _dev_ptr(x2), _dev_ptr(x1),
+                                                   _dev_ptr(out)), "chm_net_guess_noalloc")
         return out
 
     def train_step(self, H: int, W: int, crop_h: int, crop_w: int, x2s, x1s, x0s, oy, ox,

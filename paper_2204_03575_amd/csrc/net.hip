@@ -14,6 +14,7 @@
 // fixed grid and a fixed summation order: results are bitwise reproducible.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "device_util.h"
 
@@ -632,20 +633,29 @@ void check_shape(const chm_net &N, long batch, long h, long w)
         throw Failure(CHM_EINVAL, "batch * h * w exceeds the network's max_pixels");
 }
 
-// act[0] holds the BF16 features of npx = B H W pixels; y receives the output
-void forward(chm_net &N, hipStream_t st, int B, int H, int W)
+// The four layers over npx = B H W pixels: features a0 -> a1 -> a2 -> a3 ->
+// output y (a3 may alias a1)
+void forward_on(chm_net &N, hipStream_t st, int B, int H, int W, const bf16_t *a0, bf16_t *a1,
+                bf16_t *a2, bf16_t *a3, float *y)
 {
     const long npx = (long)B * H * W;
     const int g = nblk_l(npx);
-    k_conv_fwd<8, 32, true><<<g, kBlock, 0, st>>>(B, H, W, N.act[0], N.wf[0], N.params + b_offset(0),
-                                                  N.act[1], nullptr);
-    k_conv_fwd<32, 32, true><<<g, kBlock, 0, st>>>(B, H, W, N.act[1], N.wf[1], N.params + b_offset(1),
-                                                   N.act[2], nullptr);
-    k_conv_fwd<32, 32, true><<<g, kBlock, 0, st>>>(B, H, W, N.act[2], N.wf[2], N.params + b_offset(2),
-                                                   N.act[3], nullptr);
-    k_conv_fwd<32, 4, false><<<g, kBlock, 0, st>>>(B, H, W, N.act[3], N.wf[3], N.params + b_offset(3),
-                                                   nullptr, N.y);
+    k_conv_fwd<8, 32, true><<<g, kBlock, 0, st>>>(B, H, W, a0, N.wf[0], N.params + b_offset(0), a1,
+                                                  nullptr);
+    k_conv_fwd<32, 32, true><<<g, kBlock, 0, st>>>(B, H, W, a1, N.wf[1], N.params + b_offset(1), a2,
+                                                   nullptr);
+    k_conv_fwd<32, 32, true><<<g, kBlock, 0, st>>>(B, H, W, a2, N.wf[2], N.params + b_offset(2), a3,
+                                                   nullptr);
+    k_conv_fwd<32, 4, false><<<g, kBlock, 0, st>>>(B, H, W, a3, N.wf[3], N.params + b_offset(3),
+                                                   nullptr, y);
     CHM_HIP(hipGetLastError());
+}
+
+// act[0] holds the BF16 features of npx = B H W pixels; y receives the output
+// (the activations stay in act[1..3] for the backward pass)
+void forward(chm_net &N, hipStream_t st, int B, int H, int W)
+{
+    forward_on(N, st, B, H, W, N.act[0], N.act[1], N.act[2], N.act[3], N.y);
 }
 
 template <int CI, int CO>
@@ -724,15 +734,118 @@ void upload_batch(chm_net &N, hipStream_t st, int S, const double *const *x2,
     CHM_HIP(hipGetLastError());
 }
 
+// Where the guess of one H x W frame keeps its work: the sample tables
+// (pointers, crop origin, masked count; `cap` samples each), the frame
+// statistics, the features, two hidden activations and the output.
+struct GuessBufs {
+    const double **ptrs;
+    int *crop, *msum, cap;
+    double *stats;
+    bf16_t *feat, *h1, *h2;
+    float *y;
+};
+
+// features of (x2, x1) over the whole H x W grid into B.feat; stats of sample 0
+void features_into(hipStream_t st, int H, int W, const double *x2, const double *x1,
+                   const GuessBufs &B)
+{
+    BatchPtrs b{};
+    b.x2[0] = x2;
+    b.x1[0] = x1;
+    k_set_batch<<<1, kPtrBatch, 0, st>>>(b, 0, 1, B.cap, B.ptrs, B.crop, B.msum);
+    k_stats<<<1, kBlock, 0, st>>>((long)H * W, B.ptrs, B.ptrs + B.cap, nullptr, B.stats);
+    k_pack<<<nblk_l((long)H * W), kBlock, 0, st>>>(1, H, W, H, W, B.cap, B.ptrs, B.crop, B.stats,
+                                                   B.feat, nullptr, nullptr);
+    CHM_HIP(hipGetLastError());
+}
+
+GuessBufs own_bufs(chm_net &N)
+{
+    return GuessBufs{N.ptrs, N.crop, N.msum, kMaxBatch, N.stats, N.act[0], N.act[1], N.act[2], N.y};
+}
+
 // features of (x2, x1) over the whole H x W grid into act[0]; stats of sample 0
 void full_features(chm_net &N, hipStream_t st, int H, int W, const double *x2, const double *x1)
 {
     check_shape(N, 1, H, W);
-    upload_batch(N, st, 1, &x2, &x1, nullptr, nullptr, nullptr, nullptr);
-    k_stats<<<1, kBlock, 0, st>>>((long)H * W, N.ptrs, N.ptrs + kMaxBatch, nullptr, N.stats);
-    k_pack<<<nblk_l((long)H * W), kBlock, 0, st>>>(1, H, W, H, W, kMaxBatch, N.ptrs, N.crop, N.stats,
-                                                   N.act[0], nullptr, nullptr);
+    features_into(st, H, W, x2, x1, own_bufs(N));
+}
+
+// the guess of one frame: features, the network, x1 + d + sigma y
+void guess_into(chm_net &N, hipStream_t st, int H, int W, const double *x2, const double *x1,
+                double *out, const GuessBufs &B)
+{
+    features_into(st, H, W, x2, x1, B);
+    forward_on(N, st, 1, H, W, B.feat, B.h1, B.h2, B.h1, B.y);
+    const long n = (long)H * W;
+    k_guess<<<nblk_l(4 * n), kBlock, 0, st>>>(n, x2, x1, B.y, B.stats, out);
     CHM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ allocation-free guess
+// The work buffers of chm_net_guess_noalloc live in one fixed device array,
+// `scratch`, which every GPU the library runs on holds for the life of the
+// process: a header (sample tables and frame statistics), then the features,
+// two hidden activations and the output of at most kNoAllocPixels pixels.
+// In host code `scratch` names a host-side stand-in, so its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is ever handed to kernels.  Nothing in it needs to
+// start at zero: every kernel of the guess writes what the next one reads.
+constexpr long kNoAllocPixels = CHM_NET_NOALLOC_MAX_PIXELS;
+constexpr size_t kScratchHead = 1024;
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kFeatBytes = align256(kNoAllocPixels * 8 * sizeof(bf16_t));
+constexpr size_t kHidBytes = align256(kNoAllocPixels * 32 * sizeof(bf16_t));
+constexpr size_t kOutBytes = align256(kNoAllocPixels * 4 * sizeof(float));
+constexpr size_t kScratchBytes = kScratchHead + kFeatBytes + 2 * kHidBytes + kOutBytes;
+static_assert(3 * sizeof(double *) + 3 * sizeof(int) + kStat * sizeof(double) + 64 <= kScratchHead,
+              "scratch header");
+
+}  // namespace
+}  // namespace chm
+
+static __device__ __align__(256) unsigned char scratch[chm::kScratchBytes];
+
+namespace chm {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on first use)
+void *scratch_address()
+{
+    int dev = 0;
+    CHM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        throw Failure(CHM_EINVAL, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        CHM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            throw Failure(CHM_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
+}
+
+// the guess buffers carved out of the scratch array at base
+GuessBufs scratch_bufs(void *base)
+{
+    unsigned char *b = static_cast<unsigned char *>(base);
+    GuessBufs g;
+    g.ptrs = reinterpret_cast<const double **>(b);
+    g.crop = reinterpret_cast<int *>(b + 3 * sizeof(double *));
+    g.msum = g.crop + 2;
+    g.cap = 1;
+    g.stats = reinterpret_cast<double *>(b + 64);
+    g.feat = reinterpret_cast<bf16_t *>(b + kScratchHead);
+    g.h1 = reinterpret_cast<bf16_t *>(b + kScratchHead + kFeatBytes);
+    g.h2 = reinterpret_cast<bf16_t *>(b + kScratchHead + kFeatBytes + kHidBytes);
+    g.y = reinterpret_cast<float *>(b + kScratchHead + kFeatBytes + 2 * kHidBytes);
+    return g;
 }
 
 thread_local std::string g_net_create_error;
@@ -768,12 +881,8 @@ long long net_max_pixels(const chm_net *net) { return net ? net->max_px : 0; }
 void net_guess_on(chm_net *net, hipStream_t st, int H, int W, const double *x2, const double *x1,
                   double *out)
 {
-    chm_net &N = *net;
-    full_features(N, st, H, W, x2, x1);
-    forward(N, st, 1, H, W);
-    const long n = (long)H * W;
-    k_guess<<<nblk_l(4 * n), kBlock, 0, st>>>(n, x2, x1, N.y, N.stats, out);
-    CHM_HIP(hipGetLastError());
+    check_shape(*net, 1, H, W);
+    guess_into(*net, st, H, W, x2, x1, out, own_bufs(*net));
 }
 
 }  // namespace chm
@@ -830,6 +939,7 @@ int chm_net_create(int64_t max_pixels, void *stream, chm_net_t **out)
         CHM_HIP(hipMemsetAsync(N->adam_v, 0, sizeof(float) * CHM_NET_NPARAMS, st));
         refresh_bf16(*N, st);
         CHM_HIP(hipStreamSynchronize(st));
+        (void)scratch_address();   // the allocation-free guess's array on this device
         return CHM_OK;
     });
     if (rc != CHM_OK) {
@@ -983,6 +1093,23 @@ int chm_net_guess(chm_net_t *net, int32_t H, int32_t W, const double *x2, const 
     return net_guarded(net, [&]() {
         chm::net_guess_on(net, net->stream, H, W, x2, x1, guess);
         CHM_HIP(hipStreamSynchronize(net->stream));
+        return CHM_OK;
+    });
+}
+
+int chm_net_guess_noalloc(chm_net_t *net, int32_t H, int32_t W, const double *x2,
+                          const double *x1, double *guess)
+{
+    if (!net || !x2 || !x1 || !guess)
+        return net_fail(net, CHM_EINVAL, "chm_net_guess_noalloc: bad arguments");
+    if (H < 2 || W < 2 || (int64_t)H * W > CHM_NET_NOALLOC_MAX_PIXELS)
+        return net_fail(net, CHM_EINVAL,
+                        "chm_net_guess_noalloc: need H, W >= 2 and H * W <= "
+                        "CHM_NET_NOALLOC_MAX_PIXELS (" +
+                            std::to_string(CHM_NET_NOALLOC_MAX_PIXELS) + ")");
+    return net_guarded(net, [&]() {
+        using namespace chm;
+        guess_into(*net, net->stream, H, W, x2, x1, guess, scratch_bufs(scratch_address()));
         return CHM_OK;
     });
 }
