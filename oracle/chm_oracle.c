@@ -13,6 +13,27 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Host threads.  The row loops of the solve (sparse products, smoothing,    */
+/* vector updates) may be split over threads by OpenMP with a static        */
+/* schedule: each row is still computed by one thread with the same          */
+/* operations in the same order, and every sum over rows (dot products,      */
+/* norms) stays a serial loop, so the results are bitwise the same for any   */
+/* thread count.                                                              */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 #define MAXLEV 32
 
@@ -65,6 +86,7 @@ static void csr_free(csr_t *a)
 
 static void csr_mv(const csr_t *a, const double *x, double *y)
 {
+    #pragma omp parallel for schedule(static) if (a->n >= 4096)
     for (int i = 0; i < a->n; ++i) {
         double s = 0.0;
         for (int k = a->rp[i]; k < a->rp[i + 1]; ++k)
@@ -838,6 +860,7 @@ static void smooth(const orc_params_t *prm, const hier_t *h, const level_t *L, c
         double omega = 4.0 / (3.0 * L->rho);
         for (int it = 0; it < h->degree; ++it) {
             csr_mv(&L->A, x, r);
+            #pragma omp parallel for schedule(static) if (n >= 4096)
             for (int i = 0; i < n; ++i)
                 x[i] += omega * L->invdiag[i] * (b[i] - r[i]);
         }
@@ -847,15 +870,18 @@ static void smooth(const orc_params_t *prm, const hier_t *h, const level_t *L, c
     double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     double sigma = theta / delta, rho_old = 1.0 / sigma;
     csr_mv(&L->A, x, r);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         d[i] = L->invdiag[i] * (b[i] - r[i]) / theta;
     for (int k = 1; k <= h->degree; ++k) {
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             x[i] += d[i];
         if (k == h->degree)
             break;
         csr_mv(&L->A, x, r);
         double rho = 1.0 / (2.0 * sigma - rho_old);
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             d[i] = rho * rho_old * d[i] + (2.0 * rho / delta) * L->invdiag[i] * (b[i] - r[i]);
         rho_old = rho;
@@ -894,15 +920,18 @@ static void vcycle(const orc_params_t *prm, const hier_t *h, int l, const double
     double *bc = malloc(sizeof(double) * (size_t)L->nc);
     double *xc = malloc(sizeof(double) * (size_t)L->nc);
     double *e = malloc(sizeof(double) * (size_t)n);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         x[i] = 0.0;
     smooth(prm, h, L, b, x, r, d);
     csr_mv(&L->A, x, r);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         r[i] = b[i] - r[i];
     csr_mv(&L->R, r, bc);
     vcycle(prm, h, l + 1, bc, xc);
     csr_mv(&L->P, xc, e);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         x[i] += e[i];
     smooth(prm, h, L, b, x, r, d);
@@ -927,11 +956,13 @@ static void amg_stationary(const orc_params_t *prm, const hier_t *h, const doubl
     const double bnorm = prm->amg_tol > 0.0 ? sqrt(dot(n, b, b)) : 0.0;
     for (int c = 1; c < prm->amg_cycles; ++c) {
         csr_mv(&h->lev[0].A, x, r);
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             r[i] = b[i] - r[i];
         if (prm->amg_tol > 0.0 && sqrt(dot(n, r, r)) <= prm->amg_tol * bnorm)
             break;
         vcycle(prm, h, 0, r, e);
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             x[i] += e[i];
     }
@@ -949,6 +980,7 @@ static void amg_pcg(const orc_params_t *prm, const hier_t *h, int k, const doubl
     const csr_t *A = &h->lev[0].A;
     double *r = calloc((size_t)n + 1, sizeof(double)), *z = malloc(sizeof(double) * (size_t)n);
     double *d = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i) {
         x[i] = 0.0;
         r[i] = b[i];
@@ -960,6 +992,7 @@ static void amg_pcg(const orc_params_t *prm, const hier_t *h, int k, const doubl
         csr_mv(A, d, q);
         double dq = dot(n, d, q);
         double alpha = dq != 0.0 ? rz / dq : 0.0;
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i) {
             x[i] += alpha * d[i];
             r[i] -= alpha * q[i];
@@ -969,6 +1002,7 @@ static void amg_pcg(const orc_params_t *prm, const hier_t *h, int k, const doubl
         vcycle(prm, h, 0, r, z);
         double rz_new = dot(n, r, z);
         double beta = rz != 0.0 ? rz_new / rz : 0.0;
+        #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             d[i] = z[i] + beta * d[i];
         rz = rz_new;
@@ -1002,10 +1036,12 @@ static void saddle(const orc_solver_t *s, int sp, const double *x, double *y)
     double *a = malloc(sizeof(double) * (size_t)n), *b = malloc(sizeof(double) * (size_t)n);
     csr_mv(&s->M, x, a);
     csr_mv(&s->K, x + n, b);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         y[i] = a[i] + t * b[i];
     csr_mv(&s->K, x, a);
     csr_mv(&s->M, x + n, b);
+    #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         y[n + i] = t * a[i] - te * b[i];
     free(a);
@@ -1058,6 +1094,7 @@ static int fgmres(const orc_solver_t *s, int sp, const double *b, double *x, int
     double res = 0.0;
     for (;;) {
         saddle(s, sp, x, r);
+        #pragma omp parallel for schedule(static) if (n2 >= 4096)
         for (int i = 0; i < n2; ++i)
             r[i] = b[i] - r[i];
         double beta = sqrt(dot(n2, r, r));
@@ -1072,6 +1109,7 @@ static int fgmres(const orc_solver_t *s, int sp, const double *b, double *x, int
             rc = ORC_ENOCONV;
             break;
         }
+        #pragma omp parallel for schedule(static) if (n2 >= 4096)
         for (int i = 0; i < n2; ++i)
             V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i)
@@ -1085,14 +1123,17 @@ static int fgmres(const orc_solver_t *s, int sp, const double *b, double *x, int
             for (int i = 0; i <= j; ++i) {
                 double hij = dot(n2, w, V + (size_t)i * n2);
                 H[i * m + j] = hij;
+                #pragma omp parallel for schedule(static) if (n2 >= 4096)
                 for (int t = 0; t < n2; ++t)
                     w[t] -= hij * V[(size_t)i * n2 + t];
             }
             double hn = sqrt(dot(n2, w, w));
             H[(j + 1) * m + j] = hn;
-            if (hn > 0.0)
+            if (hn > 0.0) {
+                #pragma omp parallel for schedule(static) if (n2 >= 4096)
                 for (int t = 0; t < n2; ++t)
                     w[t] /= hn;
+            }
             for (int i = 0; i < j; ++i) {
                 double a = H[i * m + j], c = H[(i + 1) * m + j];
                 H[i * m + j] = cs[i] * a + sn[i] * c;
@@ -1128,9 +1169,11 @@ static int fgmres(const orc_solver_t *s, int sp, const double *b, double *x, int
                 v -= H[i * m + t] * y[t];
             y[i] = v / H[i * m + i];
         }
-        for (int i = 0; i < k; ++i)
+        for (int i = 0; i < k; ++i) {
+            #pragma omp parallel for schedule(static) if (n2 >= 4096)
             for (int t = 0; t < n2; ++t)
                 x[t] += y[i] * Z[(size_t)i * n2 + t];
+        }
     }
     *iters = total;
     *relres = bnorm > 0.0 ? res / bnorm : res;

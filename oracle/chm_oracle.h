@@ -153,6 +153,10 @@ int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun
              orc_stats_t *st);
 double orc_energy(const orc_solver_t *s, const double *php, const double *phn);
 
+/* Host threads of the solve's row loops (n > 0 sets them; returns the count in
+ * use).  Results do not depend on it. */
+int orc_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

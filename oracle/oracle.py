@@ -52,11 +52,13 @@ class orc_stats_t(C.Structure):
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no OpenMP, no vectorisation flags)."""
+    """Compile the oracle with gcc (plain -O2; OpenMP only splits row loops
+    over host threads, see orc_threads)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.run(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                        "-Wall", "-Wno-unused-function", "-o", tmp, SRC, "-lm"], check=True)
+                        "-fopenmp", "-Wall", "-Wno-unused-function", "-o", tmp, SRC, "-lm"],
+                       check=True)
         os.replace(tmp, LIB)
     return LIB
 
@@ -98,6 +100,8 @@ def load_library():
         lib.orc_step.argtypes = [vp, vp, vp, vp, vp, P(orc_stats_t)]
         lib.orc_energy.argtypes = [vp, vp, vp]
         lib.orc_energy.restype = d
+        lib.orc_threads.argtypes = [C.c_int]
+        lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -175,6 +179,12 @@ def potential(p: dict, php: float, phn: float):
     if rc:
         raise OracleError(rc, "orc_potential")
     return f.value, fp.value, fn.value
+
+
+def threads(n: int = 0) -> int:
+    """Host threads of the oracle's row loops (n > 0 sets them); the results
+    are bitwise the same for any count."""
+    return load_library().orc_threads(int(n))
 
 
 class Oracle:

@@ -52,6 +52,12 @@ def relerr(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
+def maxrel(a, b):
+    """elementwise: max |a - b| over max |b| (a single bad vertex cannot hide
+    in a 2-norm over many)"""
+    mb = np.abs(b).max()
+    return np.abs(a - b).max() / (mb if mb > 0 else 1.0)
+
 
 MESHES = [
     dict(n=(32, 32)),                                   # the 32x32 square
@@ -141,6 +147,8 @@ def run_pair(p, co, ce, g, o, steps, php=None, phn=None):
         for f in FIELDS:
             e = relerr(got[f], st[f])
             assert e <= 1e-10, (k, f, e)
+            e = maxrel(got[f], st[f])
+            assert e <= 1e-10, (k, f, "elementwise", e)
         assert np.allclose(got["phi_s"], 1 - got["phi_p"] - got["phi_n"], atol=1e-15)
         # hand the oracle's state back so each step starts from identical inputs
         g.set_fields(st["phi_p"], st["phi_n"], st["mu_p"], st["mu_n"])
@@ -171,6 +179,7 @@ def test_square32_free_running_trajectory():
     got = g.get_fields()
     for f in FIELDS:
         assert relerr(got[f], st[f]) <= 1e-10, f
+        assert maxrel(got[f], st[f]) <= 1e-10, (f, "elementwise")
     assert all(s["relres"][0] <= p["rtol"] and s["relres"][1] <= p["rtol"] for s in stats)
 
 

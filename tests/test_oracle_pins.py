@@ -638,3 +638,24 @@ def test_algorithm1_with_accurate_inner_solves():
     w2 = spla.spsolve(As, M @ spla.spsolve(As, v[n:]))
     assert np.linalg.norm(w[:n] - w1) < 1e-10 * np.linalg.norm(w1)
     assert np.linalg.norm(w[n:] - w2) < 1e-9 * np.linalg.norm(w2)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The oracle splits its row loops over host threads; each row keeps its
+    operations and every sum over rows stays serial, so a step is bitwise the
+    same on one thread and on several."""
+    p = S.preset("square32", n=(72, 64))
+    co, ce = S.make_mesh(p)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros_like(php), mu_n=np.zeros_like(php))
+    before = O.threads()
+    out = {}
+    try:
+        for nt in (1, 4):
+            O.threads(nt)
+            out[nt] = Oracle(co, ce, p).step(st)
+    finally:
+        O.threads(before)
+    assert out[1]["stats"]["iters"] == out[4]["stats"]["iters"]
+    for f in ("phi_p", "phi_n", "mu_p", "mu_n"):
+        assert np.array_equal(out[1][f], out[4][f]), f
