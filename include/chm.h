@@ -164,6 +164,15 @@ typedef struct {
      * of 4 in the kernels' traffic); 1 keeps 32-bit columns everywhere.  The
      * results are bitwise the same. */
     int32_t wide_index;
+    /* Batches (chm_create_batch): how many runs one lane of the SELL-64
+     * kernels (fine-level smoothing and products, the saddle-point operator)
+     * and of the coarsest-level solve serves: each matrix entry the lane
+     * loads is used for that many runs, so a launch over R runs streams the
+     * matrix ceil(R / runs_per_lane) times.  1, 2 or 4; 0 = 2.  Every run's
+     * arithmetic is the same for any value (bitwise the same results); it
+     * trades matrix traffic against registers per lane.  Ignored for one
+     * run. */
+    int32_t runs_per_lane;
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -226,6 +235,18 @@ int chm_set_fields_run(chm_solver_t *s, int32_t run, const double *phi_p, const 
  * every run is left at the last completed step and the failing step's stats
  * are filled. */
 int chm_step(chm_solver_t *s, int32_t nsteps, chm_stats_t *stats);
+
+/* Advance several solvers (for example the batches of a parameter sweep,
+ * one per mesh size) by nsteps time steps each, concurrently: one host thread
+ * per solver, so that the launches of solvers on different HIP streams
+ * overlap on the GPU (solvers that share a stream serialise on it).  The
+ * handles must be distinct.  stats: NULL, or `count` pointers, each NULL or
+ * room for nsteps * runs entries of that solver (as chm_step).  codes: NULL
+ * or `count` entries receiving each solver's return code.  Returns CHM_OK, or
+ * the code of the first failing solver in handle order (its chm_last_error
+ * holds the message).  Each solver takes the iterates it takes in chm_step. */
+int chm_step_many(chm_solver_t *const *solvers, int32_t count, int32_t nsteps,
+                  chm_stats_t *const *stats, int32_t *codes);
 
 /* Copy out the state (of run 0); any pointer may be NULL. */
 int chm_get_fields(chm_solver_t *s, double *phi_p, double *phi_n, double *phi_s,

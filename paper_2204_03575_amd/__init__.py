@@ -5,4 +5,4 @@ The computation lives in the HIP library ``libchm.so`` (C ABI in
 is its Python binding.
 """
 from .chm import (ENTRY_POINTS, NET_NPARAMS, ChmError, Net, Solver, chm_quadrature,  # noqa: F401
-                  flatten_params, library, params_from_dict, unflatten_params)
+                  flatten_params, library, params_from_dict, step_many, unflatten_params)

@@ -32,7 +32,7 @@ ENTRY_POINTS = [
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
     "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history",
-    "chm_net_guess_noalloc",
+    "chm_net_guess_noalloc", "chm_step_many",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -66,6 +66,7 @@ class chm_params_t(C.Structure):
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
+        ("runs_per_lane", C.c_int32),
     ]
 
 
@@ -136,6 +137,7 @@ def library():
             "chm_get_fields_run": ([vp, i32, vp, vp, vp, vp, vp, i32], C.c_int),
             "chm_boundary": ([vp, vp], C.c_int),
             "chm_get_history": ([vp, i32, vp, vp, P(i32), P(i64), i32], C.c_int),
+            "chm_step_many": ([vp, i32, i32, vp, vp], C.c_int),
             "chm_set_history": ([vp, i32, vp, vp, i32, i64, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -174,6 +176,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.amg_tol = float(p.get("amg_tol", 0.0))
     s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
     s.wide_index = int(p.get("wide_index", 0))
+    s.runs_per_lane = int(p.get("runs_per_lane", 0))
     return s
 
 
@@ -471,6 +474,29 @@ def unflatten_params(flat) -> list:
         b = flat[k:k + co].copy()
         k += co
         out.append((w, b))
+    return out
+
+
+def step_many(solvers, nsteps: int = 1):
+    """chm_step_many: advance the solvers concurrently (one host thread each;
+    give each its own stream so their launches overlap).  Returns per solver
+    what Solver.step returns."""
+    count = len(solvers)
+    handles = (C.c_void_p * count)(*[s.h for s in solvers])
+    bufs = [(chm_stats_t * max(1, nsteps * s.nb))() for s in solvers]
+    ptrs = (C.c_void_p * count)(*[C.cast(b, C.c_void_p) for b in bufs])
+    codes = (C.c_int32 * count)()
+    rc = library().chm_step_many(handles, count, nsteps, ptrs, codes)
+    out = []
+    for s, b in zip(solvers, bufs):
+        flat = [dict(iters=(x.iters[0], x.iters[1]), relres=(x.relres[0], x.relres[1]),
+                     status=x.status, clamped=x.clamped, t_step_ms=x.t_step_ms,
+                     guess_used=(x.guess_used[0], x.guess_used[1]), res0=(x.res0[0], x.res0[1]))
+                for x in b[:nsteps * s.nb]]
+        out.append(flat if s.nb == 1 else [flat[k * s.nb:(k + 1) * s.nb] for k in range(nsteps)])
+    if rc != CHM_OK:
+        bad = next(i for i in range(count) if codes[i] != CHM_OK)
+        _check(solvers[bad].h, codes[bad], f"chm_step_many (solver {bad})")
     return out
 
 

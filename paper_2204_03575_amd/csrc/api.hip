@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "chm_internal.h"
 
@@ -84,6 +85,8 @@ const char *check_params(const chm_params_t &p)
         return "unknown mass solver";
     if (p.wide_index != 0 && p.wide_index != 1)
         return "wide_index must be 0 or 1";
+    if (p.runs_per_lane != 0 && p.runs_per_lane != 1 && p.runs_per_lane != 2 && p.runs_per_lane != 4)
+        return "runs_per_lane must be 0, 1, 2 or 4";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -185,6 +188,7 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         S.prm = *params;
         S.nb = runs;
         S.nrun = 1;
+        S.rb = params->runs_per_lane > 0 ? params->runs_per_lane : 2;
         S.runs.resize(runs);
         S.hist.assign(runs, 0);
         S.steps.assign(runs, 0);
@@ -304,6 +308,41 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
         }
         return CHM_OK;
     });
+}
+
+int chm_step_many(chm_solver_t *const *solvers, int32_t count, int32_t nsteps,
+                  chm_stats_t *const *stats, int32_t *codes)
+{
+    if (!solvers || count < 1 || count > 1024 || nsteps < 0)
+        return fail(nullptr, CHM_EINVAL, "chm_step_many: bad arguments");
+    for (int i = 0; i < count; ++i) {
+        if (!solvers[i])
+            return fail(nullptr, CHM_EINVAL, "chm_step_many: NULL handle");
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == solvers[i])
+                return fail(nullptr, CHM_EINVAL, "chm_step_many: a handle appears twice");
+    }
+    std::vector<int> rc(count, CHM_OK);
+    std::vector<std::thread> pool;
+    try {
+        pool.reserve(count);
+        for (int i = 0; i < count; ++i)
+            pool.emplace_back([&, i]() { rc[i] = chm_step(solvers[i], nsteps, stats ? stats[i] : nullptr); });
+    } catch (const std::exception &e) {
+        for (std::thread &t : pool)
+            t.join();
+        return fail(nullptr, CHM_EINVAL, std::string("chm_step_many: cannot start threads: ") + e.what());
+    }
+    for (std::thread &t : pool)
+        t.join();
+    int first = CHM_OK;
+    for (int i = 0; i < count; ++i) {
+        if (codes)
+            codes[i] = rc[i];
+        if (first == CHM_OK && rc[i] != CHM_OK)
+            first = rc[i];
+    }
+    return first;
 }
 
 int chm_get_fields(chm_solver_t *h, double *phi_p, double *phi_n, double *phi_s, double *mu_p,

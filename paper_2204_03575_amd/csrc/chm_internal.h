@@ -244,6 +244,7 @@ struct Solver {
     // how many runs a launch covers (gridDim.y): nb for time steps, 1 for the
     // inspection calls, which work on run 0.
     int nb = 1, nrun = 1;
+    int rb = 2;                // batches: runs per lane of the SELL and coarsest-level kernels
     std::vector<RunPrm> runs;
     void *pots = nullptr;      // device: per-run potential parameters
     int dim = 0, nv = 0, ncell = 0, nl = 0;

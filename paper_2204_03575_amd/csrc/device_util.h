@@ -12,6 +12,8 @@
 
 #include "chm_internal.h"
 
+#include <type_traits>
+
 namespace chm {
 namespace {
 
@@ -25,6 +27,13 @@ template <class T> struct PairOf;
 template <> struct PairOf<double> { using type = double2; };
 template <> struct PairOf<float> { using type = float2; };
 template <class T> using pair_t = typename PairOf<T>::type;
+
+// a * b + c with one rounding.  The kernels that run in several variants
+// (one run or several runs per lane) write every product they add as fmad,
+// so no variant leaves the choice of which products to fuse to the compiler
+// and all variants give the same bits.
+__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <class T> __device__ inline pair_t<T> mk(T a, T b);
 template <> __device__ inline double2 mk<double>(double a, double b) { return make_double2(a, b); }
@@ -129,6 +138,10 @@ inline double2 *slot(Solver &S, int k) { return S.red + (size_t)k * kRedBlocks; 
 template <class P> __device__ inline P *run_at(P *p, long stride) { return p ? p + blockIdx.y * stride : p; }
 inline dim3 grid(int x, int runs) { return dim3(x, runs); }
 
+// runs per lane of the SELL and coarsest-level kernels of this launch (one
+// run: 1)
+inline int rb_of(const Solver &S) { return S.nrun > 1 ? S.rb : 1; }
+
 // ------------------------------------------------------------------ SpMV family (pairs)
 // SP_SET: y = A x; SP_ADD: y += A x; SP_RESID: y = b - A x
 enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
@@ -153,39 +166,59 @@ __device__ inline int sell_col(const int16_t *__restrict__ col, int idx, int row
     return row + (int)col[idx];
 }
 
-// the unrolled row product for slices at most W wide (width >= 1); diag
-// receives the row's nonzero diagonal entry (0 if it has none; the padding
-// of a short row may repeat the diagonal column, with value 0)
+// The entries of one SELL row for slices at most W wide (width >= 1):
+// entries past the slice width repeat the last column with a zero
+// coefficient, so every load is unconditional (no branch between the loads
+// and the gathers) and hits the cache line just read.
+template <int W, class T> struct SellEnt {
+    int c[W];
+    T a[W];
+};
+
+template <int W, class I, class T>
+__device__ inline void sell_load(int base, int width, int lane, int row, const I *__restrict__ col,
+                                 const T *__restrict__ val, SellEnt<W, T> &e)
+{
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+        e.c[k] = sell_col(col, idx, row);
+        const T v = val[idx];
+        e.a[k] = k < width ? v : T(0);
+    }
+}
+
+// the row product from the gathered x[c[k]], added in column order; diag
+// receives the row's nonzero diagonal entry (0 if it has none; the padding of
+// a short row may repeat the diagonal column, with value 0)
+template <int W, class T>
+__device__ inline pair_t<T> sell_dot(const SellEnt<W, T> &e, const pair_t<T> *xv, int row, T &diag)
+{
+    T ax = 0, ay = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        ax = fmad(e.a[k], xv[k].x, ax);
+        ay = fmad(e.a[k], xv[k].y, ay);
+        d = (e.c[k] == row && e.a[k] != T(0)) ? e.a[k] : d;   // not the zero padding
+    }
+    diag = d;
+    return mk<T>(ax, ay);
+}
+
+// the unrolled row product for slices at most W wide (width >= 1): every
+// column and value load, then every gather, then the products
 template <int W, class I, class T>
 __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
                                        const I *__restrict__ col, const T *__restrict__ val,
                                        const pair_t<T> *__restrict__ x, T &diag)
 {
-    // entries past the slice width repeat the last column with a zero
-    // coefficient: every load is unconditional (no branch between the
-    // loads and the gathers) and hits the cache line just read
-    int c[W];
-    T a[W];
+    SellEnt<W, T> e;
+    sell_load<W, I, T>(base, width, lane, row, col, val, e);
     pair_t<T> xv[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
-        c[k] = sell_col(col, idx, row);
-        const T v = val[idx];
-        a[k] = k < width ? v : T(0);
-    }
-#pragma unroll
     for (int k = 0; k < W; ++k)
-        xv[k] = x[c[k]];
-    T ax = 0, ay = 0, d = 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        ax += a[k] * xv[k].x;
-        ay += a[k] * xv[k].y;
-        d = (c[k] == row && a[k] != T(0)) ? a[k] : d;   // not the zero padding
-    }
-    diag = d;
-    return mk<T>(ax, ay);
+        xv[k] = x[e.c[k]];
+    return sell_dot<W, T>(e, xv, row, diag);
 }
 
 // the row product of a SELL-64 matrix; diag receives the row's diagonal
@@ -211,12 +244,75 @@ __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__re
         const T a = val[idx];
         const int c = sell_col(col, idx, row);
         const pair_t<T> xv = x[c];
-        ax += a * xv.x;
-        ay += a * xv.y;
+        ax = fmad(a, xv.x, ax);
+        ay = fmad(a, xv.y, ay);
         d = (c == row && a != T(0)) ? a : d;
     }
     diag = d;
     return mk<T>(ax, ay);
+}
+
+// ------------------------------------------------------------------ several runs per lane
+// Batched launches of the SELL kernels: block row blockIdx.y covers the RB
+// runs r0 = RB blockIdx.y, ..., r0 + RB - 1 (those below R), so every matrix
+// entry a lane loads serves RB runs and a launch over R runs streams the
+// matrix ceil(R / RB) times instead of R times.  Each run's product is the
+// single-run product (same entries, same order), so results do not depend on
+// RB.
+template <int RB> __device__ inline int run0() { return RB * (int)blockIdx.y; }
+inline dim3 grid_rb(int x, int runs, int rb) { return dim3(x, (runs + rb - 1) / rb); }
+
+// For each run r of the block: the product of SELL row `row` with
+// x + r sx, handed to f(q, r, product, diag) with q = r - r0 (a constant
+// after unrolling, so per-run arrays indexed by q stay in registers).  Slices at most kSellUnroll wide
+// (2D P1 patterns) load the row's entries once and issue every run's gathers
+// before the first product; wider slices go run by run (with one run per
+// lane, slices up to twice that width still take the unrolled path).
+template <class I, class T, int RB, class F>
+__device__ inline void sell_row_runs(const int *__restrict__ sptr, const I *__restrict__ col,
+                                     const T *__restrict__ val, const pair_t<T> *__restrict__ x,
+                                     long sx, int row, int R, F &&f)
+{
+    const int r0 = run0<RB>();
+    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
+    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    auto runs_w = [&](auto wtag) {
+        constexpr int W = decltype(wtag)::value;
+        SellEnt<W, T> e;
+        sell_load<W, I, T>(base, width, lane, row, col, val, e);
+        pair_t<T> xv[RB][W];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R)
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    xv[q][k] = x[(r0 + q) * sx + e.c[k]];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                T diag;
+                const pair_t<T> p = sell_dot<W, T>(e, xv[q], row, diag);
+                f(q, r0 + q, p, diag);
+            }
+    };
+    if (width == 0) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R)
+                f(q, r0 + q, mk<T>(0, 0), T(0));
+    } else if (width <= kSellUnroll) {
+        runs_w(std::integral_constant<int, kSellUnroll>{});
+    } else if (RB == 1 && width <= 2 * kSellUnroll) {
+        runs_w(std::integral_constant<int, RB == 1 ? 2 * kSellUnroll : 1>{});
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                T diag;
+                const pair_t<T> p = sell_row<I, T>(sptr, col, val, x + (r0 + q) * sx, row, diag);
+                f(q, r0 + q, p, diag);
+            }
+    }
 }
 
 template <int MODE, class T>
@@ -233,9 +329,10 @@ __device__ inline void spmv_store(pair_t<T> s, const pair_t<T> *__restrict__ b, 
     }
 }
 
-// per run: x advances by sx, b and y by sy
-template <int MODE, class I, class T>
-__global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
+// per run: x advances by sx, b and y by sy; RB runs per lane (block row
+// blockIdx.y), R runs in all
+template <int MODE, class I, class T, int RB>
+__global__ void __launch_bounds__(kBlock) k_spmv(int n, int R, const int *__restrict__ sptr,
                                                  const I *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const pair_t<T> *__restrict__ x, long sx,
@@ -245,23 +342,35 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    x = run_at(x, sx);
-    b = run_at(b, sy);
-    y = run_at(y, sy);
-    T diag;
-    spmv_store<MODE, T>(sell_row<I, T>(sptr, col, val, x, row, diag), b, y, row);
+    sell_row_runs<I, T, RB>(sptr, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
+        spmv_store<MODE, T>(s, b ? b + r * sy : b, y + r * sy, row);
+    });
 }
 
-// k_spmv over a SELL matrix of n rows, on its 16-bit column offsets when it
-// has them (ocol), else on its columns
+template <int MODE, class I, class T>
+void sell_spmv_i(hipStream_t st, int gx, int runs, int rb, int n, const int *sptr, const I *col,
+                 const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y, long sy)
+{
+    const dim3 g = grid_rb(gx, runs, rb);
+    if (rb >= 4)
+        k_spmv<MODE, I, T, 4><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+    else if (rb == 2)
+        k_spmv<MODE, I, T, 2><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+    else
+        k_spmv<MODE, I, T, 1><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+}
+
+// k_spmv over a SELL matrix of n rows for `runs` runs, rb of them per lane,
+// on its 16-bit column offsets when it has them (ocol), else on its columns
 template <int MODE, class T>
-void sell_spmv(hipStream_t st, dim3 g, int n, const int *sptr, const int *col, const int16_t *ocol,
-               const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y, long sy)
+void sell_spmv(hipStream_t st, int runs, int rb, int n, const int *sptr, const int *col,
+               const int16_t *ocol, const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b,
+               pair_t<T> *y, long sy)
 {
     if (ocol)
-        k_spmv<MODE, int16_t, T><<<g, kBlock, 0, st>>>(n, sptr, ocol, val, x, sx, b, y, sy);
+        sell_spmv_i<MODE, int16_t, T>(st, nblk(n), runs, rb, n, sptr, ocol, val, x, sx, b, y, sy);
     else
-        k_spmv<MODE, int, T><<<g, kBlock, 0, st>>>(n, sptr, col, val, x, sx, b, y, sy);
+        sell_spmv_i<MODE, int, T>(st, nblk(n), runs, rb, n, sptr, col, val, x, sx, b, y, sy);
 }
 
 // The same with a group of GS lanes per row (CSR), for matrices with long rows
@@ -357,9 +466,9 @@ void spmv_v_u(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
 
 // y = A x / y += A x / y = b - A x with the kernel shape chosen for the
 // matrix, for `runs` runs whose x are A.m apart and whose b, y are A.n apart
-// (or sx, sy when given)
+// (or sx, sy when given); a SELL matrix serves rb runs per lane
 template <int MODE, class T>
-void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
+void spmv_op(hipStream_t st, int runs, int rb, const MatView<T> &A, const pair_t<T> *x,
              const pair_t<T> *b, pair_t<T> *y, long sx = -1, long sy = -1)
 {
     const int n = A.n;
@@ -368,8 +477,7 @@ void spmv_op(hipStream_t st, int runs, const MatView<T> &A, const pair_t<T> *x,
     if (sy < 0)
         sy = A.n;
     if (A.gs == 0) {
-        sell_spmv<MODE, T>(st, grid(nblk(n), runs), n, A.sptr, A.col, A.ocol, A.sval, x, sx, b, y,
-                           sy);
+        sell_spmv<MODE, T>(st, runs, rb, n, A.sptr, A.col, A.ocol, A.sval, x, sx, b, y, sy);
         return;
     }
     switch (A.gs) {

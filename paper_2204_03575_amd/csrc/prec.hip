@@ -51,12 +51,12 @@ __device__ inline ChebRow<T> cheb_row(const pair_t<T> *__restrict__ b, const pai
 
 template <class T> __device__ inline pair_t<T> cheb_apply(pair_t<T> s, const ChebRow<T> &o, T c1, T c2)
 {
-    return mk<T>(o.xi.x + c1 * (o.xi.x - o.xp.x) + c2 * (o.di * (o.bb.x - s.x)),
-                 o.xi.y + c1 * (o.xi.y - o.xp.y) + c2 * (o.di * (o.bb.y - s.y)));
+    return mk<T>(fmad(c2, o.di * (o.bb.x - s.x), fmad(c1, o.xi.x - o.xp.x, o.xi.x)),
+                 fmad(c2, o.di * (o.bb.y - s.y), fmad(c1, o.xi.y - o.xp.y, o.xi.y)));
 }
 
-template <class I, class T>
-__global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ sptr,
+template <class I, class T, int RB>
+__global__ void __launch_bounds__(kBlock) k_cheb(int n, int R, const int *__restrict__ sptr,
                                                  const I *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ dinv,
@@ -67,19 +67,25 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, const int *__restrict__ 
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    b = run_at(b, n);
-    xk = run_at(xk, n);
-    xprev = run_at(xprev, n);
     // FP64: D^-1 of the row is 1 / a_ii of the entries just read, the value
     // the setup stored (the same IEEE division), so it is not loaded; the
     // FP32 path loads its rounded copy
     constexpr bool own = std::is_same<T, double>::value;
-    ChebRow<T> o = cheb_row<T>(b, xk, own ? nullptr : dinv, xprev, row, prev);
-    T diag;
-    const pair_t<T> s = sell_row<I, T>(sptr, col, val, xk, row, diag);
-    if (own)
-        o.di = T(1) / diag;
-    xprev[row] = cheb_apply<T>(s, o, c1, c2);
+    // every run's operands of the update first, then the row product
+    const int r0 = run0<RB>();
+    ChebRow<T> o[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+        if (RB == 1 || r0 + q < R) {
+            const long off = (long)(r0 + q) * n;
+            o[q] = cheb_row<T>(b + off, xk + off, own ? nullptr : dinv, xprev + off, row, prev);
+        }
+    sell_row_runs<I, T, RB>(sptr, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
+        ChebRow<T> &w = o[q];
+        if (own)
+            w.di = T(1) / diag;
+        xprev[(long)r * n + row] = cheb_apply<T>(s, w, c1, c2);
+    });
 }
 
 // The first two smoothing steps from x = 0 in one launch (SELL levels):
@@ -111,65 +117,81 @@ template <class T> __device__ inline ChebRow<T> first_row(const FirstIter<T> &x1
     return o;
 }
 
-// A x_1 over one SELL row, entries added in column order; slices at most W
-// wide take the unrolled path of sell_row_w (all column and value loads,
-// then all gathers, then the products)
-template <int W, class I, class T>
-__device__ inline pair_t<T> sell_row_first_w(int base, int width, int lane, int row,
-                                             const I *__restrict__ col, const T *__restrict__ val,
-                                             const FirstIter<T> &x1)
+// the row products A x_1 of RB runs (x_1 formed from run r's b), entries
+// loaded once on slices at most kSellUnroll wide; f(q, r, product) with
+// q = r - r0
+template <class I, class T, int RB, class F>
+__device__ inline void sell_row_first_runs(const int *__restrict__ sptr, const I *__restrict__ col,
+                                           const T *__restrict__ val, const pair_t<T> *__restrict__ b,
+                                           const T *__restrict__ dinv, T c2f, int n, int row, int R,
+                                           F &&f)
 {
-    int c[W];
-    T a[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
-        c[k] = sell_col(col, idx, row);
-        const T v = val[idx];
-        a[k] = k < width ? v : T(0);
-    }
-    pair_t<T> bv[W];
-    T dv[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        bv[k] = x1.b[c[k]];
-        dv[k] = x1.dinv[c[k]];
-    }
-    T ax = 0, ay = 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        ax += a[k] * (x1.c2 * (dv[k] * bv[k].x));
-        ay += a[k] * (x1.c2 * (dv[k] * bv[k].y));
-    }
-    return mk<T>(ax, ay);
-}
-
-template <class I, class T>
-__device__ inline pair_t<T> sell_row_first(const int *__restrict__ sptr, const I *__restrict__ col,
-                                           const T *__restrict__ val, const FirstIter<T> &x1,
-                                           int row)
-{
+    const int r0 = run0<RB>();
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-    if (width == 0)
-        return mk<T>(0, 0);
-    if (width <= kSellUnroll)
-        return sell_row_first_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x1);
-    if (width <= 2 * kSellUnroll)
-        return sell_row_first_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x1);
-    T ax = 0, ay = 0;
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const T a = val[idx];
-        const pair_t<T> xv = x1(sell_col(col, idx, row));
-        ax += a * xv.x;
-        ay += a * xv.y;
+    auto runs_w = [&](auto wtag) {
+        constexpr int W = decltype(wtag)::value;
+        int c[W];
+        T a[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+            c[k] = sell_col(col, idx, row);
+            const T v = val[idx];
+            a[k] = k < width ? v : T(0);
+        }
+        T dv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            dv[k] = dinv[c[k]];
+        pair_t<T> bv[RB][W];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R)
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    bv[q][k] = b[(long)(r0 + q) * n + c[k]];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                T ax = 0, ay = 0;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    ax = fmad(a[k], c2f * (dv[k] * bv[q][k].x), ax);
+                    ay = fmad(a[k], c2f * (dv[k] * bv[q][k].y), ay);
+                }
+                f(q, r0 + q, mk<T>(ax, ay));
+            }
+    };
+    if (width == 0) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R)
+                f(q, r0 + q, mk<T>(0, 0));
+    } else if (width <= kSellUnroll) {
+        runs_w(std::integral_constant<int, kSellUnroll>{});
+    } else if (RB == 1 && width <= 2 * kSellUnroll) {
+        runs_w(std::integral_constant<int, RB == 1 ? 2 * kSellUnroll : 1>{});
+    } else {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                const FirstIter<T> x1{b + (long)(r0 + q) * n, dinv, c2f};
+                T ax = 0, ay = 0;
+                for (int k = 0; k < width; ++k) {
+                    const int idx = base + k * kSlice + lane;
+                    const T a = val[idx];
+                    const pair_t<T> xv = x1(sell_col(col, idx, row));
+                    ax = fmad(a, xv.x, ax);
+                    ay = fmad(a, xv.y, ay);
+                }
+                f(q, r0 + q, mk<T>(ax, ay));
+            }
     }
-    return mk<T>(ax, ay);
 }
 
-template <class I, class T>
-__global__ void __launch_bounds__(kBlock) k_cheb_first(int n, const int *__restrict__ sptr,
+template <class I, class T, int RB>
+__global__ void __launch_bounds__(kBlock) k_cheb_first(int n, int R, const int *__restrict__ sptr,
                                                        const I *__restrict__ col,
                                                        const T *__restrict__ val,
                                                        const T *__restrict__ dinv,
@@ -180,11 +202,18 @@ __global__ void __launch_bounds__(kBlock) k_cheb_first(int n, const int *__restr
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    const FirstIter<T> x1{run_at(b, n), dinv, c2first};
-    const ChebRow<T> o = first_row(x1, row);
-    const pair_t<T> s = sell_row_first<I, T>(sptr, col, val, x1, row);
-    run_at(x1out, n)[row] = o.xi;
-    run_at(x2, n)[row] = cheb_apply<T>(s, o, c1, c2);
+    const int r0 = run0<RB>();
+    ChebRow<T> o[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+        if (RB == 1 || r0 + q < R)
+            o[q] = first_row(FirstIter<T>{b + (long)(r0 + q) * n, dinv, c2first}, row);
+    sell_row_first_runs<I, T, RB>(sptr, col, val, b, dinv, c2first, n, row, R,
+                                  [&](int q, int r, pair_t<T> s) {
+                                      const ChebRow<T> &w = o[q];
+                                      x1out[(long)r * n + row] = w.xi;
+                                      x2[(long)r * n + row] = cheb_apply<T>(s, w, c1, c2);
+                                  });
 }
 
 // the same for a CSR level with a group of GS lanes per row
@@ -255,8 +284,8 @@ __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ d
 // with a fixed shuffle tree.  FP64 sums in both precisions.
 constexpr int kDenseRows = kBlock / 64;
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restrict__ inv,
+template <class T, int RB>
+__global__ void __launch_bounds__(kBlock) k_dense(int n, int R, const double *__restrict__ inv,
                                                   const pair_t<T> *__restrict__ b, pair_t<T> *x)
 {
     const int lane = threadIdx.x & 63;
@@ -264,29 +293,93 @@ __global__ void __launch_bounds__(kBlock) k_dense(int n, const double *__restric
     if (row >= n)
         return;   // the whole wave: row depends on the wave only
     const double *a = inv + (size_t)row * n;
-    b = run_at(b, n);
-    double2 acc[4] = {d2(0.0, 0.0), d2(0.0, 0.0), d2(0.0, 0.0), d2(0.0, 0.0)};
+    const int r0 = run0<RB>();
+    // every run's sums over the row, each with the single-run order; the
+    // row's entries are loaded once for the RB runs
+    double2 acc[RB][4];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc[q][u] = d2(0.0, 0.0);
     int j = lane;
     for (; j + 192 < n; j += 256) {
+        double v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double v = a[j + 64 * u];
-            const pair_t<T> bv = b[j + 64 * u];
-            acc[u].x += v * double(bv.x);
-            acc[u].y += v * double(bv.y);
-        }
+        for (int u = 0; u < 4; ++u)
+            v[u] = a[j + 64 * u];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                const pair_t<T> *bq = b + (long)(r0 + q) * n;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const pair_t<T> bv = bq[j + 64 * u];
+                    acc[q][u].x = fmad(v[u], double(bv.x), acc[q][u].x);
+                    acc[q][u].y = fmad(v[u], double(bv.y), acc[q][u].y);
+                }
+            }
     }
     for (; j < n; j += 64) {
         const double v = a[j];
-        const pair_t<T> bv = b[j];
-        acc[0].x += v * double(bv.x);
-        acc[0].y += v * double(bv.y);
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                const pair_t<T> bv = b[(long)(r0 + q) * n + j];
+                acc[q][0].x = fmad(v, double(bv.x), acc[q][0].x);
+                acc[q][0].y = fmad(v, double(bv.y), acc[q][0].y);
+            }
     }
-    double2 s = d2((acc[0].x + acc[1].x) + (acc[2].x + acc[3].x),
-                   (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y));
-    s = wave_sum(s);
-    if (lane == 0)
-        run_at(x, n)[row] = mk<T>(T(s.x), T(s.y));
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        double2 s = d2((acc[q][0].x + acc[q][1].x) + (acc[q][2].x + acc[q][3].x),
+                       (acc[q][0].y + acc[q][1].y) + (acc[q][2].y + acc[q][3].y));
+        s = wave_sum(s);
+        if (lane == 0 && (RB == 1 || r0 + q < R))
+            x[(long)(r0 + q) * n + row] = mk<T>(T(s.x), T(s.y));
+    }
+}
+
+// launches with rb runs per lane (1, 2 or 4) over R runs
+template <class I, class T>
+void cheb_rb(hipStream_t st, int rb, int n, int R, const int *sptr, const I *col, const T *val,
+             const T *dinv, const pair_t<T> *b, const pair_t<T> *xk, pair_t<T> *xprev, T c1, T c2,
+             int prev)
+{
+    const dim3 g = grid_rb(nblk(n), R, rb);
+    if (rb >= 4)
+        k_cheb<I, T, 4><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+    else if (rb == 2)
+        k_cheb<I, T, 2><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+    else
+        k_cheb<I, T, 1><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+}
+
+template <class I, class T>
+void cheb_first_rb(hipStream_t st, int rb, int n, int R, const int *sptr, const I *col,
+                   const T *val, const T *dinv, const pair_t<T> *b, pair_t<T> *x1, pair_t<T> *x2,
+                   T c2f, T c1, T c2)
+{
+    const dim3 g = grid_rb(nblk(n), R, rb);
+    if (rb >= 4)
+        k_cheb_first<I, T, 4><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+    else if (rb == 2)
+        k_cheb_first<I, T, 2><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+    else
+        k_cheb_first<I, T, 1><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+}
+
+template <class T>
+void dense_rb(hipStream_t st, int rb, int n, int R, const double *inv, const pair_t<T> *b,
+              pair_t<T> *x)
+{
+    const dim3 g = grid_rb(nblk(n, kDenseRows), R, rb);
+    if (rb >= 4)
+        k_dense<T, 4><<<g, kBlock, 0, st>>>(n, R, inv, b, x);
+    else if (rb == 2)
+        k_dense<T, 2><<<g, kBlock, 0, st>>>(n, R, inv, b, x);
+    else
+        k_dense<T, 1><<<g, kBlock, 0, st>>>(n, R, inv, b, x);
 }
 
 template <class T>
@@ -521,11 +614,11 @@ void launch_cheb_first(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_
     switch (A.gs) {
     case 0:
         if (A.ocol)
-            k_cheb_first<int16_t, T><<<grid(nblk(n), R), kBlock, 0, st>>>(
-                n, A.sptr, A.ocol, A.sval, dinv, b, x1, x2, c2f, c1, c2);
+            cheb_first_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, A.sval, dinv, b, x1, x2,
+                                      c2f, c1, c2);
         else
-            k_cheb_first<int, T><<<grid(nblk(n), R), kBlock, 0, st>>>(
-                n, A.sptr, A.col, A.sval, dinv, b, x1, x2, c2f, c1, c2);
+            cheb_first_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, A.sval, dinv, b, x1, x2, c2f,
+                                  c1, c2);
         break;
     case 4:
         cheb_first_v_u<4, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
@@ -556,11 +649,11 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     switch (A.gs) {
     case 0:
         if (A.ocol)
-            k_cheb<int16_t, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.ocol, A.sval, dinv,
-                                                                    b, xk, xprev, c1, c2, prev);
+            cheb_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, A.sval, dinv, b, xk, xprev, c1,
+                                c2, prev);
         else
-            k_cheb<int, T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, A.sptr, A.col, A.sval, dinv, b,
-                                                                xk, xprev, c1, c2, prev);
+            cheb_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, A.sval, dinv, b, xk, xprev, c1, c2,
+                            prev);
         break;
     case 4:
         cheb_v_u<4, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
@@ -633,7 +726,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     hipStream_t st = S.stream;
     const int R = S.nrun;
     if (l == H.nlev - 1) {
-        k_dense<T><<<grid(nblk(L.n, kDenseRows), R), kBlock, 0, st>>>(L.n, L.inv, b, x);
+        dense_rb<T>(st, rb_of(S), L.n, R, L.inv, b, x);
         return;
     }
     const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
@@ -646,10 +739,10 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     pair_t<T> *cur = presmooth<T>(S, H, l, b, V.xt, x);
     pair_t<T> *oth = cur == x ? V.xt : x;
     const bool timed = timed_level(S, H, l);
-    spmv_op<SP_RESID, T>(st, R, L.viewA<T>(), cur, b, V.r);
-    spmv_op<SP_SET, T>(st, R, L.viewR<T>(), V.r, nullptr, Vc.b);
+    spmv_op<SP_RESID, T>(st, R, rb_of(S), L.viewA<T>(), cur, b, V.r);
+    spmv_op<SP_SET, T>(st, R, rb_of(S), L.viewR<T>(), V.r, nullptr, Vc.b);
     vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
-    spmv_op<SP_ADD, T>(st, R, L.viewP<T>(), Vc.x, nullptr, cur);
+    spmv_op<SP_ADD, T>(st, R, rb_of(S), L.viewP<T>(), Vc.x, nullptr, cur);
     if (timed)
         timer_mark(S, true);
     for (int k = 1; k <= deg; ++k) {
@@ -686,7 +779,7 @@ void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
     if (tol > 0.0 && S.prm.amg_cycles > 1)
         k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, b, slot(S, kSlotRz));
     for (int c = 1; c < S.prm.amg_cycles; ++c) {
-        spmv_op<SP_RESID, T>(st, R, L0.viewA<T>(), x, b, W.mr);
+        spmv_op<SP_RESID, T>(st, R, rb_of(S), L0.viewA<T>(), x, b, W.mr);
         if (tol > 0.0) {
             k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, W.mr, W.mr, slot(S, kSlotRz + 1));
             k_amg_flags<<<grid(1, R), kBlock, 0, st>>>(slot(S, kSlotRz), slot(S, kSlotRz + 1), G,
@@ -728,7 +821,7 @@ void schur_solve_t(Solver &S, const pair_t<T> *b, pair_t<T> *x)
     vcycle_level<T>(S, H, 0, b, d);                                    // z = V(b), r = b
     k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, d, slot(S, kSlotRz));
     for (int it = 1; it <= k; ++it) {
-        spmv_op<SP_SET, T>(st, R, A, d, nullptr, q);
+        spmv_op<SP_SET, T>(st, R, rb_of(S), A, d, nullptr, q);
         k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
         k_pcg_xr<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
                                                          slot(S, kSlotDq + it), G, it == 1,
@@ -757,7 +850,7 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
     if (R == 1) {
         stationary<T>(S, S.hM, v, w);
         schur_solve_t<T>(S, v + n, W.tmp);
-        sell_spmv<SP_SET, T>(st, grid(nblk(n), 1), n, S.sM.sptr, S.sM.col, S.sM.ocol,
+        sell_spmv<SP_SET, T>(st, 1, 1, n, S.sM.sptr, S.sM.col, S.sM.ocol,
                              mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
         schur_solve_t<T>(S, W.tmp2, w + n);
         return;
@@ -767,7 +860,7 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
     k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w, len);
     k_gather_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, v + n, len, W.h1);
     schur_solve_t<T>(S, W.h1, W.tmp);
-    sell_spmv<SP_SET, T>(st, grid(nblk(n), R), n, S.sM.sptr, S.sM.col, S.sM.ocol,
+    sell_spmv<SP_SET, T>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol,
                          mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
     schur_solve_t<T>(S, W.tmp2, W.h2);
     k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w + n, len);

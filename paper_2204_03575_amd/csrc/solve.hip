@@ -19,6 +19,53 @@ namespace {
 // row then takes the unrolled form of the loop: every column and value load,
 // then every gather, then the products in column order (slots past the slice
 // width repeat its last column with zero values)
+struct SaddleEnt {
+    int c[kSellUnroll];
+    double am[kSellUnroll], ak[kSellUnroll];
+};
+
+template <class I>
+__device__ inline void saddle_load(int base, int width, int lane, int row, const I *__restrict__ col,
+                                   const double *__restrict__ vm, const double *__restrict__ vk,
+                                   SaddleEnt &e)
+{
+#pragma unroll
+    for (int k = 0; k < kSellUnroll; ++k) {
+        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+        e.c[k] = sell_col(col, idx, row);
+        const double vmk = vm[idx], vkk = vk[idx];
+        e.am[k] = k < width ? vmk : 0.0;
+        e.ak[k] = k < width ? vkk : 0.0;
+    }
+}
+
+// y0 = M x0 + t K x1, y1 = t K x0 - te M x1 from the four row products
+__device__ inline void saddle_combine(double m0x, double m0y, double k1x, double k1y, double k0x,
+                                      double k0y, double m1x, double m1y, double2 t, double2 te,
+                                      double2 &y0, double2 &y1)
+{
+    y0 = d2(fmad(t.x, k1x, m0x), fmad(t.y, k1y, m0y));
+    y1 = d2(fmad(t.x, k0x, -(te.x * m1x)), fmad(t.y, k0y, -(te.y * m1y)));
+}
+
+__device__ inline void saddle_dot(const SaddleEnt &e, const double2 *x0, const double2 *x1, double2 t,
+                                  double2 te, double2 &y0, double2 &y1)
+{
+    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
+#pragma unroll
+    for (int k = 0; k < kSellUnroll; ++k) {
+        m0x = fmad(e.am[k], x0[k].x, m0x);
+        m0y = fmad(e.am[k], x0[k].y, m0y);
+        k1x = fmad(e.ak[k], x1[k].x, k1x);
+        k1y = fmad(e.ak[k], x1[k].y, k1y);
+        k0x = fmad(e.ak[k], x0[k].x, k0x);
+        k0y = fmad(e.ak[k], x0[k].y, k0y);
+        m1x = fmad(e.am[k], x1[k].x, m1x);
+        m1y = fmad(e.am[k], x1[k].y, m1y);
+    }
+    saddle_combine(m0x, m0y, k1x, k1y, k0x, k0y, m1x, m1y, t, te, y0, y1);
+}
+
 template <class I, bool U8>
 __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
                                   const I *__restrict__ col, const double *__restrict__ vm,
@@ -27,58 +74,40 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
-    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
     if (U8 && width > 0) {
-        int c[kSellUnroll];
-        double am[kSellUnroll], ak[kSellUnroll];
-#pragma unroll
-        for (int k = 0; k < kSellUnroll; ++k) {
-            const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
-            c[k] = sell_col(col, idx, row);
-            const double vmk = vm[idx], vkk = vk[idx];
-            am[k] = k < width ? vmk : 0.0;
-            ak[k] = k < width ? vkk : 0.0;
-        }
+        SaddleEnt e;
+        saddle_load<I>(base, width, lane, row, col, vm, vk, e);
         double2 x0[kSellUnroll], x1[kSellUnroll];
 #pragma unroll
         for (int k = 0; k < kSellUnroll; ++k) {
-            x0[k] = x[c[k]];
-            x1[k] = x[n + c[k]];
+            x0[k] = x[e.c[k]];
+            x1[k] = x[n + e.c[k]];
         }
-#pragma unroll
-        for (int k = 0; k < kSellUnroll; ++k) {
-            m0x += am[k] * x0[k].x;
-            m0y += am[k] * x0[k].y;
-            k1x += ak[k] * x1[k].x;
-            k1y += ak[k] * x1[k].y;
-            k0x += ak[k] * x0[k].x;
-            k0y += ak[k] * x0[k].y;
-            m1x += am[k] * x1[k].x;
-            m1y += am[k] * x1[k].y;
-        }
-    } else {
-        for (int k = 0; k < width; ++k) {
-            const int idx = base + k * kSlice + lane;
-            const int c = sell_col(col, idx, row);
-            const double am = vm[idx], ak = vk[idx];
-            const double2 x0 = x[c], x1 = x[n + c];
-            m0x += am * x0.x;
-            m0y += am * x0.y;
-            k1x += ak * x1.x;
-            k1y += ak * x1.y;
-            k0x += ak * x0.x;
-            k0y += ak * x0.y;
-            m1x += am * x1.x;
-            m1y += am * x1.y;
-        }
+        saddle_dot(e, x0, x1, t, te, y0, y1);
+        return;
     }
-    y0 = d2(m0x + t.x * k1x, m0y + t.y * k1y);
-    y1 = d2(t.x * k0x - te.x * m1x, t.y * k0y - te.y * m1y);
+    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
+    for (int k = 0; k < width; ++k) {
+        const int idx = base + k * kSlice + lane;
+        const int c = sell_col(col, idx, row);
+        const double am = vm[idx], ak = vk[idx];
+        const double2 x0 = x[c], x1 = x[n + c];
+        m0x = fmad(am, x0.x, m0x);
+        m0y = fmad(am, x0.y, m0y);
+        k1x = fmad(ak, x1.x, k1x);
+        k1y = fmad(ak, x1.y, k1y);
+        k0x = fmad(ak, x0.x, k0x);
+        k0y = fmad(ak, x0.y, k0y);
+        m1x = fmad(am, x1.x, m1x);
+        m1y = fmad(am, x1.y, m1y);
+    }
+    saddle_combine(m0x, m0y, k1x, k1y, k0x, k0y, m1x, m1y, t, te, y0, y1);
 }
 
-// per run, x and y advance by 2n
-template <class I, bool U8>
-__global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict__ sptr,
+// per run, x and y advance by 2n; RB runs per lane (block row blockIdx.y),
+// R in all: on U8 patterns the row's entries are loaded once for the RB runs
+template <class I, bool U8, int RB>
+__global__ void __launch_bounds__(kBlock) k_saddle(int n, int R, const int *__restrict__ sptr,
                                                    const I *__restrict__ col,
                                                    const double *__restrict__ vm,
                                                    const double *__restrict__ vk,
@@ -88,12 +117,45 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, const int *__restrict_
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    x = run_at(x, 2l * n);
-    y = run_at(y, 2l * n);
-    double2 y0, y1;
-    saddle_row<I, U8>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
-    y[row] = y0;
-    y[n + row] = y1;
+    const int r0 = run0<RB>();
+    const long len = 2l * n;
+    if (U8 && RB > 1) {
+        const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
+        const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+        if (width > 0) {
+            SaddleEnt e;
+            saddle_load<I>(base, width, lane, row, col, vm, vk, e);
+            double2 x0[RB][kSellUnroll], x1[RB][kSellUnroll];
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (r0 + q < R) {
+                    const double2 *xr = x + (r0 + q) * len;
+#pragma unroll
+                    for (int k = 0; k < kSellUnroll; ++k) {
+                        x0[q][k] = xr[e.c[k]];
+                        x1[q][k] = xr[n + e.c[k]];
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (r0 + q < R) {
+                    double2 y0, y1;
+                    saddle_dot(e, x0[q], x1[q], t, te, y0, y1);
+                    double2 *yr = y + (r0 + q) * len;
+                    yr[row] = y0;
+                    yr[n + row] = y1;
+                }
+            return;
+        }
+    }
+    for (int q = 0; q < RB; ++q)
+        if (RB == 1 || r0 + q < R) {
+            double2 y0, y1;
+            saddle_row<I, U8>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
+            double2 *yr = y + (r0 + q) * len;
+            yr[row] = y0;
+            yr[n + row] = y1;
+        }
 }
 
 // y = b - A x over a grid-stride loop, and partial sums of |y1|^2 + w2 |y2|^2
@@ -732,24 +794,31 @@ inline const Ctl &head(const Solver &S, int r)
 
 }  // namespace
 
+template <class I, bool U8>
+static void saddle_rb(Solver &S, const I *col, const double2 *x, double2 *y)
+{
+    const int n = S.nv, R = S.nrun, rb = rb_of(S);
+    const dim3 g = grid_rb(nblk(n), R, rb);
+    const double2 t = pair(S.tau_s), te = pair(S.te_s);
+    if (rb >= 4)
+        k_saddle<I, U8, 4><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+    else if (rb == 2)
+        k_saddle<I, U8, 2><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+    else
+        k_saddle<I, U8, 1><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+}
+
 void apply_saddle(Solver &S, const double2 *x, double2 *y)
 {
-    const int n = S.nv;
-    const dim3 g = grid(nblk(n), S.nrun);
     const bool u8 = S.sM.wmax <= kSellUnroll;
     if (S.sM.ocol && u8)
-        k_saddle<int16_t, true><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK,
-                                                            x, y, pair(S.tau_s), pair(S.te_s));
+        saddle_rb<int16_t, true>(S, S.sM.ocol, x, y);
     else if (S.sM.ocol)
-        k_saddle<int16_t, false><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.ocol, S.sM.val,
-                                                             S.sK, x, y, pair(S.tau_s),
-                                                             pair(S.te_s));
+        saddle_rb<int16_t, false>(S, S.sM.ocol, x, y);
     else if (u8)
-        k_saddle<int, true><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
-                                                        y, pair(S.tau_s), pair(S.te_s));
+        saddle_rb<int, true>(S, S.sM.col, x, y);
     else
-        k_saddle<int, false><<<g, kBlock, 0, S.stream>>>(n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x,
-                                                         y, pair(S.tau_s), pair(S.te_s));
+        saddle_rb<int, false>(S, S.sM.col, x, y);
 }
 
 // y = b - A x and the partials of its norms (k_saddle_resid) on M's pattern
@@ -794,8 +863,8 @@ void compute_rhs(Solver &S)
                                                                   S.qw, S.nq, n, S.x, pots, S.f,
                                                                   S.ctl);
     }
-    sell_spmv<SP_SET, double>(st, grid(nblk(n), R), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val,
-                              S.x, len, nullptr, S.b, len);
+    sell_spmv<SP_SET, double>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val, S.x,
+                              len, nullptr, S.b, len);
     boundary_rhs(S, nullptr);
     k_rhs_second<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());

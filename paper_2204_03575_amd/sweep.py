@@ -2,12 +2,16 @@
 
 Runs are grouped by mesh size; each group is one batched solver
 (chm_create_batch): its runs share the assembled matrices and both AMG
-hierarchies, and every kernel launch of a time step covers all of them.  An
-autotuner picks, per group, the preconditioner settings (Chebyshev degree and
-interval of the As hierarchy, CG steps per As solve, HIP graphs or eager
-launches) with the shortest time per step measured on the group itself, from
-the same state, at the same residual tolerance.  All computation runs in the library; this
-module only schedules it.
+hierarchies, every kernel launch of a time step covers all of them, and the
+SELL-64 and coarsest-level kernels serve several runs per lane (each matrix
+entry a lane loads is used for runs_per_lane runs).  The groups advance
+concurrently (chm_step_many): each on its own HIP stream, driven by its own
+host thread, so the latency-bound launches of one group overlap the others.
+An autotuner picks, per group, the preconditioner settings (Chebyshev degree
+and interval of the As hierarchy, CG steps per As solve) and then the runs
+per lane, each with the shortest time per step measured on the group
+itself, from the same state, at the same residual tolerance.  All
+computation runs in the library; this module only schedules it.
 """
 from __future__ import annotations
 
@@ -20,9 +24,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SIZES = (128, 192, 256, 384, 512)
-TUNE_SPACE = [dict(cheb_degree=d, schur_pcg=k, cheb_ratio=r, use_graphs=g)
-              for (d, k, r) in ((6, 2, 5.0), (5, 2, 8.0), (4, 2, 15.0), (4, 3, 30.0))
-              for g in (1, 0)]
+# stage 1: the As preconditioner; stage 2: runs per lane with the stage-1 winner
+TUNE_PREC = [dict(cheb_degree=d, schur_pcg=k, cheb_ratio=r)
+             for (d, k, r) in ((6, 2, 5.0), (5, 2, 8.0), (4, 2, 15.0), (4, 3, 30.0))]
+TUNE_RB = (1, 2, 4)
+DEFAULT_RB = 2
 
 
 def draw_runs(count: int = 64, seed: int = 20220700):
@@ -48,13 +54,15 @@ def groups(runs):
     return dict(sorted(out.items()))
 
 
-def make_group(n: int, runs, base: dict):
+def make_group(n: int, runs, base: dict, stream=None):
+    """The batched solver of one group (on `stream`, a torch stream, or the
+    current one), every run set to its initial state."""
     import synthetic as S
     from .chm import Solver
     p = dict(S.preset("square512", n=(n, n)), **base)
     co, ce = S.make_mesh(p)
     rl = [dict(chi_pn=r["chi_pn"], evap_ds=r["evap_ds"], evap_steps=r["evap_steps"]) for r in runs]
-    g = Solver(co, ce, p, runs=rl)
+    g = Solver(co, ce, p, runs=rl, stream=None if stream is None else stream.cuda_stream)
     for i, r in enumerate(runs):
         php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"], seed=r["seed"])
         g.set_fields(php, phn, run=i)
@@ -70,18 +78,44 @@ def timed_steps(g, steps: int):
     return time.perf_counter() - t0, st
 
 
+def timed_many(gs, steps: int):
+    """`steps` time steps of every solver of gs, concurrently (chm_step_many)."""
+    import torch
+    from .chm import step_many
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = step_many(gs, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
+
+
+def _time_candidate(n, runs, base, cand, steps, log):
+    g, _ = make_group(n, runs, dict(base, **cand))
+    g.step(1)
+    dt, _ = timed_steps(g, steps)
+    del g
+    log(f"#   {n}x{n} {cand}: {1e3 * dt / steps:.2f} ms/step")
+    return dt
+
+
 def autotune(n: int, runs, base: dict, steps: int = 2, log=print):
-    """The TUNE_SPACE entry with the shortest time per step for this group
-    (one warm-up step, then `steps` timed ones, from the group's initial state)."""
+    """Per group: the TUNE_PREC entry with the shortest time per step (runs per
+    lane DEFAULT_RB), then the TUNE_RB value with the shortest time for it
+    (one warm-up step, then `steps` timed ones, from the group's initial
+    state each time)."""
     best, best_t = None, float("inf")
-    for cand in TUNE_SPACE:
-        g, _ = make_group(n, runs, dict(base, **cand))
-        g.step(1)
-        dt, _ = timed_steps(g, steps)
-        del g
-        log(f"#   {n}x{n} {cand}: {1e3 * dt / steps:.2f} ms/step")
+    for cand in TUNE_PREC:
+        dt = _time_candidate(n, runs, base, dict(cand, runs_per_lane=DEFAULT_RB), steps, log)
         if dt < best_t:
-            best, best_t = cand, dt
+            best, best_t = dict(cand, runs_per_lane=DEFAULT_RB), dt
+    if len(runs) > 1:
+        for rb in TUNE_RB:
+            if rb == DEFAULT_RB:
+                continue
+            cand = dict(best, runs_per_lane=rb)
+            dt = _time_candidate(n, runs, base, cand, steps, log)
+            if dt < best_t:
+                best, best_t = cand, dt
     return best
 
 

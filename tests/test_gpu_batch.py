@@ -48,10 +48,18 @@ W512 = dict(mass_solver="chebyshev", cheb_degree_mass=5, cheb_degree=6, cheb_rat
             schur_pcg=2)
 
 
+BOX = dict(dim=3, n=(6, 5, 4), extent=(1.0, 1.0, 0.8))
+
+
 @pytest.mark.parametrize("runs,precision,guess,extra", [
     (1, "fp64", "previous", {}), (5, "fp64", "previous", {}), (7, "fp32", "previous", {}),
-    (4, "fp64", "linear", {}), (3, "fp32", "linear", W512)],
-    ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear", "3-fp32-linear-w512"])
+    (4, "fp64", "linear", {}), (3, "fp32", "linear", W512),
+    (5, "fp64", "previous", dict(runs_per_lane=1)), (5, "fp64", "linear", dict(runs_per_lane=4)),
+    (6, "fp32", "linear", dict(W512, runs_per_lane=4)), (7, "fp32", "previous", dict(runs_per_lane=4)),
+    (3, "fp64", "previous", dict(BOX, runs_per_lane=4)), (5, "fp32", "previous", dict(BOX))],
+    ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear", "3-fp32-linear-w512", "5-fp64-rb1",
+         "5-fp64-linear-rb4", "6-fp32-linear-w512-rb4", "7-fp32-rb4", "3-fp64-3d-rb4",
+         "5-fp32-3d"])
 def test_batch_runs_equal_single_runs_bitwise(runs, precision, guess, extra):
     case("batch vs single runs", runs=runs, precision=precision, guess=guess, **extra)
     from paper_2204_03575_amd import Solver
@@ -141,3 +149,40 @@ def test_batch_argument_checks():
     with pytest.raises(ChmError):
         b.set_fields(np.zeros(49), np.zeros(49), run=2)
     assert b.lib.chm_batch_size(b.h) == 2
+
+
+def test_step_many_equals_separate_steps():
+    """chm_step_many: solvers on their own streams, advanced concurrently by one
+    host thread each, take the iterates they take when stepped one by one."""
+    case("chm_step_many vs separate chm_step")
+    import torch
+
+    from paper_2204_03575_amd import Solver, step_many
+    cfgs = [(dict(S.preset("square32", n=(24, 20))), 3), (dict(S.preset("square32", n=(30, 28)), precision="fp32"), 4),
+            (dict(S.preset("square32", n=(16, 16))), 1)]
+
+    def make(p, runs, stream=None):
+        co, ce = S.make_mesh(p)
+        nv = co.shape[0]
+        g = Solver(co, ce, p, runs=run_list(runs) if runs > 1 else None,
+                   stream=None if stream is None else stream.cuda_stream)
+        for r in range(runs):
+            g.set_fields(*initial(nv, r, p), run=r)
+        return g
+
+    streams = [torch.cuda.Stream() for _ in cfgs]
+    many = [make(p, r, st) for (p, r), st in zip(cfgs, streams)]
+    got = step_many(many, 3)
+    torch.cuda.synchronize()
+    for k, (p, runs) in enumerate(cfgs):
+        one = make(p, runs)
+        ref = one.step(3)
+        keys = ("iters", "relres", "status")
+        for i in range(3):
+            a = [got[k][i]] if runs == 1 else got[k][i]
+            b = [ref[i]] if runs == 1 else ref[i]
+            assert [[x[q] for q in keys] for x in a] == [[x[q] for q in keys] for x in b], (k, i)
+        for r in range(runs):
+            fa, fb = many[k].get_fields(run=r), one.get_fields(run=r)
+            for f in FIELDS:
+                assert np.array_equal(fa[f], fb[f]), (k, r, f)
