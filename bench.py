@@ -357,6 +357,19 @@ def sweep_main(args):
         log(f"# {label}: {out['run_steps_per_s']:.1f} run-steps/s ({dt:.3f} s)")
         return out
 
+    if tuned:
+        # the groups run together, so what counts is the throughput of all of
+        # them at once: keep the per-group choices only if the whole sweep
+        # runs faster with them than with the workload's own settings
+        trial = {}
+        for label, settings in (("per-group", tuned), ("defaults", {})):
+            gs, _ = build(settings)
+            W.timed_many(gs, 2)
+            trial[label] = W.timed_many(gs, 3)[0]
+            del gs
+            log(f"# sweep-level check, {label} settings: {1e3 * trial[label] / 3:.2f} ms/step")
+        if trial["defaults"] <= trial["per-group"]:
+            tuned = {n: dict(W.TUNE_PREC[0], runs_per_lane=W.TUNE_RB[0]) for n in G}
     out_modes = {}
     plans = [("concurrent+tuned", tuned, True), ("sequential+tuned", tuned, False),
              ("concurrent+defaults", {}, True)]

@@ -39,18 +39,23 @@ template <class T> __device__ inline pair_t<T> mk(T a, T b);
 template <> __device__ inline double2 mk<double>(double a, double b) { return make_double2(a, b); }
 template <> __device__ inline float2 mk<float>(float a, float b) { return make_float2(a, b); }
 
-// XCD-aware block index.  The hardware hands workgroup b to XCD b mod 8; this
-// renumbering gives every XCD one contiguous range of blocks, so the
-// neighbouring rows that an SpMV row gathers from mostly sit in the same
-// XCD's L2.  It is a bijection of [0, gridDim.x).
+// XCD-aware block index.  The hardware hands workgroup (b, y) of a grid G
+// blocks wide to XCD (y G + b) mod 8; this renumbering gives every XCD one
+// contiguous range of the blocks of each grid row y, so the neighbouring rows
+// that an SpMV row gathers from mostly sit in the same XCD's L2.  For each y
+// it is a bijection of [0, G).
 constexpr int kXcds = 8;
 
 __device__ inline int xcd_block()
 {
     const int G = gridDim.x, b = blockIdx.x;
-    const int q = G / kXcds, r = G % kXcds;
-    const int x = b % kXcds, j = b / kXcds;
-    return x * q + min(x, r) + j;
+    const int off = (int)((blockIdx.y * (unsigned)G) % kXcds);   // rotation of row y
+    const int x = (b + off) % kXcds;                              // this block's XCD
+    const int j = (b - (x - off + kXcds) % kXcds) / kXcds;        // its rank on that XCD
+    int start = 0;                                                // blocks of earlier XCDs
+    for (int k = 0; k < x; ++k)
+        start += (G - (k - off + kXcds) % kXcds + kXcds - 1) / kXcds;
+    return start + j;
 }
 
 __device__ inline double2 wave_sum(double2 v)
