@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--n", type=int, default=512,
                     help="squares per side of the unit square (square512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--coarse-degree", type=int, default=None,
+                    help="As hierarchy: smoother degree below the finest level (overrides the "
+                         "workload's setting; 0 = the fine-level degree)")
     ap.add_argument("--wide-index", action="store_true",
                     help="keep 32-bit SELL column indices (the comparison run for the 16-bit "
                          "column offsets; bitwise the same results)")
@@ -490,6 +493,8 @@ def main():
         p = S.preset("box96")
     if args.wide_index:
         p["wide_index"] = 1
+    if args.coarse_degree is not None:
+        p["cheb_degree_coarse"] = args.coarse_degree
     if args.batch > 1:
         batch_main(args, p)
         return

@@ -173,6 +173,10 @@ typedef struct {
      * trades matrix traffic against registers per lane.  Ignored for one
      * run. */
     int32_t runs_per_lane;
+    /* As hierarchy: Chebyshev degree (or Jacobi sweeps) of the smoother on
+     * every level below the finest, over the same interval [rho/cheb_ratio,
+     * rho] of each level's own rho; 0 = cheb_degree on every level. */
+    int32_t cheb_degree_coarse;
 } chm_params_t;
 
 /* Per-step statistics. */

@@ -45,6 +45,7 @@ typedef struct {
 
 typedef struct {
     int n;
+    int degree;      /* smoother degree (Chebyshev) or sweeps (Jacobi) on this level */
     csr_t A;
     double *invdiag;
     double rho;      /* Gershgorin bound of the spectrum of D^-1 A */
@@ -57,7 +58,6 @@ typedef struct {
 typedef struct {
     int nlev;
     double ratio; /* Chebyshev interval [rho/ratio, rho] */
-    int degree;   /* Chebyshev degree or Jacobi sweeps */
     level_t lev[MAXLEV];
 } hier_t;
 
@@ -757,13 +757,14 @@ static void hier_free(hier_t *h)
     memset(h, 0, sizeof(*h));
 }
 
+/* degree: the smoother degree of the finest level; degree_coarse: of the  */
+/* levels below it (0: degree)                                            */
 static int hier_build(const orc_params_t *prm, const csr_t *A0, double ratio, int degree,
-                      hier_t *h)
+                      int degree_coarse, hier_t *h)
 {
     int rc;
     memset(h, 0, sizeof(*h));
     h->ratio = ratio;
-    h->degree = degree;
     int maxlev = prm->max_levels < MAXLEV ? prm->max_levels : MAXLEV;
     if (maxlev < 1)
         maxlev = 1;
@@ -778,6 +779,7 @@ static int hier_build(const orc_params_t *prm, const csr_t *A0, double ratio, in
     h->nlev = 1;
     for (int l = 0;; ++l) {
         level_t *L = &h->lev[l];
+        L->degree = (l > 0 && degree_coarse > 0) ? degree_coarse : degree;
         if ((rc = level_diag(L)))
             return rc;
         if (L->n <= prm->coarse_max || l + 1 >= maxlev)
@@ -858,7 +860,7 @@ static void smooth(const orc_params_t *prm, const hier_t *h, const level_t *L, c
     int n = L->n;
     if (prm->smoother == ORC_SMOOTH_JACOBI) {
         double omega = 4.0 / (3.0 * L->rho);
-        for (int it = 0; it < h->degree; ++it) {
+        for (int it = 0; it < L->degree; ++it) {
             csr_mv(&L->A, x, r);
             #pragma omp parallel for schedule(static) if (n >= 4096)
             for (int i = 0; i < n; ++i)
@@ -873,11 +875,11 @@ static void smooth(const orc_params_t *prm, const hier_t *h, const level_t *L, c
     #pragma omp parallel for schedule(static) if (n >= 4096)
     for (int i = 0; i < n; ++i)
         d[i] = L->invdiag[i] * (b[i] - r[i]) / theta;
-    for (int k = 1; k <= h->degree; ++k) {
+    for (int k = 1; k <= L->degree; ++k) {
         #pragma omp parallel for schedule(static) if (n >= 4096)
         for (int i = 0; i < n; ++i)
             x[i] += d[i];
-        if (k == h->degree)
+        if (k == L->degree)
             break;
         csr_mv(&L->A, x, r);
         double rho = 1.0 / (2.0 * sigma - rho_old);
@@ -1375,7 +1377,8 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
     if (!(prm->tau > 0.0) || !(prm->eps[0] > 0.0) || !(prm->eps[1] > 0.0)
         || !(prm->mobility[0] > 0.0) || !(prm->mobility[1] > 0.0) || prm->restart < 1
         || !(prm->cheb_ratio > 1.0) || !(prm->cheb_ratio_mass > 1.0) || prm->cheb_degree < 1
-        || prm->cheb_degree_mass < 1 || prm->amg_cycles < 1 || prm->schur_pcg < 0
+        || prm->cheb_degree_mass < 1 || prm->cheb_degree_coarse < 0 || prm->amg_cycles < 1
+        || prm->schur_pcg < 0
         || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
         || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0)
         || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol)
@@ -1406,9 +1409,10 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
                 s->As[sp].v[k] = t * s->K.v[k] + sq * s->M.v[k];
     }
     if (!rc)
-        rc = hier_build(prm, &s->M, prm->cheb_ratio_mass, prm->cheb_degree_mass, &s->hM);
+        rc = hier_build(prm, &s->M, prm->cheb_ratio_mass, prm->cheb_degree_mass, 0, &s->hM);
     for (int sp = 0; sp < 2 && !rc; ++sp)
-        rc = hier_build(prm, &s->As[sp], prm->cheb_ratio, prm->cheb_degree, &s->hA[sp]);
+        rc = hier_build(prm, &s->As[sp], prm->cheb_ratio, prm->cheb_degree,
+                        prm->cheb_degree_coarse, &s->hA[sp]);
     if (rc) {
         orc_destroy(s);
         return rc;

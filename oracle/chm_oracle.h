@@ -89,6 +89,10 @@ typedef struct {
      * over [rho/cheb_ratio_mass, rho] from zero, no coarse levels (the
      * mass hierarchy's fine-level smoother applied once). */
     int32_t mass_solver;
+    /* As hierarchies: Chebyshev degree (or Jacobi sweeps) of the smoother on
+     * the levels below the finest, each over [rho/cheb_ratio, rho] of its own
+     * rho (the paper leaves the AMG smoother open); 0 = cheb_degree. */
+    int32_t cheb_degree_coarse;
 } orc_params_t;
 
 /* FGMRES (right preconditioned, any Algorithm 1), or preconditioned MINRES

@@ -42,7 +42,7 @@ class orc_params_t(C.Structure):
         ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
-        ("amg_tol", C.c_double), ("mass_solver", C.c_int32),
+        ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("cheb_degree_coarse", C.c_int32),
     ]
 
 
@@ -142,6 +142,7 @@ def oracle_params(p: dict) -> orc_params_t:
     s.krylov = {"fgmres": 0, "minres": 1}[p.get("krylov", "fgmres")]
     s.amg_tol = float(p.get("amg_tol", 0.0))
     s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
+    s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
     return s
 
 

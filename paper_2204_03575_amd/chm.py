@@ -66,7 +66,7 @@ class chm_params_t(C.Structure):
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
-        ("runs_per_lane", C.c_int32),
+        ("runs_per_lane", C.c_int32), ("cheb_degree_coarse", C.c_int32),
     ]
 
 
@@ -177,6 +177,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
     s.wide_index = int(p.get("wide_index", 0))
     s.runs_per_lane = int(p.get("runs_per_lane", 0))
+    s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
     return s
 
 

@@ -736,7 +736,8 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         L.rho = reduce_max_host(ratio, n, tmp, st);
         if (read_int(flags, st))
             throw Failure(CHM_EINVAL, "AMG level " + std::to_string(l) + " has a non-positive diagonal");
-        chebyshev_coefficients(L, H.degree, H.ratio);
+        L.degree = (l > 0 && H.degree_coarse > 0) ? H.degree_coarse : H.degree;
+        chebyshev_coefficients(L, L.degree, H.ratio);
         if (n <= S.prm.coarse_max || l + 1 >= max_levels)
             break;
 

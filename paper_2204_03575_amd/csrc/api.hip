@@ -87,6 +87,8 @@ const char *check_params(const chm_params_t &p)
         return "wide_index must be 0 or 1";
     if (p.runs_per_lane != 0 && p.runs_per_lane != 1 && p.runs_per_lane != 2 && p.runs_per_lane != 4)
         return "runs_per_lane must be 0, 1, 2 or 4";
+    if (p.cheb_degree_coarse < 0 || p.cheb_degree_coarse > 31)
+        return "cheb_degree_coarse must be in 0..31";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -228,6 +230,7 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         S.hM.ratio = S.prm.cheb_ratio_mass;
         S.hM.jacobi = S.prm.smoother == CHM_SMOOTH_JACOBI;
         S.hA.degree = S.prm.cheb_degree;
+        S.hA.degree_coarse = S.prm.cheb_degree_coarse;
         S.hA.ratio = S.prm.cheb_ratio;
         S.hA.jacobi = S.hM.jacobi;
         chm::amg_build(S, S.hM, S.M);

@@ -110,6 +110,7 @@ template <class T> struct MatView {
 
 struct Level {
     int n = 0, nc = 0;
+    int degree = 2;      // smoother degree (Chebyshev) or sweeps (Jacobi) on this level
     Csr A, P, R;
     Sell sA, sP, sR;
     int gsA = 0, gsP = 0, gsR = 0;   // lanes per row (see MatView)
@@ -161,7 +162,8 @@ template <> inline const float *Level::dinv_t<float>() const { return fdinv; }
 
 struct Hierarchy {
     int nlev = 0;
-    int degree = 2;
+    int degree = 2;          // smoother degree of the finest level
+    int degree_coarse = 0;   // of the levels below it (0: degree)
     double ratio = 30.0;
     bool jacobi = false;
     Level lev[kMaxLevels];

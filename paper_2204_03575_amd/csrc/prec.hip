@@ -692,7 +692,7 @@ pair_t<T> *presmooth(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<
                      pair_t<T> *other)
 {
     const Level &L = H.lev[l];
-    const int deg = H.degree, R = S.nrun;
+    const int deg = L.degree, R = S.nrun;
     auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
     pair_t<T> *cur = first, *oth = other;
@@ -730,7 +730,7 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
         return;
     }
     const Vecs<T> V = vecs<T>(H, l), Vc = vecs<T>(H, l + 1);
-    const int deg = H.degree;
+    const int deg = L.degree;
     auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
     // Pre-smoothing from zero.  Every step after the first writes the buffer
@@ -771,7 +771,7 @@ void stationary(Solver &S, Hierarchy &H, const pair_t<T> *b, pair_t<T> *x)
         // the Chebyshev semi-iteration on M instead of V-cycles: the mass
         // hierarchy's fine-level smoother from zero, landing in x
         pair_t<T> *xt = vecs<T>(H, 0).xt;
-        const bool odd = H.degree % 2 == 1;
+        const bool odd = L0.degree % 2 == 1;
         presmooth<T>(S, H, 0, b, odd ? x : xt, odd ? xt : x);
         return;
     }

@@ -168,11 +168,12 @@ PRESETS = {
     # fastest per time step on this mesh: the mass block of Algorithm 1 is a
     # degree-5 Chebyshev semi-iteration (as accurate as the mass V-cycle here,
     # with no coarse levels); each As solve is 2 CG steps with V-cycles whose
-    # degree-6 Chebyshev smoother covers [rho/5, rho].
+    # degree-6 Chebyshev smoother covers [rho/5, rho] (degree 4 below the
+    # finest level).
     "square512": dict(_COMMON, dim=2, n=(512, 512), extent=(1.0, 1.0), coarse_max=2048,
                       mean_p=0.1, mean_n=0.1, steps=200, evap_ds=0.0025, evap_stop=0.3,
                       mass_solver="chebyshev", cheb_degree_mass=5,
-                      cheb_degree=6, cheb_ratio=5.0, schur_pcg=2),
+                      cheb_degree=6, cheb_ratio=5.0, schur_pcg=2, cheb_degree_coarse=4),
     # The paper's 2D experiment (Section 4): a 10 x 2.5 film (y is the height),
     # polynomial potential, phi_p = phi_n = 0.35 +- 0.01, solvent evaporation
     # through the top (k = 5e-3) and a patterned substrate at the bottom
@@ -183,10 +184,12 @@ PRESETS = {
     # 3D box of 96x96x48 cubes, Kuhn tetrahedra, 50 steps; the mass block as
     # for square512, each As solve one CG step (a V-cycle with the optimal
     # scaling): the outer iteration count hardly depends on the As accuracy
-    # here, so the cheapest As solve is the fastest.
+    # here, so the cheapest As solve is the fastest; for the same reason the
+    # levels below the finest smooth with a single step.
     "box96": dict(_COMMON, dim=3, n=(96, 96, 48), extent=(1.0, 1.0, 0.5), coarse_max=2048,
                   mean_p=0.1, mean_n=0.1, steps=50, evap_ds=0.0, evap_stop=0.0,
-                  mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=1),
+                  mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=1,
+                  cheb_degree_coarse=1),
 }
 
 

@@ -196,8 +196,13 @@ def test_square32_free_running_trajectory():
          amg_cycles=2),
     dict(cheb_degree=1, cheb_degree_mass=1),          # one smoothing step: no fused first steps
     dict(cheb_degree=2, cheb_degree_mass=2, mass_solver="chebyshev"),   # the fused steps only
+    dict(cheb_degree=4, cheb_degree_coarse=1, coarse_max=12),     # coarse levels of degree 1
+    dict(cheb_degree=6, cheb_degree_coarse=3, coarse_max=12, cheb_ratio=5.0,
+         mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=2),
+    dict(smoother="jacobi", cheb_degree=3, cheb_degree_coarse=1, coarse_max=12),
 ], ids=["poly", "jacobi", "stationary", "restart5", "tau-eps-mob", "nopot", "mass-cheb",
-        "mass-jacobi", "mass-cheb-minres", "degree1", "degree2"])
+        "mass-jacobi", "mass-cheb-minres", "degree1", "degree2", "coarse1", "coarse3",
+        "jacobi-coarse1"])
 def test_step_variants(variant):
     v = dict(variant)
     mean = v.pop("mean", (0.1, 0.1))
@@ -212,6 +217,15 @@ def test_3d_box_steps(mass):
     case("3d box 6x6x4, 2 steps", mass_solver=mass)
     p, co, ce, g, o = make(n=(6, 6, 4), dim=3, extent=(1.0, 1.0, 0.5), mass_solver=mass,
                            cheb_degree_mass=5 if mass == "chebyshev" else 2)
+    run_pair(p, co, ce, g, o, 2)
+
+
+def test_3d_box_coarse_degree_steps():
+    """the 3D box workload's setting: coarse levels smoothed with one step"""
+    case("3d box 10x9x6, coarse degree 1, 2 steps")
+    p, co, ce, g, o = make(n=(10, 9, 6), dim=3, extent=(1.0, 1.0, 0.5), mass_solver="chebyshev",
+                           cheb_degree_mass=5, schur_pcg=1, cheb_degree_coarse=1, coarse_max=30)
+    assert g.num_levels(1) >= 3
     run_pair(p, co, ce, g, o, 2)
 
 

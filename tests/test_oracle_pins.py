@@ -605,6 +605,37 @@ def test_chebyshev_smoother_error_polynomial(hier, degree, ratio):
     assert np.abs(E - E_ref).max() < 1e-11, np.abs(E - E_ref).max()
 
 
+@pytest.mark.parametrize("degree,coarse", [(4, 1), (6, 3), (2, 5), (3, 0)])
+def test_chebyshev_smoother_degree_per_level(degree, coarse):
+    """The As hierarchy smooths with cheb_degree on the finest level and with
+    cheb_degree_coarse (0: the same) below it: on every level the error
+    propagation is that level's Chebyshev polynomial of its own degree, on the
+    interval of its own rho."""
+    ratio = 8.0
+    p, co, ce, o = small((12, 10), cheb_degree=degree, cheb_degree_coarse=coarse,
+                         cheb_ratio=ratio, coarse_max=12)
+    assert o.num_levels(1) >= 3
+    for lev in range(o.num_levels(1) - 1):
+        d = o.level(1, lev)
+        n = d["n"]
+        A = sp.csr_matrix((d["A"][2], d["A"][1], d["A"][0]), shape=(n, n)).toarray()
+        E = np.zeros((n, n))
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = 1.0
+            E[:, j] = e - o.smooth(1, lev, A @ e, np.zeros(n))
+        k = degree if (lev == 0 or coarse == 0) else coarse
+        lmax = d["rho"]
+        lmin = lmax / ratio
+        theta, delta = (lmax + lmin) / 2, (lmax - lmin) / 2
+        Dh = np.sqrt(np.diag(A))
+        lam, Q = la.eigh(A / np.outer(Dh, Dh))
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(k)
+        E_ref = (Q * (Tk((theta - lam) / delta) / Tk(theta / delta))) @ Q.T
+        E_ref = E_ref * Dh[None, :] / Dh[:, None]
+        assert np.abs(E - E_ref).max() < 1e-10, (lev, k, np.abs(E - E_ref).max())
+
+
 def test_inner_cg_is_krylov_optimal():
     """k CG steps with preconditioner V minimise the As-norm error over K_k(VA, Vb)."""
     k = 3
