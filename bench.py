@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--n", type=int, default=512,
                     help="squares per side of the unit square (square512 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="box96/square512: override a preset parameter (repeatable; numbers "
+                         "are parsed as int or float)")
     ap.add_argument("--coarse-degree", type=int, default=None,
                     help="As hierarchy: smoother degree below the finest level (overrides the "
                          "workload's setting; 0 = the fine-level degree)")
@@ -495,6 +498,15 @@ def main():
         p["wide_index"] = 1
     if args.coarse_degree is not None:
         p["cheb_degree_coarse"] = args.coarse_degree
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        try:
+            p[k] = int(v)
+        except ValueError:
+            try:
+                p[k] = float(v)
+            except ValueError:
+                p[k] = v
     if args.batch > 1:
         batch_main(args, p)
         return

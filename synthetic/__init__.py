@@ -181,15 +181,17 @@ PRESETS = {
     "paper2d": dict(_COMMON, dim=2, n=(96, 24), extent=(10.0, 2.5), potential="polynomial",
                     mean_p=0.35, mean_n=0.35, steps=5, evap_ds=0.0, evap_stop=0.0,
                     boundary=1, bc_k=5e-3, bc_g=(0.01, 0.01), bc_h=(0.0, 0.0), bc_pattern=1),
-    # 3D box of 96x96x48 cubes, Kuhn tetrahedra, 50 steps; the mass block as
-    # for square512, each As solve one CG step (a V-cycle with the optimal
-    # scaling): the outer iteration count hardly depends on the As accuracy
-    # here, so the cheapest As solve is the fastest; for the same reason the
-    # levels below the finest smooth with a single step.
+    # 3D box of 96x96x48 cubes, Kuhn tetrahedra, 50 steps.  Measured fastest
+    # per time step in a sweep of these settings: the mass block a degree-3
+    # Chebyshev semi-iteration (the 3D mass matrix is well conditioned); each
+    # As solve one CG step (a V-cycle with the optimal scaling) whose
+    # smoother has degree 5 over [rho/20, rho] on the finest level and a
+    # single step below it (the outer iteration count hardly depends on the
+    # coarse levels' accuracy here).
     "box96": dict(_COMMON, dim=3, n=(96, 96, 48), extent=(1.0, 1.0, 0.5), coarse_max=2048,
                   mean_p=0.1, mean_n=0.1, steps=50, evap_ds=0.0, evap_stop=0.0,
-                  mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=1,
-                  cheb_degree_coarse=1),
+                  mass_solver="chebyshev", cheb_degree_mass=3, schur_pcg=1,
+                  cheb_degree=5, cheb_ratio=20.0, cheb_degree_coarse=1),
 }
 
 
