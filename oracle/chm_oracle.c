@@ -71,6 +71,7 @@ struct orc_solver {
     int nq;
     double qb[64 * 4], qw[64];
     int64_t step_count;
+    double vc_rho; /* measured V-cycle contraction (schur_pcg = -1), else 0 */
 };
 
 /* ------------------------------------------------------------------ */
@@ -1015,6 +1016,49 @@ static void amg_pcg(const orc_params_t *prm, const hier_t *h, int k, const doubl
     free(q);
 }
 
+/* Contraction of one V-cycle V of an As hierarchy in the As-norm, for     */
+/* choosing the number of inner CG steps (schur_pcg = -1): the power       */
+/* iteration e <- (I - V As) e, six steps, from the start e_i = 2u - 1     */
+/* with u the top 53 bits of SplitMix64 counter 2^32 + 2 i + species       */
+/* divided by 2^53; the result is ||e_6||_As / ||e_5||_As.  The V-cycle is */
+/* symmetric, so I - V As is self-adjoint in the As inner product and the  */
+/* ratio approaches its spectral radius from below.  Returns -1 when out  */
+/* of memory.                                                             */
+static double vcycle_contraction(const orc_params_t *prm, const hier_t *h, int species)
+{
+    const csr_t *A = &h->lev[0].A;
+    int n = A->n;
+    double *e = malloc(sizeof(double) * (size_t)n), *q = malloc(sizeof(double) * (size_t)n);
+    double *z = malloc(sizeof(double) * (size_t)n);
+    if (!e || !q || !z) {
+        free(e);
+        free(q);
+        free(z);
+        return -1.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        uint64_t c = (1ull << 32) + 2ull * (uint64_t)i + (uint64_t)species;
+        e[i] = 2.0 * ((double)(mix64(c) >> 11) / 9007199254740992.0) - 1.0;
+    }
+    double prev = 0.0, rho = 0.0;
+    for (int it = 0; it <= 6; ++it) {
+        csr_mv(A, e, q);
+        double a = dot(n, e, q);
+        if (it > 0)
+            rho = prev > 0.0 ? sqrt((a > 0.0 ? a : 0.0) / prev) : 0.0;
+        prev = a;
+        if (it == 6)
+            break;
+        vcycle(prm, h, 0, q, z);
+        for (int i = 0; i < n; ++i)
+            e[i] -= z[i];
+    }
+    free(e);
+    free(q);
+    free(z);
+    return rho;
+}
+
 /* the AMG solve used for the As systems of Algorithm 1 */
 static void amg_schur(const orc_params_t *prm, const hier_t *h, const double *b, double *x)
 {
@@ -1378,7 +1422,7 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
         || !(prm->mobility[0] > 0.0) || !(prm->mobility[1] > 0.0) || prm->restart < 1
         || !(prm->cheb_ratio > 1.0) || !(prm->cheb_ratio_mass > 1.0) || prm->cheb_degree < 1
         || prm->cheb_degree_mass < 1 || prm->cheb_degree_coarse < 0 || prm->amg_cycles < 1
-        || prm->schur_pcg < 0
+        || prm->schur_pcg < -1 || (prm->schur_pcg < 0 && prm->krylov != ORC_KRYLOV_FGMRES)
         || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
         || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0)
         || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol)
@@ -1413,11 +1457,30 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
     for (int sp = 0; sp < 2 && !rc; ++sp)
         rc = hier_build(prm, &s->As[sp], prm->cheb_ratio, prm->cheb_degree,
                         prm->cheb_degree_coarse, &s->hA[sp]);
+    if (!rc && prm->schur_pcg < 0) {
+        /* automatic inner CG steps from the measured V-cycle contraction */
+        double r0 = vcycle_contraction(prm, &s->hA[0], 0), r1 = vcycle_contraction(prm, &s->hA[1], 1);
+        if (r0 < 0.0 || r1 < 0.0)
+            rc = ORC_ENOMEM;
+        s->vc_rho = r0 > r1 ? r0 : r1;
+        s->prm.schur_pcg = s->vc_rho <= 0.3 ? 2 : (s->vc_rho <= 0.6 ? 4 : 6);
+    }
     if (rc) {
         orc_destroy(s);
         return rc;
     }
     *out = s;
+    return ORC_OK;
+}
+
+int orc_schur_info(const orc_solver_t *s, int32_t *schur_pcg, double *contraction)
+{
+    if (!s)
+        return ORC_EINVAL;
+    if (schur_pcg)
+        *schur_pcg = s->prm.schur_pcg;
+    if (contraction)
+        *contraction = s->vc_rho;
     return ORC_OK;
 }
 

@@ -58,7 +58,10 @@ typedef struct {
     int32_t restart;     /* FGMRES restart length m */
     int32_t max_iters;   /* total FGMRES iterations allowed per solve */
     int32_t amg_cycles;  /* V-cycles per stationary AMG solve (mass solves); the cap when amg_tol > 0 */
-    int32_t schur_pcg;   /* CG steps (one V-cycle each) per As solve; 0 = stationary */
+    int32_t schur_pcg;   /* CG steps (one V-cycle each) per As solve; 0 = stationary;
+                            -1 = chosen at creation (FGMRES only): 2 if the measured
+                            contraction of one As V-cycle is at most 0.3, 4 up to
+                            0.6, else 6 (orc_schur_info) */
     int32_t smoother;    /* ORC_SMOOTH_* */
     int32_t cheb_degree; /* As hierarchies: Chebyshev degree (pre and post) or Jacobi sweeps */
     double cheb_ratio;   /* As hierarchies: Chebyshev interval [rho/ratio, rho] */
@@ -156,6 +159,10 @@ int orc_minres(const orc_solver_t *s, int species, const double *b, double *x,
 int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun,
              orc_stats_t *st);
 double orc_energy(const orc_solver_t *s, const double *php, const double *phn);
+
+/* The CG steps per As solve in use and the measured V-cycle contraction
+ * (0 unless schur_pcg was -1). */
+int orc_schur_info(const orc_solver_t *s, int32_t *schur_pcg, double *contraction);
 
 /* Host threads of the solve's row loops (n > 0 sets them; returns the count in
  * use).  Results do not depend on it. */

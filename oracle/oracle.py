@@ -100,6 +100,7 @@ def load_library():
         lib.orc_step.argtypes = [vp, vp, vp, vp, vp, P(orc_stats_t)]
         lib.orc_energy.argtypes = [vp, vp, vp]
         lib.orc_energy.restype = d
+        lib.orc_schur_info.argtypes = [vp, P(i32), P(d)]
         lib.orc_threads.argtypes = [C.c_int]
         lib.orc_threads.restype = C.c_int
         _lib = lib
@@ -363,6 +364,14 @@ class Oracle:
         if rc:
             raise OracleError(rc, f"orc_step (stats {stats})")
         return dict(phi_p=php, phi_n=phn, mu_p=mup, mu_n=mun, stats=stats)
+
+    def schur_info(self):
+        """(CG steps per As solve in use, measured V-cycle contraction or 0)."""
+        k, rho = C.c_int32(), C.c_double()
+        rc = self.lib.orc_schur_info(self.h, C.byref(k), C.byref(rho))
+        if rc:
+            raise OracleError(rc, "orc_schur_info")
+        return k.value, rho.value
 
     def energy(self, php: np.ndarray, phn: np.ndarray) -> float:
         php = np.ascontiguousarray(php, dtype=np.float64)

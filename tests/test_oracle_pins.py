@@ -690,3 +690,65 @@ def test_oracle_threads_do_not_change_results():
     assert out[1]["stats"]["iters"] == out[4]["stats"]["iters"]
     for f in ("phi_p", "phi_n", "mu_p", "mu_n"):
         assert np.array_equal(out[1][f], out[4][f]), f
+
+
+def _film(points, **kw):
+    """the paper's film problem (10 x 2.5, Section 4) on `points` vertices per direction"""
+    from paper_2204_03575_amd import robustness as R
+    p = R.case_params(points, "fgmres", **kw)
+    co, ce = S.make_mesh(p)
+    return p, co, ce, Oracle(co, ce, p)
+
+
+@pytest.mark.parametrize("tau,k_expected", [(1e-2, 2), (1e-1, 4)])
+def test_vcycle_contraction_by_brute_force(tau, k_expected):
+    """schur_pcg = -1: the oracle measures the As-norm contraction of one
+    V-cycle by six steps of the power iteration e <- (I - V As) e from a
+    SplitMix64 start and picks 2, 4 or 6 CG steps.  Brute force: the dense
+    error propagator E = I - V As from the V-cycle's columns, the start from
+    the generator written independently in the input module, six powers of E,
+    and the As-norm ratio of the last step; the exact spectral radius of E
+    bounds it from above."""
+    p, co, ce, o = _film((40, 22), eps=10.0, tau=tau, coarse_max=16, schur_pcg=-1)
+    k, rho = o.schur_info()
+    n = o.nv
+    A = o.scipy_matrix("As0").toarray()
+    V = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        V[:, j] = o.vcycle(1, e)
+    E = np.eye(n) - V @ A
+    ratios = []
+    for sp in (0, 1):
+        u = S.splitmix64(0, (1 << 32) + 2 * np.arange(n, dtype=np.uint64) + sp)
+        e = 2.0 * ((u >> np.uint64(11)).astype(np.float64) / 2.0 ** 53) - 1.0
+        for _ in range(5):
+            e = E @ e
+        e6 = E @ e
+        ratios.append(np.sqrt((e6 @ A @ e6) / (e @ A @ e)))
+    assert ratios[1] > ratios[0]   # (this mesh) the larger ratio is the second species'
+    assert rho == pytest.approx(max(ratios), rel=1e-9)
+    # E is self-adjoint in the As inner product: its spectral radius bounds the ratio
+    L = np.linalg.cholesky(A)
+    Es = L.T @ E @ np.linalg.inv(L.T)
+    rad = np.abs(np.linalg.eigvalsh(0.5 * (Es + Es.T))).max()
+    assert rho <= rad * (1 + 1e-10) and rho >= 0.6 * rad, (rho, rad)
+    assert k == k_expected == (2 if rho <= 0.3 else 4 if rho <= 0.6 else 6)
+
+
+def test_automatic_inner_steps_equal_the_fixed_steps_they_choose():
+    """A solver with schur_pcg = -1 takes exactly the steps of one created
+    with the chosen count (the choice changes nothing else)."""
+    p, co, ce, o = _film((40, 22), eps=10.0, tau=1e-1, coarse_max=16, schur_pcg=-1)
+    k, _ = o.schur_info()
+    assert k == 4
+    fixed = Oracle(co, ce, dict(p, schur_pcg=k))
+    php, phn, _ = S.initial_fractions(o.nv, p["mean_p"], p["mean_n"])
+    st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+    a, b = o.step(st), fixed.step(st)
+    assert a["stats"]["iters"] == b["stats"]["iters"]
+    for f in ("phi_p", "phi_n", "mu_p", "mu_n"):
+        assert np.array_equal(a[f], b[f])
+    with pytest.raises(OracleError):
+        Oracle(co, ce, dict(p, schur_pcg=-1, krylov="minres"))
