@@ -114,7 +114,9 @@ typedef struct {
     int32_t restart;       /* FGMRES restart length m, 1..64 */
     int32_t max_iters;     /* Krylov iterations allowed per species and step */
     int32_t amg_cycles;    /* V-cycles per mass-matrix solve */
-    int32_t schur_pcg;     /* CG steps (one V-cycle each) per As solve; 0 = amg_cycles V-cycles */
+    int32_t schur_pcg;     /* CG steps (one V-cycle each) per As solve; 0 = amg_cycles V-cycles;
+                              -1 = chosen at setup from the measured V-cycle contraction
+                              (FGMRES only; see chm_schur_info) */
     int32_t smoother;      /* CHM_SMOOTH_* */
     int32_t cheb_degree;   /* As hierarchy: Chebyshev degree or Jacobi sweeps (1..31) */
     double cheb_ratio;     /* As hierarchy: Chebyshev interval [rho/ratio, rho] */
@@ -318,6 +320,15 @@ int chm_rhs(chm_solver_t *s, double *b);
 /* the boundary vector G of the current state (run 0) into a device pair
  * vector g (double2[n]); zero without boundary terms */
 int chm_boundary(chm_solver_t *s, double *g);
+
+/* The CG steps per As solve chm_create settled on (with schur_pcg = -1:
+ * 2 when one V-cycle of the As hierarchy contracts the As-norm error by at
+ * most 0.3, 4 up to 0.6, else 6) and that contraction, measured at setup by
+ * six steps of the power iteration e <- (I - V As) e from a seeded start
+ * (SplitMix64 counters 2^32 + 2 i + s for row i and species s, mapped to
+ * [-1, 1)), as the ratio of the As-norms of the last step (0 when schur_pcg
+ * was given).  Either pointer may be NULL. */
+int chm_schur_info(const chm_solver_t *s, int32_t *schur_pcg, double *contraction);
 
 /* Host-only: the quadrature rule of the right-hand side (barycentric points
  * [npts][dim+1], weights summing to 1); bary and w hold at least 64 points. */

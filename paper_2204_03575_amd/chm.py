@@ -32,7 +32,7 @@ ENTRY_POINTS = [
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
     "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history",
-    "chm_net_guess_noalloc", "chm_step_many",
+    "chm_net_guess_noalloc", "chm_step_many", "chm_schur_info",
 ]
 
 NET_LAYERS = ((8, 32), (32, 32), (32, 32), (32, 4))
@@ -138,6 +138,7 @@ def library():
             "chm_boundary": ([vp, vp], C.c_int),
             "chm_get_history": ([vp, i32, vp, vp, P(i32), P(i64), i32], C.c_int),
             "chm_step_many": ([vp, i32, i32, vp, vp], C.c_int),
+            "chm_schur_info": ([vp, P(i32), P(d)], C.c_int),
             "chm_set_history": ([vp, i32, vp, vp, i32, i64, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -291,6 +292,13 @@ class Solver:
             err.stats = stats
             raise err
         return stats
+
+    def schur_info(self):
+        """(CG steps per As solve in use, measured V-cycle contraction or 0)."""
+        k, rho = C.c_int32(), C.c_double()
+        _check(self.h, self.lib.chm_schur_info(self.h, C.byref(k), C.byref(rho)),
+               "chm_schur_info")
+        return k.value, rho.value
 
     def get_history(self, run: int = 0) -> dict:
         """Checkpoint data beyond the fields: the last two solutions of the

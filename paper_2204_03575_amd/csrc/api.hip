@@ -57,8 +57,10 @@ const char *check_params(const chm_params_t &p)
         return "Flory-Huggins needs positive N_p, N_n, N_s and log_floor";
     if (!(p.rtol > 0.0) || p.restart < 1 || p.restart > chm::kMaxRestart || p.max_iters < 1)
         return "need rtol > 0, 1 <= restart <= 64, max_iters >= 1";
-    if (p.amg_cycles < 1 || p.schur_pcg < 0 || p.schur_pcg > 39)
-        return "need amg_cycles >= 1 and 0 <= schur_pcg <= 39";
+    if (p.amg_cycles < 1 || p.schur_pcg < -1 || p.schur_pcg > 39)
+        return "need amg_cycles >= 1 and -1 <= schur_pcg <= 39";
+    if (p.schur_pcg < 0 && p.krylov != CHM_KRYLOV_FGMRES)
+        return "the automatic inner CG steps (schur_pcg = -1) need FGMRES";
     if (p.smoother != CHM_SMOOTH_CHEBYSHEV && p.smoother != CHM_SMOOTH_JACOBI)
         return "unknown smoother";
     if (p.cheb_degree < 1 || p.cheb_degree > 31 || p.cheb_degree_mass < 1 || p.cheb_degree_mass > 31)
@@ -93,6 +95,14 @@ const char *check_params(const chm_params_t &p)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
 }
+
+// Automatic inner CG steps per As solve (schur_pcg = -1): the power
+// iteration runs kContractionIters steps, and a V-cycle contracting by rho
+// gets 2 CG steps up to kRhoTwo, 4 up to kRhoFour, else 6.
+constexpr int kContractionIters = 6;
+constexpr double kRhoTwo = 0.3, kRhoFour = 0.6;
+
+int schur_steps_for(double rho) { return rho <= kRhoTwo ? 2 : (rho <= kRhoFour ? 4 : 6); }
 
 // one field into component `comp` of a pair vector, and back out: comp 0
 // or 1, or 2 for phi_s = 1 - phi_p - phi_n (Section 2)
@@ -238,6 +248,11 @@ int chm_create_batch(const chm_mesh_t *mesh, const chm_params_t *params, int32_t
         S.mixed = S.prm.precision == CHM_PREC_FP32;
         chm::prec_setup(S);
         chm::alloc_workspace(S);
+        if (S.prm.schur_pcg < 0) {
+            // automatic inner CG steps from the measured V-cycle contraction
+            S.vc_rho = chm::vcycle_contraction(S, kContractionIters);
+            S.prm.schur_pcg = schur_steps_for(S.vc_rho);
+        }
         if (S.prm.krylov == CHM_KRYLOV_MINRES)
             chm::minres_alloc(S);
         CHM_HIP(hipStreamSynchronize(S.stream));
@@ -731,6 +746,17 @@ int chm_get_state(chm_solver_t *h, int32_t which, double *state)
 }
 
 int chm_batch_size(const chm_solver_t *h) { return h ? h->s.nb : CHM_EINVAL; }
+
+int chm_schur_info(const chm_solver_t *h, int32_t *schur_pcg, double *contraction)
+{
+    if (!h)
+        return CHM_EINVAL;
+    if (schur_pcg)
+        *schur_pcg = h->s.prm.schur_pcg;
+    if (contraction)
+        *contraction = h->s.vc_rho;
+    return CHM_OK;
+}
 
 int chm_boundary(chm_solver_t *h, double *g)
 {

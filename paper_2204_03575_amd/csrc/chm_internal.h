@@ -292,6 +292,7 @@ struct Solver {
     int *dheads = nullptr;     // device staging of the heads of a batch
     std::vector<int64_t> steps;   // per run: completed time steps (the solvent removal counts them)
     double setup_ms = 0.0;
+    double vc_rho = 0.0;       // measured V-cycle contraction of the As hierarchy (0: not measured)
     Timer timer;
     std::string nan_where;     // where the last CHM_ENAN was detected
     // HIP graphs of the FGMRES iteration body, one per Arnoldi index j,
@@ -340,6 +341,8 @@ void prec_setup(Solver &S);   // FP32 copies and work vectors (mixed precision)
 void vcycle(Solver &S, int hier, const double2 *b, double2 *x);
 void schur_solve(Solver &S, const double2 *b, double2 *x);
 void apply_prec(Solver &S, const double2 *v, double2 *w);
+// As-norm contraction of one FP64 V-cycle of the As hierarchy (power iteration)
+double vcycle_contraction(Solver &S, int iters);
 
 // ---- boundary.hip
 void boundary_setup(Solver &S);

@@ -918,7 +918,79 @@ void narrow_hierarchy(Solver &S, Hierarchy &H)
     }
 }
 
+// ------------------------------------------------------------------ V-cycle contraction
+// SplitMix64 (Steele, Lea and Flood 2014): output for counter i of stream 0
+__device__ inline uint64_t mix64(uint64_t i)
+{
+    uint64_t z = (i + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// start vector of the power iteration: species s of row i takes counter
+// 2^32 + 2 i + s, mapped to [-1, 1) through its top 53 bits
+__global__ void __launch_bounds__(kBlock) k_seed_pairs(int n, double2 *e)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint64_t c = (1ull << 32) + 2ull * (uint64_t)i;
+    const double u0 = (double)(mix64(c) >> 11) * 0x1.0p-53, u1 = (double)(mix64(c + 1) >> 11) * 0x1.0p-53;
+    e[i] = d2(2.0 * u0 - 1.0, 2.0 * u1 - 1.0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_pairs(int n, const double2 *__restrict__ z, double2 *e)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double2 a = e[i], b = z[i];
+        e[i] = d2(a.x - b.x, a.y - b.y);
+    }
+}
+
 }  // namespace
+
+// Contraction of one FP64 V-cycle V of the As hierarchy in the As-norm: the
+// power iteration e <- (I - V As) e from a seeded start, `iters` times, for
+// both species' start vectors; returns the larger of the two ratios
+// ||e_new||_As / ||e_old||_As of the last step (the symmetric V-cycle makes
+// I - V As self-adjoint in that norm, so the ratio tends to its spectral
+// radius from below).  Run 0's work vectors; synchronises the stream.
+double vcycle_contraction(Solver &S, int iters)
+{
+    Hierarchy &H = S.hA;
+    const int n = H.lev[0].n, G = red_blocks(n);
+    hipStream_t st = S.stream;
+    S.nrun = 1;
+    double2 *e = S.w64.tmp, *q = S.w64.tmp2, *z = S.w64.mr;
+    k_seed_pairs<<<nblk(n), kBlock, 0, st>>>(n, e);
+    std::vector<double2> part(G);
+    double prev[2] = {0.0, 0.0}, rho[2] = {0.0, 0.0};
+    for (int it = 0; it <= iters; ++it) {
+        spmv_op<SP_SET, double>(st, 1, 1, H.lev[0].viewA<double>(), e, nullptr, q);
+        k_dot<double><<<G, kBlock, 0, st>>>(n, e, q, slot(S, kSlotRz));
+        CHM_HIP(hipMemcpyAsync(part.data(), slot(S, kSlotRz), sizeof(double2) * G,
+                               hipMemcpyDeviceToHost, st));
+        CHM_HIP(hipStreamSynchronize(st));
+        double a[2] = {0.0, 0.0};
+        for (int g = 0; g < G; ++g) {
+            a[0] += part[g].x;
+            a[1] += part[g].y;
+        }
+        for (int s = 0; s < 2; ++s) {
+            if (it > 0)
+                rho[s] = prev[s] > 0.0 ? std::sqrt(std::max(a[s], 0.0) / prev[s]) : 0.0;
+            prev[s] = a[s];
+        }
+        if (it == iters)
+            break;
+        vcycle_level<double>(S, H, 0, q, z);
+        k_sub_pairs<<<nblk(n), kBlock, 0, st>>>(n, z, e);
+    }
+    CHM_HIP(hipGetLastError());
+    return std::max(rho[0], rho[1]);
+}
 
 void timer_mark(Solver &S, bool begin)
 {
