@@ -1426,7 +1426,8 @@ int orc_create(int dim, int64_t nv, const double *coords, int64_t nc, const int3
         || (prm->krylov != ORC_KRYLOV_FGMRES && prm->krylov != ORC_KRYLOV_MINRES)
         || (prm->krylov == ORC_KRYLOV_MINRES && prm->schur_pcg != 0)
         || !(prm->amg_tol >= 0.0) || !isfinite(prm->amg_tol)
-        || (prm->mass_solver != ORC_MASS_AMG && prm->mass_solver != ORC_MASS_CHEBYSHEV))
+        || (prm->mass_solver != ORC_MASS_AMG && prm->mass_solver != ORC_MASS_CHEBYSHEV)
+        || (prm->range_check != 0 && prm->range_check != 1))
         return ORC_EINVAL;
     for (int64_t i = 0; i < nc * (dim + 1); ++i)
         if (cells[i] < 0 || cells[i] >= nv)
@@ -1784,7 +1785,8 @@ int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun
     int n = s->nv, clamped = 0, rc;
     double *bp = malloc(sizeof(double) * 2 * (size_t)n), *bn = malloc(sizeof(double) * 2 * (size_t)n);
     double *xp = malloc(sizeof(double) * 2 * (size_t)n), *xn = malloc(sizeof(double) * 2 * (size_t)n);
-    orc_stats_t loc = {{0, 0}, {0.0, 0.0}, 0, 0};
+    orc_stats_t loc = {{0, 0}, {0.0, 0.0}, 0, 0, 0};
+    double *np_ = NULL, *nn_ = NULL;
     if ((rc = rhs_both(s, php, phn, bp, bn, &clamped)))
         goto done;
     memcpy(xp, php, sizeof(double) * n);
@@ -1809,24 +1811,42 @@ int orc_step(orc_solver_t *s, double *php, double *phn, double *mup, double *mun
             rc = ORC_ENAN;
             goto done;
         }
-    memcpy(php, xp, sizeof(double) * n);
-    memcpy(mup, xp + n, sizeof(double) * n);
-    memcpy(phn, xn, sizeof(double) * n);
-    memcpy(mun, xn + n, sizeof(double) * n);
+    /* the new volume fractions: the solve's, then the solvent removal */
+    np_ = malloc(sizeof(double) * (size_t)n);
+    nn_ = malloc(sizeof(double) * (size_t)n);
+    if (!np_ || !nn_) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    memcpy(np_, xp, sizeof(double) * n);
+    memcpy(nn_, xn, sizeof(double) * n);
     if (s->prm.evap_ds > 0.0 && s->step_count < s->prm.evap_steps) {
         double ds = s->prm.evap_ds;
         for (int i = 0; i < n; ++i) {
-            double sum = php[i] + phn[i];
+            double sum = np_[i] + nn_[i];
             if (sum > 0.0) {
-                double gp = ds * php[i] / sum, gn = ds * phn[i] / sum;
-                php[i] += gp;
-                phn[i] += gn;
+                double gp = ds * np_[i] / sum, gn = ds * nn_[i] / sum;
+                np_[i] += gp;
+                nn_[i] += gn;
             } else {
-                php[i] += 0.5 * ds;
-                phn[i] += 0.5 * ds;
+                np_[i] += 0.5 * ds;
+                nn_[i] += 0.5 * ds;
             }
         }
     }
+    for (int i = 0; i < n; ++i) {
+        double a = np_[i], b = nn_[i], c = 1.0 - np_[i] - nn_[i];
+        if (a < 0.0 || a > 1.0 || b < 0.0 || b > 1.0 || c < 0.0 || c > 1.0)
+            loc.outside++;
+    }
+    if (s->prm.range_check && loc.outside > 0) {
+        rc = ORC_EDOMAIN;
+        goto done;
+    }
+    memcpy(php, np_, sizeof(double) * n);
+    memcpy(mup, xp + n, sizeof(double) * n);
+    memcpy(phn, nn_, sizeof(double) * n);
+    memcpy(mun, xn + n, sizeof(double) * n);
     s->step_count++;
 done:
     loc.status = rc;
@@ -1836,6 +1856,8 @@ done:
     free(bn);
     free(xp);
     free(xn);
+    free(np_);
+    free(nn_);
     return rc;
 }
 

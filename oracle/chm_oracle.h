@@ -34,6 +34,7 @@ extern "C" {
 #define ORC_ENOMEM (-2)
 #define ORC_ENOCONV (-4)
 #define ORC_ENAN (-5)
+#define ORC_EDOMAIN (-6) /* the new state leaves [0, 1] (range_check) */
 
 /* potentials */
 #define ORC_POT_FLORY_HUGGINS 0
@@ -96,6 +97,12 @@ typedef struct {
      * the levels below the finest, each over [rho/cheb_ratio, rho] of its own
      * rho (the paper leaves the AMG smoother open); 0 = cheb_degree. */
     int32_t cheb_degree_coarse;
+    /* The volume fractions are physical in [0, 1] (Section 2); a step whose
+     * new state leaves that range at any vertex (the divergence the paper
+     * records for eps = 1e-4, Section 4) is counted in orc_stats_t.outside;
+     * with range_check = 1 it also fails with ORC_EDOMAIN and leaves the
+     * state unchanged. */
+    int32_t range_check;
 } orc_params_t;
 
 /* FGMRES (right preconditioned, any Algorithm 1), or preconditioned MINRES
@@ -112,6 +119,7 @@ typedef struct {
     double relres[2];
     int32_t status;
     int32_t clamped;
+    int32_t outside; /* vertices whose phi_p, phi_n or phi_s lies outside [0, 1] after the step */
 } orc_stats_t;
 
 typedef struct orc_solver orc_solver_t;

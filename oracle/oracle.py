@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 POTENTIALS = {"flory_huggins": 0, "polynomial": 1, "none": 2}
 SMOOTHERS = {"chebyshev": 0, "jacobi": 1}
-CODES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -4: "ENOCONV", -5: "ENAN"}
+CODES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -4: "ENOCONV", -5: "ENAN", -6: "EDOMAIN"}
 
 
 class OracleError(RuntimeError):
@@ -43,12 +43,13 @@ class orc_params_t(C.Structure):
         ("boundary", C.c_int32), ("bc_k", C.c_double), ("bc_g", C.c_double * 2),
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("cheb_degree_coarse", C.c_int32),
+        ("range_check", C.c_int32),
     ]
 
 
 class orc_stats_t(C.Structure):
     _fields_ = [("iters", C.c_int32 * 2), ("relres", C.c_double * 2),
-                ("status", C.c_int32), ("clamped", C.c_int32)]
+                ("status", C.c_int32), ("clamped", C.c_int32), ("outside", C.c_int32)]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -144,6 +145,7 @@ def oracle_params(p: dict) -> orc_params_t:
     s.amg_tol = float(p.get("amg_tol", 0.0))
     s.mass_solver = {"amg": 0, "chebyshev": 1}[p.get("mass_solver", "amg")]
     s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
+    s.range_check = int(p.get("range_check", 0))
     return s
 
 
@@ -360,7 +362,7 @@ class Oracle:
         st = orc_stats_t()
         rc = self.lib.orc_step(self.h, _ptr(php), _ptr(phn), _ptr(mup), _ptr(mun), C.byref(st))
         stats = dict(iters=(st.iters[0], st.iters[1]), relres=(st.relres[0], st.relres[1]),
-                     status=st.status, clamped=st.clamped)
+                     status=st.status, clamped=st.clamped, outside=st.outside)
         if rc:
             raise OracleError(rc, f"orc_step (stats {stats})")
         return dict(phi_p=php, phi_n=phn, mu_p=mup, mu_n=mun, stats=stats)

@@ -752,3 +752,36 @@ def test_automatic_inner_steps_equal_the_fixed_steps_they_choose():
         assert np.array_equal(a[f], b[f])
     with pytest.raises(OracleError):
         Oracle(co, ce, dict(p, schur_pcg=-1, krylov="minres"))
+
+
+def test_eps_1e4_leaves_the_physical_range():
+    """The paper records that its film run diverges at eps = 1e-4 (Section 4,
+    Fig. 4) while eps = 1e-3 and larger behave.  Here the volume fractions
+    leave [0, 1] at eps = 1e-4 within 40 steps on the 100 x 50 film; the step
+    reports how many vertices are outside (checked by brute force on the
+    returned state), and with range_check = 1 that step fails with EDOMAIN and
+    leaves the state as it was.  At eps = 1e-3 every step stays inside."""
+    def run(eps, steps, **kw):
+        p, co, ce, o = _film((100, 50), eps=eps, schur_pcg=2, **kw)
+        php, phn, _ = S.initial_fractions(o.nv, p["mean_p"], p["mean_n"])
+        st = dict(phi_p=php, phi_n=phn, mu_p=np.zeros(o.nv), mu_n=np.zeros(o.nv))
+        for k in range(steps):
+            prev = st
+            try:
+                st = o.step(st)
+            except OracleError as e:
+                return k, prev, e
+            phs = 1.0 - st["phi_p"] - st["phi_n"]
+            bad = int(((st["phi_p"] < 0) | (st["phi_p"] > 1) | (st["phi_n"] < 0)
+                       | (st["phi_n"] > 1) | (phs < 0) | (phs > 1)).sum())
+            assert st["stats"]["outside"] == bad, k
+            if bad:
+                return k, st, None
+        return steps, st, None
+
+    k, st, err = run(1e-3, 40)
+    assert k == 40 and err is None
+    k, st, err = run(1e-4, 40)
+    assert k < 40 and err is None and st["stats"]["outside"] > 0
+    k2, prev, err = run(1e-4, 40, range_check=1)
+    assert k2 == k and isinstance(err, OracleError) and err.code == -6
