@@ -49,6 +49,7 @@ extern "C" {
 #define CHM_EHIP (-3)     /* a HIP runtime call failed */
 #define CHM_ENOCONV (-4)  /* the Krylov method did not reach rtol within max_iters */
 #define CHM_ENAN (-5)     /* a non-finite value appeared */
+#define CHM_EDOMAIN (-6)  /* the new state leaves [0, 1] (range_check = 1) */
 
 #define CHM_POT_FLORY_HUGGINS 0 /* eq. logarithmicpotential (Section 2) */
 #define CHM_POT_POLYNOMIAL 1    /* eq. polynomial_potential (Section 4) */
@@ -179,6 +180,13 @@ typedef struct {
      * every level below the finest, over the same interval [rho/cheb_ratio,
      * rho] of each level's own rho; 0 = cheb_degree on every level. */
     int32_t cheb_degree_coarse;
+    /* The volume fractions are physical in [0, 1] (Section 2).  Every step
+     * counts the vertices at which its new state (after the solvent removal)
+     * has phi_p, phi_n or phi_s outside that range (chm_stats_t.outside; the
+     * paper records such a divergence for eps = 1e-4, Section 4).  1: such a
+     * step fails with CHM_EDOMAIN and no run is advanced; 0: it is only
+     * counted. */
+    int32_t range_check;
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -191,6 +199,7 @@ typedef struct {
     int32_t guess_used[2]; /* CHM_GUESS_* (chm_net.h) of the start each species'
                               solve used: 0 the previous state */
     double res0[2];        /* relative residual of that start per species */
+    int32_t outside;       /* vertices of the new state with a fraction outside [0, 1] */
 } chm_stats_t;
 
 /* Build the solver: upload the mesh, colour the cells, assemble M and K by
@@ -239,7 +248,7 @@ int chm_set_fields_run(chm_solver_t *s, int32_t run, const double *phi_p, const 
  * stats may be NULL or hold nsteps * runs entries (step-major: entry
  * k * runs + r for run r of step k).  On CHM_ENOCONV / CHM_ENAN (of any run)
  * every run is left at the last completed step and the failing step's stats
- * are filled. */
+ * are filled; likewise on CHM_EDOMAIN (range_check = 1). */
 int chm_step(chm_solver_t *s, int32_t nsteps, chm_stats_t *stats);
 
 /* Advance several solvers (for example the batches of a parameter sweep,

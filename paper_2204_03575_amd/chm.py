@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchm.so")
 
 CHM_OK, CHM_EINVAL, CHM_ENOMEM, CHM_EHIP, CHM_ENOCONV, CHM_ENAN = 0, -1, -2, -3, -4, -5
+CHM_EDOMAIN = -6
 CODES = {0: "CHM_OK", -1: "CHM_EINVAL", -2: "CHM_ENOMEM", -3: "CHM_EHIP", -4: "CHM_ENOCONV",
-         -5: "CHM_ENAN"}
+         -5: "CHM_ENAN", -6: "CHM_EDOMAIN"}
 POTENTIALS = {"flory_huggins": 0, "polynomial": 1, "none": 2}
 SMOOTHERS = {"chebyshev": 0, "jacobi": 1}
 
@@ -67,6 +68,7 @@ class chm_params_t(C.Structure):
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
         ("runs_per_lane", C.c_int32), ("cheb_degree_coarse", C.c_int32),
+        ("range_check", C.c_int32),
     ]
 
 
@@ -78,7 +80,7 @@ class chm_run_t(C.Structure):
 class chm_stats_t(C.Structure):
     _fields_ = [("iters", C.c_int32 * 2), ("relres", C.c_double * 2), ("status", C.c_int32),
                 ("clamped", C.c_int32), ("t_step_ms", C.c_double), ("guess_used", C.c_int32 * 2),
-                ("res0", C.c_double * 2)]
+                ("res0", C.c_double * 2), ("outside", C.c_int32)]
 
 
 _lib = None
@@ -179,6 +181,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.wide_index = int(p.get("wide_index", 0))
     s.runs_per_lane = int(p.get("runs_per_lane", 0))
     s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
+    s.range_check = int(p.get("range_check", 0))
     return s
 
 
@@ -283,7 +286,7 @@ class Solver:
         flat = [dict(iters=(s.iters[0], s.iters[1]), relres=(s.relres[0], s.relres[1]),
                      status=s.status, clamped=s.clamped, t_step_ms=s.t_step_ms,
                      guess_used=(s.guess_used[0], s.guess_used[1]),
-                     res0=(s.res0[0], s.res0[1]))
+                     res0=(s.res0[0], s.res0[1]), outside=s.outside)
                 for s in st[:nsteps * nb]]
         stats = flat if nb == 1 else [flat[k * nb:(k + 1) * nb] for k in range(nsteps)]
         if rc != CHM_OK:
@@ -500,7 +503,8 @@ def step_many(solvers, nsteps: int = 1):
     for s, b in zip(solvers, bufs):
         flat = [dict(iters=(x.iters[0], x.iters[1]), relres=(x.relres[0], x.relres[1]),
                      status=x.status, clamped=x.clamped, t_step_ms=x.t_step_ms,
-                     guess_used=(x.guess_used[0], x.guess_used[1]), res0=(x.res0[0], x.res0[1]))
+                     guess_used=(x.guess_used[0], x.guess_used[1]), res0=(x.res0[0], x.res0[1]),
+                     outside=x.outside)
                 for x in b[:nsteps * s.nb]]
         out.append(flat if s.nb == 1 else [flat[k * s.nb:(k + 1) * s.nb] for k in range(nsteps)])
     if rc != CHM_OK:

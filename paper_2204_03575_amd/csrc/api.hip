@@ -91,6 +91,8 @@ const char *check_params(const chm_params_t &p)
         return "runs_per_lane must be 0, 1, 2 or 4";
     if (p.cheb_degree_coarse < 0 || p.cheb_degree_coarse > 31)
         return "cheb_degree_coarse must be in 0..31";
+    if (p.range_check != 0 && p.range_check != 1)
+        return "range_check must be 0 or 1";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -322,7 +324,9 @@ int chm_step(chm_solver_t *h, int32_t nsteps, chm_stats_t *stats)
             if (rc != CHM_OK)
                 return fail(h, rc, rc == CHM_ENOCONV
                                        ? "the Krylov method did not converge within max_iters"
-                                       : "non-finite value in the solve (" + h->s.nan_where + ")");
+                                       : rc == CHM_EDOMAIN
+                                             ? "the new state leaves [0, 1] (" + h->s.nan_where + ")"
+                                             : "non-finite value in the solve (" + h->s.nan_where + ")");
         }
         return CHM_OK;
     });

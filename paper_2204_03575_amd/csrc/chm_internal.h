@@ -198,6 +198,8 @@ struct Ctl {
     int clamped;         // log-argument clamps in the last right-hand side
     int nan;             // a non-finite value was seen
     int guess_used[2];   // CHM_GUESS_* of the start the step used
+    int outside;         // vertices of the new state with a fraction outside [0, 1]
+    int pad_[3];
     // large part
     double H[2][(kMaxRestart + 1) * kMaxRestart];
     double cs[2][kMaxRestart], sn[2][kMaxRestart];

@@ -409,7 +409,7 @@ __global__ void k_pack_heads(const Ctl *__restrict__ c, int *out)
         out[blockIdx.y * words + i] = src[i];
 }
 
-// the counters of a step: clamps, non-finite flag, starts used
+// the counters of a step: clamps, non-finite flag, starts used, vertices outside [0, 1]
 __global__ void k_ctl_reset(Ctl *c)
 {
     c += blockIdx.y;
@@ -418,7 +418,29 @@ __global__ void k_ctl_reset(Ctl *c)
         c->nan = 0;
         c->guess_used[0] = 0;
         c->guess_used[1] = 0;
+        c->outside = 0;
     }
+}
+
+// vertices of the state (per run: phi is the first half of a block vector of
+// 2n) whose phi_p, phi_n or phi_s = 1 - phi_p - phi_n lies outside [0, 1],
+// added to the run's count (integer sums, so the order does not matter)
+__global__ void __launch_bounds__(kBlock) k_outside(int n, const double2 *__restrict__ x, Ctl *c)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0)
+        cnt = 0;
+    __syncthreads();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double2 v = run_at(x, 2l * n)[i];
+        const double s = 1.0 - v.x - v.y;
+        if (v.x < 0.0 || v.x > 1.0 || v.y < 0.0 || v.y > 1.0 || s < 0.0 || s > 1.0)
+            atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt)
+        atomicAdd(&c[blockIdx.y].outside, cnt);
 }
 
 // v0 = r / ||r|| for active species, 0 otherwise (per run, r and v advance by len)
@@ -1180,27 +1202,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
         CHM_HIP(hipGetLastError());
     }
     if (rc == CHM_OK) {
+        // the new state: the solve's solution, then the solvent removal, in
+        // the candidate buffer S.xl (the current state stays until commit)
         k_finite<<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.ctl);
-        read_ctl(S);
-        for (int r = 0; r < R; ++r)
-            if (head(S, r).nan) {
-                rc = CHM_ENAN;
-                S.nan_where = "final iterate, run " + std::to_string(r);
-                break;
-            }
-    }
-    for (int r = 0; r < R; ++r) {
-        const Ctl &h = head(S, r);
-        stats[r].clamped = h.clamped;
-        stats[r].guess_used[0] = h.guess_used[0];
-        stats[r].guess_used[1] = h.guess_used[1];
-    }
-    if (rc == CHM_OK) {
-        std::swap(S.yh1, S.yh2);   // y_{n-1} becomes y_{n-2}
-        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.yh1);
-        for (int r = 0; r < R; ++r)
-            S.hist[r] = std::min(S.hist[r] + 1, 2);
-        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.x);
+        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.xl);
         Evap e{};
         bool evap = false;
         for (int r = 0; r < R; ++r) {
@@ -1209,7 +1214,39 @@ int step_once(Solver &S, chm_stats_t *st_out)
             evap = evap || e.ds[r] > 0.0;
         }
         if (evap)
-            k_evaporate<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.x, e);
+            k_evaporate<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.xl, e);
+        k_outside<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.xl, S.ctl);
+        CHM_HIP(hipGetLastError());
+        read_ctl(S);
+        for (int r = 0; r < R; ++r)
+            if (head(S, r).nan) {
+                rc = CHM_ENAN;
+                S.nan_where = "final iterate, run " + std::to_string(r);
+                break;
+            }
+        if (rc == CHM_OK && S.prm.range_check)
+            for (int r = 0; r < R; ++r)
+                if (head(S, r).outside) {
+                    rc = CHM_EDOMAIN;
+                    S.nan_where = "run " + std::to_string(r) + ": " +
+                                  std::to_string(head(S, r).outside) +
+                                  " vertices with a volume fraction outside [0, 1]";
+                    break;
+                }
+    }
+    for (int r = 0; r < R; ++r) {
+        const Ctl &h = head(S, r);
+        stats[r].clamped = h.clamped;
+        stats[r].guess_used[0] = h.guess_used[0];
+        stats[r].guess_used[1] = h.guess_used[1];
+        stats[r].outside = h.outside;
+    }
+    if (rc == CHM_OK) {
+        std::swap(S.yh1, S.yh2);   // y_{n-1} becomes y_{n-2}
+        k_copy<double2><<<grid(nblk(len), R), kBlock, 0, st>>>(len, S.xk, S.yh1);
+        for (int r = 0; r < R; ++r)
+            S.hist[r] = std::min(S.hist[r] + 1, 2);
+        std::swap(S.x, S.xl);   // commit the candidate state
         CHM_HIP(hipGetLastError());
         CHM_HIP(hipStreamSynchronize(st));
         for (int r = 0; r < R; ++r)
