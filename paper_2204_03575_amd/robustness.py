@@ -21,7 +21,10 @@ Each case prints one JSON line: mesh, parameters, the worst (over species)
 iteration count of every step, the time per step (both species, measured
 around each step with the device synchronised), and the setup time.  The
 paper's own figures (its CPU, per linear system) are in PAPER_FIGURES for
-context.  All computation runs in the library.
+context.  With --after N every variant starts from the state after N time
+steps of the production solver (the same state for all three, fields and
+chemical potentials), as in the paper's runs after 1000 steps on the 2D
+meshes (Section 4, Fig. 2).  All computation runs in the library.
 """
 from __future__ import annotations
 
@@ -52,6 +55,9 @@ PAPER_FIGURES = {
     "eps": {1e-4: (17, 4.82), 1e-3: (13, 4.06), 1e-2: (10, 3.35), 1e-1: (9, 3.49),
             1.0: (8, 3.92), 10.0: (7, 4.15)},
     "tau": {1e-7: (10, 2.32), 1e-6: (11, 2.83), 1e-5: (12, 3.44), 1e-4: (13, 4.0)},
+    # steps 1001 to 1020 (Fig. 2)
+    "mesh2d_after1000": {(100, 50): (15, 0.086), (200, 100): (16, 0.27), (400, 200): (15, 1.06),
+                         (800, 400): (14, 4.42), (1600, 800): (13, 20.3)},
 }
 
 VARIANTS = {
@@ -75,7 +81,33 @@ def case_params(points, variant: str, **kw) -> dict:
     return p
 
 
-def run_case(points, variant: str, steps: int = 20, log=None, **kw) -> dict:
+def advance(points, nsteps: int, log=None, chunk: int = 100, **kw):
+    """The state after `nsteps` time steps of the production solver from the
+    seeded initial state: (phi_p, phi_n, mu_p, mu_n) as host arrays."""
+    import torch
+    import synthetic as S
+    from .chm import Solver
+    p = case_params(points, "fgmres", **kw)
+    co, ce = S.make_mesh(p)
+    g = Solver(co, ce, p)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
+    g.set_fields(php, phn)
+    t0 = time.perf_counter()
+    done = 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        st = g.step(k)      # raises on a failed step
+        done += k
+        if log:
+            torch.cuda.synchronize()
+            log(f"# advance {tuple(points)}: {done} of {nsteps} steps, "
+                f"{time.perf_counter() - t0:.1f} s, last iterations {st[-1]['iters']}")
+    f = g.get_fields()
+    del g
+    return f["phi_p"], f["phi_n"], f["mu_p"], f["mu_n"]
+
+
+def run_case(points, variant: str, steps: int = 20, log=None, start=None, **kw) -> dict:
     import numpy as np
     import torch
     import synthetic as S
@@ -87,8 +119,11 @@ def run_case(points, variant: str, steps: int = 20, log=None, **kw) -> dict:
     g = Solver(co, ce, p)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
-    g.set_fields(php, phn)
+    if start is None:
+        php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
+        g.set_fields(php, phn)
+    else:
+        g.set_fields(*start)
     if log:
         log(f"# {variant} {tuple(points)}: mesh {t0 - tm:.2f} s, setup {setup_s:.2f} s, "
             f"initial state {time.perf_counter() - t0 - setup_s:.2f} s")
@@ -153,16 +188,21 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--max-vertices", type=int, default=6_000_000)
     ap.add_argument("--min-vertices", type=int, default=0)
+    ap.add_argument("--after", type=int, default=0, metavar="N",
+                    help="start every variant from the state after N production steps")
     ap.add_argument("--progress", action="store_true", help="log every step on stderr")
     a = ap.parse_args(argv)
     log = (lambda m: print(m, file=sys.stderr, flush=True)) if a.progress else None
     for pts, kw, key in cases(a.sweep, a.max_vertices):
         if _count(pts) < a.min_vertices:
             continue
-        ref = PAPER_FIGURES[key[0]].get(key[1])
+        fig = key[0] + (f"_after{a.after}" if a.after else "")
+        ref = PAPER_FIGURES.get(fig, {}).get(key[1])
+        start = advance(pts, a.after, log=log, **kw) if a.after else None
         for v in a.variants.split(","):
-            r = run_case(pts, v, a.steps, log=log, **kw)
+            r = run_case(pts, v, a.steps, log=log, start=start, **kw)
             r["sweep"] = a.sweep
+            r["after_steps"] = a.after
             r["paper_worst_iters"], r["paper_s_per_system"] = ref if ref else (None, None)
             print(json.dumps(r), flush=True)
 
