@@ -190,8 +190,12 @@ __device__ inline void sell_row_first_runs(const int *__restrict__ sptr, const I
     }
 }
 
+// (the register budget of at most 4 waves per SIMD lets the compiler issue
+// every load of a 16-wide row before the first product; with the default
+// budget it interleaved the FP64 gathers with waits)
 template <class I, class T, int RB>
-__global__ void __launch_bounds__(kBlock) k_cheb_first(int n, int R, const int *__restrict__ sptr,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_cheb_first(int n, int R, const int *__restrict__ sptr,
                                                        const I *__restrict__ col,
                                                        const T *__restrict__ val,
                                                        const T *__restrict__ dinv,

@@ -15,27 +15,29 @@ namespace {
 
 // ------------------------------------------------------------------ saddle-point operator
 // y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
-// U8: every slice of the pattern is at most kSellUnroll wide (2D meshes); the
-// row then takes the unrolled form of the loop: every column and value load,
-// then every gather, then the products in column order (slots past the slice
-// width repeat its last column with zero values)
+// A row is taken kSellUnroll entries at a time: every column and value load of
+// the group, then every gather, then the products in column order (slots past
+// the slice width repeat its last column with zero values).  U8: every slice
+// of the pattern is at most kSellUnroll wide (2D meshes), so a row is one group.
 struct SaddleEnt {
     int c[kSellUnroll];
     double am[kSellUnroll], ak[kSellUnroll];
 };
 
+// entries k0, ..., k0 + kSellUnroll - 1 of the row (k0 < width)
 template <class I>
 __device__ inline void saddle_load(int base, int width, int lane, int row, const I *__restrict__ col,
                                    const double *__restrict__ vm, const double *__restrict__ vk,
-                                   SaddleEnt &e)
+                                   SaddleEnt &e, int k0 = 0)
 {
 #pragma unroll
     for (int k = 0; k < kSellUnroll; ++k) {
-        const int idx = base + (k < width ? k : width - 1) * kSlice + lane;
+        const int kk = k0 + k;
+        const int idx = base + (kk < width ? kk : width - 1) * kSlice + lane;
         e.c[k] = sell_col(col, idx, row);
         const double vmk = vm[idx], vkk = vk[idx];
-        e.am[k] = k < width ? vmk : 0.0;
-        e.ak[k] = k < width ? vkk : 0.0;
+        e.am[k] = kk < width ? vmk : 0.0;
+        e.ak[k] = kk < width ? vkk : 0.0;
     }
 }
 
@@ -48,22 +50,34 @@ __device__ inline void saddle_combine(double m0x, double m0y, double k1x, double
     y1 = d2(fmad(t.x, k0x, -(te.x * m1x)), fmad(t.y, k0y, -(te.y * m1y)));
 }
 
+// the four row products (M x0, K x1, K x0, M x1 per species), continued over
+// one group of entries in column order
+struct SaddleAcc {
+    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
+};
+
+__device__ inline void saddle_acc(const SaddleEnt &e, const double2 *x0, const double2 *x1,
+                                  SaddleAcc &a)
+{
+#pragma unroll
+    for (int k = 0; k < kSellUnroll; ++k) {
+        a.m0x = fmad(e.am[k], x0[k].x, a.m0x);
+        a.m0y = fmad(e.am[k], x0[k].y, a.m0y);
+        a.k1x = fmad(e.ak[k], x1[k].x, a.k1x);
+        a.k1y = fmad(e.ak[k], x1[k].y, a.k1y);
+        a.k0x = fmad(e.ak[k], x0[k].x, a.k0x);
+        a.k0y = fmad(e.ak[k], x0[k].y, a.k0y);
+        a.m1x = fmad(e.am[k], x1[k].x, a.m1x);
+        a.m1y = fmad(e.am[k], x1[k].y, a.m1y);
+    }
+}
+
 __device__ inline void saddle_dot(const SaddleEnt &e, const double2 *x0, const double2 *x1, double2 t,
                                   double2 te, double2 &y0, double2 &y1)
 {
-    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
-#pragma unroll
-    for (int k = 0; k < kSellUnroll; ++k) {
-        m0x = fmad(e.am[k], x0[k].x, m0x);
-        m0y = fmad(e.am[k], x0[k].y, m0y);
-        k1x = fmad(e.ak[k], x1[k].x, k1x);
-        k1y = fmad(e.ak[k], x1[k].y, k1y);
-        k0x = fmad(e.ak[k], x0[k].x, k0x);
-        k0y = fmad(e.ak[k], x0[k].y, k0y);
-        m1x = fmad(e.am[k], x1[k].x, m1x);
-        m1y = fmad(e.am[k], x1[k].y, m1y);
-    }
-    saddle_combine(m0x, m0y, k1x, k1y, k0x, k0y, m1x, m1y, t, te, y0, y1);
+    SaddleAcc a;
+    saddle_acc(e, x0, x1, a);
+    saddle_combine(a.m0x, a.m0y, a.k1x, a.k1y, a.k0x, a.k0y, a.m1x, a.m1y, t, te, y0, y1);
 }
 
 template <class I, bool U8>
@@ -86,28 +100,26 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
         saddle_dot(e, x0, x1, t, te, y0, y1);
         return;
     }
-    double m0x = 0, m0y = 0, k1x = 0, k1y = 0, k0x = 0, k0y = 0, m1x = 0, m1y = 0;
-    for (int k = 0; k < width; ++k) {
-        const int idx = base + k * kSlice + lane;
-        const int c = sell_col(col, idx, row);
-        const double am = vm[idx], ak = vk[idx];
-        const double2 x0 = x[c], x1 = x[n + c];
-        m0x = fmad(am, x0.x, m0x);
-        m0y = fmad(am, x0.y, m0y);
-        k1x = fmad(ak, x1.x, k1x);
-        k1y = fmad(ak, x1.y, k1y);
-        k0x = fmad(ak, x0.x, k0x);
-        k0y = fmad(ak, x0.y, k0y);
-        m1x = fmad(am, x1.x, m1x);
-        m1y = fmad(am, x1.y, m1y);
+    SaddleAcc a;
+    for (int k0 = 0; k0 < width; k0 += kSellUnroll) {
+        SaddleEnt e;
+        saddle_load<I>(base, width, lane, row, col, vm, vk, e, k0);
+        double2 x0[kSellUnroll], x1[kSellUnroll];
+#pragma unroll
+        for (int k = 0; k < kSellUnroll; ++k) {
+            x0[k] = x[e.c[k]];
+            x1[k] = x[n + e.c[k]];
+        }
+        saddle_acc(e, x0, x1, a);
     }
-    saddle_combine(m0x, m0y, k1x, k1y, k0x, k0y, m1x, m1y, t, te, y0, y1);
+    saddle_combine(a.m0x, a.m0y, a.k1x, a.k1y, a.k0x, a.k0y, a.m1x, a.m1y, t, te, y0, y1);
 }
 
 // per run, x and y advance by 2n; RB runs per lane (block row blockIdx.y),
 // R in all: on U8 patterns the row's entries are loaded once for the RB runs
 template <class I, bool U8, int RB>
-__global__ void __launch_bounds__(kBlock) k_saddle(int n, int R, const int *__restrict__ sptr,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_saddle(int n, int R, const int *__restrict__ sptr,
                                                    const I *__restrict__ col,
                                                    const double *__restrict__ vm,
                                                    const double *__restrict__ vk,
@@ -162,7 +174,8 @@ __global__ void __launch_bounds__(kBlock) k_saddle(int n, int R, const int *__re
 // per species (y1, y2: the two block rows; w2 = 1 gives the 2-norm; per run:
 // vectors advance by 2n, part by one run's slots)
 template <class I, bool U8>
-__global__ void __launch_bounds__(kBlock) k_saddle_resid(int n, const int *__restrict__ sptr,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_saddle_resid(int n, const int *__restrict__ sptr,
                                                          const I *__restrict__ col,
                                                          const double *__restrict__ vm,
                                                          const double *__restrict__ vk,
