@@ -24,5 +24,8 @@ def test_sweeps_cover_the_papers_figures():
     assert [c[1]["eps"] for c in R.cases("eps", 10 ** 9)] == R.EPS
     assert [c[1]["tau"] for c in R.cases("tau", 10 ** 9)] == R.TAU
     assert [c[0] for c in R.cases("mesh2d", 400_000)] == R.MESHES_2D[:4]
-    for sweep, figs in R.PAPER_FIGURES.items():
-        assert len(figs) == len(R.cases(sweep, 10 ** 9))
+    for fig, figs in R.PAPER_FIGURES.items():
+        if fig == "mesh2d_after1000":   # Fig. 2: the 2D meshes up to 1600 x 800
+            assert sorted(figs) == sorted(R.MESHES_2D[:5])
+            continue
+        assert len(figs) == len(R.cases(fig, 10 ** 9))
