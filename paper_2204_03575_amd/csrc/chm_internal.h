@@ -261,6 +261,11 @@ struct Solver {
     int ncolors = 0;
     std::vector<int> color_ptr;   // host copy of colour offsets
     int *color_cells = nullptr;
+    // per vertex, the slots cell * nl + corner of its cells in colour order,
+    // SELL-64 (slice offsets vslot_ptr, vslot_stored entries with padding);
+    // vslot_pos: the position of each slot in that layout
+    int *vslot_ptr = nullptr, *vslot = nullptr, *vslot_pos = nullptr;
+    int vslot_stored = 0;
     // quadrature (barycentric points, weights summing to 1)
     int nq = 0;
     double *qb = nullptr, *qw = nullptr;
@@ -282,6 +287,7 @@ struct Solver {
     double2 *V = nullptr, *Z = nullptr;   // [Krylov index][run][2n]
     double2 *xl = nullptr;     // linear-extrapolation candidate
     double2 *f = nullptr;      // potential term of the right-hand side (pairs)
+    double2 *fslot = nullptr;  // its quadrature per cell and corner, before the gather
     Work<double> w64;
     Work<float> w32;
     float *fsM = nullptr;      // FP32 SELL values of M (Algorithm 1's product with M)

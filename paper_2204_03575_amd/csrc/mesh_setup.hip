@@ -256,6 +256,37 @@ __global__ void k_color_fill(const int *color, int ncell, int *cursor, int *list
         list[base[col] + pos] = c;
 }
 
+// 64 times the largest number of cells at a vertex of each 64-vertex slice
+__global__ void k_slot_width(const int *__restrict__ inc_ptr, int nv, int *w)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= (nv + kSlice - 1) / kSlice)
+        return;
+    int m = 0;
+    for (int v = s * kSlice; v < nv && v < (s + 1) * kSlice; ++v)
+        m = max(m, inc_ptr[v + 1] - inc_ptr[v]);
+    w[s] = m * kSlice;
+}
+
+// slot cell * nl + a appended to the list of vertex v = cells[cell * nl + a]
+// for the cells of one colour (no two share a vertex: one writer per
+// cursor).  The lists are SELL-64: entry k of vertex v at sptr[v / 64] +
+// 64 k + v % 64; pos records where each slot went.
+__global__ void k_slot_fill(const int *__restrict__ list, int count, const int *__restrict__ cells,
+                            int nl, const int *__restrict__ sptr, int *cursor, int *slot, int *pos)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count)
+        return;
+    const int c = list[t];
+    for (int a = 0; a < nl; ++a) {
+        const int v = cells[(size_t)c * nl + a];
+        const int p = sptr[v / kSlice] + cursor[v]++ * kSlice + v % kSlice;
+        slot[p] = c * nl + a;
+        pos[(size_t)c * nl + a] = p;
+    }
+}
+
 // element geometry: gradients of the barycentric coordinates and the volume
 __device__ inline bool element_geometry(int dim, const double *coords, const int *vtx,
                                         double g[4][3], double *vol)
@@ -557,6 +588,39 @@ void mesh_setup(Solver &S)
     S.color_cells = pool.get<int>(ncell);
     k_color_fill<<<blocks_for(ncell), kBlock, 0, st>>>(colA, ncell, ccount, S.color_cells);
     CHM_HIP(hipGetLastError());
+
+    // slots cell * nl + corner of every vertex, listed colour by colour (a
+    // colour holds at most one cell at a vertex, so each vertex's cursor has
+    // one writer per launch), in a SELL-64 layout padded with slot 0
+    const int nsl = (nv + kSlice - 1) / kSlice;
+    S.vslot_ptr = pool.get<int>(nsl + 1);
+    k_slot_width<<<blocks_for(nsl), kBlock, 0, st>>>(inc_ptr, nv, S.vslot_ptr);
+    CHM_HIP(hipGetLastError());
+    {
+        std::vector<int> w(nsl);
+        CHM_HIP(hipMemcpyAsync(w.data(), S.vslot_ptr, sizeof(int) * nsl, hipMemcpyDeviceToHost, st));
+        CHM_HIP(hipStreamSynchronize(st));
+        long total = 0;
+        for (int x : w)
+            total += x;
+        if (total > 0x7fffffffl)
+            throw Failure(CHM_EINVAL, "mesh too large for the right-hand side's slot lists");
+    }
+    scan_exclusive(S.vslot_ptr, nsl, S.vslot_ptr + nsl, pool, st);
+    S.vslot_stored = read_int(S.vslot_ptr + nsl, st);
+    S.vslot = pool.get<int>(S.vslot_stored);
+    fill_int(S.vslot, 0, S.vslot_stored, st);
+    S.vslot_pos = pool.get<int>((size_t)ncell * nl);
+    fill_int(cursor, 0, nv, st);
+    for (int c = 0; c < S.ncolors; ++c) {
+        const int cnt = S.color_ptr[c + 1] - S.color_ptr[c];
+        if (cnt == 0)
+            continue;
+        k_slot_fill<<<blocks_for(cnt), kBlock, 0, st>>>(S.color_cells + S.color_ptr[c], cnt, S.cells,
+                                                        nl, S.vslot_ptr, cursor, S.vslot,
+                                                        S.vslot_pos);
+        CHM_HIP(hipGetLastError());
+    }
 
     // assembly by coloured scatter
     Csr &M = S.M;

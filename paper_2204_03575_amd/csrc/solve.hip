@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(kBlock) k_finite(int len, const double2 *__res
 // ------------------------------------------------------------------ right-hand side
 struct Pot {
     int kind;
-    double Np, Nn, Ns, chi_pn, chi_ps, chi_ns, floor_;
+    double iNp, iNn, iNs, chi_pn, chi_ps, chi_ns, floor_;   // iN*: 1 / N*
 };
 
 __device__ inline double clog(double v, double fl, int &clamps)
@@ -624,9 +624,9 @@ __device__ inline void dpot(const Pot &P, double p, double q, double &fp, double
     if (P.kind == CHM_POT_FLORY_HUGGINS) {
         const double lp = clog(p, P.floor_, clamps), lq = clog(q, P.floor_, clamps);
         const double ls = clog(s, P.floor_, clamps);
-        const double es = (ls + 1.0) / P.Ns;
-        fp = (lp + 1.0) / P.Np - es + P.chi_pn * q + P.chi_ps * (s - p) - P.chi_ns * q;
-        fq = (lq + 1.0) / P.Nn - es + P.chi_pn * p - P.chi_ps * p + P.chi_ns * (s - q);
+        const double es = (ls + 1.0) * P.iNs;
+        fp = (lp + 1.0) * P.iNp - es + P.chi_pn * q + P.chi_ps * (s - p) - P.chi_ns * q;
+        fq = (lq + 1.0) * P.iNn - es + P.chi_pn * p - P.chi_ps * p + P.chi_ns * (s - q);
     } else if (P.kind == CHM_POT_POLYNOMIAL) {
         fp = 7.0 * p * q * q - 0.2 * s;
         fq = 7.0 * p * p * q - 0.2 * s;
@@ -636,28 +636,27 @@ __device__ inline void dpot(const Pot &P, double p, double q, double &fp, double
     }
 }
 
-// f[v] += sum over the quadrature of f'(phi_h) lambda_v |T| for the cells of
-// one colour (no two share a vertex, so the += are race free).  Per run: the
-// state x (phi is its first half) advances by 2n, f by n, and the run has its
-// own potential parameters and clamp counter.
+// Per cell and corner a: sum over the quadrature of f'(phi_h) lambda_a (times
+// |T| in the gather below), for every cell in one launch, stored at the
+// slot's place pos[cell * NL + a] in the vertices' slot lists.  Per run: the
+// state x (phi is its first half) advances by 2n, the slot values by
+// `stored`, and the run has its own potential parameters and clamp counter.
 template <int NL>
-__global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ list, int count,
-                                                      const int *__restrict__ cells,
-                                                      const double *__restrict__ vol,
+__global__ void __launch_bounds__(kBlock) k_rhs_cells(int ncell, const int *__restrict__ cells,
                                                       const double *__restrict__ qb,
                                                       const double *__restrict__ qw, int nq, int n,
                                                       const double2 *__restrict__ phi,
-                                                      const Pot *__restrict__ pots, double2 *f,
-                                                      Ctl *ctl)
+                                                      const Pot *__restrict__ pots,
+                                                      const int *__restrict__ pos, long stored,
+                                                      double2 *slot, Ctl *ctl)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= count)
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell)
         return;
     phi = run_at(phi, 2l * n);
-    f = run_at(f, (long)n);
+    slot = run_at(slot, stored);
     const Pot P = pots[blockIdx.y];
     int *clamped = &ctl[blockIdx.y].clamped;
-    const int c = list[t];
     int vtx[NL];
     double2 ph[NL], acc[NL];
 #pragma unroll
@@ -685,14 +684,52 @@ __global__ void __launch_bounds__(kBlock) k_rhs_color(const int *__restrict__ li
             acc[a].y += wq * fr * l;
         }
     }
-    const double vc = vol[c];
 #pragma unroll
-    for (int a = 0; a < NL; ++a) {
-        const double2 o = f[vtx[a]];
-        f[vtx[a]] = d2(o.x + vc * acc[a].x, o.y + vc * acc[a].y);
-    }
+    for (int a = 0; a < NL; ++a)
+        slot[pos[(size_t)c * NL + a]] = acc[a];
     if (clamps)
         atomicAdd(clamped, clamps);
+}
+
+// f[v] = sum of |T| times the value of slot (T, v) over the cells T at v, in
+// colour order (the vertex's slot list is sorted that way): the sum a scatter
+// of one colour after the other forms, without a launch per colour.  The
+// lists are SELL-64 (lane = vertex of the slice, entry k at sptr + 64 k), so
+// the loads of a wave are contiguous; padding has slot 0 and value 0.  Per
+// run: the slot values advance by `stored`, f by n.
+template <int NL>
+__global__ void __launch_bounds__(kBlock) k_rhs_gather(int n, const int *__restrict__ sptr,
+                                                       const int *__restrict__ vslot,
+                                                       const double *__restrict__ vol, long stored,
+                                                       const double2 *__restrict__ slot, double2 *f)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n)
+        return;
+    slot = run_at(slot, stored);
+    const int sl = __builtin_amdgcn_readfirstlane(v / kSlice), lane = v % kSlice;
+    const int base = sptr[sl], width = (sptr[sl + 1] - base) / kSlice;
+    double2 s = d2(0.0, 0.0);
+    constexpr int U = 8;
+    for (int k0 = 0; k0 < width; k0 += U) {
+        int e[U];
+        double2 a[U];
+        double vc[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int p = base + (k0 + k < width ? k0 + k : width - 1) * kSlice + lane;
+            e[k] = vslot[p];
+            a[k] = slot[p];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            vc[k] = vol[e[k] / NL];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (k0 + k < width)
+                s = d2(fmad(vc[k], a[k].x, s.x), fmad(vc[k], a[k].y, s.y));
+    }
+    run_at(f, (long)n)[v] = s;
 }
 
 // b1 = -(tau'/eps) f (per run: f advances by n, b1, the second half of the
@@ -883,20 +920,18 @@ void compute_rhs(Solver &S)
     const long len = 2l * n;
     hipStream_t st = S.stream;
     const Pot *pots = static_cast<const Pot *>(S.pots);
-    k_zero<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f);
-    for (int c = 0; c < S.ncolors; ++c) {
-        const int cnt = S.color_ptr[c + 1] - S.color_ptr[c];
-        if (!cnt)
-            continue;
-        const int *list = S.color_cells + S.color_ptr[c];
-        if (S.nl == 3)
-            k_rhs_color<3><<<grid(nblk(cnt), R), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb,
-                                                                  S.qw, S.nq, n, S.x, pots, S.f,
-                                                                  S.ctl);
-        else
-            k_rhs_color<4><<<grid(nblk(cnt), R), kBlock, 0, st>>>(list, cnt, S.cells, S.vol, S.qb,
-                                                                  S.qw, S.nq, n, S.x, pots, S.f,
-                                                                  S.ctl);
+    const int nc = S.ncell;
+    const long ns = S.vslot_stored;
+    if (S.nl == 3) {
+        k_rhs_cells<3><<<grid(nblk(nc), R), kBlock, 0, st>>>(nc, S.cells, S.qb, S.qw, S.nq, n, S.x,
+                                                             pots, S.vslot_pos, ns, S.fslot, S.ctl);
+        k_rhs_gather<3><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.vslot_ptr, S.vslot, S.vol, ns,
+                                                             S.fslot, S.f);
+    } else {
+        k_rhs_cells<4><<<grid(nblk(nc), R), kBlock, 0, st>>>(nc, S.cells, S.qb, S.qw, S.nq, n, S.x,
+                                                             pots, S.vslot_pos, ns, S.fslot, S.ctl);
+        k_rhs_gather<4><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.vslot_ptr, S.vslot, S.vol, ns,
+                                                             S.fslot, S.f);
     }
     sell_spmv<SP_SET, double>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val, S.x,
                               len, nullptr, S.b, len);
@@ -921,6 +956,9 @@ void alloc_workspace(Solver &S)
     S.V = p.get<double2>(nb * len * (S.m + 1));
     S.Z = p.get<double2>(nb * len * S.m);
     S.f = p.get<double2>(nb * n);
+    S.fslot = p.get<double2>(nb * (size_t)S.vslot_stored);
+    // the padding of the slot lists adds zero
+    fill_double(reinterpret_cast<double *>(S.fslot), 0.0, 2 * nb * (size_t)S.vslot_stored, S.stream);
     S.stage = p.get<double>(n);
     S.red = p.get<double2>(nb * kSlotStride);
     S.gsp1 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
@@ -931,7 +969,7 @@ void alloc_workspace(Solver &S)
     fill_int(reinterpret_cast<int *>(S.ctl), 0, nb * sizeof(Ctl) / sizeof(int), S.stream);
     std::vector<Pot> pots(nb);
     for (size_t r = 0; r < nb; ++r)
-        pots[r] = Pot{S.prm.potential, S.prm.Np, S.prm.Nn, S.prm.Ns, S.runs[r].chi_pn,
+        pots[r] = Pot{S.prm.potential, 1.0 / S.prm.Np, 1.0 / S.prm.Nn, 1.0 / S.prm.Ns, S.runs[r].chi_pn,
                       S.runs[r].chi_ps, S.runs[r].chi_ns, S.prm.log_floor};
     Pot *dp = p.get<Pot>(nb);
     CHM_HIP(hipMemcpyAsync(dp, pots.data(), nb * sizeof(Pot), hipMemcpyHostToDevice, S.stream));
