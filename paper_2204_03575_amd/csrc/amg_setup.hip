@@ -849,14 +849,15 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
     // One lane per row (SELL-64) for rows the unrolled SELL path covers (up to
     // 16 entries: the fine levels of P1 meshes in 2D and 3D) when there are
     // enough rows to fill the chip; otherwise a power-of-two group of lanes
-    // per row, enough to reach about 128k threads but no wider than the rows.
+    // per row, enough to reach about 128k threads and to cover an average row
+    // in two passes of four entries per lane, but no wider than the rows.
     auto lanes_per_row = [](const Csr &A) {
         const double avg = A.n > 0 ? double(A.nnz) / A.n : 0.0;
         const long target = 131072;
         if (avg < 16.0 && A.n >= target)
             return 0;
         int want = 4;
-        while (want < 32 && (long)want * A.n < target)
+        while (want < 32 && ((long)want * A.n < target || want * 8 < avg))
             want *= 2;
         int cap = 4;
         while (cap < 32 && cap < avg)

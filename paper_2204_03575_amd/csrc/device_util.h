@@ -46,10 +46,10 @@ template <> __device__ inline float2 mk<float>(float a, float b) { return make_f
 // it is a bijection of [0, G).
 constexpr int kXcds = 8;
 
-__device__ inline int xcd_block()
+// the new index of block b of grid row y in a grid G blocks wide
+__host__ __device__ inline int xcd_rank(int G, int b, unsigned y)
 {
-    const int G = gridDim.x, b = blockIdx.x;
-    const int off = (int)((blockIdx.y * (unsigned)G) % kXcds);   // rotation of row y
+    const int off = (int)((y * (unsigned)G) % kXcds);             // rotation of row y
     const int x = (b + off) % kXcds;                              // this block's XCD
     const int j = (b - (x - off + kXcds) % kXcds) / kXcds;        // its rank on that XCD
     int start = 0;                                                // blocks of earlier XCDs
@@ -57,6 +57,8 @@ __device__ inline int xcd_block()
         start += (G - (k - off + kXcds) % kXcds + kXcds - 1) / kXcds;
     return start + j;
 }
+
+__device__ inline int xcd_block() { return xcd_rank(gridDim.x, blockIdx.x, blockIdx.y); }
 
 __device__ inline double2 wave_sum(double2 v)
 {
