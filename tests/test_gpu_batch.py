@@ -186,3 +186,39 @@ def test_step_many_equals_separate_steps():
             fa, fb = many[k].get_fields(run=r), one.get_fields(run=r)
             for f in FIELDS:
                 assert np.array_equal(fa[f], fb[f]), (k, r, f)
+
+
+def test_step_many_failure_stays_in_its_solver():
+    """A solver whose step fails (here: no convergence within 2 iterations) reports
+    its error code and keeps its state; the other solvers of the same call
+    advance as if stepped alone."""
+    case("chm_step_many with one failing solver")
+    import torch
+
+    from paper_2204_03575_amd import ChmError, Solver, step_many
+    from paper_2204_03575_amd.chm import CHM_ENOCONV
+    good_p = dict(S.preset("square32", n=(24, 20)))
+    bad_p = dict(S.preset("square32", n=(20, 18)), max_iters=2)
+
+    def make(p, stream=None):
+        co, ce = S.make_mesh(p)
+        g = Solver(co, ce, p, stream=None if stream is None else stream.cuda_stream)
+        g.set_fields(*initial(co.shape[0], 0, p))
+        return g
+
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    good, bad = make(good_p, streams[0]), make(bad_p, streams[1])
+    before = bad.get_fields()
+    with pytest.raises(ChmError) as err:
+        step_many([good, bad], 1)
+    assert err.value.code == CHM_ENOCONV
+    torch.cuda.synchronize()
+    after = bad.get_fields()
+    for f in FIELDS:
+        assert np.array_equal(before[f], after[f]), f
+    ref = make(good_p)
+    ref.step(1)
+    fa, fb = good.get_fields(), ref.get_fields()
+    for f in FIELDS:
+        assert np.array_equal(fa[f], fb[f]), f
+

@@ -134,6 +134,35 @@ def test_operator_preconditioner_rhs_match(mesh):
     assert relerr(b0, r0) <= 1e-13 and relerr(b1, r1) <= 1e-13
 
 
+@pytest.mark.parametrize("mesh", MESHES[:3], ids=lambda m: "x".join(map(str, m["n"])))
+def test_rhs_over_the_range_of_the_logarithm(mesh):
+    """f' of Flory-Huggins (N_p = N_n = 20) for states whose quadrature values span
+    the logarithm's arguments.  State A: phi_p and phi_n log-uniform in
+    [1e-14, 0.45] (below the 1e-12 floor they are clamped), so phi_s >= 0.1.
+    State B: phi_p in [0.55, 0.98] or [1.02, 1.5] and phi_n in [1e-14, 0.01], so
+    phi_s is at least 0.01 or negative (clamped) at every vertex.  phi_s =
+    1 - phi_p - phi_n loses the digits of the sum where it is small, so states
+    with phi_s just above the floor at a vertex are left out: there the
+    right-hand side is as sensitive to the rounding of phi_p + phi_n as to the
+    logarithm."""
+    case("rhs over the logarithm's range", **mesh)
+    p, co, ce, g, o = make(**mesh)
+    nv = co.shape[0]
+    rng = np.random.default_rng(11)
+    u = rng.uniform(size=(4, nv))
+    side = rng.integers(0, 2, nv)
+    states = [
+        (10.0 ** (-14 + 13.65 * u[0]), 10.0 ** (-14 + 13.65 * u[1])),
+        (np.where(side == 0, 0.55 + 0.43 * u[2], 1.02 + 0.48 * u[2]), 10.0 ** (-14 + 12 * u[3])),
+    ]
+    for php, phn in states:
+        g.set_fields(php, phn)
+        b0, b1 = g.rhs()
+        r0, r1 = o.rhs(php, phn)
+        assert relerr(b0, r0) <= 1e-13 and relerr(b1, r1) <= 1e-13
+        assert maxrel(b0, r0) <= 1e-12 and maxrel(b1, r1) <= 1e-12
+
+
 def run_pair(p, co, ce, g, o, steps, php=None, phn=None):
     if php is None:
         php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"])
