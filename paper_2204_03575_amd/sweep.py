@@ -25,12 +25,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SIZES = (128, 192, 256, 384, 512)
 # The tuner starts from the workload's own settings (the 512x512 preset: As
-# smoother of degree 6 over [rho/5, rho], 2 CG steps per As solve; 2 runs per
+# smoother of degree 7 over [rho/5, rho], 2 CG steps per As solve; 2 runs per
 # lane), then tries the other runs per lane, then the other As settings with
 # the best runs per lane; a candidate replaces the best only when it is at
 # least TUNE_MARGIN faster (timing noise must not pick a worse setting).
 TUNE_PREC = [dict(cheb_degree=d, schur_pcg=k, cheb_ratio=r)
-             for (d, k, r) in ((6, 2, 5.0), (5, 2, 8.0), (4, 2, 15.0), (4, 3, 30.0))]
+             for (d, k, r) in ((7, 2, 5.0), (6, 2, 5.0), (5, 2, 8.0), (4, 2, 15.0))]
 TUNE_RB = (2, 1, 4)
 TUNE_MARGIN = 0.03
 TUNE_WARMUP, TUNE_STEPS = 2, 3

@@ -168,12 +168,12 @@ PRESETS = {
     # fastest per time step on this mesh: the mass block of Algorithm 1 is a
     # degree-5 Chebyshev semi-iteration (as accurate as the mass V-cycle here,
     # with no coarse levels); each As solve is 2 CG steps with V-cycles whose
-    # degree-6 Chebyshev smoother covers [rho/5, rho] (degree 4 below the
+    # degree-7 Chebyshev smoother covers [rho/5, rho] (degree 4 below the
     # finest level).
     "square512": dict(_COMMON, dim=2, n=(512, 512), extent=(1.0, 1.0), coarse_max=2048,
                       mean_p=0.1, mean_n=0.1, steps=200, evap_ds=0.0025, evap_stop=0.3,
                       mass_solver="chebyshev", cheb_degree_mass=5,
-                      cheb_degree=6, cheb_ratio=5.0, schur_pcg=2, cheb_degree_coarse=4),
+                      cheb_degree=7, cheb_ratio=5.0, schur_pcg=2, cheb_degree_coarse=4),
     # The paper's 2D experiment (Section 4): a 10 x 2.5 film (y is the height),
     # polynomial potential, phi_p = phi_n = 0.35 +- 0.01, solvent evaporation
     # through the top (k = 5e-3) and a patterned substrate at the bottom
