@@ -61,8 +61,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_cheb_box96_counters.md.  Keyed by workload and
 # precision, for the default 16-bit SELL column offsets; None where the counters were not
 # taken (or the kernel changed since, or with --wide-index).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.06e6, ("square512", "fp32"): 20.46e6,
-                            ("box96", "fp64"): 99.06e6, ("box96", "fp32"): 58.76e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.13e6, ("square512", "fp32"): 20.49e6,
+                            ("box96", "fp64"): 99.07e6, ("box96", "fp32"): 58.96e6}
 
 
 def parse():
