@@ -297,7 +297,7 @@ struct Solver {
     double2 *hfin = nullptr;   // finalised Gram-Schmidt coefficients of both passes
     Ctl *ctl = nullptr;        // device, one per run
     Ctl *hctl = nullptr;       // pinned host mirror (heads), one per run
-    int *dheads = nullptr;     // device staging of the heads of a batch
+    int *dheads = nullptr;     // device address of hctl (the heads are written there)
     std::vector<int64_t> steps;   // per run: completed time steps (the solvent removal counts them)
     double setup_ms = 0.0;
     double vc_rho = 0.0;       // measured V-cycle contraction of the As hierarchy (0: not measured)

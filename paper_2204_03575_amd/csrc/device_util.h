@@ -508,17 +508,14 @@ void spmv_op(hipStream_t st, int runs, int rb, const MatView<T> &A, const pair_t
 // FP64; per run, a and b advance by n and part by one run's slots.  A thread
 // adds its elements i, i + stride, ... in that order; it loads four of them
 // at a time, so a pass costs one memory round trip, not four.
+// this thread's share of the two species' dot products a . b: elements i0,
+// i0 + stride, ... in that order, four loads in flight per pass
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restrict__ a,
-                                                const pair_t<T> *__restrict__ b, double2 *part)
+__device__ inline double2 dot_share(int n, const pair_t<T> *__restrict__ a,
+                                    const pair_t<T> *__restrict__ b, int i0, int stride)
 {
-    __shared__ double2 sh[kBlock / 64];
-    a = run_at(a, n);
-    b = run_at(b, n);
-    part = run_at(part, kSlotStride);
     double2 acc = d2(0.0, 0.0);
-    const int stride = gridDim.x * kBlock;
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    int i = i0;
     for (; i + 3 * stride < n; i += 4 * stride) {
         pair_t<T> x[4], y[4];
 #pragma unroll
@@ -528,18 +525,57 @@ __global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restri
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            acc.x += double(x[u].x) * double(y[u].x);
-            acc.y += double(x[u].y) * double(y[u].y);
+            acc.x = fmad(double(x[u].x), double(y[u].x), acc.x);
+            acc.y = fmad(double(x[u].y), double(y[u].y), acc.y);
         }
     }
     for (; i < n; i += stride) {
         const pair_t<T> x = a[i], y = b[i];
-        acc.x += double(x.x) * double(y.x);
-        acc.y += double(x.y) * double(y.y);
+        acc.x = fmad(double(x.x), double(y.x), acc.x);
+        acc.y = fmad(double(x.y), double(y.y), acc.y);
     }
+    return acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(int n, const pair_t<T> *__restrict__ a,
+                                                const pair_t<T> *__restrict__ b, double2 *part)
+{
+    __shared__ double2 sh[kBlock / 64];
+    a = run_at(a, n);
+    b = run_at(b, n);
+    part = run_at(part, kSlotStride);
+    const double2 acc = dot_share<T>(n, a, b, blockIdx.x * kBlock + threadIdx.x,
+                                     gridDim.x * kBlock);
     const double2 s = block_sum(acc, sh);
     if (threadIdx.x == 0)
         part[blockIdx.x] = s;
+}
+
+// two dot products a1 . b1 and a2 . b2 in one launch, each with the partials
+// k_dot writes for it (the same elements per thread, the same order)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot2(int n, const pair_t<T> *__restrict__ a1,
+                                                 const pair_t<T> *__restrict__ b1, double2 *part1,
+                                                 const pair_t<T> *__restrict__ a2,
+                                                 const pair_t<T> *__restrict__ b2, double2 *part2)
+{
+    __shared__ double2 sh[kBlock / 64];
+    a1 = run_at(a1, n);
+    b1 = run_at(b1, n);
+    a2 = run_at(a2, n);
+    b2 = run_at(b2, n);
+    part1 = run_at(part1, kSlotStride);
+    part2 = run_at(part2, kSlotStride);
+    const int i0 = blockIdx.x * kBlock + threadIdx.x, stride = gridDim.x * kBlock;
+    const double2 acc1 = dot_share<T>(n, a1, b1, i0, stride);
+    const double2 acc2 = dot_share<T>(n, a2, b2, i0, stride);
+    const double2 s1 = block_sum(acc1, sh);
+    const double2 s2 = block_sum(acc2, sh);
+    if (threadIdx.x == 0) {
+        part1[blockIdx.x] = s1;
+        part2[blockIdx.x] = s2;
+    }
 }
 
 // per run, a and b advance by n

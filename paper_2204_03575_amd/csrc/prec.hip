@@ -823,10 +823,13 @@ void schur_solve_t(Solver &S, const pair_t<T> *b, pair_t<T> *x)
     // buffer not holding the direction, which k_pcg_dir then updates in place
     pair_t<T> *d = W.pcg_z;
     vcycle_level<T>(S, H, 0, b, d);                                    // z = V(b), r = b
-    k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, b, d, slot(S, kSlotRz));
     for (int it = 1; it <= k; ++it) {
         spmv_op<SP_SET, T>(st, R, rb_of(S), A, d, nullptr, q);
-        k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
+        if (it == 1)   // r . z and d . q of the first step (d = z) in one launch
+            k_dot2<T><<<grid(G, R), kBlock, 0, st>>>(n, b, d, slot(S, kSlotRz), d, q,
+                                                     slot(S, kSlotDq + 1));
+        else
+            k_dot<T><<<grid(G, R), kBlock, 0, st>>>(n, d, q, slot(S, kSlotDq + it));
         k_pcg_xr<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, x, r, b, d, q, slot(S, kSlotRz + it - 1),
                                                          slot(S, kSlotDq + it), G, it == 1,
                                                          it < k);

@@ -413,13 +413,16 @@ __global__ void k_deactivate(Ctl *c, Flags act)
     }
 }
 
-// the heads of the runs' control blocks, back to back, for one copy to the host
+// the heads of the runs' control blocks, back to back, written straight into
+// pinned (coherent) host memory through its device address; the host reads
+// them after synchronising the stream
 __global__ void k_pack_heads(const Ctl *__restrict__ c, int *out)
 {
     constexpr int words = (int)(kCtlHead / sizeof(int));
     const int *src = reinterpret_cast<const int *>(c + blockIdx.y);
     for (int i = threadIdx.x; i < words; i += blockDim.x)
         out[blockIdx.y * words + i] = src[i];
+    __threadfence_system();
 }
 
 // the counters of a step: clamps, non-finite flag, starts used, vertices outside [0, 1]
@@ -1008,8 +1011,9 @@ void alloc_workspace(Solver &S)
     Pot *dp = p.get<Pot>(nb);
     CHM_HIP(hipMemcpyAsync(dp, pots.data(), nb * sizeof(Pot), hipMemcpyHostToDevice, S.stream));
     S.pots = dp;
-    CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), nb * kCtlHead, hipHostMallocDefault));
-    S.dheads = p.get<int>(nb * kCtlHead / sizeof(int));
+    CHM_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.hctl), nb * kCtlHead,
+                          hipHostMallocCoherent | hipHostMallocMapped));
+    CHM_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&S.dheads), S.hctl, 0));
     k_zero<<<grid(nblk(len), (int)nb), kBlock, 0, S.stream>>>((int)len, S.x);
     CHM_HIP(hipStreamSynchronize(S.stream));
 }
@@ -1023,12 +1027,8 @@ constexpr long kHStride = 2 * (kMaxRestart + 1);                  // per run
 // directly; a batch: packed on the device first, then one copy)
 void copy_heads(Solver &S, hipStream_t st)
 {
-    if (S.nrun == 1) {
-        CHM_HIP(hipMemcpyAsync(S.hctl, S.ctl, kCtlHead, hipMemcpyDeviceToHost, st));
-        return;
-    }
     k_pack_heads<<<grid(1, S.nrun), 64, 0, st>>>(S.ctl, S.dheads);
-    CHM_HIP(hipMemcpyAsync(S.hctl, S.dheads, S.nrun * kCtlHead, hipMemcpyDeviceToHost, st));
+    CHM_HIP(hipGetLastError());
 }
 
 void read_ctl(Solver &S)
