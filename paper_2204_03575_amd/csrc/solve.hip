@@ -610,40 +610,6 @@ struct Pot {
     double iNp, iNn, iNs, chi_pn, chi_ps, chi_ns, floor_;   // iN*: 1 / N*
 };
 
-// Natural logarithm of a positive finite x, about a third of the FP64 work
-// of the library's log.  With x = m 2^e, m in [sqrt(1/2), sqrt(2)), and
-// f = m - 1 (exact), s = f / (2 + f):
-//   log(m) = 2 atanh(s) = 2 s + s Q(s^2),  Q(z) = sum_{k >= 1} 2 z^k / (2k + 1),
-// and 2 s = f - s f, so log(m) = f - s (f - Q).  |s| <= 0.1716, so z <= 0.0295
-// and the terms past k = 10 are below 2^-60 relative.  ln 2 = ln2_hi +
-// ln2_lo with ln2_hi holding 42 significant bits, so e ln2_hi is exact.
-// Error: about one unit in the last place.
-__device__ inline double log_pos(double x)
-{
-    constexpr double ln2_hi = 0x1.62e42fefa3800p-1, ln2_lo = 0x1.ef35793c76730p-45;
-    int e;
-    double m = frexp(x, &e);   // [1/2, 1)
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        --e;
-    }
-    const double f = m - 1.0, s = f / (2.0 + f), z = s * s;
-    double q = 2.0 / 21.0;
-    q = fmad(q, z, 2.0 / 19.0);
-    q = fmad(q, z, 2.0 / 17.0);
-    q = fmad(q, z, 2.0 / 15.0);
-    q = fmad(q, z, 2.0 / 13.0);
-    q = fmad(q, z, 2.0 / 11.0);
-    q = fmad(q, z, 2.0 / 9.0);
-    q = fmad(q, z, 2.0 / 7.0);
-    q = fmad(q, z, 2.0 / 5.0);
-    q = fmad(q, z, 2.0 / 3.0);
-    q *= z;
-    const double de = (double)e;
-    const double r = f - s * (f - q);
-    return fmad(de, ln2_hi, r + de * ln2_lo);
-}
-
 __device__ inline double clog(double v, double fl, int &clamps)
 {
     if (v < fl) {
