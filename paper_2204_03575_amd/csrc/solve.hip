@@ -213,7 +213,7 @@ k_saddle_resid(int n, const int *__restrict__ sptr,
 // len = 2n.  The grid (up to kGsBlocks blocks per run) keeps several blocks
 // per CU.  The Krylov vectors are [index][run][len] (index stride ks = runs
 // len); per run, w advances by len, h by hs and the partials by ps.
-constexpr int kChunk = 8;
+constexpr int kChunk = 4;
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *__restrict__ V,
