@@ -237,13 +237,13 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *
             double2 wv = w[i];
             for (int v = 0; v < nvec; ++v) {
                 const double2 hv = h[v], vv = V[(size_t)v * ks + i];
-                wv.x -= hv.x * vv.x;
-                wv.y -= hv.y * vv.y;
+                wv.x = fmad(-hv.x, vv.x, wv.x);
+                wv.y = fmad(-hv.y, vv.y, wv.y);
             }
             w[i] = wv;
             if (MODE == 2) {
-                nrm.x += wv.x * wv.x;
-                nrm.y += wv.y * wv.y;
+                nrm.x = fmad(wv.x, wv.x, nrm.x);
+                nrm.y = fmad(wv.y, wv.y, nrm.y);
             }
         }
     }
@@ -263,8 +263,8 @@ __global__ void __launch_bounds__(kBlock) k_gs(int len, long ks, const double2 *
             for (int c = 0; c < kChunk; ++c) {
                 if (v0 + c < nvec) {
                     const double2 vv = V[(size_t)(v0 + c) * ks + i];
-                    acc[c].x += vv.x * wv.x;
-                    acc[c].y += vv.y * wv.y;
+                    acc[c].x = fmad(vv.x, wv.x, acc[c].x);
+                    acc[c].y = fmad(vv.y, wv.y, acc[c].y);
                 }
             }
         }
@@ -313,15 +313,15 @@ __global__ void __launch_bounds__(kBlock) k_gs1_reg(int len, long ks, const doub
         for (int v = 0; v < NV; ++v) {
             if (v < nvec) {
                 const double2 hv = h[v];
-                wv.x -= hv.x * vv[v].x;
-                wv.y -= hv.y * vv[v].y;
+                wv.x = fmad(-hv.x, vv[v].x, wv.x);
+                wv.y = fmad(-hv.y, vv[v].y, wv.y);
             }
         }
         w[i] = wv;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            acc[v].x += vv[v].x * wv.x;
-            acc[v].y += vv[v].y * wv.y;
+            acc[v].x = fmad(vv[v].x, wv.x, acc[v].x);
+            acc[v].y = fmad(vv[v].y, wv.y, acc[v].y);
         }
     }
 #pragma unroll
@@ -330,6 +330,87 @@ __global__ void __launch_bounds__(kBlock) k_gs1_reg(int len, long ks, const doub
             const double2 t = block_sum(acc[v], sh);
             if (threadIdx.x == 0)
                 part[(size_t)v * G + blockIdx.x] = t;
+        }
+    }
+}
+
+// MODE 1 for more than NV basis vectors: the update runs over every vector,
+// the first NV held in registers for their dots as in k_gs1_reg; the dots of
+// the others take a second sweep over the updated w (each thread reads back
+// its own elements) in groups of kChunk.  The update and every partial follow
+// the orders of k_gs<1>, so the results are bitwise the same, and the first
+// NV vectors are read once instead of twice.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gs1_split(int len, long ks,
+                                                      const double2 *__restrict__ V, int nvec,
+                                                      double2 *w, const double2 *__restrict__ hin,
+                                                      long hs, double2 *part, long ps)
+{
+    __shared__ double2 sh[kBlock / 64];
+    __shared__ double2 h[kMaxRestart + 1];
+    const int G = gridDim.x;
+    const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
+    V = run_at(V, len);
+    w = run_at(w, len);
+    hin = run_at(hin, hs);
+    part = run_at(part, ps);
+    for (int v = threadIdx.x; v < nvec; v += kBlock)
+        h[v] = hin[v];
+    __syncthreads();
+    double2 acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        acc[v] = d2(0.0, 0.0);
+#pragma unroll 1
+    for (int i = start; i < len; i += stride) {
+        double2 vv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)   // nvec > NV: every slot is a basis vector
+            vv[v] = V[(size_t)v * ks + i];
+        double2 wv = w[i];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double2 hv = h[v];
+            wv.x = fmad(-hv.x, vv[v].x, wv.x);
+            wv.y = fmad(-hv.y, vv[v].y, wv.y);
+        }
+        for (int v = NV; v < nvec; ++v) {
+            const double2 hv = h[v], x = V[(size_t)v * ks + i];
+            wv.x = fmad(-hv.x, x.x, wv.x);
+            wv.y = fmad(-hv.y, x.y, wv.y);
+        }
+        w[i] = wv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc[v].x = fmad(vv[v].x, wv.x, acc[v].x);
+            acc[v].y = fmad(vv[v].y, wv.y, acc[v].y);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double2 t = block_sum(acc[v], sh);
+        if (threadIdx.x == 0)
+            part[(size_t)v * G + blockIdx.x] = t;
+    }
+    for (int v0 = NV; v0 < nvec; v0 += kChunk) {
+        double2 a2[kChunk];
+        for (int c = 0; c < kChunk; ++c)
+            a2[c] = d2(0.0, 0.0);
+        for (int i = start; i < len; i += stride) {
+            const double2 wv = w[i];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                if (v0 + c < nvec) {
+                    const double2 vv = V[(size_t)(v0 + c) * ks + i];
+                    a2[c].x = fmad(vv.x, wv.x, a2[c].x);
+                    a2[c].y = fmad(vv.y, wv.y, a2[c].y);
+                }
+            }
+        }
+        for (int c = 0; c < kChunk && v0 + c < nvec; ++c) {
+            const double2 t = block_sum(a2[c], sh);
+            if (threadIdx.x == 0)
+                part[(size_t)(v0 + c) * G + blockIdx.x] = t;
         }
     }
 }
@@ -1029,8 +1110,8 @@ void iteration_body(Solver &S, int j)
         k_gs1_reg<16><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride,
                                                       S.gsp2, kGsStride);
     else
-        k_gs<1><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride, S.gsp2,
-                                                kGsStride);
+        k_gs1_split<16><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h1, kHStride,
+                                                        S.gsp2, kGsStride);
     k_finish<<<grid(j + 1, R), kBlock, 0, st>>>(S.gsp2, kGsStride, Gg, h2, kHStride);
     k_gs<2><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h2, kHStride, S.gsp3,
                                             kGsBlocks);
