@@ -285,6 +285,7 @@ struct Solver {
     double2 *xk = nullptr;     // FGMRES iterate (committed to x on success)
     double2 *b = nullptr, *r = nullptr;
     double2 *V = nullptr, *Z = nullptr;   // [Krylov index][run][2n]
+    float2 *Z32 = nullptr;     // Z in FP32 (FP32 preconditioner: its results are FP32)
     double2 *xl = nullptr;     // linear-extrapolation candidate
     double2 *f = nullptr;      // potential term of the right-hand side (pairs)
     double2 *fslot = nullptr;  // its quadrature per cell and corner, before the gather
@@ -349,6 +350,9 @@ void prec_setup(Solver &S);   // FP32 copies and work vectors (mixed precision)
 void vcycle(Solver &S, int hier, const double2 *b, double2 *x);
 void schur_solve(Solver &S, const double2 *b, double2 *x);
 void apply_prec(Solver &S, const double2 *v, double2 *w);
+// the FP32 preconditioner with an FP32 result; narrowed: S.w32.vin already
+// holds v in FP32
+void apply_prec32(Solver &S, const double2 *v, float2 *w, bool narrowed);
 // As-norm contraction of one FP64 V-cycle of the As hierarchy (power iteration)
 double vcycle_contraction(Solver &S, int iters);
 

@@ -1098,4 +1098,11 @@ void apply_prec(Solver &S, const double2 *v, double2 *w)
     widen(S, len, S.w32.wout, w);
 }
 
+void apply_prec32(Solver &S, const double2 *v, float2 *w, bool narrowed)
+{
+    if (!narrowed)
+        narrow(S, 2 * S.nv, v, S.w32.vin);
+    apply_prec_t<float>(S, S.w32.vin, w);
+}
+
 }  // namespace chm

@@ -13,6 +13,14 @@ namespace chm {
 
 namespace {
 
+// a pair vector entry as FP64 (an FP32 entry converts exactly)
+__device__ inline double2 ld2(const double2 *p, long i) { return p[i]; }
+__device__ inline double2 ld2(const float2 *p, long i)
+{
+    const float2 v = p[i];
+    return d2((double)v.x, (double)v.y);
+}
+
 // ------------------------------------------------------------------ saddle-point operator
 // y0 = M x0 + t K x1; y1 = t K x0 - te M x1 (per species t, te)
 // A row is taken kSellUnroll entries at a time: every column and value load of
@@ -80,10 +88,10 @@ __device__ inline void saddle_dot(const SaddleEnt &e, const double2 *x0, const d
     saddle_combine(a.m0x, a.m0y, a.k1x, a.k1y, a.k0x, a.k0y, a.m1x, a.m1y, t, te, y0, y1);
 }
 
-template <class I, bool U8>
+template <class I, bool U8, class XT = double2>
 __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
                                   const I *__restrict__ col, const double *__restrict__ vm,
-                                  const double *__restrict__ vk, const double2 *__restrict__ x,
+                                  const double *__restrict__ vk, const XT *__restrict__ x,
                                   double2 t, double2 te, double2 &y0, double2 &y1)
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
@@ -94,8 +102,8 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
         double2 x0[kSellUnroll], x1[kSellUnroll];
 #pragma unroll
         for (int k = 0; k < kSellUnroll; ++k) {
-            x0[k] = x[e.c[k]];
-            x1[k] = x[n + e.c[k]];
+            x0[k] = ld2(x, e.c[k]);
+            x1[k] = ld2(x, n + e.c[k]);
         }
         saddle_dot(e, x0, x1, t, te, y0, y1);
         return;
@@ -107,8 +115,8 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
         double2 x0[kSellUnroll], x1[kSellUnroll];
 #pragma unroll
         for (int k = 0; k < kSellUnroll; ++k) {
-            x0[k] = x[e.c[k]];
-            x1[k] = x[n + e.c[k]];
+            x0[k] = ld2(x, e.c[k]);
+            x1[k] = ld2(x, n + e.c[k]);
         }
         saddle_acc(e, x0, x1, a);
     }
@@ -117,13 +125,13 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
 
 // per run, x and y advance by 2n; RB runs per lane (block row blockIdx.y),
 // R in all: on U8 patterns the row's entries are loaded once for the RB runs
-template <class I, bool U8, int RB>
+template <class I, bool U8, int RB, class XT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_saddle(int n, int R, const int *__restrict__ sptr,
                                                    const I *__restrict__ col,
                                                    const double *__restrict__ vm,
                                                    const double *__restrict__ vk,
-                                                   const double2 *__restrict__ x, double2 *y,
+                                                   const XT *__restrict__ x, double2 *y,
                                                    double2 t, double2 te)
 {
     const int row = xcd_block() * kBlock + threadIdx.x;
@@ -141,11 +149,11 @@ k_saddle(int n, int R, const int *__restrict__ sptr,
 #pragma unroll
             for (int q = 0; q < RB; ++q)
                 if (r0 + q < R) {
-                    const double2 *xr = x + (r0 + q) * len;
+                    const XT *xr = x + (r0 + q) * len;
 #pragma unroll
                     for (int k = 0; k < kSellUnroll; ++k) {
-                        x0[q][k] = xr[e.c[k]];
-                        x1[q][k] = xr[n + e.c[k]];
+                        x0[q][k] = ld2(xr, e.c[k]);
+                        x1[q][k] = ld2(xr, n + e.c[k]);
                     }
                 }
 #pragma unroll
@@ -163,7 +171,7 @@ k_saddle(int n, int R, const int *__restrict__ sptr,
     for (int q = 0; q < RB; ++q)
         if (RB == 1 || r0 + q < R) {
             double2 y0, y1;
-            saddle_row<I, U8>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
+            saddle_row<I, U8, XT>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
             double2 *yr = y + (r0 + q) * len;
             yr[row] = y0;
             yr[n + row] = y1;
@@ -622,7 +630,10 @@ __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
 }
 
 // v_{j+1} = w / ||w|| for species still active, 0 otherwise (per run, v advances by len)
-__global__ void __launch_bounds__(kBlock) k_scale_next(int len, double2 *v, const Ctl *__restrict__ c)
+// (with v32: also its FP32 copy, the input the FP32 preconditioner takes
+// next, so that it need not narrow v_{j+1} itself)
+__global__ void __launch_bounds__(kBlock) k_scale_next(int len, double2 *v, const Ctl *__restrict__ c,
+                                                       float2 *v32)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= len)
@@ -632,7 +643,10 @@ __global__ void __launch_bounds__(kBlock) k_scale_next(int len, double2 *v, cons
     const double s0 = (c->active[0] && c->hn[0] > 0.0) ? 1.0 / c->hn[0] : 0.0;
     const double s1 = (c->active[1] && c->hn[1] > 0.0) ? 1.0 / c->hn[1] : 0.0;
     const double2 vv = v[i];
-    v[i] = d2(vv.x * s0, vv.y * s1);
+    const double2 out = d2(vv.x * s0, vv.y * s1);
+    v[i] = out;
+    if (v32)
+        run_at(v32, len)[i] = make_float2((float)out.x, (float)out.y);
 }
 
 // back substitution of the rotated Hessenberg system, k[s] columns per species
@@ -656,8 +670,11 @@ __global__ void k_trisolve(Ctl *c, int m)
 
 // x += sum_{i < kmax} Z_i y_i, per species (Z is [index][run][len], index
 // stride ks; per run x advances by len)
+// (Z in FP64, or in FP32 where the preconditioner computes in FP32: its
+// results are FP32 values, which convert exactly)
+template <class ZT>
 __global__ void __launch_bounds__(kBlock) k_update_x(int len, long ks, double2 *x,
-                                                     const double2 *__restrict__ Z, int kmax,
+                                                     const ZT *__restrict__ Z, int kmax,
                                                      const Ctl *__restrict__ c)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -668,9 +685,9 @@ __global__ void __launch_bounds__(kBlock) k_update_x(int len, long ks, double2 *
     Z = run_at(Z, len);
     double2 xv = x[i];
     for (int t = 0; t < kmax; ++t) {
-        const double2 z = Z[(size_t)t * ks + i];
-        xv.x += c->y[0][t] * z.x;
-        xv.y += c->y[1][t] * z.y;
+        const double2 z = ld2(Z, (size_t)t * ks + i);
+        xv.x = fmad(c->y[0][t], z.x, xv.x);
+        xv.y = fmad(c->y[1][t], z.y, xv.y);
     }
     x[i] = xv;
 }
@@ -950,32 +967,38 @@ inline const Ctl &head(const Solver &S, int r)
 
 }  // namespace
 
-template <class I, bool U8>
-static void saddle_rb(Solver &S, const I *col, const double2 *x, double2 *y)
+template <class I, bool U8, class XT>
+static void saddle_rb(Solver &S, const I *col, const XT *x, double2 *y)
 {
     const int n = S.nv, R = S.nrun, rb = rb_of(S);
     const dim3 g = grid_rb(nblk(n), R, rb);
     const double2 t = pair(S.tau_s), te = pair(S.te_s);
     if (rb >= 4)
-        k_saddle<I, U8, 4><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+        k_saddle<I, U8, 4, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
+                                                           y, t, te);
     else if (rb == 2)
-        k_saddle<I, U8, 2><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+        k_saddle<I, U8, 2, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
+                                                           y, t, te);
     else
-        k_saddle<I, U8, 1><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x, y, t, te);
+        k_saddle<I, U8, 1, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
+                                                           y, t, te);
 }
 
-void apply_saddle(Solver &S, const double2 *x, double2 *y)
+template <class XT>
+static void apply_saddle_t(Solver &S, const XT *x, double2 *y)
 {
     const bool u8 = S.sM.wmax <= kSellUnroll;
     if (S.sM.ocol && u8)
-        saddle_rb<int16_t, true>(S, S.sM.ocol, x, y);
+        saddle_rb<int16_t, true, XT>(S, S.sM.ocol, x, y);
     else if (S.sM.ocol)
-        saddle_rb<int16_t, false>(S, S.sM.ocol, x, y);
+        saddle_rb<int16_t, false, XT>(S, S.sM.ocol, x, y);
     else if (u8)
-        saddle_rb<int, true>(S, S.sM.col, x, y);
+        saddle_rb<int, true, XT>(S, S.sM.col, x, y);
     else
-        saddle_rb<int, false>(S, S.sM.col, x, y);
+        saddle_rb<int, false, XT>(S, S.sM.col, x, y);
 }
+
+void apply_saddle(Solver &S, const double2 *x, double2 *y) { apply_saddle_t<double2>(S, x, y); }
 
 // y = b - A x and the partials of its norms (k_saddle_resid) on M's pattern
 static void saddle_resid(Solver &S, dim3 g, const double2 *x, double2 *y, double2 *part, double w2)
@@ -1038,7 +1061,11 @@ void alloc_workspace(Solver &S)
     S.b = p.get<double2>(nb * len);
     S.r = p.get<double2>(nb * len);
     S.V = p.get<double2>(nb * len * (S.m + 1));
-    S.Z = p.get<double2>(nb * len * S.m);
+    // the preconditioned vectors: FP32 where the preconditioner computes in FP32
+    if (S.mixed)
+        S.Z32 = p.get<float2>(nb * len * S.m);
+    else
+        S.Z = p.get<double2>(nb * len * S.m);
     S.f = p.get<double2>(nb * n);
     S.fslot = p.get<double2>(nb * (size_t)S.vslot_stored);
     // the padding of the slot lists adds zero
@@ -1095,10 +1122,17 @@ void iteration_body(Solver &S, int j)
     const long ks = (long)R * len;   // Krylov index stride: [index][run][len]
     hipStream_t st = S.stream;
     const int Gg = (int)std::min<long>(kGsBlocks, nblk(len));
-    double2 *vj = S.V + (size_t)j * ks, *zj = S.Z + (size_t)j * ks;
+    double2 *vj = S.V + (size_t)j * ks;
     double2 *w = S.V + (size_t)(j + 1) * ks;
-    apply_prec(S, vj, zj);
-    apply_saddle(S, zj, w);
+    if (S.mixed) {   // z_j stays FP32; v_j (j > 0) came with its FP32 copy
+        float2 *zj = S.Z32 + (size_t)j * ks;
+        apply_prec32(S, vj, zj, j > 0);
+        apply_saddle_t<float2>(S, zj, w);
+    } else {
+        double2 *zj = S.Z + (size_t)j * ks;
+        apply_prec(S, vj, zj);
+        apply_saddle(S, zj, w);
+    }
     double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
     k_gs<0><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, nullptr, kHStride, S.gsp1,
                                             kGsStride);
@@ -1116,7 +1150,8 @@ void iteration_body(Solver &S, int j)
     k_gs<2><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, h2, kHStride, S.gsp3,
                                             kGsBlocks);
     k_givens<<<grid(1, R), kBlock, 0, st>>>(S.ctl, j, m, h1, h2, kHStride, S.gsp3, kGsBlocks, Gg);
-    k_scale_next<<<grid(nblk(len), R), kBlock, 0, st>>>(len, w, S.ctl);
+    k_scale_next<<<grid(nblk(len), R), kBlock, 0, st>>>(len, w, S.ctl,
+                                                        S.mixed ? S.w32.vin : nullptr);
     CHM_HIP(hipGetLastError());
     copy_heads(S, st);
 }
@@ -1330,7 +1365,10 @@ int step_once(Solver &S, chm_stats_t *st_out)
         if (rc)
             break;
         k_trisolve<<<grid(1, R), 64, 0, st>>>(S.ctl, m);
-        k_update_x<<<grid(nblk(len), R), kBlock, 0, st>>>(len, ks, S.xk, S.Z, kmax, S.ctl);
+        if (S.mixed)
+            k_update_x<<<grid(nblk(len), R), kBlock, 0, st>>>(len, ks, S.xk, S.Z32, kmax, S.ctl);
+        else
+            k_update_x<<<grid(nblk(len), R), kBlock, 0, st>>>(len, ks, S.xk, S.Z, kmax, S.ctl);
         CHM_HIP(hipGetLastError());
     }
     if (rc == CHM_OK) {
