@@ -82,6 +82,9 @@ extern "C" {
 #define CHM_MASS_AMG 0
 #define CHM_MASS_CHEBYSHEV 1
 
+#define CHM_ORTHO_DCGS2 0
+#define CHM_ORTHO_CGS2 1
+
 typedef struct chm_solver chm_solver_t;
 
 /* A conforming simplex mesh: triangles (dim 2) or tetrahedra (dim 3).
@@ -187,6 +190,18 @@ typedef struct {
      * step fails with CHM_EDOMAIN and no run is advanced; 0: it is only
      * counted. */
     int32_t range_check;
+    /* Orthogonalisation of the FGMRES basis (the Arnoldi process of the
+     * Krylov method the paper solves the saddle-point system with, Section
+     * 3).  CHM_ORTHO_DCGS2 (0, the default): classical Gram-Schmidt twice per
+     * vector, the second pass delayed to the next iteration, where it shares
+     * a sweep over the basis with the first pass of the next vector: two
+     * sweeps per iteration.  The preconditioner then takes each basis vector
+     * after its first pass, which FGMRES allows (the stored preconditioned
+     * vectors define the solution space; the Hessenberg column of the
+     * previous iteration is corrected for the second pass).
+     * CHM_ORTHO_CGS2: both passes in the vector's own iteration, three
+     * sweeps.  Both build the same Krylov space and differ by rounding. */
+    int32_t ortho;
 } chm_params_t;
 
 /* Per-step statistics. */

@@ -68,7 +68,7 @@ class chm_params_t(C.Structure):
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
         ("runs_per_lane", C.c_int32), ("cheb_degree_coarse", C.c_int32),
-        ("range_check", C.c_int32),
+        ("range_check", C.c_int32), ("ortho", C.c_int32),
     ]
 
 
@@ -182,6 +182,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.runs_per_lane = int(p.get("runs_per_lane", 0))
     s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
     s.range_check = int(p.get("range_check", 0))
+    s.ortho = {"dcgs2": 0, "cgs2": 1}[p.get("ortho", "dcgs2")]
     return s
 
 

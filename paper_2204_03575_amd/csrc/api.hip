@@ -93,6 +93,8 @@ const char *check_params(const chm_params_t &p)
         return "cheb_degree_coarse must be in 0..31";
     if (p.range_check != 0 && p.range_check != 1)
         return "range_check must be 0 or 1";
+    if (p.ortho != CHM_ORTHO_CGS2 && p.ortho != CHM_ORTHO_DCGS2)
+        return "ortho must be CHM_ORTHO_CGS2 or CHM_ORTHO_DCGS2";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;

@@ -205,6 +205,11 @@ struct Ctl {
     double cs[2][kMaxRestart], sn[2][kMaxRestart];
     double g[2][kMaxRestart + 1];
     double y[2][kMaxRestart];
+    // delayed reorthogonalisation: the last Hessenberg column before the
+    // rotations (its last two entries change when the next iteration makes
+    // the newest basis vector final) and the cycle's initial residual norm
+    double hlast[2][kMaxRestart + 1];
+    double beta[2];
 };
 constexpr size_t kCtlHead = offsetof(Ctl, H);
 static_assert(kCtlHead % 16 == 0, "control-block heads are packed back to back");

@@ -423,6 +423,155 @@ __global__ void __launch_bounds__(kBlock) k_gs1_split(int len, long ks,
     }
 }
 
+// ------------------------------------------------------------------ delayed reorthogonalisation
+// With ortho = CHM_ORTHO_DCGS2, the second Gram-Schmidt pass of each basis
+// vector runs in the iteration after it.  In iteration j, V_0..V_{j-1} are
+// final, V_j holds u_j (the previous w after one projection, divided by its
+// norm; the preconditioner took u_j) and V_{j+1} holds w = A z_j.  One sweep
+// forms the dot products of V_0..V_j with u_j and with w.  The second makes
+// v_j final, v_j = (u_j - sum_k s_k V_k) / nu with s_k = V_k . u_j and
+// nu^2 = u_j . u_j - |s|^2, projects w on V_0..V_{j-1} and on the final v_j,
+// and sums |w|^2 of the result.  At j = 0, V_0 is the normalised residual,
+// already final: s is empty and nu = 1.
+
+// dot products of V_0..V_j with u = V_j (partial rows 0..j) and with w
+// (rows j+1..2j+1), C basis vectors per sweep; per run as k_gs
+template <int C>
+__global__ void __launch_bounds__(kBlock) k_dgs_dots(int len, long ks,
+                                                     const double2 *__restrict__ V, int j,
+                                                     const double2 *__restrict__ w,
+                                                     double2 *part, long ps)
+{
+    __shared__ double2 sh[kBlock / 64];
+    const int G = gridDim.x;
+    const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
+    V = run_at(V, len);
+    w = run_at(w, len);
+    part = run_at(part, ps);
+    const double2 *u = V + (size_t)j * ks;
+    for (int v0 = 0; v0 <= j; v0 += C) {
+        double2 au[C], aw[C];
+        for (int c = 0; c < C; ++c) {
+            au[c] = d2(0.0, 0.0);
+            aw[c] = d2(0.0, 0.0);
+        }
+        for (int i = start; i < len; i += stride) {
+            const double2 uv = u[i], wv = w[i];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (v0 + c <= j) {
+                    const double2 vv = V[(size_t)(v0 + c) * ks + i];
+                    au[c].x = fmad(vv.x, uv.x, au[c].x);
+                    au[c].y = fmad(vv.y, uv.y, au[c].y);
+                    aw[c].x = fmad(vv.x, wv.x, aw[c].x);
+                    aw[c].y = fmad(vv.y, wv.y, aw[c].y);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {   // constant trip count: the sums stay in registers
+            if (v0 + c <= j) {
+                const double2 a = block_sum(au[c], sh);
+                if (threadIdx.x == 0)
+                    part[(size_t)(v0 + c) * G + blockIdx.x] = a;
+                const double2 b = block_sum(aw[c], sh);
+                if (threadIdx.x == 0)
+                    part[(size_t)(j + 1 + v0 + c) * G + blockIdx.x] = b;
+            }
+        }
+    }
+}
+
+// The delayed pass's scalars from the finished dot products h (rows as
+// k_dgs_dots writes them), per species: nu, 1 / nu and the component of w
+// along the final v_j, (w . u - s . t) / nu with t_k = V_k . w.  A zero u (a
+// species no longer iterating) gives nu = 0 and zeros.  The update sweep and
+// the Givens step both call this on the same values, so they agree bitwise.
+struct DgsCoef {
+    double2 nu, inv, hjj;
+};
+
+__device__ inline double dgs_one(double a, double b, double ss, double st, double &nu, double &inv)
+{
+    const double nu2 = a - ss;
+    nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    return nu > 0.0 ? (b - st) / nu : 0.0;
+}
+
+__device__ inline DgsCoef dgs_coef(const double2 *h, int j)
+{
+    DgsCoef r;
+    if (j == 0) {
+        r.nu = d2(1.0, 1.0);
+        r.inv = d2(1.0, 1.0);
+        r.hjj = h[1];
+        return r;
+    }
+    double2 ss = d2(0.0, 0.0), st = d2(0.0, 0.0);
+    for (int k = 0; k < j; ++k) {
+        const double2 sk = h[k], tk = h[j + 1 + k];
+        ss.x = fmad(sk.x, sk.x, ss.x);
+        ss.y = fmad(sk.y, sk.y, ss.y);
+        st.x = fmad(sk.x, tk.x, st.x);
+        st.y = fmad(sk.y, tk.y, st.y);
+    }
+    const double2 a = h[j], b = h[2 * j + 1];
+    r.hjj.x = dgs_one(a.x, b.x, ss.x, st.x, r.nu.x, r.inv.x);
+    r.hjj.y = dgs_one(a.y, b.y, ss.y, st.y, r.nu.y, r.inv.y);
+    return r;
+}
+
+// v_j final (written over u_j, j > 0) and w -= sum_{k<j} t_k V_k + h_jj v_j,
+// with partials of |w|^2 (per run: hin advances by hs, part by ps)
+__global__ void __launch_bounds__(kBlock) k_dgs_update(int len, long ks, double2 *V, int j,
+                                                       double2 *w,
+                                                       const double2 *__restrict__ hin, long hs,
+                                                       double2 *part, long ps)
+{
+    __shared__ double2 sh[kBlock / 64];
+    __shared__ double2 sc[kMaxRestart], tc[kMaxRestart];
+    __shared__ DgsCoef cf;
+    const int G = gridDim.x;
+    const int start = blockIdx.x * kBlock + threadIdx.x, stride = G * kBlock;
+    V = run_at(V, len);
+    w = run_at(w, len);
+    hin = run_at(hin, hs);
+    part = run_at(part, ps);
+    for (int k = threadIdx.x; k < j; k += kBlock) {
+        sc[k] = hin[k];
+        tc[k] = hin[j + 1 + k];
+    }
+    if (threadIdx.x == 0)
+        cf = dgs_coef(hin, j);
+    __syncthreads();
+    const DgsCoef f = cf;
+    double2 *u = V + (size_t)j * ks;
+    double2 nrm = d2(0.0, 0.0);
+    for (int i = start; i < len; i += stride) {
+        double2 uv = u[i], wv = w[i];
+        for (int k = 0; k < j; ++k) {
+            const double2 vv = V[(size_t)k * ks + i], sk = sc[k], tk = tc[k];
+            uv.x = fmad(-sk.x, vv.x, uv.x);
+            uv.y = fmad(-sk.y, vv.y, uv.y);
+            wv.x = fmad(-tk.x, vv.x, wv.x);
+            wv.y = fmad(-tk.y, vv.y, wv.y);
+        }
+        uv.x *= f.inv.x;
+        uv.y *= f.inv.y;
+        wv.x = fmad(-f.hjj.x, uv.x, wv.x);
+        wv.y = fmad(-f.hjj.y, uv.y, wv.y);
+        if (j > 0)
+            u[i] = uv;
+        w[i] = wv;
+        nrm.x = fmad(wv.x, wv.x, nrm.x);
+        nrm.y = fmad(wv.y, wv.y, nrm.y);
+    }
+    const double2 t = block_sum(nrm, sh);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = t;
+}
+
 // out[v] = sum of the G partials of vector v; block v handles vector v
 // (thread t adds g = t, t + 256, ... in order, then a fixed block tree);
 // per run, part advances by ps and out by hs
@@ -490,6 +639,7 @@ __global__ void k_cycle_init(Ctl *c, Flags act)
     c->active[s] = act.a[2 * blockIdx.y + s];
     c->k[s] = 0;
     c->g[s][0] = sqrt(c->nrm[s]);
+    c->beta[s] = c->g[s][0];
 }
 
 // keep only the species the host still lets iterate
@@ -620,6 +770,98 @@ __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
     c->g[s][j] = cs * gj;
     c->k[s] = j + 1;
     const double est = fabs(c->g[s][j + 1]);
+    c->resest[s] = est;
+    if (!isfinite(est) || !isfinite(hn)) {
+        c->nan = 1;
+        c->active[s] = 0;
+    } else if (est <= c->tol[s] || hn == 0.0) {
+        c->active[s] = 0;
+    }
+}
+
+// The Givens step of the delayed pass (ortho = CHM_ORTHO_DCGS2).  Making
+// v_j final changes the column of the previous iteration: the |w_{j-1}| it
+// had along u_j becomes |w_{j-1}| s_k along V_k and |w_{j-1}| nu along v_j.
+// That column is rotated again by the rotations before it and gets a new
+// rotation; then column j (t_k, h_jj, |w|) is rotated, g is formed again from
+// the cycle's |r| through every rotation, and the convergence test runs on
+// |g[j+1]| as in k_givens.
+__device__ inline void rotate_col(double *cl, int upto, const double *cs, const double *sn)
+{
+    for (int i = 0; i < upto; ++i) {
+        const double a = cl[i], b = cl[i + 1];
+        cl[i] = cs[i] * a + sn[i] * b;
+        cl[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+}
+
+__device__ inline void new_rotation(double a, double b, double &cs, double &sn, double &rr)
+{
+    rr = sqrt(a * a + b * b);
+    cs = 1.0;
+    sn = 0.0;
+    if (rr != 0.0) {
+        cs = a / rr;
+        sn = b / rr;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_givens_d(Ctl *c, int j, int m,
+                                                     const double2 *__restrict__ hin, long hs,
+                                                     const double2 *__restrict__ p3, long ps, int G)
+{
+    __shared__ double2 nn[1];
+    __shared__ double2 hl[2 * (kMaxRestart + 1)];
+    __shared__ double col[2][kMaxRestart + 1];
+    c += blockIdx.y;
+    hin = run_at(hin, hs);
+    p3 = run_at(p3, ps);
+    for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock)
+        hl[t] = hin[t];
+    reduce_parts(p3, 1, G, nn);   // ends with a block barrier
+    const int s = threadIdx.x;
+    if (s >= 2 || !c->active[s])
+        return;
+    const DgsCoef f = dgs_coef(hl, j);
+    auto pick = [s](double2 v) { return s == 0 ? v.x : v.y; };
+    double *H = c->H[s], *hr = c->hlast[s], *cs = c->cs[s], *sn = c->sn[s], *g = c->g[s];
+    double *cl = col[s];
+    const double hn = sqrt(s == 0 ? nn[0].x : nn[0].y);
+    double rr;
+    if (j > 0) {
+        const double hp = c->hn[s];   // |w_{j-1}| after its one projection
+        for (int k = 0; k < j; ++k)
+            hr[k] = fmad(hp, pick(hl[k]), hr[k]);
+        hr[j] = hp * pick(f.nu);
+        for (int k = 0; k <= j; ++k)
+            cl[k] = hr[k];
+        rotate_col(cl, j - 1, cs, sn);
+        for (int i = 0; i < j - 1; ++i)
+            H[i * m + (j - 1)] = cl[i];
+        new_rotation(cl[j - 1], cl[j], cs[j - 1], sn[j - 1], rr);
+        H[(j - 1) * m + (j - 1)] = rr;
+    }
+    for (int k = 0; k < j; ++k)
+        hr[k] = pick(hl[j + 1 + k]);
+    hr[j] = pick(f.hjj);
+    hr[j + 1] = hn;
+    for (int k = 0; k <= j + 1; ++k)
+        cl[k] = hr[k];
+    rotate_col(cl, j, cs, sn);
+    for (int i = 0; i < j; ++i)
+        H[i * m + j] = cl[i];
+    new_rotation(cl[j], cl[j + 1], cs[j], sn[j], rr);
+    H[j * m + j] = rr;
+    H[(j + 1) * m + j] = 0.0;
+    g[0] = c->beta[s];
+    for (int i = 0; i <= j; ++i) {
+        const double gi = g[i];
+        g[i] = cs[i] * gi;
+        g[i + 1] = -sn[i] * gi;
+    }
+    c->hn[s] = hn;
+    c->k[s] = j + 1;
+    const double est = fabs(g[j + 1]);
     c->resest[s] = est;
     if (!isfinite(est) || !isfinite(hn)) {
         c->nan = 1;
@@ -1072,7 +1314,8 @@ void alloc_workspace(Solver &S)
     fill_double(reinterpret_cast<double *>(S.fslot), 0.0, 2 * nb * (size_t)S.vslot_stored, S.stream);
     S.stage = p.get<double>(n);
     S.red = p.get<double2>(nb * kSlotStride);
-    S.gsp1 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
+    // (twice the rows for the delayed pass's dots with u_j and with w)
+    S.gsp1 = p.get<double2>(nb * 2 * (kMaxRestart + 1) * kGsBlocks);
     S.gsp2 = p.get<double2>(nb * (kMaxRestart + 1) * kGsBlocks);
     S.gsp3 = p.get<double2>(nb * kGsBlocks);
     S.hfin = p.get<double2>(nb * 2 * (kMaxRestart + 1));
@@ -1112,7 +1355,8 @@ void read_ctl(Solver &S)
 }
 
 // One Arnoldi step j of FGMRES for both species of every run: z_j =
-// Prec(v_j) (Algorithm 1), w = A z_j, two Gram-Schmidt passes, the Givens
+// Prec(v_j) (Algorithm 1), w = A z_j, the Gram-Schmidt sweeps (the delayed
+// pair of CHM_ORTHO_DCGS2, or both passes of CHM_ORTHO_CGS2), the Givens
 // update and v_{j+1} = w/|w|, then the heads of the control blocks are copied
 // to pinned host memory.  Everything is enqueued on S.stream without host
 // synchronisation, so the sequence can be captured as a graph.
@@ -1132,6 +1376,21 @@ void iteration_body(Solver &S, int j)
         double2 *zj = S.Z + (size_t)j * ks;
         apply_prec(S, vj, zj);
         apply_saddle(S, zj, w);
+    }
+    if (S.prm.ortho == CHM_ORTHO_DCGS2) {
+        k_dgs_dots<kChunk><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j, w, S.gsp1,
+                                                           2 * kGsStride);
+        k_finish<<<grid(2 * (j + 1), R), kBlock, 0, st>>>(S.gsp1, 2 * kGsStride, Gg, S.hfin,
+                                                          kHStride);
+        k_dgs_update<<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j, w, S.hfin, kHStride,
+                                                     S.gsp3, kGsBlocks);
+        k_givens_d<<<grid(1, R), kBlock, 0, st>>>(S.ctl, j, m, S.hfin, kHStride, S.gsp3,
+                                                  kGsBlocks, Gg);
+        k_scale_next<<<grid(nblk(len), R), kBlock, 0, st>>>(len, w, S.ctl,
+                                                            S.mixed ? S.w32.vin : nullptr);
+        CHM_HIP(hipGetLastError());
+        copy_heads(S, st);
+        return;
     }
     double2 *h1 = S.hfin, *h2 = S.hfin + kMaxRestart + 1;
     k_gs<0><<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j + 1, w, nullptr, kHStride, S.gsp1,

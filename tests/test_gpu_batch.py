@@ -56,10 +56,11 @@ BOX = dict(dim=3, n=(6, 5, 4), extent=(1.0, 1.0, 0.8))
     (4, "fp64", "linear", {}), (3, "fp32", "linear", W512),
     (5, "fp64", "previous", dict(runs_per_lane=1)), (5, "fp64", "linear", dict(runs_per_lane=4)),
     (6, "fp32", "linear", dict(W512, runs_per_lane=4)), (7, "fp32", "previous", dict(runs_per_lane=4)),
-    (3, "fp64", "previous", dict(BOX, runs_per_lane=4)), (5, "fp32", "previous", dict(BOX))],
+    (3, "fp64", "previous", dict(BOX, runs_per_lane=4)), (5, "fp32", "previous", dict(BOX)),
+    (5, "fp64", "linear", dict(ortho="cgs2")), (4, "fp32", "previous", dict(BOX, ortho="cgs2"))],
     ids=["1-fp64", "5-fp64", "7-fp32", "4-fp64-linear", "3-fp32-linear-w512", "5-fp64-rb1",
          "5-fp64-linear-rb4", "6-fp32-linear-w512-rb4", "7-fp32-rb4", "3-fp64-3d-rb4",
-         "5-fp32-3d"])
+         "5-fp32-3d", "5-fp64-linear-cgs2", "4-fp32-3d-cgs2"])
 def test_batch_runs_equal_single_runs_bitwise(runs, precision, guess, extra):
     case("batch vs single runs", runs=runs, precision=precision, guess=guess, **extra)
     from paper_2204_03575_amd import Solver

@@ -229,9 +229,14 @@ def test_square32_free_running_trajectory():
     dict(cheb_degree=6, cheb_degree_coarse=3, coarse_max=12, cheb_ratio=5.0,
          mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=2),
     dict(smoother="jacobi", cheb_degree=3, cheb_degree_coarse=1, coarse_max=12),
+    dict(ortho="cgs2"),                               # both Gram-Schmidt passes in one iteration
+    dict(ortho="cgs2", restart=5),
+    dict(restart=2),                                  # a cycle of two: one delayed pass
+    dict(ortho="cgs2", cheb_degree=6, cheb_degree_coarse=3, coarse_max=12, cheb_ratio=5.0,
+         mass_solver="chebyshev", cheb_degree_mass=5, schur_pcg=2),
 ], ids=["poly", "jacobi", "stationary", "restart5", "tau-eps-mob", "nopot", "mass-cheb",
         "mass-jacobi", "mass-cheb-minres", "degree1", "degree2", "coarse1", "coarse3",
-        "jacobi-coarse1"])
+        "jacobi-coarse1", "cgs2", "cgs2-restart5", "restart2", "cgs2-coarse3"])
 def test_step_variants(variant):
     v = dict(variant)
     mean = v.pop("mean", (0.1, 0.1))
@@ -249,11 +254,13 @@ def test_3d_box_steps(mass):
     run_pair(p, co, ce, g, o, 2)
 
 
-def test_3d_box_coarse_degree_steps():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_3d_box_coarse_degree_steps(ortho):
     """the 3D box workload's setting: coarse levels smoothed with one step"""
-    case("3d box 10x9x6, coarse degree 1, 2 steps")
+    case("3d box 10x9x6, coarse degree 1, 2 steps", ortho=ortho)
     p, co, ce, g, o = make(n=(10, 9, 6), dim=3, extent=(1.0, 1.0, 0.5), mass_solver="chebyshev",
-                           cheb_degree_mass=5, schur_pcg=1, cheb_degree_coarse=1, coarse_max=30)
+                           cheb_degree_mass=5, schur_pcg=1, cheb_degree_coarse=1, coarse_max=30,
+                           ortho=ortho)
     assert g.num_levels(1) >= 3
     run_pair(p, co, ce, g, o, 2)
 
@@ -302,14 +309,15 @@ def test_nan_is_reported():
     assert ei.value.code == CHM_ENAN
 
 
-def test_graph_replays_match_eager_bitwise():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_graph_replays_match_eager_bitwise(ortho):
     """Each FGMRES iteration captured as a HIP graph and replayed over several
     steps (with eager right-hand sides and host synchronisation in between)
     gives the eager kernels' results bit for bit, step by step."""
-    case("graphs vs eager, 28x26, 4 steps")
+    case("graphs vs eager, 28x26, 4 steps", ortho=ortho)
     runs = []
     for graphs in (0, 1):
-        p, co, ce, g, o = make(n=(28, 26), use_graphs=graphs)
+        p, co, ce, g, o = make(n=(28, 26), use_graphs=graphs, ortho=ortho)
         php, phn, _ = S.initial_fractions(o.nv, 0.1, 0.1)
         g.set_fields(php, phn)
         per_step = []
