@@ -34,6 +34,11 @@ enum : int { OUT = 0, UND = 1, IN = 2 };
 
 inline int nblk(long n, int bs = kBlock) { return (int)std::max<long>(1, (n + bs - 1) / bs); }
 
+// The residual-and-restriction product RR = [R | -R A] is formed where its
+// rows average at most this many entries (two passes of four entries on 32
+// lanes); longer rows (3D patterns) run faster as the two products.
+constexpr double kFuseRowMax = 256.0;
+
 __device__ inline uint64_t splitmix_at(uint64_t i)
 {
     uint64_t z = (i + 1u) * 0x9E3779B97F4A7C15ull;
@@ -416,6 +421,38 @@ __global__ void k_rows_compress(const int *off, int n, const uint64_t *keys, con
             cv[o] += x;
         }
         prev = c;
+    }
+}
+
+// ---- RR = [R | -R A]: per row, R's entries, then those of R A with their
+// columns shifted by n and their values negated ----
+__global__ void __launch_bounds__(kBlock) k_rr_count(const int *__restrict__ rp1,
+                                                     const int *__restrict__ rp2, int m, int *rp)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < m)
+        rp[i] = (rp1[i + 1] - rp1[i]) + (rp2[i + 1] - rp2[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rr_fill(const int *__restrict__ rp1,
+                                                    const int *__restrict__ ci1,
+                                                    const double *__restrict__ v1,
+                                                    const int *__restrict__ rp2,
+                                                    const int *__restrict__ ci2,
+                                                    const double *__restrict__ v2, int m, int n,
+                                                    const int *__restrict__ rp, int *ci, double *v)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m)
+        return;
+    int o = rp[i];
+    for (int k = rp1[i]; k < rp1[i + 1]; ++k, ++o) {
+        ci[o] = ci1[k];
+        v[o] = v1[k];
+    }
+    for (int k = rp2[i]; k < rp2[i + 1]; ++k, ++o) {
+        ci[o] = n + ci2[k];
+        v[o] = -v2[k];
     }
 }
 
@@ -806,6 +843,28 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         Csr AP;
         Pool tmp2;
         spgemm(A, L.P, AP, tmp2, tmp, st);
+        // RR = [R | -R A] for the residual and its restriction in one
+        // product, where its rows are short enough (R A holds at least R's
+        // entries, so R's rows bound it from below)
+        if (2.0 * L.R.nnz <= kFuseRowMax * (double)nc) {
+            Csr RA;
+            spgemm(L.R, A, RA, tmp2, tmp, st);
+            if ((double)L.R.nnz + RA.nnz <= kFuseRowMax * (double)nc) {
+                Csr &RR = L.RR;
+                RR.n = nc;
+                RR.m = 2 * n;
+                RR.rp = pool.get<int>(nc + 1);
+                k_rr_count<<<nblk(nc), kBlock, 0, st>>>(L.R.rp, RA.rp, nc, RR.rp);
+                CHM_HIP(hipGetLastError());
+                scan_exclusive(RR.rp, nc, RR.rp + nc, tmp, st);
+                RR.nnz = read_int(RR.rp + nc, st);
+                RR.ci = pool.get<int>(std::max(1, RR.nnz));
+                RR.v = pool.get<double>(std::max(1, RR.nnz));
+                k_rr_fill<<<nblk(nc), kBlock, 0, st>>>(L.R.rp, L.R.ci, L.R.v, RA.rp, RA.ci, RA.v,
+                                                       nc, n, RR.rp, RR.ci, RR.v);
+                CHM_HIP(hipGetLastError());
+            }
+        }
         Level &C = H.lev[l + 1];
         C = Level();
         C.n = nc;
@@ -884,6 +943,9 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
             L.gsR = lanes_per_row(L.R);
             L.uP = unroll(L.P, L.gsP);
             L.uR = unroll(L.R, L.gsR);
+            // RR is always a CSR-vector product (at least 4 lanes per row)
+            L.gsRR = std::max(4, lanes_per_row(L.RR));
+            L.uRR = unroll(L.RR, L.gsRR);
         }
         const size_t len = (size_t)S.nb * L.n;   // all runs of the batch
         H.x[l] = pool.get<double2>(len);

@@ -115,6 +115,12 @@ struct Level {
     Sell sA, sP, sR;
     int gsA = 0, gsP = 0, gsR = 0;   // lanes per row (see MatView)
     int uA = 1, uP = 1, uR = 1;      // CSR entries per lane and pass (see MatView)
+    // the residual and its restriction in one product: row i of RR is row i
+    // of R (columns j < n, applied to b) followed by row i of -R A (columns
+    // n + j, applied to x), so RR [b; x] = R (b - A x); CSR, rows of the next
+    // level (empty on the coarsest level and where its rows would be long)
+    Csr RR;
+    int gsRR = 0, uRR = 1;
     double *dinv = nullptr;
     double rho = 0.0;
     int *agg = nullptr;
@@ -125,11 +131,12 @@ struct Level {
     double *inv = nullptr;
     // FP32 copies of the values for the mixed-precision preconditioner
     float *fA_s = nullptr, *fA_c = nullptr, *fP_s = nullptr, *fP_c = nullptr;
-    float *fR_s = nullptr, *fR_c = nullptr, *fdinv = nullptr;
+    float *fR_s = nullptr, *fR_c = nullptr, *fdinv = nullptr, *fRR_c = nullptr;
 
     template <class T> MatView<T> viewA() const;
     template <class T> MatView<T> viewP() const;
     template <class T> MatView<T> viewR() const;
+    template <class T> MatView<T> viewRR() const;
     template <class T> const T *dinv_t() const;
 };
 
@@ -157,6 +164,8 @@ template <> inline MatView<double> Level::viewR<double>() const { return make_vi
 template <> inline MatView<float> Level::viewA<float>() const { return make_view<float>(A, sA, gsA, uA, fA_s, fA_c); }
 template <> inline MatView<float> Level::viewP<float>() const { return make_view<float>(P, sP, gsP, uP, fP_s, fP_c); }
 template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, uR, fR_s, fR_c); }
+template <> inline MatView<double> Level::viewRR<double>() const { return make_view<double>(RR, Sell(), gsRR, uRR, nullptr, RR.v); }
+template <> inline MatView<float> Level::viewRR<float>() const { return make_view<float>(RR, Sell(), gsRR, uRR, nullptr, fRR_c); }
 template <> inline const double *Level::dinv_t<double>() const { return dinv; }
 template <> inline const float *Level::dinv_t<float>() const { return fdinv; }
 

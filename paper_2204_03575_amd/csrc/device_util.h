@@ -538,6 +538,71 @@ void spmv_op(hipStream_t st, int runs, int rb, const MatView<T> &A, const pair_t
     }
 }
 
+// The residual of a level and its restriction in one product:
+// y = RR [b; x] = R (b - A x), with RR = [R | -R A] (n_c rows, columns j < n
+// taken from b and n + j from x).  Same lane groups and passes as k_spmv_v;
+// per run, b and x advance by n and y by n_c.
+template <class T> struct GatherBX {
+    const pair_t<T> *__restrict__ b;
+    const pair_t<T> *__restrict__ x;
+    int n;
+    __device__ pair_t<T> operator()(int j) const { return *(j < n ? b + j : x + (j - n)); }
+};
+
+template <int GS, int U, class T>
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(int nc, int n, const int *__restrict__ rp,
+                                                           const int *__restrict__ ci,
+                                                           const T *__restrict__ v,
+                                                           const pair_t<T> *__restrict__ b,
+                                                           const pair_t<T> *__restrict__ x,
+                                                           pair_t<T> *y)
+{
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= nc)
+        return;
+    b = run_at(b, (long)n);
+    x = run_at(x, (long)n);
+    y = run_at(y, (long)nc);
+    const pair_t<T> s = row_dot_g<GS, U, T>(rp, ci, v, GatherBX<T>{b, x, n}, row, lane);
+    if (lane == 0)
+        y[row] = s;
+}
+
+template <int GS, class T>
+void resid_restrict_u(hipStream_t st, int runs, const MatView<T> &RR, const pair_t<T> *b,
+                      const pair_t<T> *x, pair_t<T> *y)
+{
+    const dim3 g = grid(nblk((long)GS * RR.n), runs);
+    const int n = RR.m / 2;
+    if (RR.u >= 4)
+        k_resid_restrict<GS, 4, T><<<g, kBlock, 0, st>>>(RR.n, n, RR.rp, RR.ci, RR.cval, b, x, y);
+    else if (RR.u == 2)
+        k_resid_restrict<GS, 2, T><<<g, kBlock, 0, st>>>(RR.n, n, RR.rp, RR.ci, RR.cval, b, x, y);
+    else
+        k_resid_restrict<GS, 1, T><<<g, kBlock, 0, st>>>(RR.n, n, RR.rp, RR.ci, RR.cval, b, x, y);
+}
+
+template <class T>
+void resid_restrict(hipStream_t st, int runs, const MatView<T> &RR, const pair_t<T> *b,
+                    const pair_t<T> *x, pair_t<T> *y)
+{
+    switch (RR.gs) {
+    case 4:
+        resid_restrict_u<4, T>(st, runs, RR, b, x, y);
+        break;
+    case 8:
+        resid_restrict_u<8, T>(st, runs, RR, b, x, y);
+        break;
+    case 16:
+        resid_restrict_u<16, T>(st, runs, RR, b, x, y);
+        break;
+    default:
+        resid_restrict_u<32, T>(st, runs, RR, b, x, y);
+        break;
+    }
+}
+
 // ------------------------------------------------------------------ vector kernels
 // per-block partial sums of the two species' dot products, accumulated in
 // FP64; per run, a and b advance by n and part by one run's slots.  A thread

@@ -743,8 +743,12 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     pair_t<T> *cur = presmooth<T>(S, H, l, b, V.xt, x);
     pair_t<T> *oth = cur == x ? V.xt : x;
     const bool timed = timed_level(S, H, l);
-    spmv_op<SP_RESID, T>(st, R, rb_of(S), L.viewA<T>(), cur, b, V.r);
-    spmv_op<SP_SET, T>(st, R, rb_of(S), L.viewR<T>(), V.r, nullptr, Vc.b);
+    if (L.RR.nnz > 0) {   // b_c = R (b - A x) in one product
+        resid_restrict<T>(st, R, L.viewRR<T>(), b, cur, Vc.b);
+    } else {
+        spmv_op<SP_RESID, T>(st, R, rb_of(S), L.viewA<T>(), cur, b, V.r);
+        spmv_op<SP_SET, T>(st, R, rb_of(S), L.viewR<T>(), V.r, nullptr, Vc.b);
+    }
     vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
     spmv_op<SP_ADD, T>(st, R, rb_of(S), L.viewP<T>(), Vc.x, nullptr, cur);
     if (timed)
@@ -921,6 +925,8 @@ void narrow_hierarchy(Solver &S, Hierarchy &H)
             break;   // the coarsest level solves with its FP64 inverse
         narrow_matrix(pool, st, L.P, L.sP, L.gsP, L.fP_s, L.fP_c);
         narrow_matrix(pool, st, L.R, L.sR, L.gsR, L.fR_s, L.fR_c);
+        if (L.RR.nnz > 0)
+            L.fRR_c = narrow_copy(pool, st, L.RR.v, (long)L.RR.nnz);
         L.fdinv = narrow_copy(pool, st, L.dinv, L.n);
     }
 }
