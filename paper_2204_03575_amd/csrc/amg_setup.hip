@@ -424,8 +424,8 @@ __global__ void k_rows_compress(const int *off, int n, const uint64_t *keys, con
     }
 }
 
-// ---- RR = [R | -R A]: per row, R's entries, then those of R A with their
-// columns shifted by n and their values negated ----
+// ---- [A1 | s A2]: per row, A1's entries, then those of A2 with their
+// columns shifted by n (A1's column count) and their values times s ----
 __global__ void __launch_bounds__(kBlock) k_rr_count(const int *__restrict__ rp1,
                                                      const int *__restrict__ rp2, int m, int *rp)
 {
@@ -440,7 +440,8 @@ __global__ void __launch_bounds__(kBlock) k_rr_fill(const int *__restrict__ rp1,
                                                     const int *__restrict__ rp2,
                                                     const int *__restrict__ ci2,
                                                     const double *__restrict__ v2, int m, int n,
-                                                    const int *__restrict__ rp, int *ci, double *v)
+                                                    double sign, const int *__restrict__ rp,
+                                                    int *ci, double *v)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= m)
@@ -452,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_rr_fill(const int *__restrict__ rp1,
     }
     for (int k = rp2[i]; k < rp2[i + 1]; ++k, ++o) {
         ci[o] = n + ci2[k];
-        v[o] = -v2[k];
+        v[o] = sign * v2[k];
     }
 }
 
@@ -748,6 +749,55 @@ void chebyshev_coefficients(Level &L, int degree, double ratio)
 
 }  // namespace
 
+// One lane per row (SELL-64) for rows the unrolled SELL path covers (up to
+// 16 entries: the fine levels of P1 meshes in 2D and 3D) when there are
+// enough rows to fill the chip; otherwise a power-of-two group of lanes per
+// row, enough to reach about 128k threads and to cover an average row in two
+// passes of four entries per lane, but no wider than the rows.
+int lanes_per_row(const Csr &A)
+{
+    const double avg = A.n > 0 ? double(A.nnz) / A.n : 0.0;
+    const long target = 131072;
+    if (avg < 16.0 && A.n >= target)
+        return 0;
+    int want = 4;
+    while (want < 32 && ((long)want * A.n < target || want * 8 < avg))
+        want *= 2;
+    int cap = 4;
+    while (cap < 32 && cap < avg)
+        cap *= 2;
+    return std::min(want, cap);
+}
+
+// entries per CSR lane and pass: about the average row length over the
+// lanes, so short rows do not load padding and long rows keep four loads in
+// flight per lane
+int unroll(const Csr &A, int gs)
+{
+    const double per_lane = (gs > 0 && A.n > 0) ? double(A.nnz) / A.n / gs : 1.0;
+    return per_lane > 2.0 ? 4 : (per_lane > 1.0 ? 2 : 1);
+}
+
+// [A1 | s A2] row by row (A1, A2 with the same rows; A2's columns shifted by
+// the column count of A1), into pool
+void concat_rows(const Csr &A1, const Csr &A2, double sign, Csr &C, Pool &pool, Pool &tmp,
+                 hipStream_t st)
+{
+    const int m = A1.n;
+    C.n = m;
+    C.m = A1.m + A2.m;
+    C.rp = pool.get<int>(m + 1);
+    k_rr_count<<<nblk(m), kBlock, 0, st>>>(A1.rp, A2.rp, m, C.rp);
+    CHM_HIP(hipGetLastError());
+    scan_exclusive(C.rp, m, C.rp + m, tmp, st);
+    C.nnz = read_int(C.rp + m, st);
+    C.ci = pool.get<int>(std::max(1, C.nnz));
+    C.v = pool.get<double>(std::max(1, C.nnz));
+    k_rr_fill<<<nblk(m), kBlock, 0, st>>>(A1.rp, A1.ci, A1.v, A2.rp, A2.ci, A2.v, m, A1.m, sign,
+                                           C.rp, C.ci, C.v);
+    CHM_HIP(hipGetLastError());
+}
+
 void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
 {
     hipStream_t st = S.stream;
@@ -849,22 +899,13 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         if (2.0 * L.R.nnz <= kFuseRowMax * (double)nc) {
             Csr RA;
             spgemm(L.R, A, RA, tmp2, tmp, st);
-            if ((double)L.R.nnz + RA.nnz <= kFuseRowMax * (double)nc) {
-                Csr &RR = L.RR;
-                RR.n = nc;
-                RR.m = 2 * n;
-                RR.rp = pool.get<int>(nc + 1);
-                k_rr_count<<<nblk(nc), kBlock, 0, st>>>(L.R.rp, RA.rp, nc, RR.rp);
-                CHM_HIP(hipGetLastError());
-                scan_exclusive(RR.rp, nc, RR.rp + nc, tmp, st);
-                RR.nnz = read_int(RR.rp + nc, st);
-                RR.ci = pool.get<int>(std::max(1, RR.nnz));
-                RR.v = pool.get<double>(std::max(1, RR.nnz));
-                k_rr_fill<<<nblk(nc), kBlock, 0, st>>>(L.R.rp, L.R.ci, L.R.v, RA.rp, RA.ci, RA.v,
-                                                       nc, n, RR.rp, RR.ci, RR.v);
-                CHM_HIP(hipGetLastError());
-            }
+            if ((double)L.R.nnz + RA.nnz <= kFuseRowMax * (double)nc)
+                concat_rows(L.R, RA, -1.0, L.RR, pool, tmp, st);
         }
+        // AM = [A | A P] for the prolongation and the first post-smoothing
+        // step in one product, on CSR levels with short enough rows
+        if (lanes_per_row(A) > 0 && (double)A.nnz + AP.nnz <= kFuseRowMax * (double)n)
+            concat_rows(A, AP, 1.0, L.AM, pool, tmp, st);
         Level &C = H.lev[l + 1];
         C = Level();
         C.n = nc;
@@ -905,31 +946,6 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
     }
 
     // SELL copies, kernel shapes and work vectors
-    // One lane per row (SELL-64) for rows the unrolled SELL path covers (up to
-    // 16 entries: the fine levels of P1 meshes in 2D and 3D) when there are
-    // enough rows to fill the chip; otherwise a power-of-two group of lanes
-    // per row, enough to reach about 128k threads and to cover an average row
-    // in two passes of four entries per lane, but no wider than the rows.
-    auto lanes_per_row = [](const Csr &A) {
-        const double avg = A.n > 0 ? double(A.nnz) / A.n : 0.0;
-        const long target = 131072;
-        if (avg < 16.0 && A.n >= target)
-            return 0;
-        int want = 4;
-        while (want < 32 && ((long)want * A.n < target || want * 8 < avg))
-            want *= 2;
-        int cap = 4;
-        while (cap < 32 && cap < avg)
-            cap *= 2;
-        return std::min(want, cap);
-    };
-    // entries per CSR lane and pass: about the average row length over the
-    // lanes, so short rows do not load padding and long rows keep four loads
-    // in flight per lane
-    auto unroll = [](const Csr &A, int gs) {
-        const double per_lane = (gs > 0 && A.n > 0) ? double(A.nnz) / A.n / gs : 1.0;
-        return per_lane > 2.0 ? 4 : (per_lane > 1.0 ? 2 : 1);
-    };
     for (int l = 0; l < H.nlev; ++l) {
         Level &L = H.lev[l];
         const bool o16 = S.prm.wide_index == 0;
@@ -946,6 +962,8 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
             // RR is always a CSR-vector product (at least 4 lanes per row)
             L.gsRR = std::max(4, lanes_per_row(L.RR));
             L.uRR = unroll(L.RR, L.gsRR);
+            L.gsAM = std::max(4, lanes_per_row(L.AM));
+            L.uAM = unroll(L.AM, L.gsAM);
         }
         const size_t len = (size_t)S.nb * L.n;   // all runs of the batch
         H.x[l] = pool.get<double2>(len);

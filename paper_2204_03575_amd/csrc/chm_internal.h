@@ -121,6 +121,12 @@ struct Level {
     // level (empty on the coarsest level and where its rows would be long)
     Csr RR;
     int gsRR = 0, uRR = 1;
+    // the prolongation and the first post-smoothing step in one launch: row
+    // i of AM is row i of A (columns j < n, applied to x) followed by row i of
+    // A P (columns n + k, applied to the coarse correction e), so AM [x; e] =
+    // A (x + P e); CSR levels only, empty where its rows would be long
+    Csr AM;
+    int gsAM = 0, uAM = 1;
     double *dinv = nullptr;
     double rho = 0.0;
     int *agg = nullptr;
@@ -132,11 +138,13 @@ struct Level {
     // FP32 copies of the values for the mixed-precision preconditioner
     float *fA_s = nullptr, *fA_c = nullptr, *fP_s = nullptr, *fP_c = nullptr;
     float *fR_s = nullptr, *fR_c = nullptr, *fdinv = nullptr, *fRR_c = nullptr;
+    float *fAM_c = nullptr;
 
     template <class T> MatView<T> viewA() const;
     template <class T> MatView<T> viewP() const;
     template <class T> MatView<T> viewR() const;
     template <class T> MatView<T> viewRR() const;
+    template <class T> MatView<T> viewAM() const;
     template <class T> const T *dinv_t() const;
 };
 
@@ -166,6 +174,8 @@ template <> inline MatView<float> Level::viewP<float>() const { return make_view
 template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, uR, fR_s, fR_c); }
 template <> inline MatView<double> Level::viewRR<double>() const { return make_view<double>(RR, Sell(), gsRR, uRR, nullptr, RR.v); }
 template <> inline MatView<float> Level::viewRR<float>() const { return make_view<float>(RR, Sell(), gsRR, uRR, nullptr, fRR_c); }
+template <> inline MatView<double> Level::viewAM<double>() const { return make_view<double>(AM, Sell(), gsAM, uAM, nullptr, AM.v); }
+template <> inline MatView<float> Level::viewAM<float>() const { return make_view<float>(AM, Sell(), gsAM, uAM, nullptr, fAM_c); }
 template <> inline const double *Level::dinv_t<double>() const { return dinv; }
 template <> inline const float *Level::dinv_t<float>() const { return fdinv; }
 

@@ -266,6 +266,45 @@ __global__ void __launch_bounds__(kBlock) k_cheb_v(int n, const int *__restrict_
     xprev[row] = cheb_apply<T>(s, o, c1, c2);
 }
 
+// The prolongation and the first post-smoothing step in one launch (CSR
+// levels): x0 = x + P e and x1 = x0 + c2 D^-1 (b - A x0), with A x0 from
+// AM [x; e] = A x + (A P) e (no gather of x0, which the launch writes).  x0
+// goes to x0out (the next step's previous iterate) and x1 to x1out; neither
+// may be x.  Per run, b, x and the outputs advance by n, e by nc.
+template <int GS, int U, class T>
+__global__ void __launch_bounds__(kBlock) k_prolong_cheb_v(int n, int nc, const int *__restrict__ arp,
+                                                           const int *__restrict__ aci,
+                                                           const T *__restrict__ av,
+                                                           const int *__restrict__ prp,
+                                                           const int *__restrict__ pci,
+                                                           const T *__restrict__ pv,
+                                                           const T *__restrict__ dinv,
+                                                           const pair_t<T> *__restrict__ b,
+                                                           const pair_t<T> *__restrict__ x,
+                                                           const pair_t<T> *__restrict__ e,
+                                                           pair_t<T> *x0out, pair_t<T> *x1out, T c2)
+{
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    const int row = t / GS, lane = t % GS;
+    if (row >= n)
+        return;
+    b = run_at(b, n);
+    x = run_at(x, n);
+    e = run_at(e, nc);
+    const pair_t<T> s = row_dot_g<GS, U, T>(arp, aci, av, GatherBX<T>{x, e, n}, row, lane);
+    const pair_t<T> pe = row_dot<GS, 1, T>(prp, pci, pv, e, row, lane);
+    if (lane != 0)
+        return;
+    const pair_t<T> xi = x[row];
+    ChebRow<T> o;
+    o.bb = b[row];
+    o.xi = mk<T>(xi.x + pe.x, xi.y + pe.y);
+    o.di = dinv[row];
+    o.xp = mk<T>(0, 0);
+    run_at(x0out, n)[row] = o.xi;
+    run_at(x1out, n)[row] = cheb_apply<T>(s, o, T(0), c2);
+}
+
 // first smoothing step from x = 0: x = c2 D^-1 b
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cheb0(int n, const T *__restrict__ dinv,
@@ -723,6 +762,49 @@ pair_t<T> *presmooth(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<
     return cur;
 }
 
+template <int GS, class T>
+void prolong_cheb_u(hipStream_t st, int R, const MatView<T> &AM, const MatView<T> &P,
+                    const T *dinv, const pair_t<T> *b, const pair_t<T> *x, const pair_t<T> *e,
+                    pair_t<T> *x0, pair_t<T> *x1, T c2)
+{
+    const dim3 g = grid(nblk((long)GS * AM.n), R);
+    const int nc = AM.m - AM.n;
+    if (AM.u >= 4)
+        k_prolong_cheb_v<GS, 4, T><<<g, kBlock, 0, st>>>(AM.n, nc, AM.rp, AM.ci, AM.cval, P.rp,
+                                                          P.ci, P.cval, dinv, b, x, e, x0, x1, c2);
+    else if (AM.u == 2)
+        k_prolong_cheb_v<GS, 2, T><<<g, kBlock, 0, st>>>(AM.n, nc, AM.rp, AM.ci, AM.cval, P.rp,
+                                                          P.ci, P.cval, dinv, b, x, e, x0, x1, c2);
+    else
+        k_prolong_cheb_v<GS, 1, T><<<g, kBlock, 0, st>>>(AM.n, nc, AM.rp, AM.ci, AM.cval, P.rp,
+                                                          P.ci, P.cval, dinv, b, x, e, x0, x1, c2);
+}
+
+template <class T>
+void prolong_cheb(Solver &S, const Level &L, const pair_t<T> *b, const pair_t<T> *x,
+                  const pair_t<T> *e, pair_t<T> *x0, pair_t<T> *x1, double c2d)
+{
+    const MatView<T> AM = L.viewAM<T>(), P = L.viewP<T>();
+    const T *dinv = L.dinv_t<T>();
+    const T c2 = T(c2d);
+    const int R = S.nrun;
+    hipStream_t st = S.stream;
+    switch (AM.gs) {
+    case 4:
+        prolong_cheb_u<4, T>(st, R, AM, P, dinv, b, x, e, x0, x1, c2);
+        break;
+    case 8:
+        prolong_cheb_u<8, T>(st, R, AM, P, dinv, b, x, e, x0, x1, c2);
+        break;
+    case 16:
+        prolong_cheb_u<16, T>(st, R, AM, P, dinv, b, x, e, x0, x1, c2);
+        break;
+    default:
+        prolong_cheb_u<32, T>(st, R, AM, P, dinv, b, x, e, x0, x1, c2);
+        break;
+    }
+}
+
 template <class T>
 void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> *x)
 {
@@ -737,12 +819,17 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     const int deg = L.degree;
     auto c1 = [&](int k) { return (H.jacobi || k == 1) ? 0.0 : L.cheb_c1[k]; };
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
+    const bool timed = timed_level(S, H, l);
+    // the prolongation fused with the first post-smoothing step (CSR levels
+    // with AM): pre-smoothing then ends in xt, and the post-smoothing steps
+    // alternate between x and r so that the last one lands in x
+    const bool fused_post = L.AM.nnz > 0 && !timed;
     // Pre-smoothing from zero.  Every step after the first writes the buffer
     // not holding the current iterate; 2 deg - 1 such steps follow the first,
     // so starting in xt leaves the result in x.
-    pair_t<T> *cur = presmooth<T>(S, H, l, b, V.xt, x);
+    pair_t<T> *cur = fused_post && deg % 2 == 0 ? presmooth<T>(S, H, l, b, x, V.xt)
+                                                : presmooth<T>(S, H, l, b, V.xt, x);
     pair_t<T> *oth = cur == x ? V.xt : x;
-    const bool timed = timed_level(S, H, l);
     if (L.RR.nnz > 0) {   // b_c = R (b - A x) in one product
         resid_restrict<T>(st, R, L.viewRR<T>(), b, cur, Vc.b);
     } else {
@@ -750,6 +837,16 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
         spmv_op<SP_SET, T>(st, R, rb_of(S), L.viewR<T>(), V.r, nullptr, Vc.b);
     }
     vcycle_level<T>(S, H, l + 1, Vc.b, Vc.x);
+    if (fused_post) {
+        // x_0 = cur + P e into a, x_1 into c; steps 2.. alternate, x_deg in x
+        pair_t<T> *a0 = deg % 2 == 0 ? x : V.r, *a1 = deg % 2 == 0 ? V.r : x;
+        prolong_cheb<T>(S, L, b, cur, Vc.x, a0, a1, c2(1));
+        for (int k = 2; k <= deg; ++k) {
+            launch_cheb<T>(S, H, l, b, a1, a0, c1(k), c2(k), !H.jacobi);
+            std::swap(a0, a1);
+        }
+        return;
+    }
     spmv_op<SP_ADD, T>(st, R, rb_of(S), L.viewP<T>(), Vc.x, nullptr, cur);
     if (timed)
         timer_mark(S, true);
@@ -927,6 +1024,8 @@ void narrow_hierarchy(Solver &S, Hierarchy &H)
         narrow_matrix(pool, st, L.R, L.sR, L.gsR, L.fR_s, L.fR_c);
         if (L.RR.nnz > 0)
             L.fRR_c = narrow_copy(pool, st, L.RR.v, (long)L.RR.nnz);
+        if (L.AM.nnz > 0)
+            L.fAM_c = narrow_copy(pool, st, L.AM.v, (long)L.AM.nnz);
         L.fdinv = narrow_copy(pool, st, L.dinv, L.n);
     }
 }
