@@ -426,13 +426,15 @@ __global__ void __launch_bounds__(kBlock) k_gs1_split(int len, long ks,
 // ------------------------------------------------------------------ delayed reorthogonalisation
 // With ortho = CHM_ORTHO_DCGS2, the second Gram-Schmidt pass of each basis
 // vector runs in the iteration after it.  In iteration j, V_0..V_{j-1} are
-// final, V_j holds u_j (the previous w after one projection, divided by its
-// norm; the preconditioner took u_j) and V_{j+1} holds w = A z_j.  One sweep
-// forms the dot products of V_0..V_j with u_j and with w.  The second makes
-// v_j final, v_j = (u_j - sum_k s_k V_k) / nu with s_k = V_k . u_j and
-// nu^2 = u_j . u_j - |s|^2, projects w on V_0..V_{j-1} and on the final v_j,
-// and sums |w|^2 of the result.  At j = 0, V_0 is the normalised residual,
-// already final: s is empty and nu = 1.
+// final, V_j holds u_j (the previous w after one projection, not
+// normalised; the preconditioner took u_j) and V_{j+1} holds w = A z_j.  One
+// sweep forms the dot products of V_0..V_j with u_j and with w.  The second
+// makes v_j final, v_j = (u_j - sum_k s_k V_k) / nu with s_k = V_k . u_j and
+// nu^2 = u_j . u_j - |s|^2 (the second pass and the normalisation at once),
+// projects w on V_0..V_{j-1} and on the final v_j, and sums |w|^2 of the
+// result.  At j = 0, V_0 is the normalised residual, already final: s is
+// empty and nu = 1.  FGMRES takes any vector as the preconditioner's input,
+// so the stored z_j = Prec(u_j) define the solution space as they are.
 
 // dot products of V_0..V_j with u = V_j (partial rows 0..j) and with w
 // (rows j+1..2j+1), C basis vectors per sweep; per run as k_gs
@@ -523,11 +525,17 @@ __device__ inline DgsCoef dgs_coef(const double2 *h, int j)
 }
 
 // v_j final (written over u_j, j > 0) and w -= sum_{k<j} t_k V_k + h_jj v_j,
-// with partials of |w|^2 (per run: hin advances by hs, part by ps)
+// with partials of |w|^2 (per run: hin advances by hs, part by ps).  The
+// projected w stays unnormalised: it is u_{j+1}, which the next iteration's
+// sweep normalises together with its second pass.  A species no longer
+// iterating gets w = 0.  With w32, the FP32 copy the FP32 preconditioner
+// takes next: w times 1 / |u_j| (the previous |w|, 1 at j = 0), so its
+// scale stays near one however far the basis norms drift.
 __global__ void __launch_bounds__(kBlock) k_dgs_update(int len, long ks, double2 *V, int j,
                                                        double2 *w,
                                                        const double2 *__restrict__ hin, long hs,
-                                                       double2 *part, long ps)
+                                                       double2 *part, long ps,
+                                                       const Ctl *__restrict__ c, float2 *w32)
 {
     __shared__ double2 sh[kBlock / 64];
     __shared__ double2 sc[kMaxRestart], tc[kMaxRestart];
@@ -546,6 +554,11 @@ __global__ void __launch_bounds__(kBlock) k_dgs_update(int len, long ks, double2
         cf = dgs_coef(hin, j);
     __syncthreads();
     const DgsCoef f = cf;
+    c += blockIdx.y;
+    const double on0 = c->active[0] ? 1.0 : 0.0, on1 = c->active[1] ? 1.0 : 0.0;
+    const double sc0 = j == 0 ? 1.0 : (c->hn[0] > 0.0 ? 1.0 / c->hn[0] : 0.0);
+    const double sc1 = j == 0 ? 1.0 : (c->hn[1] > 0.0 ? 1.0 / c->hn[1] : 0.0);
+    w32 = run_at(w32, len);
     double2 *u = V + (size_t)j * ks;
     double2 nrm = d2(0.0, 0.0);
     for (int i = start; i < len; i += stride) {
@@ -559,11 +572,13 @@ __global__ void __launch_bounds__(kBlock) k_dgs_update(int len, long ks, double2
         }
         uv.x *= f.inv.x;
         uv.y *= f.inv.y;
-        wv.x = fmad(-f.hjj.x, uv.x, wv.x);
-        wv.y = fmad(-f.hjj.y, uv.y, wv.y);
+        wv.x = on0 * fmad(-f.hjj.x, uv.x, wv.x);
+        wv.y = on1 * fmad(-f.hjj.y, uv.y, wv.y);
         if (j > 0)
             u[i] = uv;
         w[i] = wv;
+        if (w32)
+            w32[i] = make_float2((float)(wv.x * sc0), (float)(wv.y * sc1));
         nrm.x = fmad(wv.x, wv.x, nrm.x);
         nrm.y = fmad(wv.y, wv.y, nrm.y);
     }
@@ -780,8 +795,9 @@ __global__ void __launch_bounds__(kBlock) k_givens(Ctl *c, int j, int m,
 }
 
 // The Givens step of the delayed pass (ortho = CHM_ORTHO_DCGS2).  Making
-// v_j final changes the column of the previous iteration: the |w_{j-1}| it
-// had along u_j becomes |w_{j-1}| s_k along V_k and |w_{j-1}| nu along v_j.
+// v_j final changes the column of the previous iteration: its entry |u_j|
+// (the norm of w_{j-1} after one projection) becomes s_k along V_k and nu
+// along v_j.
 // That column is rotated again by the rotations before it and gets a new
 // rotation; then column j (t_k, h_jj, |w|) is rotated, g is formed again from
 // the cycle's |r| through every rotation, and the convergence test runs on
@@ -829,10 +845,11 @@ __global__ void __launch_bounds__(kBlock) k_givens_d(Ctl *c, int j, int m,
     const double hn = sqrt(s == 0 ? nn[0].x : nn[0].y);
     double rr;
     if (j > 0) {
-        const double hp = c->hn[s];   // |w_{j-1}| after its one projection
+        // u_j is w_{j-1} after its one projection, unnormalised: its parts
+        // s_k along V_k and nu along v_j are column j-1's corrections
         for (int k = 0; k < j; ++k)
-            hr[k] = fmad(hp, pick(hl[k]), hr[k]);
-        hr[j] = hp * pick(f.nu);
+            hr[k] += pick(hl[k]);
+        hr[j] = pick(f.nu);
         for (int k = 0; k <= j; ++k)
             cl[k] = hr[k];
         rotate_col(cl, j - 1, cs, sn);
@@ -1383,11 +1400,10 @@ void iteration_body(Solver &S, int j)
         k_finish<<<grid(2 * (j + 1), R), kBlock, 0, st>>>(S.gsp1, 2 * kGsStride, Gg, S.hfin,
                                                           kHStride);
         k_dgs_update<<<grid(Gg, R), kBlock, 0, st>>>(len, ks, S.V, j, w, S.hfin, kHStride,
-                                                     S.gsp3, kGsBlocks);
+                                                     S.gsp3, kGsBlocks, S.ctl,
+                                                     S.mixed ? S.w32.vin : nullptr);
         k_givens_d<<<grid(1, R), kBlock, 0, st>>>(S.ctl, j, m, S.hfin, kHStride, S.gsp3,
                                                   kGsBlocks, Gg);
-        k_scale_next<<<grid(nblk(len), R), kBlock, 0, st>>>(len, w, S.ctl,
-                                                            S.mixed ? S.w32.vin : nullptr);
         CHM_HIP(hipGetLastError());
         copy_heads(S, st);
         return;
