@@ -826,21 +826,34 @@ __global__ void __launch_bounds__(kBlock) k_givens_d(Ctl *c, int j, int m,
                                                      const double2 *__restrict__ hin, long hs,
                                                      const double2 *__restrict__ p3, long ps, int G)
 {
+    // the dots, the previous rotations and the last raw column are staged in
+    // LDS by the whole block, so the sequential loops below touch no global
+    // memory; the results are written back at the end
     __shared__ double2 nn[1];
     __shared__ double2 hl[2 * (kMaxRestart + 1)];
-    __shared__ double col[2][kMaxRestart + 1];
+    __shared__ double col[2][kMaxRestart + 1], hrl[2][kMaxRestart + 1];
+    __shared__ double csl[2][kMaxRestart], snl[2][kMaxRestart], gl[2][kMaxRestart + 1];
     c += blockIdx.y;
     hin = run_at(hin, hs);
     p3 = run_at(p3, ps);
     for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock)
         hl[t] = hin[t];
+    for (int t = threadIdx.x; t < 2 * (j + 1); t += kBlock) {
+        const int s = t / (j + 1), i = t % (j + 1);
+        hrl[s][i] = c->hlast[s][i];
+    }
+    for (int t = threadIdx.x; t < 2 * j; t += kBlock) {
+        const int s = t / j, i = t % j;
+        csl[s][i] = c->cs[s][i];
+        snl[s][i] = c->sn[s][i];
+    }
     reduce_parts(p3, 1, G, nn);   // ends with a block barrier
     const int s = threadIdx.x;
     if (s >= 2 || !c->active[s])
         return;
     const DgsCoef f = dgs_coef(hl, j);
     auto pick = [s](double2 v) { return s == 0 ? v.x : v.y; };
-    double *H = c->H[s], *hr = c->hlast[s], *cs = c->cs[s], *sn = c->sn[s], *g = c->g[s];
+    double *H = c->H[s], *hr = hrl[s], *cs = csl[s], *sn = snl[s], *g = gl[s];
     double *cl = col[s];
     const double hn = sqrt(s == 0 ? nn[0].x : nn[0].y);
     double rr;
@@ -876,6 +889,16 @@ __global__ void __launch_bounds__(kBlock) k_givens_d(Ctl *c, int j, int m,
         g[i] = cs[i] * gi;
         g[i + 1] = -sn[i] * gi;
     }
+    for (int i = 0; i <= j + 1; ++i) {
+        c->hlast[s][i] = hr[i];
+        c->g[s][i] = g[i];
+    }
+    if (j > 0) {
+        c->cs[s][j - 1] = cs[j - 1];
+        c->sn[s][j - 1] = sn[j - 1];
+    }
+    c->cs[s][j] = cs[j];
+    c->sn[s][j] = sn[j];
     c->hn[s] = hn;
     c->k[s] = j + 1;
     const double est = fabs(g[j + 1]);
