@@ -202,6 +202,10 @@ typedef struct {
      * CHM_ORTHO_CGS2: both passes in the vector's own iteration, three
      * sweeps.  Both build the same Krylov space and differ by rounding. */
     int32_t ortho;
+    /* 1: never use value tables (chm_value_table); the kernels read every
+     * value.  0, the default: tables where they fit.  The results are
+     * bitwise the same either way. */
+    int32_t values_direct;
 } chm_params_t;
 
 /* Per-step statistics. */
@@ -328,6 +332,15 @@ int chm_level_info(const chm_solver_t *s, int32_t hierarchy, int32_t level, int6
  * wide_index parameter), else 4.  Either pointer may be NULL. */
 int chm_level_layout(const chm_solver_t *s, int32_t hierarchy, int32_t level,
                      int32_t *lanes_per_row, int32_t *index_bytes);
+/* Value tables: where a SELL-64 matrix with 16-bit column offsets holds at
+ * most 2048 distinct values (uniform meshes: 5 to 7 at 512 x 512, a few
+ * hundred on the 3D box, where summation order splits equal sums), the
+ * kernels read a 2-byte index per entry into the table of those values
+ * instead of the value: the same value, so bitwise the same results, with
+ * 2 bytes per entry instead of 8 (4 in FP32).  *values: the table size for
+ * hierarchy 0 or 1 at `level` (its A), or hierarchy -1 with level 0 for M and
+ * level 1 for K; 0 = no table (values read directly). */
+int chm_value_table(const chm_solver_t *s, int32_t hierarchy, int32_t level, int32_t *values);
 /* Host buffers; agg/P arrays are left untouched on the coarsest level. */
 int chm_level_get(chm_solver_t *s, int32_t hierarchy, int32_t level, int32_t *a_rowptr,
                   int32_t *a_col, double *a_val, int32_t *agg, int32_t *p_rowptr,

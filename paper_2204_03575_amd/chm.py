@@ -32,7 +32,7 @@ ENTRY_POINTS = [
     "chm_net_get_params", "chm_net_features", "chm_net_forward", "chm_net_gradients",
     "chm_net_adam", "chm_net_guess", "chm_net_train_step", "chm_set_guess", "chm_get_state",
     "chm_create_batch", "chm_batch_size", "chm_set_fields_run", "chm_get_fields_run",
-    "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history",
+    "chm_boundary", "chm_level_layout", "chm_get_history", "chm_set_history", "chm_value_table",
     "chm_net_guess_noalloc", "chm_step_many", "chm_schur_info",
 ]
 
@@ -68,7 +68,7 @@ class chm_params_t(C.Structure):
         ("bc_h", C.c_double * 2), ("bc_pattern", C.c_int32), ("krylov", C.c_int32),
         ("amg_tol", C.c_double), ("mass_solver", C.c_int32), ("wide_index", C.c_int32),
         ("runs_per_lane", C.c_int32), ("cheb_degree_coarse", C.c_int32),
-        ("range_check", C.c_int32), ("ortho", C.c_int32),
+        ("range_check", C.c_int32), ("ortho", C.c_int32), ("values_direct", C.c_int32),
     ]
 
 
@@ -107,6 +107,7 @@ def library():
             "chm_num_levels": ([vp, i32], C.c_int),
             "chm_level_info": ([vp, i32, i32, P(i64), P(i64), P(i64), P(d)], C.c_int),
             "chm_level_layout": ([vp, i32, i32, P(i32), P(i32)], C.c_int),
+            "chm_value_table": ([vp, i32, i32, P(i32)], C.c_int),
             "chm_level_get": ([vp, i32, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "chm_vcycle": ([vp, i32, vp, vp], C.c_int),
             "chm_schur_solve": ([vp, vp, vp], C.c_int),
@@ -183,6 +184,7 @@ def params_from_dict(p: dict) -> chm_params_t:
     s.cheb_degree_coarse = int(p.get("cheb_degree_coarse", 0))
     s.range_check = int(p.get("range_check", 0))
     s.ortho = {"dcgs2": 0, "cgs2": 1}[p.get("ortho", "dcgs2")]
+    s.values_direct = int(p.get("values_direct", 0))
     return s
 
 
@@ -370,6 +372,14 @@ class Solver:
         rc = self.lib.chm_level_layout(self.h, hier, lev, C.byref(lanes), C.byref(ib))
         _check(self.h, rc, "chm_level_layout")
         return lanes.value, ib.value
+
+    def value_table(self, hier: int, lev: int = 0) -> int:
+        """Distinct values in the value table of a level's A (hier 0 or 1), or
+        of M (hier -1, lev 0) / K (hier -1, lev 1); 0 = no table."""
+        m = C.c_int32()
+        rc = self.lib.chm_value_table(self.h, hier, lev, C.byref(m))
+        _check(self.h, rc, "chm_value_table")
+        return m.value
 
     def level(self, hier: int, lev: int) -> dict:
         n, na, npp = C.c_int64(), C.c_int64(), C.c_int64()

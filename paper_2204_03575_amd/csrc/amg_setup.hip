@@ -951,6 +951,8 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         const bool o16 = S.prm.wide_index == 0;
         csr_to_sell(L.A, L.sA, pool, st, o16);
         L.gsA = lanes_per_row(L.A);
+        if (L.gsA == 0 && L.sA.ocol && !S.prm.values_direct)   // values through a table
+            L.vtA = value_table(L.sA.val, L.sA.stored, pool, st);
         L.uA = unroll(L.A, L.gsA);
         if (l + 1 < H.nlev) {
             csr_to_sell(L.P, L.sP, pool, st, o16);

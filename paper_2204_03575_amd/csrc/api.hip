@@ -95,6 +95,8 @@ const char *check_params(const chm_params_t &p)
         return "range_check must be 0 or 1";
     if (p.ortho != CHM_ORTHO_CGS2 && p.ortho != CHM_ORTHO_DCGS2)
         return "ortho must be CHM_ORTHO_CGS2 or CHM_ORTHO_DCGS2";
+    if (p.values_direct != 0 && p.values_direct != 1)
+        return "values_direct must be 0 or 1";
     if (p.krylov == CHM_KRYLOV_MINRES && p.schur_pcg != 0)
         return "MINRES needs a symmetric positive definite preconditioner: schur_pcg = 0";
     return nullptr;
@@ -549,6 +551,23 @@ int chm_level_layout(const chm_solver_t *h, int32_t hierarchy, int32_t level,
         *lanes_per_row = lanes;
     if (index_bytes)
         *index_bytes = (lanes == 0 && ocol) ? 2 : 4;
+    return CHM_OK;
+}
+
+int chm_value_table(const chm_solver_t *h, int32_t hierarchy, int32_t level, int32_t *values)
+{
+    if (!h || !values)
+        return CHM_EINVAL;
+    if (hierarchy == -1) {
+        if (level != 0 && level != 1)
+            return CHM_EINVAL;
+        *values = level == 0 ? h->s.vtM.m : h->s.vtK.m;
+        return CHM_OK;
+    }
+    const chm::Hierarchy *H = hier_of(h, hierarchy);
+    if (!H || level < 0 || level >= H->nlev)
+        return CHM_EINVAL;
+    *values = H->lev[level].vtA.m;
     return CHM_OK;
 }
 

@@ -28,6 +28,7 @@
 namespace chm {
 
 constexpr int kSlice = 64;      // SELL slice height = wavefront size
+constexpr int kSellUnroll = 8;  // SELL rows up to this wide take the fully unrolled path
 constexpr int kBlock = 256;     // threads per block for row kernels
 constexpr int kMaxLevels = 24;
 constexpr int kMaxRestart = 64;
@@ -84,6 +85,15 @@ struct Csr {       // device CSR
     double *v = nullptr;
 };
 
+// A value table of a matrix (see value_table): tab[ix[e]] is entry e's value.
+constexpr int kVtMax = 2048;   // two FP64 tables fit 32 KB of LDS
+struct ValueTable {
+    uint16_t *ix = nullptr;
+    double *tab = nullptr;
+    float *ftab = nullptr;   // the table in FP32, for the FP32 preconditioner
+    int m = 0;
+};
+
 struct Sell {      // device SELL-64
     int n = 0, nslices = 0;
     int64_t stored = 0;   // padded entry count
@@ -106,6 +116,10 @@ template <class T> struct MatView {
     const int *sptr = nullptr, *col = nullptr, *rp = nullptr, *ci = nullptr;
     const int16_t *ocol = nullptr;              // SELL column offsets (see Sell), or null
     const T *sval = nullptr, *cval = nullptr;
+    // the SELL values through a value table (vtab[vix[e]]), or null
+    const uint16_t *vix = nullptr;
+    const T *vtab = nullptr;
+    int vm = 0;   // table entries
 };
 
 struct Level {
@@ -113,6 +127,7 @@ struct Level {
     int degree = 2;      // smoother degree (Chebyshev) or sweeps (Jacobi) on this level
     Csr A, P, R;
     Sell sA, sP, sR;
+    ValueTable vtA;   // sA's values as a table, where it has few distinct values
     int gsA = 0, gsP = 0, gsR = 0;   // lanes per row (see MatView)
     int uA = 1, uP = 1, uR = 1;      // CSR entries per lane and pass (see MatView)
     // the residual and its restriction in one product: row i of RR is row i
@@ -148,6 +163,11 @@ struct Level {
     template <class T> const T *dinv_t() const;
 };
 
+// The FP32 kernels read a value table only on patterns with slices wider
+// than kSellUnroll entries (3D): a 4-byte value against a 2-byte index saves
+// too little to pay for the lookup on the 8-wide 2D rows (measured).
+inline bool fp32_table(const Sell &S) { return S.wmax > kSellUnroll; }
+
 template <class T>
 inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, int u, const T *sv, const T *cv)
 {
@@ -166,10 +186,26 @@ inline MatView<T> make_view(const Csr &C, const Sell &S, int gs, int u, const T 
     v.cval = cv;
     return v;
 }
-template <> inline MatView<double> Level::viewA<double>() const { return make_view<double>(A, sA, gsA, uA, sA.val, A.v); }
+template <> inline MatView<double> Level::viewA<double>() const
+{
+    MatView<double> v = make_view<double>(A, sA, gsA, uA, sA.val, A.v);
+    v.vix = vtA.ix;
+    v.vtab = vtA.tab;
+    v.vm = vtA.m;
+    return v;
+}
 template <> inline MatView<double> Level::viewP<double>() const { return make_view<double>(P, sP, gsP, uP, sP.val, P.v); }
 template <> inline MatView<double> Level::viewR<double>() const { return make_view<double>(R, sR, gsR, uR, sR.val, R.v); }
-template <> inline MatView<float> Level::viewA<float>() const { return make_view<float>(A, sA, gsA, uA, fA_s, fA_c); }
+template <> inline MatView<float> Level::viewA<float>() const
+{
+    MatView<float> v = make_view<float>(A, sA, gsA, uA, fA_s, fA_c);
+    if (fp32_table(sA)) {
+        v.vix = vtA.ix;
+        v.vtab = vtA.ftab;
+        v.vm = vtA.m;
+    }
+    return v;
+}
 template <> inline MatView<float> Level::viewP<float>() const { return make_view<float>(P, sP, gsP, uP, fP_s, fP_c); }
 template <> inline MatView<float> Level::viewR<float>() const { return make_view<float>(R, sR, gsR, uR, fR_s, fR_c); }
 template <> inline MatView<double> Level::viewRR<double>() const { return make_view<double>(RR, Sell(), gsRR, uRR, nullptr, RR.v); }
@@ -298,6 +334,7 @@ struct Solver {
     Csr M, K, As;       // As values share M's pattern
     Sell sM;            // SELL of the pattern with M values
     double *sK = nullptr, *sAs = nullptr;  // SELL values of K and As on sM's layout
+    ValueTable vtM, vtK;   // sM's and sK's values as tables, where they have few distinct values
     double tau_s[2], te_s[2];
 
     Hierarchy hM, hA;
@@ -360,6 +397,10 @@ double reduce_max_host(const double *d, int n, Pool &pool, hipStream_t s);
 // square and every offset fits
 void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s, bool offsets16);
 void sell_values(const Csr &A, const Sell &S, const double *csr_vals, double *sell_vals, hipStream_t s);
+// The distinct values of v[0..n) (as bit patterns, at most kVtMax of them) in
+// ascending bit order, and each entry's 16-bit position among them; m = 0
+// (no table) when there are more.
+ValueTable value_table(const double *v, int64_t n, Pool &pool, hipStream_t s);
 
 // ---- mesh_setup.hip
 void build_quadrature(int dim, std::vector<double> &bary, std::vector<double> &w);

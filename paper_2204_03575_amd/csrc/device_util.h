@@ -195,8 +195,8 @@ enum SpmvMode { SP_SET = 0, SP_ADD = 1, SP_RESID = 2 };
 // twice that, take a fully unrolled path that issues every column and value
 // load of the row, then every gather of x, before the first product: two
 // dependent memory round trips instead of one per group of entries.  The
-// products are added in column order either way.
-constexpr int kSellUnroll = 8;
+// products are added in column order either way.  (kSellUnroll = 8, in the
+// internal header.)
 
 // Column of SELL entry idx, which belongs to row `row`: stored as a 32-bit
 // column (I = int), or as a 16-bit offset from the row (I = int16_t; square
@@ -208,6 +208,57 @@ __device__ inline int sell_col(const int16_t *__restrict__ col, int idx, int row
     return row + (int)col[idx];
 }
 
+// The values of a SELL matrix as the kernels read them: stored per entry
+// (VPlain), or as a 16-bit index per entry into the table of the matrix's
+// distinct values (VTab, uniform meshes: a few to a few hundred values), which
+// gives the same value.
+template <class T> struct VPlain {
+    const T *__restrict__ v;
+    __device__ T operator[](int i) const { return v[i]; }
+};
+template <class T> struct VTab {
+    const uint16_t *__restrict__ ix;
+    const T *__restrict__ tab;
+    int m;   // table entries
+    __device__ T operator[](int i) const { return tab[ix[i]]; }
+};
+
+// A table staged in LDS by the block (the kernels read it through this):
+// a short lookup instead of a dependent global load per entry.
+template <class T> struct VLds {
+    const uint16_t *__restrict__ ix;
+    const T *tab;   // LDS
+    __device__ T operator[](int i) const { return tab[ix[i]]; }
+};
+
+// The accessor a kernel reads with: plain values as they are; a table copied
+// into the block's dynamic LDS at `lds` (every thread of the block must call
+// this, before any early return, since it ends with a barrier).
+template <class VA> struct Staged {
+    using type = VA;
+    static constexpr size_t bytes(const VA &) { return 0; }
+    __device__ static VA stage(const VA &v, void *) { return v; }
+};
+template <class T> struct Staged<VTab<T>> {
+    using type = VLds<T>;
+    static size_t bytes(const VTab<T> &v) { return (size_t)v.m * sizeof(T); }
+    __device__ static VLds<T> stage(const VTab<T> &v, void *lds)
+    {
+        T *t = static_cast<T *>(lds);
+        for (int i = threadIdx.x; i < v.m; i += blockDim.x)
+            t[i] = v.tab[i];
+        __syncthreads();
+        return VLds<T>{v.ix, t};
+    }
+};
+template <class VA> inline size_t lds_bytes(const VA &v) { return Staged<VA>::bytes(v); }
+// the same on the device (the offset of a second table in a kernel's LDS)
+template <class T> __device__ inline size_t lds_bytes_dev(const VPlain<T> &) { return 0; }
+template <class T> __device__ inline size_t lds_bytes_dev(const VTab<T> &v)
+{
+    return (size_t)v.m * sizeof(T);
+}
+
 // The entries of one SELL row for slices at most W wide (width >= 1):
 // entries past the slice width repeat the last column with a zero
 // coefficient, so every load is unconditional (no branch between the loads
@@ -217,9 +268,9 @@ template <int W, class T> struct SellEnt {
     T a[W];
 };
 
-template <int W, class I, class T>
+template <int W, class I, class T, class VA>
 __device__ inline void sell_load(int base, int width, int lane, int row, const I *__restrict__ col,
-                                 const T *__restrict__ val, SellEnt<W, T> &e)
+                                 const VA &val, SellEnt<W, T> &e)
 {
 #pragma unroll
     for (int k = 0; k < W; ++k) {
@@ -249,9 +300,9 @@ __device__ inline pair_t<T> sell_dot(const SellEnt<W, T> &e, const pair_t<T> *xv
 
 // the unrolled row product for slices at most W wide (width >= 1): every
 // column and value load, then every gather, then the products
-template <int W, class I, class T>
+template <int W, class I, class T, class VA>
 __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
-                                       const I *__restrict__ col, const T *__restrict__ val,
+                                       const I *__restrict__ col, const VA &val,
                                        const pair_t<T> *__restrict__ x, T &diag)
 {
     SellEnt<W, T> e;
@@ -265,9 +316,9 @@ __device__ inline pair_t<T> sell_row_w(int base, int width, int lane, int row,
 
 // the row product of a SELL-64 matrix; diag receives the row's diagonal
 // entry (0 if it has none; callers that do not use it lose the selects)
-template <class I, class T>
+template <class I, class T, class VA>
 __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__restrict__ col,
-                                     const T *__restrict__ val, const pair_t<T> *__restrict__ x,
+                                     const VA &val, const pair_t<T> *__restrict__ x,
                                      int row, T &diag)
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
@@ -276,9 +327,9 @@ __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__re
     if (width == 0)
         return mk<T>(0, 0);
     if (width <= kSellUnroll)
-        return sell_row_w<kSellUnroll, I, T>(base, width, lane, row, col, val, x, diag);
+        return sell_row_w<kSellUnroll, I, T, VA>(base, width, lane, row, col, val, x, diag);
     if (width <= 2 * kSellUnroll)
-        return sell_row_w<2 * kSellUnroll, I, T>(base, width, lane, row, col, val, x, diag);
+        return sell_row_w<2 * kSellUnroll, I, T, VA>(base, width, lane, row, col, val, x, diag);
     T ax = 0, ay = 0, d = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
@@ -310,9 +361,9 @@ inline dim3 grid_rb(int x, int runs, int rb) { return dim3(x, (runs + rb - 1) / 
 // (2D P1 patterns) load the row's entries once and issue every run's gathers
 // before the first product; wider slices go run by run (with one run per
 // lane, slices up to twice that width still take the unrolled path).
-template <class I, class T, int RB, class F>
+template <class I, class T, int RB, class VA, class F>
 __device__ inline void sell_row_runs(const int *__restrict__ sptr, const I *__restrict__ col,
-                                     const T *__restrict__ val, const pair_t<T> *__restrict__ x,
+                                     const VA &val, const pair_t<T> *__restrict__ x,
                                      long sx, int row, int R, F &&f)
 {
     const int r0 = run0<RB>();
@@ -351,7 +402,7 @@ __device__ inline void sell_row_runs(const int *__restrict__ sptr, const I *__re
         for (int q = 0; q < RB; ++q)
             if (RB == 1 || r0 + q < R) {
                 T diag;
-                const pair_t<T> p = sell_row<I, T>(sptr, col, val, x + (r0 + q) * sx, row, diag);
+                const pair_t<T> p = sell_row<I, T, VA>(sptr, col, val, x + (r0 + q) * sx, row, diag);
                 f(q, r0 + q, p, diag);
             }
     }
@@ -373,46 +424,55 @@ __device__ inline void spmv_store(pair_t<T> s, const pair_t<T> *__restrict__ b, 
 
 // per run: x advances by sx, b and y by sy; RB runs per lane (block row
 // blockIdx.y), R runs in all
-template <int MODE, class I, class T, int RB>
+template <int MODE, class I, class T, int RB, class VA>
 __global__ void __launch_bounds__(kBlock) k_spmv(int n, int R, const int *__restrict__ sptr,
-                                                 const I *__restrict__ col,
-                                                 const T *__restrict__ val,
+                                                 const I *__restrict__ col, const VA val0,
                                                  const pair_t<T> *__restrict__ x, long sx,
                                                  const pair_t<T> *__restrict__ b, pair_t<T> *y,
                                                  long sy)
 {
+    extern __shared__ __align__(8) unsigned char lds_tab[];
+    using VS = typename Staged<VA>::type;
+    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
-    sell_row_runs<I, T, RB>(sptr, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
+    sell_row_runs<I, T, RB, VS>(sptr, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
         spmv_store<MODE, T>(s, b ? b + r * sy : b, y + r * sy, row);
     });
 }
 
-template <int MODE, class I, class T>
+template <int MODE, class I, class T, class VA>
 void sell_spmv_i(hipStream_t st, int gx, int runs, int rb, int n, const int *sptr, const I *col,
-                 const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y, long sy)
+                 const VA &val, const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y,
+                 long sy)
 {
     const dim3 g = grid_rb(gx, runs, rb);
+    const size_t lb = lds_bytes(val);
     if (rb >= 4)
-        k_spmv<MODE, I, T, 4><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+        k_spmv<MODE, I, T, 4, VA><<<g, kBlock, lb, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
     else if (rb == 2)
-        k_spmv<MODE, I, T, 2><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+        k_spmv<MODE, I, T, 2, VA><<<g, kBlock, lb, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
     else
-        k_spmv<MODE, I, T, 1><<<g, kBlock, 0, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
+        k_spmv<MODE, I, T, 1, VA><<<g, kBlock, lb, st>>>(n, runs, sptr, col, val, x, sx, b, y, sy);
 }
 
 // k_spmv over a SELL matrix of n rows for `runs` runs, rb of them per lane,
 // on its 16-bit column offsets when it has them (ocol), else on its columns
 template <int MODE, class T>
 void sell_spmv(hipStream_t st, int runs, int rb, int n, const int *sptr, const int *col,
-               const int16_t *ocol, const T *val, const pair_t<T> *x, long sx, const pair_t<T> *b,
-               pair_t<T> *y, long sy)
+               const int16_t *ocol, const T *val, const uint16_t *vix, const T *vtab, int vm,
+               const pair_t<T> *x, long sx, const pair_t<T> *b, pair_t<T> *y, long sy)
 {
-    if (ocol)
-        sell_spmv_i<MODE, int16_t, T>(st, nblk(n), runs, rb, n, sptr, ocol, val, x, sx, b, y, sy);
+    if (ocol && vix)
+        sell_spmv_i<MODE, int16_t, T, VTab<T>>(st, nblk(n), runs, rb, n, sptr, ocol,
+                                               VTab<T>{vix, vtab, vm}, x, sx, b, y, sy);
+    else if (ocol)
+        sell_spmv_i<MODE, int16_t, T, VPlain<T>>(st, nblk(n), runs, rb, n, sptr, ocol,
+                                                 VPlain<T>{val}, x, sx, b, y, sy);
     else
-        sell_spmv_i<MODE, int, T>(st, nblk(n), runs, rb, n, sptr, col, val, x, sx, b, y, sy);
+        sell_spmv_i<MODE, int, T, VPlain<T>>(st, nblk(n), runs, rb, n, sptr, col, VPlain<T>{val},
+                                             x, sx, b, y, sy);
 }
 
 // The same with a group of GS lanes per row (CSR), for matrices with long rows
@@ -519,7 +579,8 @@ void spmv_op(hipStream_t st, int runs, int rb, const MatView<T> &A, const pair_t
     if (sy < 0)
         sy = A.n;
     if (A.gs == 0) {
-        sell_spmv<MODE, T>(st, runs, rb, n, A.sptr, A.col, A.ocol, A.sval, x, sx, b, y, sy);
+        sell_spmv<MODE, T>(st, runs, rb, n, A.sptr, A.col, A.ocol, A.sval, A.vix, A.vtab, A.vm,
+                           x, sx, b, y, sy);
         return;
     }
     switch (A.gs) {

@@ -659,6 +659,10 @@ void mesh_setup(Solver &S)
     S.sAs = pool.get<double>(S.sM.stored);
     sell_values(M, S.sM, S.K.v, S.sK, st);
     sell_values(M, S.sM, S.As.v, S.sAs, st);
+    if (S.sM.ocol && !S.prm.values_direct) {   // value tables go with the 16-bit column offsets
+        S.vtM = value_table(S.sM.val, S.sM.stored, pool, st);
+        S.vtK = value_table(S.sK, S.sM.stored, pool, st);
+    }
 
     // quadrature
     std::vector<double> qb, qw;

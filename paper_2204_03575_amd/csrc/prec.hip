@@ -55,15 +55,17 @@ template <class T> __device__ inline pair_t<T> cheb_apply(pair_t<T> s, const Che
                  fmad(c2, o.di * (o.bb.y - s.y), fmad(c1, o.xi.y - o.xp.y, o.xi.y)));
 }
 
-template <class I, class T, int RB>
+template <class I, class T, int RB, class VA>
 __global__ void __launch_bounds__(kBlock) k_cheb(int n, int R, const int *__restrict__ sptr,
-                                                 const I *__restrict__ col,
-                                                 const T *__restrict__ val,
+                                                 const I *__restrict__ col, const VA val0,
                                                  const T *__restrict__ dinv,
                                                  const pair_t<T> *__restrict__ b,
                                                  const pair_t<T> *__restrict__ xk, pair_t<T> *xprev,
                                                  T c1, T c2, int prev)
 {
+    extern __shared__ __align__(8) unsigned char lds_tab[];
+    using VS = typename Staged<VA>::type;
+    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, int R, const int *__rest
             const long off = (long)(r0 + q) * n;
             o[q] = cheb_row<T>(b + off, xk + off, own ? nullptr : dinv, xprev + off, row, prev);
         }
-    sell_row_runs<I, T, RB>(sptr, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
+    sell_row_runs<I, T, RB, VS>(sptr, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
         ChebRow<T> &w = o[q];
         if (own)
             w.di = T(1) / diag;
@@ -120,9 +122,9 @@ template <class T> __device__ inline ChebRow<T> first_row(const FirstIter<T> &x1
 // the row products A x_1 of RB runs (x_1 formed from run r's b), entries
 // loaded once on slices at most kSellUnroll wide; f(q, r, product) with
 // q = r - r0
-template <class I, class T, int RB, class F>
+template <class I, class T, int RB, class VA, class F>
 __device__ inline void sell_row_first_runs(const int *__restrict__ sptr, const I *__restrict__ col,
-                                           const T *__restrict__ val, const pair_t<T> *__restrict__ b,
+                                           const VA &val, const pair_t<T> *__restrict__ b,
                                            const T *__restrict__ dinv, T c2f, int n, int row, int R,
                                            F &&f)
 {
@@ -193,16 +195,18 @@ __device__ inline void sell_row_first_runs(const int *__restrict__ sptr, const I
 // (the register budget of at most 4 waves per SIMD lets the compiler issue
 // every load of a 16-wide row before the first product; with the default
 // budget it interleaved the FP64 gathers with waits)
-template <class I, class T, int RB>
+template <class I, class T, int RB, class VA>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_cheb_first(int n, int R, const int *__restrict__ sptr,
-                                                       const I *__restrict__ col,
-                                                       const T *__restrict__ val,
+                                                       const I *__restrict__ col, const VA val0,
                                                        const T *__restrict__ dinv,
                                                        const pair_t<T> *__restrict__ b,
                                                        pair_t<T> *x1out, pair_t<T> *x2, T c2first,
                                                        T c1, T c2)
 {
+    extern __shared__ __align__(8) unsigned char lds_tab[];
+    using VS = typename Staged<VA>::type;
+    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
@@ -212,7 +216,7 @@ k_cheb_first(int n, int R, const int *__restrict__ sptr,
     for (int q = 0; q < RB; ++q)
         if (RB == 1 || r0 + q < R)
             o[q] = first_row(FirstIter<T>{b + (long)(r0 + q) * n, dinv, c2first}, row);
-    sell_row_first_runs<I, T, RB>(sptr, col, val, b, dinv, c2first, n, row, R,
+    sell_row_first_runs<I, T, RB, VS>(sptr, col, val, b, dinv, c2first, n, row, R,
                                   [&](int q, int r, pair_t<T> s) {
                                       const ChebRow<T> &w = o[q];
                                       x1out[(long)r * n + row] = w.xi;
@@ -384,32 +388,40 @@ __global__ void __launch_bounds__(kBlock) k_dense(int n, int R, const double *__
 }
 
 // launches with rb runs per lane (1, 2 or 4) over R runs
-template <class I, class T>
-void cheb_rb(hipStream_t st, int rb, int n, int R, const int *sptr, const I *col, const T *val,
+template <class I, class T, class VA>
+void cheb_rb(hipStream_t st, int rb, int n, int R, const int *sptr, const I *col, const VA &val,
              const T *dinv, const pair_t<T> *b, const pair_t<T> *xk, pair_t<T> *xprev, T c1, T c2,
              int prev)
 {
     const dim3 g = grid_rb(nblk(n), R, rb);
+    const size_t lb = lds_bytes(val);
     if (rb >= 4)
-        k_cheb<I, T, 4><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+        k_cheb<I, T, 4, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2,
+                                                  prev);
     else if (rb == 2)
-        k_cheb<I, T, 2><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+        k_cheb<I, T, 2, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2,
+                                                  prev);
     else
-        k_cheb<I, T, 1><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2, prev);
+        k_cheb<I, T, 1, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, xk, xprev, c1, c2,
+                                                  prev);
 }
 
-template <class I, class T>
+template <class I, class T, class VA>
 void cheb_first_rb(hipStream_t st, int rb, int n, int R, const int *sptr, const I *col,
-                   const T *val, const T *dinv, const pair_t<T> *b, pair_t<T> *x1, pair_t<T> *x2,
+                   const VA &val, const T *dinv, const pair_t<T> *b, pair_t<T> *x1, pair_t<T> *x2,
                    T c2f, T c1, T c2)
 {
     const dim3 g = grid_rb(nblk(n), R, rb);
+    const size_t lb = lds_bytes(val);
     if (rb >= 4)
-        k_cheb_first<I, T, 4><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+        k_cheb_first<I, T, 4, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f,
+                                                        c1, c2);
     else if (rb == 2)
-        k_cheb_first<I, T, 2><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+        k_cheb_first<I, T, 2, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f,
+                                                        c1, c2);
     else
-        k_cheb_first<I, T, 1><<<g, kBlock, 0, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f, c1, c2);
+        k_cheb_first<I, T, 1, VA><<<g, kBlock, lb, st>>>(n, R, sptr, col, val, dinv, b, x1, x2, c2f,
+                                                        c1, c2);
 }
 
 template <class T>
@@ -599,6 +611,15 @@ template <> Work<float> &work<float>(Solver &S) { return S.w32; }
 template <class T> const T *mass_sell_values(const Solver &S);
 template <> const double *mass_sell_values<double>(const Solver &S) { return S.sM.val; }
 template <> const float *mass_sell_values<float>(const Solver &S) { return S.fsM; }
+template <class T> const T *mass_sell_table(const Solver &S);
+template <> const double *mass_sell_table<double>(const Solver &S) { return S.vtM.tab; }
+template <> const float *mass_sell_table<float>(const Solver &S) { return S.vtM.ftab; }
+template <class T> const uint16_t *mass_sell_index(const Solver &S);
+template <> const uint16_t *mass_sell_index<double>(const Solver &S) { return S.vtM.ix; }
+template <> const uint16_t *mass_sell_index<float>(const Solver &S)
+{
+    return fp32_table(S.sM) ? S.vtM.ix : nullptr;
+}
 
 // ------------------------------------------------------------------ V-cycle (host)
 // The event timer brackets each run of back-to-back smoothing launches on the
@@ -656,12 +677,15 @@ void launch_cheb_first(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_
     hipStream_t st = S.stream;
     switch (A.gs) {
     case 0:
-        if (A.ocol)
-            cheb_first_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, A.sval, dinv, b, x1, x2,
-                                      c2f, c1, c2);
+        if (A.ocol && A.vix)
+            cheb_first_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, VTab<T>{A.vix, A.vtab, A.vm},
+                                      dinv, b, x1, x2, c2f, c1, c2);
+        else if (A.ocol)
+            cheb_first_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, VPlain<T>{A.sval}, dinv, b,
+                                      x1, x2, c2f, c1, c2);
         else
-            cheb_first_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, A.sval, dinv, b, x1, x2, c2f,
-                                  c1, c2);
+            cheb_first_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, VPlain<T>{A.sval}, dinv, b, x1,
+                                  x2, c2f, c1, c2);
         break;
     case 4:
         cheb_first_v_u<4, T>(st, R, A, dinv, b, x1, x2, c2f, c1, c2);
@@ -691,12 +715,15 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     hipStream_t st = S.stream;
     switch (A.gs) {
     case 0:
-        if (A.ocol)
-            cheb_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, A.sval, dinv, b, xk, xprev, c1,
-                                c2, prev);
+        if (A.ocol && A.vix)
+            cheb_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, VTab<T>{A.vix, A.vtab, A.vm}, dinv, b,
+                                xk, xprev, c1, c2, prev);
+        else if (A.ocol)
+            cheb_rb<int16_t, T>(st, rb_of(S), n, R, A.sptr, A.ocol, VPlain<T>{A.sval}, dinv, b, xk,
+                                xprev, c1, c2, prev);
         else
-            cheb_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, A.sval, dinv, b, xk, xprev, c1, c2,
-                            prev);
+            cheb_rb<int, T>(st, rb_of(S), n, R, A.sptr, A.col, VPlain<T>{A.sval}, dinv, b, xk, xprev,
+                            c1, c2, prev);
         break;
     case 4:
         cheb_v_u<4, T>(st, R, A, dinv, b, xk, xprev, c1, c2, prev);
@@ -713,14 +740,16 @@ void launch_cheb(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, const pair_
     }
     if (timed_level(S, H, l)) {
         // algorithmic bytes: column index (2 B as a SELL offset, else 4) +
-        // value per nonzero (once per launch); per row D^-1 (except the FP64
-        // SELL kernel, which takes it from the diagonal entry) and per row
-        // and run x_k (gathered once), b, x_{k-1} (when read) and the
-        // written x_{k+1}
+        // value per nonzero (its 2-byte index into the value table where the
+        // matrix has one; the table itself stays in cache), once per launch;
+        // per row D^-1 (except the FP64 SELL kernel, which takes it from the
+        // diagonal entry) and per row and run x_k (gathered once), b, x_{k-1}
+        // (when read) and the written x_{k+1}
         const long long ib = (A.gs == 0 && A.ocol) ? 2 : 4;
+        const long long vb = (A.gs == 0 && A.ocol && A.vix) ? 2 : (long long)sizeof(T);
         const bool own = A.gs == 0 && std::is_same<T, double>::value;
         S.timer.count += 1;
-        S.timer.bytes += (ib + (long long)sizeof(T)) * L.A.nnz +
+        S.timer.bytes += (ib + vb) * L.A.nnz +
                          (own ? 0ll : (long long)sizeof(T) * L.n) +
                          (long long)R * (prev ? 8 : 6) * sizeof(T) * L.n;
     }
@@ -959,7 +988,8 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
         stationary<T>(S, S.hM, v, w);
         schur_solve_t<T>(S, v + n, W.tmp);
         sell_spmv<SP_SET, T>(st, 1, 1, n, S.sM.sptr, S.sM.col, S.sM.ocol,
-                             mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
+                             mass_sell_values<T>(S), mass_sell_index<T>(S), mass_sell_table<T>(S), S.vtM.m, W.tmp, n,
+                             nullptr, W.tmp2, n);
         schur_solve_t<T>(S, W.tmp2, w + n);
         return;
     }
@@ -969,7 +999,8 @@ void apply_prec_t(Solver &S, const pair_t<T> *v, pair_t<T> *w)
     k_gather_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, v + n, len, W.h1);
     schur_solve_t<T>(S, W.h1, W.tmp);
     sell_spmv<SP_SET, T>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol,
-                         mass_sell_values<T>(S), W.tmp, n, nullptr, W.tmp2, n);
+                         mass_sell_values<T>(S), mass_sell_index<T>(S), mass_sell_table<T>(S), S.vtM.m, W.tmp, n,
+                         nullptr, W.tmp2, n);
     schur_solve_t<T>(S, W.tmp2, W.h2);
     k_scatter_half<T><<<grid(nblk(n), R), kBlock, 0, st>>>(n, W.h2, w + n, len);
 }
@@ -1018,6 +1049,8 @@ void narrow_hierarchy(Solver &S, Hierarchy &H)
         // A on every level: the fine one also serves the inner CG and the
         // stationary cycles when it is the coarsest
         narrow_matrix(pool, st, L.A, L.sA, L.gsA, L.fA_s, L.fA_c);
+        if (L.vtA.m > 0)
+            L.vtA.ftab = narrow_copy(pool, st, L.vtA.tab, (long)L.vtA.m);
         if (l == H.nlev - 1)
             break;   // the coarsest level solves with its FP64 inverse
         narrow_matrix(pool, st, L.P, L.sP, L.gsP, L.fP_s, L.fP_c);
@@ -1161,6 +1194,8 @@ void prec_setup(Solver &S)
     F.vin = p.get<float2>(2 * nb * n);
     F.wout = p.get<float2>(2 * nb * n);
     S.fsM = narrow_copy(p, S.stream, S.sM.val, (long)S.sM.stored);
+    if (S.vtM.m > 0)
+        S.vtM.ftab = narrow_copy(p, S.stream, S.vtM.tab, (long)S.vtM.m);
     narrow_hierarchy(S, S.hM);
     narrow_hierarchy(S, S.hA);
     CHM_HIP(hipStreamSynchronize(S.stream));

@@ -33,10 +33,9 @@ struct SaddleEnt {
 };
 
 // entries k0, ..., k0 + kSellUnroll - 1 of the row (k0 < width)
-template <class I>
+template <class I, class VA>
 __device__ inline void saddle_load(int base, int width, int lane, int row, const I *__restrict__ col,
-                                   const double *__restrict__ vm, const double *__restrict__ vk,
-                                   SaddleEnt &e, int k0 = 0)
+                                   const VA &vm, const VA &vk, SaddleEnt &e, int k0 = 0)
 {
 #pragma unroll
     for (int k = 0; k < kSellUnroll; ++k) {
@@ -88,17 +87,17 @@ __device__ inline void saddle_dot(const SaddleEnt &e, const double2 *x0, const d
     saddle_combine(a.m0x, a.m0y, a.k1x, a.k1y, a.k0x, a.k0y, a.m1x, a.m1y, t, te, y0, y1);
 }
 
-template <class I, bool U8, class XT = double2>
+template <class I, bool U8, class XT, class VA>
 __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
-                                  const I *__restrict__ col, const double *__restrict__ vm,
-                                  const double *__restrict__ vk, const XT *__restrict__ x,
-                                  double2 t, double2 te, double2 &y0, double2 &y1)
+                                  const I *__restrict__ col, const VA &vm, const VA &vk,
+                                  const XT *__restrict__ x, double2 t, double2 te, double2 &y0,
+                                  double2 &y1)
 {
     const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
     const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
     if (U8 && width > 0) {
         SaddleEnt e;
-        saddle_load<I>(base, width, lane, row, col, vm, vk, e);
+        saddle_load<I, VA>(base, width, lane, row, col, vm, vk, e);
         double2 x0[kSellUnroll], x1[kSellUnroll];
 #pragma unroll
         for (int k = 0; k < kSellUnroll; ++k) {
@@ -111,7 +110,7 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
     SaddleAcc a;
     for (int k0 = 0; k0 < width; k0 += kSellUnroll) {
         SaddleEnt e;
-        saddle_load<I>(base, width, lane, row, col, vm, vk, e, k0);
+        saddle_load<I, VA>(base, width, lane, row, col, vm, vk, e, k0);
         double2 x0[kSellUnroll], x1[kSellUnroll];
 #pragma unroll
         for (int k = 0; k < kSellUnroll; ++k) {
@@ -125,15 +124,15 @@ __device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
 
 // per run, x and y advance by 2n; RB runs per lane (block row blockIdx.y),
 // R in all: on U8 patterns the row's entries are loaded once for the RB runs
-template <class I, bool U8, int RB, class XT>
+template <class I, bool U8, int RB, class XT, class VA>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
-k_saddle(int n, int R, const int *__restrict__ sptr,
-                                                   const I *__restrict__ col,
-                                                   const double *__restrict__ vm,
-                                                   const double *__restrict__ vk,
-                                                   const XT *__restrict__ x, double2 *y,
-                                                   double2 t, double2 te)
+k_saddle(int n, int R, const int *__restrict__ sptr, const I *__restrict__ col, const VA vm0,
+         const VA vk0, const XT *__restrict__ x, double2 *y, double2 t, double2 te)
 {
+    extern __shared__ __align__(8) unsigned char lds_tab[];
+    using VS = typename Staged<VA>::type;
+    const VS vm = Staged<VA>::stage(vm0, lds_tab);
+    const VS vk = Staged<VA>::stage(vk0, lds_tab + lds_bytes_dev(vm0));
     const int row = xcd_block() * kBlock + threadIdx.x;
     if (row >= n)
         return;
@@ -144,7 +143,7 @@ k_saddle(int n, int R, const int *__restrict__ sptr,
         const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
         if (width > 0) {
             SaddleEnt e;
-            saddle_load<I>(base, width, lane, row, col, vm, vk, e);
+            saddle_load<I, VS>(base, width, lane, row, col, vm, vk, e);
             double2 x0[RB][kSellUnroll], x1[RB][kSellUnroll];
 #pragma unroll
             for (int q = 0; q < RB; ++q)
@@ -171,7 +170,7 @@ k_saddle(int n, int R, const int *__restrict__ sptr,
     for (int q = 0; q < RB; ++q)
         if (RB == 1 || r0 + q < R) {
             double2 y0, y1;
-            saddle_row<I, U8, XT>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
+            saddle_row<I, U8, XT, VS>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
             double2 *yr = y + (r0 + q) * len;
             yr[row] = y0;
             yr[n + row] = y1;
@@ -181,18 +180,20 @@ k_saddle(int n, int R, const int *__restrict__ sptr,
 // y = b - A x over a grid-stride loop, and partial sums of |y1|^2 + w2 |y2|^2
 // per species (y1, y2: the two block rows; w2 = 1 gives the 2-norm; per run:
 // vectors advance by 2n, part by one run's slots)
-template <class I, bool U8>
+template <class I, bool U8, class VA>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
-k_saddle_resid(int n, const int *__restrict__ sptr,
-                                                         const I *__restrict__ col,
-                                                         const double *__restrict__ vm,
-                                                         const double *__restrict__ vk,
+k_saddle_resid(int n, const int *__restrict__ sptr, const I *__restrict__ col, const VA vm0,
+               const VA vk0,
                                                          const double2 *__restrict__ x,
                                                          const double2 *__restrict__ b, double2 *y,
                                                          double2 t, double2 te, double2 *part,
                                                          double w2)
 {
     __shared__ double2 sh[kBlock / 64];
+    extern __shared__ __align__(8) unsigned char lds_tab[];
+    using VS = typename Staged<VA>::type;
+    const VS vm = Staged<VA>::stage(vm0, lds_tab);
+    const VS vk = Staged<VA>::stage(vk0, lds_tab + lds_bytes_dev(vm0));
     x = run_at(x, 2l * n);
     b = run_at(b, 2l * n);
     y = run_at(y, 2l * n);
@@ -200,7 +201,7 @@ k_saddle_resid(int n, const int *__restrict__ sptr,
     double2 nrm = d2(0.0, 0.0);
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
         double2 y0, y1;
-        saddle_row<I, U8>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+        saddle_row<I, U8, double2, VS>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
         const double2 b0 = b[row], b1 = b[n + row];
         y0 = d2(b0.x - y0.x, b0.y - y0.y);
         y1 = d2(b1.x - y1.x, b1.y - y1.y);
@@ -1249,35 +1250,45 @@ inline const Ctl &head(const Solver &S, int r)
 
 }  // namespace
 
-template <class I, bool U8, class XT>
-static void saddle_rb(Solver &S, const I *col, const XT *x, double2 *y)
+template <class I, bool U8, class XT, class VA>
+static void saddle_rb(Solver &S, const I *col, const VA &vm, const VA &vk, const XT *x, double2 *y)
 {
     const int n = S.nv, R = S.nrun, rb = rb_of(S);
     const dim3 g = grid_rb(nblk(n), R, rb);
     const double2 t = pair(S.tau_s), te = pair(S.te_s);
+    const size_t lb = lds_bytes(vm) + lds_bytes(vk);
     if (rb >= 4)
-        k_saddle<I, U8, 4, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
-                                                           y, t, te);
+        k_saddle<I, U8, 4, XT, VA><<<g, kBlock, lb, S.stream>>>(n, R, S.sM.sptr, col, vm, vk, x, y,
+                                                               t, te);
     else if (rb == 2)
-        k_saddle<I, U8, 2, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
-                                                           y, t, te);
+        k_saddle<I, U8, 2, XT, VA><<<g, kBlock, lb, S.stream>>>(n, R, S.sM.sptr, col, vm, vk, x, y,
+                                                               t, te);
     else
-        k_saddle<I, U8, 1, XT><<<g, kBlock, 0, S.stream>>>(n, R, S.sM.sptr, col, S.sM.val, S.sK, x,
-                                                           y, t, te);
+        k_saddle<I, U8, 1, XT, VA><<<g, kBlock, lb, S.stream>>>(n, R, S.sM.sptr, col, vm, vk, x, y,
+                                                               t, te);
 }
 
 template <class XT>
 static void apply_saddle_t(Solver &S, const XT *x, double2 *y)
 {
     const bool u8 = S.sM.wmax <= kSellUnroll;
-    if (S.sM.ocol && u8)
-        saddle_rb<int16_t, true, XT>(S, S.sM.ocol, x, y);
+    using VP = VPlain<double>;
+    using VT = VTab<double>;
+    const VP pm{S.sM.val}, pk{S.sK};
+    const bool tab = S.sM.ocol && S.vtM.ix && S.vtK.ix;
+    const VT tm{S.vtM.ix, S.vtM.tab, S.vtM.m}, tk{S.vtK.ix, S.vtK.tab, S.vtK.m};
+    if (tab && u8)
+        saddle_rb<int16_t, true, XT, VT>(S, S.sM.ocol, tm, tk, x, y);
+    else if (tab)
+        saddle_rb<int16_t, false, XT, VT>(S, S.sM.ocol, tm, tk, x, y);
+    else if (S.sM.ocol && u8)
+        saddle_rb<int16_t, true, XT, VP>(S, S.sM.ocol, pm, pk, x, y);
     else if (S.sM.ocol)
-        saddle_rb<int16_t, false, XT>(S, S.sM.ocol, x, y);
+        saddle_rb<int16_t, false, XT, VP>(S, S.sM.ocol, pm, pk, x, y);
     else if (u8)
-        saddle_rb<int, true, XT>(S, S.sM.col, x, y);
+        saddle_rb<int, true, XT, VP>(S, S.sM.col, pm, pk, x, y);
     else
-        saddle_rb<int, false, XT>(S, S.sM.col, x, y);
+        saddle_rb<int, false, XT, VP>(S, S.sM.col, pm, pk, x, y);
 }
 
 void apply_saddle(Solver &S, const double2 *x, double2 *y) { apply_saddle_t<double2>(S, x, y); }
@@ -1287,18 +1298,31 @@ static void saddle_resid(Solver &S, dim3 g, const double2 *x, double2 *y, double
 {
     const int n = S.nv;
     const bool u8 = S.sM.wmax <= kSellUnroll;
-    if (S.sM.ocol && u8)
-        k_saddle_resid<int16_t, true><<<g, kBlock, 0, S.stream>>>(
-            n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+    using VP = VPlain<double>;
+    using VT = VTab<double>;
+    const VP pm{S.sM.val}, pk{S.sK};
+    const bool tab = S.sM.ocol && S.vtM.ix && S.vtK.ix;
+    const VT tm{S.vtM.ix, S.vtM.tab, S.vtM.m}, tk{S.vtK.ix, S.vtK.tab, S.vtK.m};
+    const double2 t = pair(S.tau_s), te = pair(S.te_s);
+    const size_t lbt = lds_bytes(tm) + lds_bytes(tk);
+    if (tab && u8)
+        k_saddle_resid<int16_t, true, VT><<<g, kBlock, lbt, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, tm, tk, x, S.b, y, t, te, part, w2);
+    else if (tab)
+        k_saddle_resid<int16_t, false, VT><<<g, kBlock, lbt, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, tm, tk, x, S.b, y, t, te, part, w2);
+    else if (S.sM.ocol && u8)
+        k_saddle_resid<int16_t, true, VP><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, pm, pk, x, S.b, y, t, te, part, w2);
     else if (S.sM.ocol)
-        k_saddle_resid<int16_t, false><<<g, kBlock, 0, S.stream>>>(
-            n, S.sM.sptr, S.sM.ocol, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+        k_saddle_resid<int16_t, false, VP><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.ocol, pm, pk, x, S.b, y, t, te, part, w2);
     else if (u8)
-        k_saddle_resid<int, true><<<g, kBlock, 0, S.stream>>>(
-            n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+        k_saddle_resid<int, true, VP><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.col, pm, pk, x, S.b, y, t, te, part, w2);
     else
-        k_saddle_resid<int, false><<<g, kBlock, 0, S.stream>>>(
-            n, S.sM.sptr, S.sM.col, S.sM.val, S.sK, x, S.b, y, pair(S.tau_s), pair(S.te_s), part, w2);
+        k_saddle_resid<int, false, VP><<<g, kBlock, 0, S.stream>>>(
+            n, S.sM.sptr, S.sM.col, pm, pk, x, S.b, y, t, te, part, w2);
 }
 
 // b = (M phi + tau G, -(tau'/eps) f) for the current state of every run
@@ -1322,8 +1346,8 @@ void compute_rhs(Solver &S)
         k_rhs_gather<4><<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.vslot_ptr, S.vslot, S.vol, ns,
                                                              S.fslot, S.f);
     }
-    sell_spmv<SP_SET, double>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val, S.x,
-                              len, nullptr, S.b, len);
+    sell_spmv<SP_SET, double>(st, R, rb_of(S), n, S.sM.sptr, S.sM.col, S.sM.ocol, S.sM.val,
+                              S.vtM.ix, S.vtM.tab, S.vtM.m, S.x, len, nullptr, S.b, len);
     boundary_rhs(S, nullptr);
     k_rhs_second<<<grid(nblk(n), R), kBlock, 0, st>>>(n, S.f, S.b + n, pair(S.te_s));
     CHM_HIP(hipGetLastError());

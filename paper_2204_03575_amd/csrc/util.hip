@@ -280,6 +280,133 @@ void csr_to_sell(const Csr &A, Sell &S, Pool &pool, hipStream_t s, bool offsets1
     }
 }
 
+// ---- value tables: the distinct values of an array (compared as bit
+// patterns) in ascending bit order, and a 16-bit index per entry ----
+constexpr unsigned long long kVtEmpty = 0x7FF8DEADBEEF0001ull;   // a NaN no kernel writes
+constexpr int kVtSlots = 16384;                                  // hash slots (power of two)
+
+__device__ inline unsigned vt_hash(unsigned long long k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    return (unsigned)k;
+}
+
+// every value's bit pattern into an open-addressing set; a pattern equal to
+// the empty marker or a full probe sequence sets *bad
+__global__ void __launch_bounds__(256) k_vt_insert(const double *__restrict__ v, int64_t n,
+                                                   unsigned long long *slots, int *bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (__hip_atomic_load(bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;   // too many values for a table: stop early
+        const unsigned long long key = (unsigned long long)__double_as_longlong(v[i]);
+        if (key == kVtEmpty) {
+            *bad = 1;
+            return;
+        }
+        unsigned h = vt_hash(key) & (kVtSlots - 1);
+        int probe = 0;
+        for (; probe < 64; ++probe, h = (h + 1) & (kVtSlots - 1)) {
+            // read past the L1 cache, which other CUs' inserts do not update
+            const unsigned long long cur =
+                __hip_atomic_load(slots + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur == key)
+                break;
+            if (cur == kVtEmpty) {
+                const unsigned long long prev = atomicCAS(slots + h, kVtEmpty, key);
+                if (prev == kVtEmpty || prev == key)
+                    break;
+            }
+        }
+        if (probe == 64)
+            *bad = 1;
+    }
+}
+
+// the occupied slots, packed (in no particular order) and counted
+__global__ void __launch_bounds__(256) k_vt_pack(const unsigned long long *slots,
+                                                 unsigned long long *keys, int *count)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kVtSlots || slots[i] == kVtEmpty)
+        return;
+    keys[atomicAdd(count, 1)] = slots[i];
+}
+
+// sorted table: key k goes to its rank among the (distinct) keys
+__global__ void __launch_bounds__(256) k_vt_rank(const unsigned long long *__restrict__ keys,
+                                                 int m, unsigned long long *tab)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m)
+        return;
+    const unsigned long long k = keys[i];
+    int r = 0;
+    for (int j = 0; j < m; ++j)
+        r += keys[j] < k;
+    tab[r] = k;
+}
+
+// each entry's position in the sorted table (binary search on bit patterns)
+__global__ void __launch_bounds__(256) k_vt_index(const double *__restrict__ v, int64_t n,
+                                                  const unsigned long long *__restrict__ tab,
+                                                  int m, uint16_t *ix)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long key = (unsigned long long)__double_as_longlong(v[i]);
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (tab[mid] < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        ix[i] = (uint16_t)lo;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_vt_fill(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        p[i] = kVtEmpty;
+}
+
+ValueTable value_table(const double *v, int64_t n, Pool &pool, hipStream_t s)
+{
+    ValueTable t;
+    if (n <= 0)
+        return t;
+    Pool tmp;
+    unsigned long long *slots = tmp.get<unsigned long long>(kVtSlots);
+    unsigned long long *keys = tmp.get<unsigned long long>(kVtSlots);
+    int *flags = tmp.get<int>(2);
+    k_vt_fill<<<kVtSlots / 256, 256, 0, s>>>(slots, kVtSlots);
+    fill_int(flags, 0, 2, s);
+    const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    k_vt_insert<<<grid, 256, 0, s>>>(v, n, slots, flags);
+    k_vt_pack<<<kVtSlots / 256, 256, 0, s>>>(slots, keys, flags + 1);
+    CHM_HIP(hipGetLastError());
+    int hf[2];
+    CHM_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    CHM_HIP(hipStreamSynchronize(s));
+    const int m = hf[1];
+    if (hf[0] || m <= 0 || m > kVtMax)
+        return t;   // no table: the kernels read the values themselves
+    unsigned long long *tab = pool.get<unsigned long long>(m);
+    k_vt_rank<<<(m + 255) / 256, 256, 0, s>>>(keys, m, tab);
+    t.ix = pool.get<uint16_t>(n);
+    k_vt_index<<<grid, 256, 0, s>>>(v, n, tab, m, t.ix);
+    CHM_HIP(hipGetLastError());
+    t.tab = reinterpret_cast<double *>(tab);
+    t.m = m;
+    CHM_HIP(hipStreamSynchronize(s));   // the scratch pool is freed on return
+    return t;
+}
+
 void sell_values(const Csr &A, const Sell &S, const double *csr_vals, double *sell_vals,
                  hipStream_t s)
 {
