@@ -61,8 +61,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_cheb_box96_counters.md.  Keyed by workload and
 # precision, for the default 16-bit SELL column offsets; None where the counters were not
 # taken (or the kernel changed since, or with --wide-index).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 35.13e6, ("square512", "fp32"): 20.49e6,
-                            ("box96", "fp64"): 99.07e6, ("box96", "fp32"): 58.96e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 24.09e6, ("square512", "fp32"): 20.49e6,
+                            ("box96", "fp64"): 58.23e6, ("box96", "fp32"): 44.68e6}
 
 
 def parse():
@@ -99,6 +99,9 @@ def parse():
                     help="keep 32-bit SELL column indices (the comparison run for the 16-bit "
                          "column offsets; bitwise the same results)")
     ap.add_argument("--no-timer", action="store_true", help="do not time the dominant kernel")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip timing the dominant kernel once more with every value read per "
+                         "entry (values_direct = 1)")
     ap.add_argument("--kernel-steps", type=int, default=2,
                     help="time steps of the event-timed pass of the dominant kernel")
     ap.add_argument("--no-mixed", action="store_true",
@@ -588,6 +591,28 @@ def main():
                                          "kernels": "torch.mul(x, 1.0) and torch.sum(x), "
                                                     "1 GiB FP64, HIP events"}
         out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+        out["roofline"]["value_tables"] = {
+            "as_fine": g.value_table(1, 0), "mass_fine": g.value_table(0, 0),
+            "M": g.value_table(-1, 0), "K": g.value_table(-1, 1),
+            "note": "distinct values per table; 0 = values read per entry"}
+        if not args.no_direct:
+            # the same launches reading every value (values_direct = 1): the
+            # bytes the tables save and the time they buy
+            gd = Solver(co, ce, dict(p, values_direct=1))
+            gd.set_fields(php, phn)
+            gd.step(1)
+            gd.timer_enable(0, True)
+            gd.step(args.kernel_steps)
+            dl, dms, dbytes = gd.timer_read()
+            gd.timer_enable(0, False)
+            d_avg = dms * 1e-3 / max(1, dl)
+            d_per = dbytes / max(1, dl)
+            d_ach = d_per / d_avg / 1e9 if d_avg > 0 else 0.0
+            out["roofline"]["direct_values"] = {
+                "avg_us": d_avg * 1e6, "bytes_per_launch": d_per, "achieved": d_ach,
+                "frac": d_ach / HBM_PEAK_GBS, "launches": dl,
+                "time_ratio_tables_vs_direct": avg_s / d_avg if d_avg > 0 else None}
+            del gd
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
