@@ -814,6 +814,8 @@ void prolong_cheb(Solver &S, const Level &L, const pair_t<T> *b, const pair_t<T>
                   const pair_t<T> *e, pair_t<T> *x0, pair_t<T> *x1, double c2d)
 {
     const MatView<T> AM = L.viewAM<T>(), P = L.viewP<T>();
+    if (!AM.cval || !P.cval || !P.rp)
+        throw Failure(CHM_EINVAL, "fused prolongation without CSR values of [A | A P] and P");
     const T *dinv = L.dinv_t<T>();
     const T c2 = T(c2d);
     const int R = S.nrun;
@@ -852,7 +854,9 @@ void vcycle_level(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<T> 
     // the prolongation fused with the first post-smoothing step (CSR levels
     // with AM): pre-smoothing then ends in xt, and the post-smoothing steps
     // alternate between x and r so that the last one lands in x
-    const bool fused_post = L.AM.nnz > 0 && !timed;
+    // (it reads P's CSR values, which the FP32 copy holds only where P's
+    // kernels use the CSR layout too)
+    const bool fused_post = L.AM.nnz > 0 && L.gsP > 0 && !timed;
     // Pre-smoothing from zero.  Every step after the first writes the buffer
     // not holding the current iterate; 2 deg - 1 such steps follow the first,
     // so starting in xt leaves the result in x.
