@@ -38,6 +38,11 @@ inline int nblk(long n, int bs = kBlock) { return (int)std::max<long>(1, (n + bs
 // rows average at most this many entries (two passes of four entries on 32
 // lanes); longer rows (3D patterns) run faster as the two products.
 constexpr double kFuseRowMax = 256.0;
+// R A is formed to try the fusion only on levels whose A averages at most this
+// many entries per row: the 2D P1 levels (7 and 11.3 entries) give RR rows of
+// 72 and 139, the 3D ones (15 and 40 entries) rows of 339 and 1,112, so on a
+// 3D hierarchy the product was formed only to be thrown away.
+constexpr double kFuseArow = 12.0;
 
 __device__ inline uint64_t splitmix_at(uint64_t i)
 {
@@ -895,8 +900,9 @@ void amg_build(Solver &S, Hierarchy &H, const Csr &A0)
         spgemm(A, L.P, AP, tmp2, tmp, st);
         // RR = [R | -R A] for the residual and its restriction in one
         // product, where its rows are short enough (R A holds at least R's
-        // entries, so R's rows bound it from below)
-        if (2.0 * L.R.nnz <= kFuseRowMax * (double)nc) {
+        // entries, so R's rows bound it from below), and only tried on levels
+        // whose A rows are short
+        if (A.nnz <= kFuseArow * (double)n && 2.0 * L.R.nnz <= kFuseRowMax * (double)nc) {
             Csr RA;
             spgemm(L.R, A, RA, tmp2, tmp, st);
             if ((double)L.R.nnz + RA.nnz <= kFuseRowMax * (double)nc)
