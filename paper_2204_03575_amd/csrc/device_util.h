@@ -239,14 +239,48 @@ template <class VA> struct Staged {
     static constexpr size_t bytes(const VA &) { return 0; }
     __device__ static VA stage(const VA &v, void *) { return v; }
 };
+// N table entries per thread (entries i = thread + j kBlock; the kernels that
+// stage tables run blocks of kBlock threads), every load issued before the
+// first LDS write: a loop that stores after each load waits a whole memory
+// round trip per pass.  Past the end (m >= 1) the last entry is loaded again
+// and not stored.
+template <int N, class T>
+__device__ inline void stage_entries(const T *__restrict__ tab, int m, T *t)
+{
+    T v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        v[j] = tab[min((int)threadIdx.x + j * kBlock, m - 1)];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+        if (i < m)
+            t[i] = v[j];
+    }
+    // every load completes here, stored or not: a load left in flight past
+    // the barrier would make each later write of its registers wait for it
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        __asm__ volatile("" ::"v"(v[j]));
+}
+
 template <class T> struct Staged<VTab<T>> {
     using type = VLds<T>;
     static size_t bytes(const VTab<T> &v) { return (size_t)v.m * sizeof(T); }
     __device__ static VLds<T> stage(const VTab<T> &v, void *lds)
     {
+        static_assert(kVtMax <= 8 * kBlock, "a table takes at most 8 entries per thread");
         T *t = static_cast<T *>(lds);
-        for (int i = threadIdx.x; i < v.m; i += blockDim.x)
-            t[i] = v.tab[i];
+        const int passes = (v.m + kBlock - 1) / kBlock;   // 0 (no table) to 8
+        if (passes == 1) {
+            if ((int)threadIdx.x < v.m)
+                t[threadIdx.x] = v.tab[threadIdx.x];
+        } else if (passes == 2)
+            stage_entries<2, T>(v.tab, v.m, t);
+        else if (passes > 2 && passes <= 4)
+            stage_entries<4, T>(v.tab, v.m, t);
+        else if (passes > 4)
+            stage_entries<8, T>(v.tab, v.m, t);
         __syncthreads();
         return VLds<T>{v.ix, t};
     }

@@ -65,23 +65,26 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, int R, const int *__rest
 {
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
-    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
-    if (row >= n)
-        return;
     // FP64: D^-1 of the row is 1 / a_ii of the entries just read, the value
     // the setup stored (the same IEEE division), so it is not loaded; the
     // FP32 path loads its rounded copy
     constexpr bool own = std::is_same<T, double>::value;
-    // every run's operands of the update first, then the row product
+    // every run's operands of the update first (in flight while the block
+    // stages its value table), then the row product
     const int r0 = run0<RB>();
     ChebRow<T> o[RB];
+    if (row < n) {
 #pragma unroll
-    for (int q = 0; q < RB; ++q)
-        if (RB == 1 || r0 + q < R) {
-            const long off = (long)(r0 + q) * n;
-            o[q] = cheb_row<T>(b + off, xk + off, own ? nullptr : dinv, xprev + off, row, prev);
-        }
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R) {
+                const long off = (long)(r0 + q) * n;
+                o[q] = cheb_row<T>(b + off, xk + off, own ? nullptr : dinv, xprev + off, row, prev);
+            }
+    }
+    const VS val = Staged<VA>::stage(val0, lds_tab);
+    if (row >= n)
+        return;
     sell_row_runs<I, T, RB, VS>(sptr, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
         ChebRow<T> &w = o[q];
         if (own)
@@ -206,16 +209,18 @@ k_cheb_first(int n, int R, const int *__restrict__ sptr,
 {
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
-    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
+    const int r0 = run0<RB>();
+    ChebRow<T> o[RB];   // loaded while the block stages its value table
+    if (row < n) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (RB == 1 || r0 + q < R)
+                o[q] = first_row(FirstIter<T>{b + (long)(r0 + q) * n, dinv, c2first}, row);
+    }
+    const VS val = Staged<VA>::stage(val0, lds_tab);
     if (row >= n)
         return;
-    const int r0 = run0<RB>();
-    ChebRow<T> o[RB];
-#pragma unroll
-    for (int q = 0; q < RB; ++q)
-        if (RB == 1 || r0 + q < R)
-            o[q] = first_row(FirstIter<T>{b + (long)(r0 + q) * n, dinv, c2first}, row);
     sell_row_first_runs<I, T, RB, VS>(sptr, col, val, b, dinv, c2first, n, row, R,
                                   [&](int q, int r, pair_t<T> s) {
                                       const ChebRow<T> &w = o[q];
