@@ -379,6 +379,20 @@ __device__ inline pair_t<T> sell_row(const int *__restrict__ sptr, const I *__re
     return mk<T>(ax, ay);
 }
 
+// The bounds of the SELL-64 slice that holds `row` (wave-uniform: a wave's
+// 64 rows form one slice).  Rows past n take the last slice, so a kernel
+// can load the bounds before its early return (in flight with its other
+// prologue loads) and stay in bounds.
+struct SliceAt {
+    int base, width;
+};
+__device__ inline SliceAt slice_at(const int *__restrict__ sptr, int row, int n)
+{
+    const int s = __builtin_amdgcn_readfirstlane(min(row, n - 1) / kSlice);
+    const int base = sptr[s];
+    return SliceAt{base, (sptr[s + 1] - base) / kSlice};
+}
+
 // ------------------------------------------------------------------ several runs per lane
 // Batched launches of the SELL kernels: block row blockIdx.y covers the RB
 // runs r0 = RB blockIdx.y, ..., r0 + RB - 1 (those below R), so every matrix
@@ -396,13 +410,13 @@ inline dim3 grid_rb(int x, int runs, int rb) { return dim3(x, (runs + rb - 1) / 
 // before the first product; wider slices go run by run (with one run per
 // lane, slices up to twice that width still take the unrolled path).
 template <class I, class T, int RB, class VA, class F>
-__device__ inline void sell_row_runs(const int *__restrict__ sptr, const I *__restrict__ col,
-                                     const VA &val, const pair_t<T> *__restrict__ x,
-                                     long sx, int row, int R, F &&f)
+__device__ inline void sell_row_runs(const int *__restrict__ sptr, SliceAt sl,
+                                     const I *__restrict__ col, const VA &val,
+                                     const pair_t<T> *__restrict__ x, long sx, int row, int R,
+                                     F &&f)
 {
     const int r0 = run0<RB>();
-    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    const int lane = row % kSlice, base = sl.base, width = sl.width;
     auto runs_w = [&](auto wtag) {
         constexpr int W = decltype(wtag)::value;
         SellEnt<W, T> e;
@@ -467,11 +481,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, int R, const int *__rest
 {
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
-    const VS val = Staged<VA>::stage(val0, lds_tab);
     const int row = xcd_block() * kBlock + threadIdx.x;
+    const SliceAt sl = slice_at(sptr, row, n);   // loaded while the table is staged
+    const VS val = Staged<VA>::stage(val0, lds_tab);
     if (row >= n)
         return;
-    sell_row_runs<I, T, RB, VS>(sptr, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
+    sell_row_runs<I, T, RB, VS>(sptr, sl, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
         spmv_store<MODE, T>(s, b ? b + r * sy : b, y + r * sy, row);
     });
 }

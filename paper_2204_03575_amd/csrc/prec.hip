@@ -82,10 +82,11 @@ __global__ void __launch_bounds__(kBlock) k_cheb(int n, int R, const int *__rest
                 o[q] = cheb_row<T>(b + off, xk + off, own ? nullptr : dinv, xprev + off, row, prev);
             }
     }
+    const SliceAt sl = slice_at(sptr, row, n);
     const VS val = Staged<VA>::stage(val0, lds_tab);
     if (row >= n)
         return;
-    sell_row_runs<I, T, RB, VS>(sptr, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
+    sell_row_runs<I, T, RB, VS>(sptr, sl, col, val, xk, n, row, R, [&](int q, int r, pair_t<T> s, T diag) {
         ChebRow<T> &w = o[q];
         if (own)
             w.di = T(1) / diag;
@@ -126,14 +127,13 @@ template <class T> __device__ inline ChebRow<T> first_row(const FirstIter<T> &x1
 // loaded once on slices at most kSellUnroll wide; f(q, r, product) with
 // q = r - r0
 template <class I, class T, int RB, class VA, class F>
-__device__ inline void sell_row_first_runs(const int *__restrict__ sptr, const I *__restrict__ col,
+__device__ inline void sell_row_first_runs(SliceAt sl, const I *__restrict__ col,
                                            const VA &val, const pair_t<T> *__restrict__ b,
                                            const T *__restrict__ dinv, T c2f, int n, int row, int R,
                                            F &&f)
 {
     const int r0 = run0<RB>();
-    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    const int lane = row % kSlice, base = sl.base, width = sl.width;
     auto runs_w = [&](auto wtag) {
         constexpr int W = decltype(wtag)::value;
         int c[W];
@@ -218,10 +218,11 @@ k_cheb_first(int n, int R, const int *__restrict__ sptr,
             if (RB == 1 || r0 + q < R)
                 o[q] = first_row(FirstIter<T>{b + (long)(r0 + q) * n, dinv, c2first}, row);
     }
+    const SliceAt sl = slice_at(sptr, row, n);
     const VS val = Staged<VA>::stage(val0, lds_tab);
     if (row >= n)
         return;
-    sell_row_first_runs<I, T, RB, VS>(sptr, col, val, b, dinv, c2first, n, row, R,
+    sell_row_first_runs<I, T, RB, VS>(sl, col, val, b, dinv, c2first, n, row, R,
                                   [&](int q, int r, pair_t<T> s) {
                                       const ChebRow<T> &w = o[q];
                                       x1out[(long)r * n + row] = w.xi;
