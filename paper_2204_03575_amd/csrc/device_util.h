@@ -238,6 +238,11 @@ template <class VA> struct Staged {
     using type = VA;
     static constexpr size_t bytes(const VA &) { return 0; }
     __device__ static VA stage(const VA &v, void *) { return v; }
+    __device__ static void stage2(const VA &a, const VA &b, void *, VA &sa, VA &sb)
+    {
+        sa = a;
+        sb = b;
+    }
 };
 // N table entries per thread (entries i = thread + j kBlock; the kernels that
 // stage tables run blocks of kBlock threads), every load issued before the
@@ -264,6 +269,31 @@ __device__ inline void stage_entries(const T *__restrict__ tab, int m, T *t)
         __asm__ volatile("" ::"v"(v[j]));
 }
 
+// the same for two tables (the second stored after the first), all loads
+// of both issued before the first write
+template <int N, class T>
+__device__ inline void stage_entries2(const T *__restrict__ ta, int ma, const T *__restrict__ tb,
+                                      int mb, T *t)
+{
+    T va[N], vb[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        va[j] = ta[min((int)threadIdx.x + j * kBlock, ma - 1)];
+        vb[j] = tb[min((int)threadIdx.x + j * kBlock, mb - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+        if (i < ma)
+            t[i] = va[j];
+        if (i < mb)
+            t[ma + i] = vb[j];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        __asm__ volatile("" ::"v"(va[j]), "v"(vb[j]));
+}
+
 template <class T> struct Staged<VTab<T>> {
     using type = VLds<T>;
     static size_t bytes(const VTab<T> &v) { return (size_t)v.m * sizeof(T); }
@@ -283,6 +313,24 @@ template <class T> struct Staged<VTab<T>> {
             stage_entries<8, T>(v.tab, v.m, t);
         __syncthreads();
         return VLds<T>{v.ix, t};
+    }
+    // two tables (both with entries) behind one barrier: a's at lds, b's after it
+    __device__ static void stage2(const VTab<T> &a, const VTab<T> &b, void *lds, VLds<T> &sa,
+                                  VLds<T> &sb)
+    {
+        T *t = static_cast<T *>(lds);
+        const int passes = (max(a.m, b.m) + kBlock - 1) / kBlock;   // 1 to 8
+        if (passes == 1)
+            stage_entries2<1, T>(a.tab, a.m, b.tab, b.m, t);
+        else if (passes == 2)
+            stage_entries2<2, T>(a.tab, a.m, b.tab, b.m, t);
+        else if (passes > 2 && passes <= 4)
+            stage_entries2<4, T>(a.tab, a.m, b.tab, b.m, t);
+        else if (passes > 4)
+            stage_entries2<8, T>(a.tab, a.m, b.tab, b.m, t);
+        __syncthreads();
+        sa = VLds<T>{a.ix, t};
+        sb = VLds<T>{b.ix, t + a.m};
     }
 };
 template <class VA> inline size_t lds_bytes(const VA &v) { return Staged<VA>::bytes(v); }

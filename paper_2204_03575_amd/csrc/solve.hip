@@ -88,13 +88,11 @@ __device__ inline void saddle_dot(const SaddleEnt &e, const double2 *x0, const d
 }
 
 template <class I, bool U8, class XT, class VA>
-__device__ inline void saddle_row(int n, int row, const int *__restrict__ sptr,
-                                  const I *__restrict__ col, const VA &vm, const VA &vk,
-                                  const XT *__restrict__ x, double2 t, double2 te, double2 &y0,
-                                  double2 &y1)
+__device__ inline void saddle_row(int n, int row, SliceAt sl, const I *__restrict__ col,
+                                  const VA &vm, const VA &vk, const XT *__restrict__ x, double2 t,
+                                  double2 te, double2 &y0, double2 &y1)
 {
-    const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
-    const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+    const int lane = row % kSlice, base = sl.base, width = sl.width;
     if (U8 && width > 0) {
         SaddleEnt e;
         saddle_load<I, VA>(base, width, lane, row, col, vm, vk, e);
@@ -131,16 +129,16 @@ k_saddle(int n, int R, const int *__restrict__ sptr, const I *__restrict__ col, 
 {
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
-    const VS vm = Staged<VA>::stage(vm0, lds_tab);
-    const VS vk = Staged<VA>::stage(vk0, lds_tab + lds_bytes_dev(vm0));
     const int row = xcd_block() * kBlock + threadIdx.x;
+    const SliceAt sl = slice_at(sptr, row, n);   // in flight while the tables are staged
+    VS vm, vk;
+    Staged<VA>::stage2(vm0, vk0, lds_tab, vm, vk);
     if (row >= n)
         return;
     const int r0 = run0<RB>();
     const long len = 2l * n;
     if (U8 && RB > 1) {
-        const int s = __builtin_amdgcn_readfirstlane(row / kSlice), lane = row % kSlice;
-        const int base = sptr[s], width = (sptr[s + 1] - base) / kSlice;
+        const int lane = row % kSlice, base = sl.base, width = sl.width;
         if (width > 0) {
             SaddleEnt e;
             saddle_load<I, VS>(base, width, lane, row, col, vm, vk, e);
@@ -170,7 +168,7 @@ k_saddle(int n, int R, const int *__restrict__ sptr, const I *__restrict__ col, 
     for (int q = 0; q < RB; ++q)
         if (RB == 1 || r0 + q < R) {
             double2 y0, y1;
-            saddle_row<I, U8, XT, VS>(n, row, sptr, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
+            saddle_row<I, U8, XT, VS>(n, row, sl, col, vm, vk, x + (r0 + q) * len, t, te, y0, y1);
             double2 *yr = y + (r0 + q) * len;
             yr[row] = y0;
             yr[n + row] = y1;
@@ -192,8 +190,8 @@ k_saddle_resid(int n, const int *__restrict__ sptr, const I *__restrict__ col, c
     __shared__ double2 sh[kBlock / 64];
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
-    const VS vm = Staged<VA>::stage(vm0, lds_tab);
-    const VS vk = Staged<VA>::stage(vk0, lds_tab + lds_bytes_dev(vm0));
+    VS vm, vk;
+    Staged<VA>::stage2(vm0, vk0, lds_tab, vm, vk);
     x = run_at(x, 2l * n);
     b = run_at(b, 2l * n);
     y = run_at(y, 2l * n);
@@ -201,7 +199,7 @@ k_saddle_resid(int n, const int *__restrict__ sptr, const I *__restrict__ col, c
     double2 nrm = d2(0.0, 0.0);
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
         double2 y0, y1;
-        saddle_row<I, U8, double2, VS>(n, row, sptr, col, vm, vk, x, t, te, y0, y1);
+        saddle_row<I, U8, double2, VS>(n, row, slice_at(sptr, row, n), col, vm, vk, x, t, te, y0, y1);
         const double2 b0 = b[row], b1 = b[n + row];
         y0 = d2(b0.x - y0.x, b0.y - y0.y);
         y1 = d2(b1.x - y1.x, b1.y - y1.y);
