@@ -61,8 +61,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_cheb_box96_counters.md.  Keyed by workload and
 # precision, for the default 16-bit SELL column offsets; None where the counters were not
 # taken (or the kernel changed since, or with --wide-index).
-TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 24.09e6, ("square512", "fp32"): 20.49e6,
-                            ("box96", "fp64"): 58.23e6, ("box96", "fp32"): 44.68e6}
+TRAFFIC_BYTES_PER_LAUNCH = {("square512", "fp64"): 24.12e6, ("square512", "fp32"): 20.51e6,
+                            ("box96", "fp64"): 57.29e6, ("box96", "fp32"): 44.79e6}
 
 
 def parse():

@@ -775,7 +775,15 @@ pair_t<T> *presmooth(Solver &S, Hierarchy &H, int l, const pair_t<T> *b, pair_t<
     auto c2 = [&](int k) { return H.jacobi ? L.jac_omega : L.cheb_c2[k]; };
     pair_t<T> *cur = first, *oth = other;
     int k0 = 2;   // the first step k_cheb handles
-    if (deg >= 2) {
+    // FP64 SELL levels with a value table and slices wider than kSellUnroll
+    // (3D patterns) take step 1 as its own light launch and step 2 as a k_cheb
+    // step (x_1 gathered once, the same bits): the fused launch gathers b and
+    // D^-1 per entry of its 16-wide rows (18.9 us on the 96x96x48 box against
+    // 5.2 + 12.0 us).  FP32 and the 2D patterns gain nothing from the split.
+    const MatView<T> A = L.viewA<T>();
+    const bool fuse12 = !(std::is_same<T, double>::value && A.gs == 0 && A.ocol && A.vix &&
+                          L.sA.wmax > kSellUnroll);
+    if (deg >= 2 && fuse12) {
         // steps 1 and 2 in one launch; x_1 and x_2 land where the two
         // launches would put them
         launch_cheb_first<T>(S, H, l, b, cur, oth, c2(1), c1(2), c2(2));
