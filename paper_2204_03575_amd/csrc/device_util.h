@@ -530,12 +530,21 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, int R, const int *__rest
     extern __shared__ __align__(8) unsigned char lds_tab[];
     using VS = typename Staged<VA>::type;
     const int row = xcd_block() * kBlock + threadIdx.x;
-    const SliceAt sl = slice_at(sptr, row, n);   // loaded while the table is staged
+    // one run per lane: the row's y (SP_ADD) or b (SP_RESID) is loaded with the
+    // slice bounds, in flight while the table is staged
+    constexpr bool pre = RB == 1 && MODE != SP_SET;
+    pair_t<T> o = mk<T>(0, 0);
+    if (pre && row < n)
+        o = (MODE == SP_ADD ? y : b)[(long)run0<RB>() * sy + row];
+    const SliceAt sl = slice_at(sptr, row, n);
     const VS val = Staged<VA>::stage(val0, lds_tab);
     if (row >= n)
         return;
     sell_row_runs<I, T, RB, VS>(sptr, sl, col, val, x, sx, row, R, [&](int, int r, pair_t<T> s, T) {
-        spmv_store<MODE, T>(s, b ? b + r * sy : b, y + r * sy, row);
+        if (pre)
+            y[r * sy + row] = MODE == SP_ADD ? mk<T>(o.x + s.x, o.y + s.y) : mk<T>(o.x - s.x, o.y - s.y);
+        else
+            spmv_store<MODE, T>(s, b ? b + r * sy : b, y + r * sy, row);
     });
 }
 
