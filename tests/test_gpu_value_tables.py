@@ -102,3 +102,44 @@ def test_tables_in_a_batch_same_bits():
         f1, f0 = g1.get_fields(run=r), g0.get_fields(run=r)
         for f in FIELDS:
             assert np.array_equal(f1[f], f0[f]), (r, f)
+
+
+def layered_box(nx, ny, nz):
+    """Kuhn box of [0,1/32]^2 x [0,0.5] whose nz cell layers all differ in
+    thickness (nearly cubic cells on 8 x 8 x 64): every layer adds its own
+    element values, so the assembled M and K hold between 1,025 and 2,048
+    distinct values (about 1,300 each) and their tables take the largest
+    staging path (up to 8 entries per thread of a 256-thread block)."""
+    co, ce = S.mesh_box_3d(nx, ny, nz, 1.0 / 32, 1.0 / 32, 1.0)
+    t = 1.0 + 0.125 * np.arange(nz)
+    zs = np.concatenate([[0.0], np.cumsum(t)]) / np.sum(t) * 0.5
+    k = np.rint(co[:, 2] * nz).astype(int)
+    co = co.copy()
+    co[:, 2] = zs[k]
+    return co, ce
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tables_of_more_than_1024_values_same_bits(precision):
+    case("tables of 1,025-2,048 values vs direct values", precision=precision)
+    from paper_2204_03575_amd import Solver
+    co, ce = layered_box(8, 8, 64)
+    p = S.preset("square32", dim=3, n=(8, 8, 64), extent=(1.0 / 32, 1.0 / 32, 0.5),
+                 precision=precision)
+    php, phn, _ = S.initial_fractions(co.shape[0], p["mean_p"], p["mean_n"], seed=S.BASE_SEED)
+    out = []
+    for direct in (0, 1):
+        g = Solver(co, ce, dict(p, values_direct=direct))
+        g.set_fields(php, phn)
+        out.append((g, g.step(2)))
+    (g1, s1), (g0, s0) = out
+    m_m, m_k = g1.value_table(-1, 0), g1.value_table(-1, 1)
+    print(f"[tables] M {m_m} K {m_k}", flush=True)
+    assert 1024 < max(m_m, m_k) <= 2048 and min(m_m, m_k) > 0
+    assert g0.value_table(-1, 0) == 0 and g0.value_table(-1, 1) == 0
+    for k in range(2):
+        assert s1[k]["iters"] == s0[k]["iters"], k
+        assert s1[k]["relres"] == s0[k]["relres"], k
+    f1, f0 = g1.get_fields(), g0.get_fields()
+    for f in FIELDS:
+        assert np.array_equal(f1[f], f0[f]), f
